@@ -1,0 +1,158 @@
+/*
+ * libtbkrylov -- local Krylov-subspace density-matrix solve for linear-scaling
+ * tight-binding molecular dynamics on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Iitaka, "GPU-accelerated large-scale quantum molecular dynamics
+ * simulation of 3-dimensional C60 polymers"):
+ *   - Sec. 2, Eq. (1): a non-self-consistent tight-binding Hamiltonian with
+ *     on-site energies and two-centre hoppings; here an orthogonal sp3
+ *     Slater-Koster model, orbitals (s, px, py, pz) on every atom.
+ *   - Sec. 2, Eq. (2): the one-body density matrix rho = sum_m |m> f(e_m) <m|,
+ *     forces <F_i> = Tr[rho F_i] with F_i = -dH/dR_i.
+ *   - Sec. 2 (locality): every target atom i is solved using only the atoms
+ *     inside a cutoff sphere of radius r_cluster around it (cost O(n^3 N)).
+ *   - Sec. 3, Eq. (4): that local problem is projected on the Krylov subspace
+ *     K_r(H, Phi_i) = span{Phi_i, H Phi_i, ..., H^{r-1} Phi_i} seeded with the
+ *     target atom's orbitals (here all four of them, as one seed block), built
+ *     by the Lanczos recursion of Eqs. (6)-(9) in block form; the projected
+ *     block-tridiagonal matrix is diagonalised (Sec. 3, the LAPACK step).
+ *
+ * Conventions
+ *   - Every function returns an int status: TB_OK (0) or a negative TB_E* code;
+ *     tb_last_error() then holds a message.
+ *   - Pointers are DEVICE pointers unless their name ends in _host.
+ *   - Arrays are row-major (C order). Units: Angstrom, eV, eV/Angstrom.
+ *   - All work is enqueued on the stream given to tb_create; no function
+ *     synchronises the stream implicitly except tb_rho_layout (it returns a
+ *     host count) and tb_get_stats. Outputs are valid after a stream sync.
+ *   - The caller owns every input and output buffer. The context owns every
+ *     work buffer (neighbour and cluster lists, Hamiltonian pair data, Krylov
+ *     bases, projected matrices, eigen data, the chemical potential); it sizes
+ *     them once in tb_create from the capacities given there.
+ *   - Call order per geometry: tb_build_local_H -> tb_krylov_rho ->
+ *     tb_energy_forces. A call out of order returns TB_ESTATE.
+ */
+#ifndef TBKRYLOV_H
+#define TBKRYLOV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TB_OK = 0,
+  TB_EINVAL = -1,       /* null, non-finite or out-of-range argument */
+  TB_ECUTOFF = -2,      /* cutoff >= half a periodic box length */
+  TB_ECAPACITY = -3,    /* a list or Krylov size exceeds the tb_create capacity */
+  TB_EMU = -4,          /* electron count outside (0, 8N) */
+  TB_EUNSUPPORTED = -5, /* feature not provided (e.g. a non-orthorhombic cell) */
+  TB_EHIP = -6,         /* HIP runtime error; message holds the HIP error text */
+  TB_ESTATE = -7,       /* functions called out of order */
+  TB_EDEVICE = -8       /* a kernel raised its error flag (see tb_get_stats) */
+};
+
+/* Precision of the Krylov recursion (H.V products, basis storage and the
+ * re-orthogonalisation). Projected eigensolve, chemical potential, block
+ * normalisation norms, density-matrix assembly and forces are FP64 always. */
+enum { TB_FP64 = 0, TB_FP32 = 1 };
+
+/* Tight-binding parameters of the Xu-form carbon model (Sec. 4 names the
+ * Xu parameter set, cutoff 2.6 A). Hopping scale s(r) = (r0/r)^n
+ * exp{n[-(r/rc)^nc + (r0/rc)^nc]} below r1, the cubic
+ * s_tail[0] + s_tail[1] x + s_tail[2] x^2 + s_tail[3] x^3 (x = r - r1) on
+ * [r1, rm), zero beyond rm. The pair term phi(r) has the same form with
+ * (phi0, d0, m, mc, dc, d1, dm, phi_tail); E_rep = sum_i F(sum_j phi(r_ij)),
+ * F(x) = sum_k frep[k] x^k. struct_size must equal sizeof(tb_params). */
+typedef struct {
+  int64_t struct_size;
+  double eps_s, eps_p, v_sss, v_sps, v_pps, v_ppp; /* eV */
+  double r0, n, nc, rc, r1, rm, s_tail[4];
+  double phi0, d0, m, mc, dc, d1, dm, phi_tail[4], frep[5];
+} tb_params;
+
+typedef struct tb_ctx tb_ctx;
+
+/* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream). Capacities: at most
+ * n_atoms_max atoms, n_cluster_max atoms per cutoff sphere, r_max Krylov
+ * block steps; hop lists hold at most 24 neighbours within max(rm, dm).
+ * Allocates all work memory (size reported by tb_get_stats). */
+int tb_create(tb_ctx **ctx, int hip_device, void *hip_stream,
+              int64_t n_atoms_max, int n_cluster_max, int r_max);
+
+int tb_destroy(tb_ctx *ctx);
+
+/* Sec. 2 locality + Eq. (1): minimum-image neighbour lists, cutoff spheres
+ * C_i = {i} + {j : |d_ij| < r_cluster} (sorted by j), Slater-Koster pair data
+ * for every ordered pair closer than rm, and each sphere's local block
+ * structure. Two atoms a, b of C_i are coupled iff |x_b - x_a| < rm, where x
+ * is the position relative to the target atom i (minimum image).
+ *   pos       [n_atoms][3] device, Angstrom.
+ *   cell_host [3][3] row vectors of an orthorhombic box (off-diagonals 0).
+ *   periodic_host[3] 0/1 per axis; a non-periodic axis ignores the box.
+ * n_cluster_out [n_atoms] (device, nullable) receives |C_i|.
+ * Errors: TB_EINVAL, TB_ECUTOFF (r_cluster or rm >= half a periodic box
+ * length), TB_EUNSUPPORTED (non-orthorhombic), TB_ECAPACITY (raised on the
+ * next call from the device flag when a list overflows). */
+int tb_build_local_H(tb_ctx *ctx, int64_t n_atoms, const double *pos,
+                     const double *cell_host, const int *periodic_host,
+                     const tb_params *p_host, double r_cluster,
+                     int *n_cluster_out);
+
+/* Sec. 3: for every target atom, r block steps of the block Lanczos
+ * recursion (Eqs. 6-9 with 4x4 blocks A_k, B_k, seed = the atom's four
+ * orbitals) with full re-orthogonalisation, the eigensolve of the projected
+ * block-tridiagonal T, the global chemical potential and the density-matrix
+ * blocks of Eq. (2) restricted to the Krylov space:
+ *     rho[:, i] = Q Y f(Lambda) Y[0:4, :]^T,  f(e) = 2 / (1 + exp((e - mu)/kT)).
+ *   r           block steps (1 <= r <= r_max) unless r_per_atom is given.
+ *   r_per_atom  [n_atoms] device int, nullable: per-atom r.
+ *   mu          fixed chemical potential in eV, or NaN: then mu solves
+ *               sum_i sum_m f(lambda_m^i) w_m^i = n_electrons
+ *               (w_m^i = weight of Ritz pair m on the seed block).
+ *   precision   TB_FP64 or TB_FP32 (see the enum).
+ *   mu_out      device double (nullable) receives mu.
+ *   rho_out     [nnz_pairs][4][4] device: rho_out[p][a][b] = rho_{j a, i b}
+ *               for the pair list of tb_rho_layout (target i, row atom j).
+ * Errors: TB_EINVAL, TB_ECAPACITY, TB_EMU, TB_ESTATE. */
+int tb_krylov_rho(tb_ctx *ctx, int r, const int *r_per_atom, double kT,
+                  double mu, double n_electrons, int precision,
+                  double *mu_out, double *rho_out);
+
+/* Pair list of rho_out: for target atom i, the rows row_ptr[i] ..
+ * row_ptr[i+1]-1 hold j = i first, then the atoms within rm of i in
+ * increasing index. nnz_pairs_host receives the count (host). row_ptr
+ * [n_atoms+1] and col_j [nnz] are device arrays (nullable: count only).
+ * Synchronises the stream. Valid after tb_build_local_H. */
+int tb_rho_layout(tb_ctx *ctx, int64_t *nnz_pairs_host, int64_t *row_ptr,
+                  int *col_j);
+
+/* Sec. 2: band energy, entropy term, repulsion and forces from the density
+ * blocks of the last tb_krylov_rho:
+ *   E_band = sum_i sum_m lambda_m f_m w_m,
+ *   -TS    = -kT sum_i sum_m w_m 2 s(f_m/2),  s(q) = -q ln q - (1-q) ln(1-q),
+ *   E_rep  = sum_i F(sum_j phi(r_ij)),
+ *   F_k    = -sum_i sum_{j in hop(i)} Tr[(dH_ij/dR_k) rho_ji] - dE_rep/dR_k.
+ *   e_out  [4] device: E_band, -TS, E_rep, E_tot = E_band - TS + E_rep (eV).
+ *   forces [n_atoms][3] device, eV/Angstrom (nullable).
+ * Errors: TB_ESTATE, TB_EHIP. */
+int tb_energy_forces(tb_ctx *ctx, double *e_out, double *forces);
+
+/* Diagnostics (host): counters of the last calls. stats_host receives
+ * up to n_stats values: [0] device error flags, [1] max cluster size,
+ * [2] max hop count, [3] max local couplings per sphere, [4] total
+ * deflated columns, [5] atoms whose recursion stopped early (invariant
+ * space), [6] max eigen-iteration count, [7] work memory bytes,
+ * [8] re-orthogonalisation second passes. Synchronises the stream. */
+int tb_get_stats(tb_ctx *ctx, int64_t *stats_host, int n_stats);
+
+/* Message for the last nonzero status on this thread. */
+const char *tb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TBKRYLOV_H */

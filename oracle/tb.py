@@ -1,0 +1,237 @@
+"""Per-atom projected eigensolve, global chemical potential, density matrix,
+band energy, entropy, repulsion and forces.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Following the paper (Secs. 2-3):
+  * per target atom i: H^(i) on the cutoff sphere, orthonormal basis Q of
+    K_r(H^(i), Phi_i), T = Q^T H^(i) Q, T = Y diag(lambda) Y^T (the small
+    eigenproblem the paper hands to LAPACK);
+  * the density matrix of Eq. (2), rho = sum_m |m> f(eps_m) <m|, is taken in
+    the Krylov space: the column block of seed i is
+        rho[:, i] = Q Y f(Lambda) Y[0:4, :]^T
+    and its rows on atom j give rho_{j alpha, i beta};
+  * occupation f(eps) = 2 / (1 + exp((eps - mu)/kT)) (spin factor 2);
+  * one global mu with sum_i sum_m f(lambda_m^(i)) w_m^(i) = N_e, where
+    w_m^(i) = sum_{beta<4} Y[beta, m]^2 is the weight of Ritz pair m on the
+    seed block; found by 100 bisection steps on
+    [min lambda - 50 kT, max lambda + 50 kT];
+  * E_band = sum_i sum_m lambda_m f_m w_m = sum_i sum_j Tr[H_ij rho_ji];
+    S/k_B = sum_i sum_m w_m 2 s(f_m/2), s(q) = -q ln q - (1-q) ln(1-q);
+    A = E_band - kT S/k_B;  E_rep = sum_i F(sum_j phi(r_ij));  E = A + E_rep;
+  * force (Sec. 2: <F_i> = Tr[rho F_i], F_i = -dH/dR_i):
+        F_k = - sum_i sum_{j in hop(i)} Tr[(dH_ij/dR_k) rho_ji] - dE_rep/dR_k.
+"""
+from __future__ import annotations
+
+import os
+import multiprocessing as mp
+
+import numpy as np
+
+from . import geometry, krylov, model
+
+N_BISECT = 100
+
+
+# ------------------------------------------------------------ occupation
+def fermi(eps, mu, kT):
+    """2/(1+exp(x)), x = (eps-mu)/kT, evaluated without overflow."""
+    x = (np.asarray(eps, dtype=np.float64) - mu) / kT
+    e = np.exp(-np.abs(x))
+    return np.where(x > 0, 2.0 * e / (1.0 + e), 2.0 / (1.0 + e))
+
+
+def entropy_per_level(eps, mu, kT):
+    """2 * s(f/2) with s(q) = -q ln q - (1-q) ln(1-q).
+
+    With q = 1/(1+e^x): s = ln(1+e^{-|x|}) + |x| e^{-|x|}/(1+e^{-|x|}), which is
+    the same function (s is symmetric under q <-> 1-q) with no cancellation.
+    """
+    x = np.abs((np.asarray(eps, dtype=np.float64) - mu) / kT)
+    e = np.exp(-x)
+    return 2.0 * (np.log1p(e) + x * e / (1.0 + e))
+
+
+def electron_count(mu, lams, ws, kT):
+    return float(sum(np.sum(fermi(l, mu, kT) * w) for l, w in zip(lams, ws)))
+
+
+def chemical_potential(lams, ws, n_electrons, kT, n_iter=N_BISECT):
+    lo = min(float(np.min(l)) for l in lams) - 50.0 * kT
+    hi = max(float(np.max(l)) for l in lams) + 50.0 * kT
+    for _ in range(n_iter):
+        mid = 0.5 * (lo + hi)
+        if electron_count(mid, lams, ws, kT) < n_electrons:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+# --------------------------------------------------------- per-atom solve
+def atom_solve(i, pos, cell, periodic, p, r_cut, r, full_column=False,
+               route="arnoldi", reorth=True):
+    """Krylov solve for target atom i.
+
+    Returns dict with lam [d], w [d], J (global ids: i then hop(i) sorted),
+    P = (Q Y) restricted to the rows of J, shape (4|J|, d), Y1 = Y[0:4, :],
+    and with full_column also the cluster ids and Q Y on all cluster rows.
+    """
+    idx, x = geometry.cluster(i, pos, cell, periodic, r_cut)
+    H = krylov.cluster_hamiltonian(x, p)
+    if route == "arnoldi":
+        Q, _w = krylov.block_krylov_basis(H, r, reorth=reorth)
+        T = Q.T @ H @ Q
+        T = 0.5 * (T + T.T)
+    else:
+        Q, T = krylov.block_lanczos(H, r, reorth=reorth)
+    lam, Y = np.linalg.eigh(T)
+    w = np.sum(Y[:4, :] ** 2, axis=0)
+    rloc = np.linalg.norm(x, axis=1)
+    j_local = np.nonzero((rloc < p["rm"]) & (np.arange(len(idx)) > 0))[0]
+    j_local = j_local[np.argsort(idx[j_local])]
+    J_local = np.concatenate([[0], j_local])
+    rows = (4 * J_local[:, None] + np.arange(4)[None, :]).ravel()
+    QY = Q @ Y
+    out = {"i": i, "lam": lam, "w": w, "J": idx[J_local], "P": QY[rows, :],
+           "Y1": Y[:4, :].copy(), "n_cluster": len(idx), "dim": Q.shape[1]}
+    if full_column:
+        out["cluster"] = idx
+        out["QY"] = QY
+    return out
+
+
+def rho_blocks_from(sol, mu, kT):
+    """rho_{j alpha, i beta} for j in J: array (|J|, 4, 4), [p][alpha][beta]."""
+    f = fermi(sol["lam"], mu, kT)
+    col = (sol["P"] * f[None, :]) @ sol["Y1"].T          # (4|J|, 4)
+    return col.reshape(-1, 4, 4)
+
+
+def rho_column_full(sol, mu, kT):
+    f = fermi(sol["lam"], mu, kT)
+    return ((sol["QY"] * f[None, :]) @ sol["Y1"].T).reshape(-1, 4, 4)
+
+
+# ------------------------------------------------------------ repulsion
+def repulsion(pos, cell, periodic, p):
+    """E_rep and its forces -dE_rep/dR (N,3)."""
+    N = pos.shape[0]
+    nb, dv = geometry.neighbour_lists(pos, cell, periodic, p["dm"])
+    xs = np.array([np.sum(model.phi_pair(np.linalg.norm(d, axis=1), p)) if len(d) else 0.0
+                   for d in dv])
+    e_rep = float(np.sum(model.f_embed(xs, p)))
+    dF = model.f_embed_deriv(xs, p)
+    grad = np.zeros((N, 3))
+    for i in range(N):
+        if len(nb[i]) == 0:
+            continue
+        rr = np.linalg.norm(dv[i], axis=1)
+        g = (dF[i] * model.phi_pair_deriv(rr, p) / rr)[:, None] * dv[i]   # d/d(d_ij)
+        grad[nb[i]] += g
+        grad[i] -= g.sum(axis=0)
+    return e_rep, -grad
+
+
+# ---------------------------------------------------------- parallel map
+_G = {}
+
+
+def _worker(i):
+    g = _G
+    return atom_solve(i, g["pos"], g["cell"], g["periodic"], g["p"], g["r_cut"],
+                      int(g["r_of"](i)), full_column=g["full_column"],
+                      route=g["route"], reorth=g["reorth"])
+
+
+def _limit_blas():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, r_per_atom=None,
+                full_column=False, route="arnoldi", reorth=True, processes=None):
+    """atom_solve over a list of atoms, in worker processes (one BLAS thread each)."""
+    r_of = (lambda i: r_per_atom[i]) if r_per_atom is not None else (lambda i: r)
+    _G.update(pos=pos, cell=cell, periodic=periodic, p=p, r_cut=r_cut, r_of=r_of,
+              full_column=full_column, route=route, reorth=reorth)
+    atoms = list(atoms)
+    if processes is None:
+        processes = len(os.sched_getaffinity(0))
+    processes = max(1, min(processes, len(atoms)))
+    if processes == 1 or len(atoms) < 4:
+        return [_worker(i) for i in atoms]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(processes, initializer=_limit_blas) as pool:
+        return pool.map(_worker, atoms, chunksize=max(1, len(atoms) // (4 * processes)))
+
+
+# --------------------------------------------------------------- driver
+def run(pos, cell, periodic, p, r_cut, r, kT, n_electrons=None, mu=None,
+        r_per_atom=None, atoms=None, force_atoms=None, full_column=False,
+        route="arnoldi", reorth=True, processes=None):
+    """The whole path for one geometry.
+
+    atoms=None solves every atom; mu must then be None (bisection on
+    n_electrons) or given.  With a subset of atoms, mu must be given, and
+    forces are returned for force_atoms (each needs itself and hop() solved).
+    """
+    pos = np.asarray(pos, dtype=np.float64)
+    N = pos.shape[0]
+    all_atoms = atoms is None
+    atoms = list(range(N)) if all_atoms else list(atoms)
+    sols = solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, r_per_atom,
+                       full_column, route, reorth, processes)
+    by_atom = {s["i"]: s for s in sols}
+    if mu is None:
+        if not all_atoms:
+            raise ValueError("chemical potential by bisection needs every atom")
+        mu = chemical_potential([s["lam"] for s in sols], [s["w"] for s in sols],
+                                n_electrons, kT)
+    rho = {s["i"]: rho_blocks_from(s, mu, kT) for s in sols}
+    e_band = float(sum(np.sum(s["lam"] * fermi(s["lam"], mu, kT) * s["w"]) for s in sols))
+    ent = float(sum(np.sum(s["w"] * entropy_per_level(s["lam"], mu, kT)) for s in sols))
+    out = {"mu": mu, "sols": by_atom, "rho": rho, "e_band": e_band,
+           "entropy": ent, "free_band": e_band - kT * ent}
+    # trace identity check quantity: sum_i sum_j Tr[H_ij rho_ji]
+    tr = 0.0
+    for s in sols:
+        i = s["i"]
+        d = geometry.min_image(pos[s["J"][1:]] - pos[i], cell, periodic)
+        blocks = np.concatenate([model.onsite_block(p)[None], model.sk_blocks(d, p)], axis=0)
+        tr += float(np.einsum("pba,pab->", blocks, rho[i]))
+    out["trace_HRho"] = tr
+    if full_column:
+        out["rho_full"] = {s["i"]: rho_column_full(s, mu, kT) for s in sols}
+    # forces
+    if all_atoms or force_atoms is not None:
+        e_rep, f_rep = repulsion(pos, cell, periodic, p)
+        grad = np.zeros((N, 3))
+        for s in sols:
+            i = s["i"]
+            J = s["J"][1:]
+            if len(J) == 0:
+                continue
+            d = geometry.min_image(pos[J] - pos[i], cell, periodic)
+            dH = model.sk_blocks_grad(d, p)                  # (|J|, 3, 4, 4) [c][beta][alpha]
+            g = np.einsum("pcba,pab->pc", dH, rho[i][1:])   # d Tr[H_ij rho_ji] / d d_c
+            grad[J] += g
+            grad[i] -= g.sum(axis=0)
+        forces = -grad + f_rep
+        out.update(e_rep=e_rep, forces=forces,
+                   e_total=e_band - kT * ent + e_rep)
+        if force_atoms is not None:
+            need = set()
+            nb, _ = geometry.neighbour_lists(pos, cell, periodic, p["rm"])
+            for k in force_atoms:
+                need.add(k)
+                need.update(int(j) for j in nb[k])
+            missing = need - set(by_atom)
+            if missing:
+                raise ValueError(f"forces on {force_atoms} need solves of {sorted(missing)}")
+            out["forces_sampled"] = {int(k): forces[k] for k in force_atoms}
+    return out
