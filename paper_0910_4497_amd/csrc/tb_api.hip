@@ -1,0 +1,335 @@
+// C-ABI of libtbkrylov: argument validation, work-buffer ownership and the
+// launch sequence of the kernels. See include/tbkrylov.h for the contract.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "tb_internal.h"
+
+namespace tbk {
+__global__ void k_zero_int(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+__global__ void k_zero_i64(int64_t* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+}  // namespace tbk
+
+using namespace tbk;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess) return fail(TB_EHIP, "%s: %s", #expr, hipGetErrorString(_e));   \
+  } while (0)
+
+static const int MU_ITERS = 64;
+
+extern "C" const char* tb_last_error(void) { return g_err.c_str(); }
+
+template <typename T>
+static hipError_t alloc(tb_ctx* c, T** p, size_t count) {
+  const size_t b = count * sizeof(T) > 0 ? count * sizeof(T) : 16;
+  c->bytes += b;
+  return hipMalloc((void**)p, b);
+}
+
+extern "C" int tb_destroy(tb_ctx* c) {
+  if (!c) return TB_OK;
+  int dev_prev = 0;
+  hipGetDevice(&dev_prev);
+  hipSetDevice(c->device);
+  void* ptrs[] = {c->hop_n, c->hop_j, c->hop_rev, c->hop_d, c->pair64, c->pair32, c->clu_n, c->clu_j,
+                  c->loc_off, c->loc_ent, c->hnorm, c->jloc, c->row_ptr, c->col_j, c->vbuf, c->tab,
+                  c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->rot_cs, c->rot_p,
+                  c->rot_n, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  hipSetDevice(dev_prev);
+  delete c;
+  return TB_OK;
+}
+
+extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t n_atoms_max,
+                         int n_cluster_max, int r_max) {
+  if (!out) return fail(TB_EINVAL, "ctx pointer is null");
+  *out = nullptr;
+  if (n_atoms_max < 1 || n_atoms_max > (1 << 24)) return fail(TB_EINVAL, "n_atoms_max out of range");
+  if (n_cluster_max < 1 || n_cluster_max > NCLUSTER_LIMIT)
+    return fail(TB_EINVAL, "n_cluster_max must be in [1, %d]", NCLUSTER_LIMIT);
+  if (r_max < 1 || r_max > RMAX_LIMIT) return fail(TB_EINVAL, "r_max must be in [1, %d]", RMAX_LIMIT);
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (hip_device < 0 || hip_device >= ndev) return fail(TB_EINVAL, "hip_device %d not present", hip_device);
+  HIP_TRY(hipSetDevice(hip_device));
+  tb_ctx* c = new tb_ctx();
+  memset((void*)c, 0, sizeof(tb_ctx));
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  c->na_max = n_atoms_max;
+  c->nc_max = n_cluster_max;
+  c->r_max = r_max;
+  c->emax = (int64_t)n_cluster_max * ZMAX;
+  const int64_t dmax = 4 * (int64_t)r_max;
+  c->rot_max = 2 * dmax * dmax + 16 * dmax;
+  if (c->rot_max > 65535 * 16) c->rot_max = 65535 * 16;
+
+  // persistent Krylov workgroups: as many as fit on the device at once
+  const size_t lds = lanczos_lds_bytes(n_cluster_max, r_max, false);
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+  if (lds > prop.sharedMemPerBlock && lds > 160 * 1024) {
+    delete c;
+    return fail(TB_ECAPACITY, "n_cluster_max=%d, r_max=%d need %zu B of LDS per workgroup", n_cluster_max,
+                r_max, lds);
+  }
+  hipError_t e = lanczos_set_lds(lds);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(TB_ECAPACITY, "LDS request of %zu B refused: %s", lds, hipGetErrorString(e));
+  }
+  int per_cu = (int)((160 * 1024) / (lds + 1024));
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 2) per_cu = 2;
+  c->n_wg_lanczos = prop.multiProcessorCount * per_cu;
+  if (c->n_wg_lanczos > n_atoms_max) c->n_wg_lanczos = (int)n_atoms_max;
+
+  const int64_t N = n_atoms_max, NC = n_cluster_max;
+  hipError_t a = hipSuccess;
+#define ALLOC(ptr, cnt) \
+  if (a == hipSuccess) a = alloc(c, &c->ptr, (size_t)(cnt));
+  ALLOC(hop_n, N);
+  ALLOC(hop_j, N * ZMAX);
+  ALLOC(hop_rev, N * ZMAX);
+  ALLOC(hop_d, N * ZMAX * 4);
+  ALLOC(pair64, N * ZMAX * 4);
+  ALLOC(pair32, N * ZMAX * 4);
+  ALLOC(clu_n, N);
+  ALLOC(clu_j, N * NC);
+  ALLOC(loc_off, N * (NC + 1));
+  ALLOC(loc_ent, N * c->emax);
+  ALLOC(hnorm, N);
+  ALLOC(jloc, N * JMAX);
+  ALLOC(row_ptr, N + 1);
+  ALLOC(col_j, N * JMAX);
+  ALLOC(tab, N * r_max * 32);
+  ALLOC(kused, N);
+  ALLOC(work_counter, 16);
+  ALLOC(lam, N * dmax);
+  ALLOC(wgt, N * dmax);
+  ALLOC(y1, N * 4 * dmax);
+  ALLOC(rot_cs, N * c->rot_max * 2);
+  ALLOC(rot_p, N * c->rot_max);
+  ALLOC(rot_n, N);
+  ALLOC(mu_state, 16);
+  ALLOC(partial, 4096);
+  ALLOC(counter, 16);
+  ALLOC(xrep, 2 * N);
+  ALLOC(eparts, 8);
+  ALLOC(stats, ST_NSTATS);
+#undef ALLOC
+  if (a == hipSuccess) {
+    double* vb = nullptr;
+    a = alloc(c, &vb, (size_t)c->n_wg_lanczos * r_max * 4 * NC * 4);
+    c->vbuf = vb;
+  }
+  if (a == hipSuccess) {
+    double* v = nullptr;
+    a = alloc(c, &v, (size_t)N * 4 * JMAX * dmax);
+    c->vj = v;
+  }
+  if (a != hipSuccess) {
+    tb_destroy(c);
+    return fail(TB_EHIP, "work allocation of %zu B failed: %s", c->bytes, hipGetErrorString(a));
+  }
+  HIP_TRY(hipMemset(c->counter, 0, 16 * sizeof(unsigned int)));
+  HIP_TRY(hipMemset(c->stats, 0, ST_NSTATS * sizeof(int64_t)));
+  HIP_TRY(hipMemset(c->mu_state, 0, 16 * sizeof(double)));
+  HIP_TRY(hipMemset(c->kused, 0, N * sizeof(int)));
+  HIP_TRY(hipMemset(c->rot_n, 0, N * sizeof(int)));
+  HIP_TRY(hipDeviceSynchronize());
+  c->nnz_pairs = -1;
+  *out = c;
+  return TB_OK;
+}
+
+static bool finite_params(const tb_params* p) {
+  const double* v = &p->eps_s;
+  const int nd = (int)((sizeof(tb_params) - sizeof(int64_t)) / sizeof(double));
+  for (int q = 0; q < nd; ++q)
+    if (!isfinite(v[q])) return false;
+  return true;
+}
+
+extern "C" int tb_build_local_H(tb_ctx* c, int64_t n_atoms, const double* pos, const double* cell_host,
+                                const int* periodic_host, const tb_params* p, double r_cluster,
+                                int* n_cluster_out) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (!pos || !cell_host || !periodic_host || !p) return fail(TB_EINVAL, "null argument");
+  if (n_atoms < 1 || n_atoms > c->na_max)
+    return fail(TB_ECAPACITY, "n_atoms=%lld outside [1, %lld]", (long long)n_atoms, (long long)c->na_max);
+  if (p->struct_size != (int64_t)sizeof(tb_params))
+    return fail(TB_EINVAL, "tb_params.struct_size=%lld, expected %zu", (long long)p->struct_size,
+                sizeof(tb_params));
+  if (!finite_params(p)) return fail(TB_EINVAL, "non-finite model parameter");
+  if (!(p->r1 > 0 && p->rm > p->r1 && p->d1 > 0 && p->dm > p->d1 && p->rc > 0 && p->dc > 0))
+    return fail(TB_EINVAL, "radial cutoffs must satisfy 0 < r1 < rm and 0 < d1 < dm");
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      if (a != b && cell_host[3 * a + b] != 0.0)
+        return fail(TB_EUNSUPPORTED, "only orthorhombic cells are supported");
+  const double r_list = p->rm > p->dm ? p->rm : p->dm;
+  if (!isfinite(r_cluster) || r_cluster <= r_list)
+    return fail(TB_EINVAL, "r_cluster=%g must exceed the hopping/pair cutoff %g", r_cluster, r_list);
+  Box box;
+  for (int a = 0; a < 3; ++a) {
+    box.per[a] = periodic_host[a] ? 1 : 0;
+    box.L[a] = cell_host[4 * a];
+    if (box.per[a]) {
+      if (!(isfinite(box.L[a]) && box.L[a] > 0)) return fail(TB_EINVAL, "periodic box length %d invalid", a);
+      if (r_cluster >= 0.5 * box.L[a])
+        return fail(TB_ECUTOFF, "r_cluster=%g >= half the box length %g on axis %d", r_cluster, box.L[a], a);
+    } else {
+      box.L[a] = 1.0;
+    }
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  Model M;
+  memcpy(&M, &p->eps_s, sizeof(Model));
+  c->model = M;
+  c->box = box;
+  c->r_cluster = r_cluster;
+  c->n_atoms = n_atoms;
+  const int n = (int)n_atoms;
+  hipStream_t st = c->stream;
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, c->stats, ST_NSTATS);
+  launch_build(c, pos, r_list, st);
+  if (n_cluster_out) HIP_TRY(hipMemcpyAsync(n_cluster_out, c->clu_n, n * sizeof(int), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipGetLastError());
+  c->stage = 1;
+  c->nnz_pairs = -1;
+  return TB_OK;
+}
+
+extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT, double mu, double n_electrons,
+                             int precision, double* mu_out, double* rho_out) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (c->stage < 1) return fail(TB_ESTATE, "tb_build_local_H must be called first");
+  if (!rho_out) return fail(TB_EINVAL, "rho_out is null");
+  if (r < 1 || r > c->r_max) return fail(TB_ECAPACITY, "r=%d outside [1, %d]", r, c->r_max);
+  if (!(isfinite(kT) && kT > 0)) return fail(TB_EINVAL, "kT must be positive and finite");
+  if (precision != TB_FP64 && precision != TB_FP32) return fail(TB_EINVAL, "unknown precision %d", precision);
+  const bool fixed = !isnan(mu);
+  if (fixed && !isfinite(mu)) return fail(TB_EINVAL, "mu must be finite or NaN");
+  const int n = (int)c->n_atoms;
+  if (!fixed && !(isfinite(n_electrons) && n_electrons > 0 && n_electrons < 8.0 * n))
+    return fail(TB_EMU, "n_electrons=%g outside (0, %d)", n_electrons, 8 * n);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  c->kT = kT;
+  c->precision = precision;
+  const bool fp32 = precision == TB_FP32;
+  // K4: block Lanczos
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 16);
+  LanczosArgs la;
+  la.n_atoms = n; la.r_default = r; la.r_per_atom = r_per_atom;
+  la.clu_n = c->clu_n; la.clu_j = c->clu_j; la.loc_off = c->loc_off; la.loc_ent = c->loc_ent;
+  la.hnorm = c->hnorm; la.jloc = c->jloc; la.hop_n = c->hop_n;
+  la.pair = fp32 ? (const void*)c->pair32 : (const void*)c->pair64;
+  la.nc_max = c->nc_max; la.emax = c->emax; la.r_max = c->r_max;
+  la.eps_s = c->model.eps_s; la.eps_p = c->model.eps_p; la.v_sss = c->model.v_sss;
+  la.v_sps = c->model.v_sps; la.v_pps = c->model.v_pps; la.v_ppp = c->model.v_ppp;
+  la.vbuf = c->vbuf; la.tab = c->tab; la.kused = c->kused; la.vj = c->vj;
+  la.counter = c->work_counter; la.stats = c->stats;
+  const size_t lds = lanczos_lds_bytes(c->nc_max, c->r_max, fp32);
+  launch_lanczos(la, fp32, c->n_wg_lanczos < n ? c->n_wg_lanczos : n, lds, st);
+  // K5: projected eigensolve
+  EigArgs ea;
+  ea.n_atoms = n; ea.r_max = c->r_max; ea.tab = c->tab; ea.kused = c->kused;
+  ea.lam = c->lam; ea.wgt = c->wgt; ea.y1 = c->y1;
+  ea.rot_cs = c->rot_cs; ea.rot_p = c->rot_p; ea.rot_n = c->rot_n; ea.rot_max = c->rot_max;
+  ea.stats = c->stats;
+  launch_eig(ea, st);
+  // K6: chemical potential and spectral sums
+  MuArgs ma;
+  ma.n_pairs = (int64_t)n * 4 * c->r_max;
+  ma.lam = c->lam; ma.wgt = c->wgt; ma.kT = kT; ma.n_e = n_electrons;
+  ma.state = c->mu_state; ma.partial = c->partial; ma.counter = c->counter;
+  ma.eparts = c->eparts; ma.mu_out = mu_out;
+  launch_mu(ma, mu, fixed, MU_ITERS, st);
+  // K7: density-matrix blocks
+  RhoArgs ra;
+  ra.n_atoms = n; ra.r_max = c->r_max; ra.kused = c->kused; ra.hop_n = c->hop_n; ra.clu_j = c->clu_j;
+  ra.nc_max = c->nc_max; ra.lam = c->lam; ra.y1 = c->y1; ra.rot_cs = c->rot_cs; ra.rot_p = c->rot_p;
+  ra.rot_n = c->rot_n; ra.rot_max = c->rot_max; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
+  ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out;
+  launch_rho(ra, st);
+  HIP_TRY(hipGetLastError());
+  c->rho_last = rho_out;
+  c->stage = 2;
+  return TB_OK;
+}
+
+extern "C" int tb_rho_layout(tb_ctx* c, int64_t* nnz_pairs_host, int64_t* row_ptr, int* col_j) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (c->stage < 1) return fail(TB_ESTATE, "tb_build_local_H must be called first");
+  if (!nnz_pairs_host) return fail(TB_EINVAL, "nnz_pairs_host is null");
+  HIP_TRY(hipSetDevice(c->device));
+  int64_t nnz = 0;
+  HIP_TRY(hipMemcpyAsync(&nnz, c->row_ptr + c->n_atoms, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *nnz_pairs_host = nnz;
+  c->nnz_pairs = nnz;
+  if (row_ptr)
+    HIP_TRY(hipMemcpyAsync(row_ptr, c->row_ptr, (c->n_atoms + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (col_j) HIP_TRY(hipMemcpyAsync(col_j, c->col_j, nnz * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+  return TB_OK;
+}
+
+extern "C" int tb_energy_forces(tb_ctx* c, double* e_out, double* forces) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (c->stage < 2) return fail(TB_ESTATE, "tb_krylov_rho must be called first");
+  if (!e_out) return fail(TB_EINVAL, "e_out is null");
+  HIP_TRY(hipSetDevice(c->device));
+  ForceArgs fa;
+  fa.n_atoms = (int)c->n_atoms; fa.M = c->model;
+  fa.hop_n = c->hop_n; fa.hop_j = c->hop_j; fa.hop_rev = c->hop_rev; fa.hop_d = c->hop_d;
+  fa.row_ptr = c->row_ptr; fa.rho = c->rho_last; fa.xrep = c->xrep; fa.forces = forces;
+  fa.eparts = c->eparts; fa.kT = c->kT; fa.e_out = e_out;
+  launch_forces(fa, c->stream);
+  HIP_TRY(hipGetLastError());
+  return TB_OK;
+}
+
+extern "C" int tb_get_stats(tb_ctx* c, int64_t* stats_host, int n_stats) {
+  if (!c || !stats_host) return fail(TB_EINVAL, "null argument");
+  HIP_TRY(hipSetDevice(c->device));
+  int64_t s[ST_NSTATS];
+  HIP_TRY(hipMemcpyAsync(s, c->stats, sizeof s, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  s[ST_MEMORY] = (int64_t)c->bytes;
+  for (int q = 0; q < n_stats && q < ST_NSTATS; ++q) stats_host[q] = s[q];
+  if (s[ST_FLAGS] & (FL_HOP_OVERFLOW | FL_CLUSTER_OVERFLOW | FL_COUPLING_OVERFLOW))
+    return fail(TB_ECAPACITY, "device list overflow (flags 0x%llx)", (unsigned long long)s[ST_FLAGS]);
+  if (s[ST_FLAGS]) return fail(TB_EDEVICE, "device error flags 0x%llx", (unsigned long long)s[ST_FLAGS]);
+  return TB_OK;
+}

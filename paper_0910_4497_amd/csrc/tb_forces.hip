@@ -1,0 +1,132 @@
+// Energies and forces (Sec. 2: <F_i> = Tr[rho F_i] with F_i = -dH/dR_i).
+//
+// For the ordered pair (i -> j), d = R_j - R_i, H_ij = s(|d|) M(h) with the
+// Slater-Koster matrix M(h), and the rho block X = rho_ji^T of seed i,
+//   g_ij = d Tr[H_ij rho_ji] / d d
+//        = h [s' (V_sss X_ss + V_sps h.u + V_ppp tr X_pp + D h.X_pp.h)
+//             - (s/r)(V_sps h.u + 2 D h.X_pp.h)]
+//          + (s/r) [V_sps u + D (X_pp h + X_pp^T h)],
+// D = V_pps - V_ppp, u_a = X_{s,a} - X_{a,s}. The pair adds +g to the energy
+// gradient on R_j and -g on R_i, so for atom k
+//   F_k = sum_{j in hop(k)} (g_kj - g_jk) + repulsive part,
+// gathered per atom (no atomics, fixed order). Repulsion
+// E_rep = sum_i F(x_i), x_i = sum_j phi(r_ij), gives
+//   F_k += sum_j (F'(x_k) + F'(x_j)) phi'(r_kj) d_kj / r_kj.
+#include "tb_internal.h"
+
+namespace tbk {
+
+constexpr int F_NT = 256;
+
+
+__device__ __forceinline__ void pair_grad(const Model& M, const double* dvec, const double* rho,
+                                          double (&g)[3]) {
+  const double r = dvec[3];
+  double s, ds;
+  hop_scale(M, r, s, ds);
+  if (s == 0.0 && ds == 0.0) { g[0] = g[1] = g[2] = 0.0; return; }
+  const double h[3] = {dvec[0] / r, dvec[1] / r, dvec[2] / r};
+  // X[b][a] = rho[a][b]
+  double X[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) X[b][a] = rho[a * 4 + b];
+  const double D = M.v_pps - M.v_ppp;
+  double u[3], Xh[3], XTh[3];
+  double hu = 0.0, trp = 0.0, hXh = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = X[0][1 + a] - X[1 + a][0];
+    hu += h[a] * u[a];
+    trp += X[1 + a][1 + a];
+    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) { t1 += X[1 + a][1 + b] * h[b]; t2 += h[b] * X[1 + b][1 + a]; }
+    Xh[a] = t1; XTh[a] = t2;
+    hXh += h[a] * t1;
+  }
+  const double sr = s / r;
+  const double radial = ds * (M.v_sss * X[0][0] + M.v_sps * hu + M.v_ppp * trp + D * hXh)
+                        - sr * (M.v_sps * hu + 2.0 * D * hXh);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) g[c] = h[c] * radial + sr * (M.v_sps * u[c] + D * (Xh[c] + XTh[c]));
+}
+
+__global__ void __launch_bounds__(F_NT) k_rep_x(ForceArgs g) {
+  const int i = blockIdx.x * F_NT + threadIdx.x;
+  if (i >= g.n_atoms) return;
+  double x = 0.0;
+  const int nh = g.hop_n[i];
+  for (int t = 0; t < nh; ++t) {
+    double phi, dphi;
+    pair_term(g.M, g.hop_d[((size_t)i * ZMAX + t) * 4 + 3], phi, dphi);
+    x += phi;
+  }
+  const double* c = g.M.frep;
+  const double F = c[0] + x * (c[1] + x * (c[2] + x * (c[3] + x * c[4])));
+  const double dF = c[1] + x * (2.0 * c[2] + x * (3.0 * c[3] + x * 4.0 * c[4]));
+  g.xrep[2 * i] = dF;
+  g.xrep[2 * i + 1] = F;
+}
+
+__global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
+  const int k = blockIdx.x * F_NT + threadIdx.x;
+  if (k >= g.n_atoms || !g.forces) return;
+  double F[3] = {0.0, 0.0, 0.0};
+  const int nh = g.hop_n[k];
+  const int64_t pk = g.row_ptr[k];
+  const double dFk = g.xrep[2 * k];
+  for (int t = 0; t < nh; ++t) {
+    const size_t q = (size_t)k * ZMAX + t;
+    const int j = g.hop_j[q];
+    const double* dv = g.hop_d + 4 * q;
+    double gkj[3], gjk[3];
+    pair_grad(g.M, dv, g.rho + (size_t)(pk + 1 + t) * 16, gkj);
+    const int rt = g.hop_rev[q];
+    if (rt >= 0) {
+      const size_t qj = (size_t)j * ZMAX + rt;
+      pair_grad(g.M, g.hop_d + 4 * qj, g.rho + (size_t)(g.row_ptr[j] + 1 + rt) * 16, gjk);
+    } else {
+      gjk[0] = gjk[1] = gjk[2] = 0.0;     // only after a list overflow (flagged)
+    }
+    double phi, dphi;
+    pair_term(g.M, dv[3], phi, dphi);
+    const double rep = (dFk + g.xrep[2 * j]) * dphi / dv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F[c] += gkj[c] - gjk[c] + rep * dv[c];
+  }
+  g.forces[3 * k] = F[0];
+  g.forces[3 * k + 1] = F[1];
+  g.forces[3 * k + 2] = F[2];
+}
+
+// Single block: fixed-order sum of the per-atom repulsive energies, then the
+// energy record.
+__global__ void __launch_bounds__(F_NT) k_energy(ForceArgs g) {
+  __shared__ double red[F_NT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < g.n_atoms; i += F_NT) s += g.xrep[2 * i + 1];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = 0.0;
+    for (int w = 0; w < F_NT / 64; ++w) e += red[w];
+    const double eb = g.eparts[0], ts = -g.kT * g.eparts[1];
+    g.eparts[2] = e;
+    g.e_out[0] = eb;
+    g.e_out[1] = ts;
+    g.e_out[2] = e;
+    g.e_out[3] = eb + ts + e;
+  }
+}
+
+void launch_forces(const ForceArgs& a, hipStream_t st) {
+  const int nb = (a.n_atoms + F_NT - 1) / F_NT;
+  hipLaunchKernelGGL(k_rep_x, dim3(nb), dim3(F_NT), 0, st, a);
+  hipLaunchKernelGGL(k_forces, dim3(nb), dim3(F_NT), 0, st, a);
+  hipLaunchKernelGGL(k_energy, dim3(1), dim3(F_NT), 0, st, a);
+}
+
+}  // namespace tbk

@@ -1,0 +1,201 @@
+// Internal definitions shared by the HIP kernels and the host API of
+// libtbkrylov. Device code is written for gfx950 (CDNA4, 64-lane waves).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tbkrylov.h"
+
+struct tb_ctx;
+
+namespace tbk {
+
+constexpr int ZMAX = 24;           // neighbours within max(rm, dm) per atom
+constexpr int JMAX = ZMAX + 1;     // rho row atoms per target: itself + hop list
+constexpr int LOCAL_BITS = 11;     // local atom index bits in a packed coupling
+constexpr int NCLUSTER_LIMIT = (1 << LOCAL_BITS) - 1;
+constexpr int RMAX_LIMIT = 256;
+
+// Device-side error / statistics words (int64 each).
+enum StatSlot {
+  ST_FLAGS = 0, ST_MAX_CLUSTER = 1, ST_MAX_HOP = 2, ST_MAX_COUPLINGS = 3,
+  ST_DEFLATED = 4, ST_EARLY_STOP = 5, ST_MAX_EIG_ITERS = 6, ST_MEMORY = 7,
+  ST_REORTH2 = 8, ST_NSTATS = 16
+};
+enum FlagBits {
+  FL_HOP_OVERFLOW = 1, FL_CLUSTER_OVERFLOW = 2, FL_COUPLING_OVERFLOW = 4,
+  FL_NONFINITE = 8, FL_EIG_NOCONV = 16, FL_ROTLOG_OVERFLOW = 32
+};
+
+// Model parameters as the kernels see them (plain struct, passed by value).
+struct Model {
+  double eps_s, eps_p, v_sss, v_sps, v_pps, v_ppp;
+  double r0, n, nc, rc, r1, rm, s_tail[4];
+  double phi0, d0, m, mc, dc, d1, dm, phi_tail[4], frep[5];
+};
+
+struct Box {
+  double L[3];
+  int per[3];
+};
+
+// --------------------------------------------------------------- helpers
+__device__ __forceinline__ double mic(double d, double L, int per) {
+  return per ? d - L * rint(d / L) : d;
+}
+
+// Xu-form scaled function pre * (r0/r)^ex * exp{ex[-(r/rc)^exc + (r0/rc)^exc]}
+// below r1, cubic tail on [r1, rmax), zero beyond; value and r-derivative.
+__device__ __forceinline__ void xu_radial(double r, double pre, double r0, double ex,
+                                          double exc, double rc, double r1, double rmax,
+                                          const double* tail, double& val, double& dval) {
+  if (r >= rmax) { val = 0.0; dval = 0.0; return; }
+  if (r >= r1) {
+    double x = r - r1;
+    val = tail[0] + x * (tail[1] + x * (tail[2] + x * tail[3]));
+    dval = tail[1] + x * (2.0 * tail[2] + x * 3.0 * tail[3]);
+    return;
+  }
+  double q = pow(r / rc, exc);
+  double q0 = pow(r0 / rc, exc);
+  val = pre * pow(r0 / r, ex) * exp(ex * (q0 - q));
+  dval = val * (-ex / r) * (1.0 + exc * q);
+}
+
+__device__ __forceinline__ void hop_scale(const Model& M, double r, double& s, double& ds) {
+  xu_radial(r, 1.0, M.r0, M.n, M.nc, M.rc, M.r1, M.rm, M.s_tail, s, ds);
+}
+
+__device__ __forceinline__ void pair_term(const Model& M, double r, double& phi, double& dphi) {
+  xu_radial(r, M.phi0, M.d0, M.m, M.mc, M.dc, M.d1, M.dm, M.phi_tail, phi, dphi);
+}
+
+// 64-lane wave reductions through cross-lane shuffles.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+
+// ------------------------------------------------------------ kernel args
+struct LanczosArgs {
+  int n_atoms, r_default;
+  const int* r_per_atom;
+  const int* clu_n; const int* clu_j; const int* loc_off; const uint16_t* loc_ent;
+  const double* hnorm; const int* jloc; const int* hop_n;
+  const void* pair;            // [N][ZMAX][4] double or float: hx hy hz s
+  int nc_max; int64_t emax; int r_max;
+  double eps_s, eps_p, v_sss, v_sps, v_pps, v_ppp;
+  void* vbuf;                  // [WG][r_max][4*nc_max][4]
+  double* tab;                 // [N][r_max][2][16]: A_k, B_k
+  int* kused;
+  void* vj;                    // [N][4*JMAX][4*r_max]
+  int* counter;
+  int64_t* stats;
+};
+size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32);
+void launch_lanczos(const LanczosArgs& a, bool fp32, int n_wg, size_t lds, hipStream_t st);
+hipError_t lanczos_set_lds(size_t lds);
+int lanczos_threads();
+
+struct EigArgs {
+  int n_atoms, r_max;
+  const double* tab; const int* kused;
+  double* lam; double* wgt; double* y1;
+  double* rot_cs; uint16_t* rot_p; int* rot_n; int64_t rot_max;
+  int64_t* stats;
+};
+struct RhoArgs {
+  int n_atoms, r_max;
+  const int* kused; const int* hop_n; const int* clu_j; int nc_max;
+  const double* lam; const double* y1;
+  const double* rot_cs; const uint16_t* rot_p; const int* rot_n; int64_t rot_max;
+  const void* vj; int vj_fp32;
+  const int64_t* row_ptr;
+  const double* mu_state; double kT;
+  double* rho;
+};
+size_t eig_lds_bytes(int r_max);
+size_t rho_lds_bytes(int r_max);
+void launch_eig(const EigArgs& a, hipStream_t st);
+void launch_rho(const RhoArgs& a, hipStream_t st);
+
+struct MuArgs {
+  int64_t n_pairs;             // atoms * 4 r_max (padding has w = 0)
+  const double* lam; const double* wgt;
+  double kT, n_e;
+  double* state; double* partial; unsigned int* counter;
+  double* eparts; double* mu_out;
+};
+int mu_blocks(int64_t n_pairs);
+void launch_mu(const MuArgs& a, double mu_fixed, bool fixed, int n_iter, hipStream_t st);
+
+struct ForceArgs {
+  int n_atoms;
+  Model M;
+  const int* hop_n; const int* hop_j; const int* hop_rev; const double* hop_d;
+  const int64_t* row_ptr;
+  const double* rho;          // [pairs][4][4]: rho[p][a][b] = rho_{j a, i b}
+  double* xrep;               // [N][2]: F'(x_i), F(x_i)
+  double* forces;             // [N][3] (nullable)
+  double* eparts; double kT;
+  double* e_out;
+};
+void launch_forces(const ForceArgs& a, hipStream_t st);
+
+// K1-K3 and the rho pair layout for the geometry in pos (device).
+void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st);
+
+}  // namespace tbk
+
+// Context (host struct; all pointers are device memory unless noted).
+struct tb_ctx {
+  int device;
+  hipStream_t stream;
+  int64_t na_max;
+  int nc_max, r_max;
+  int64_t emax;          // couplings per sphere
+  int64_t rot_max;       // rotation-log entries per atom
+  int n_wg_lanczos;      // persistent workgroups of the Krylov kernel
+  size_t bytes;
+
+  // state
+  int stage;             // 0 none, 1 lists built, 2 rho built
+  int64_t n_atoms;
+  tbk::Model model;
+  tbk::Box box;
+  double r_cluster;
+  double kT;
+  int precision;
+  int64_t nnz_pairs;     // host copy (valid after tb_rho_layout)
+  const double* rho_last; // rho_out of the last tb_krylov_rho
+
+  // lists (K1-K3)
+  int* hop_n; int* hop_j; int* hop_rev; double* hop_d;     // [N][ZMAX][4]: dx dy dz r
+  double* pair64; float* pair32;                           // [N][ZMAX][4]: hx hy hz s
+  int* clu_n; int* clu_j;                                  // [N][NC]
+  int* loc_off; uint16_t* loc_ent;                         // [N][NC+1], [N][EMAX]
+  double* hnorm;                                           // [N]
+  int* jloc;                                               // [N][JMAX]
+  int64_t* row_ptr;                                        // [N+1]
+  int* col_j;                                              // [N*JMAX] (pairs, compact)
+  // Krylov (K4)
+  void* vbuf;            // [WG][RMAX][4*NC][4] f64 or f32
+  double* tab;           // [N][RMAX][2][16]
+  int* kused;            // [N]
+  void* vj;              // [N][4*JMAX][4*RMAX] f64 or f32
+  int* work_counter;     // persistent-kernel atom queue
+  // eigen (K5/K7)
+  double* lam; double* wgt; double* y1;                    // [N][D], [N][D], [N][4][D]
+  double* rot_cs; uint16_t* rot_p; int* rot_n;             // [N][ROT][2], [N][ROT], [N]
+  // mu / energies (K6/K8)
+  double* mu_state;      // [8]: lo, hi, mu, done, N(mu) ...
+  double* partial;       // [NPART][4]
+  unsigned int* counter; // last-block counters
+  double* xrep;          // [N]: sum_j phi, then F'(x)
+  double* eparts;        // [4] band, entropy, rep, count
+  int64_t* stats;        // [ST_NSTATS]
+};

@@ -1,0 +1,265 @@
+// Neighbour lists, cutoff spheres, Slater-Koster pair data and the local
+// coupling structure of every sphere (Sec. 2: locality; Eq. 1: Hamiltonian).
+//
+//   k_lists      one workgroup per atom i scans all j in order and compacts
+//                (order-preserving) the hop list {j : |d_ij| < r_list} and
+//                the sphere C_i = {i} + {j : |d_ij| < r_cluster}, both sorted
+//                by j. Brute force over j keeps the lists deterministic; at
+//                the sizes here (N <= ~2e4) it is a small part of a step.
+//   k_pairs      per ordered pair: direction cosines h = d/|d| and the hopping
+//                scale s(|d|) (FP64 and FP32 copies), and the reverse slot.
+//   k_local      one workgroup per sphere: local couplings (a -> b, slot) with
+//                the cluster-frame rule |x_b - x_a| < rm, x = position
+//                relative to the target; Frobenius norm of the local H; the
+//                local indices of the rho row atoms J = {i} + hop(i).
+//   k_rowptr     prefix sum of 1 + |hop(i)| (rho pair layout).
+#include "tb_internal.h"
+
+namespace tbk {
+
+constexpr int LIST_NT = 256;
+
+__device__ __forceinline__ void stat_max(int64_t* stats, int slot, int64_t v) {
+  atomicMax((unsigned long long*)&stats[slot], (unsigned long long)v);
+}
+__device__ __forceinline__ void stat_flag(int64_t* stats, int64_t bits) {
+  atomicOr((unsigned long long*)&stats[ST_FLAGS], (unsigned long long)bits);
+}
+
+__global__ void __launch_bounds__(LIST_NT)
+k_lists(int n, const double* __restrict__ pos, Box box, double r_list, double r_cluster,
+        int nc_max, int* __restrict__ hop_n, int* __restrict__ hop_j, double* __restrict__ hop_d,
+        int* __restrict__ clu_n, int* __restrict__ clu_j, int64_t* stats) {
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int s_cnt[2][LIST_NT / 64];
+  __shared__ int s_base[2];
+  if (tid == 0) { s_base[0] = 0; s_base[1] = 1; }   // sphere slot 0 is the target
+  const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+  if (tid == 0) clu_j[(int64_t)i * nc_max] = i;
+  const double rl2 = r_list * r_list, rc2 = r_cluster * r_cluster;
+  bool nonfinite = !(isfinite(xi) && isfinite(yi) && isfinite(zi));
+  __syncthreads();
+  for (int base = 0; base < n; base += LIST_NT) {
+    const int j = base + tid;
+    bool in_hop = false, in_clu = false;
+    double dx = 0, dy = 0, dz = 0, r2 = 0;
+    if (j < n && j != i) {
+      dx = mic(pos[3 * j] - xi, box.L[0], box.per[0]);
+      dy = mic(pos[3 * j + 1] - yi, box.L[1], box.per[1]);
+      dz = mic(pos[3 * j + 2] - zi, box.L[2], box.per[2]);
+      r2 = dx * dx + dy * dy + dz * dz;
+      in_hop = r2 < rl2;
+      in_clu = r2 < rc2;
+      if (!isfinite(r2)) nonfinite = true;
+    }
+    const uint64_t bh = __ballot(in_hop), bc = __ballot(in_clu);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int ph = __popcll(bh & below), pc = __popcll(bc & below);
+    if (lane == 0) { s_cnt[0][wave] = __popcll(bh); s_cnt[1][wave] = __popcll(bc); }
+    __syncthreads();
+    int oh = s_base[0], oc = s_base[1];
+    for (int w = 0; w < wave; ++w) { oh += s_cnt[0][w]; oc += s_cnt[1][w]; }
+    if (in_hop) {
+      const int slot = oh + ph;
+      if (slot < ZMAX) {
+        const int64_t q = (int64_t)i * ZMAX + slot;
+        hop_j[q] = j;
+        hop_d[4 * q] = dx; hop_d[4 * q + 1] = dy; hop_d[4 * q + 2] = dz; hop_d[4 * q + 3] = sqrt(r2);
+      }
+    }
+    if (in_clu) {
+      const int slot = oc + pc;
+      if (slot < nc_max) clu_j[(int64_t)i * nc_max + slot] = j;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int th = 0, tc = 0;
+      for (int w = 0; w < LIST_NT / 64; ++w) { th += s_cnt[0][w]; tc += s_cnt[1][w]; }
+      s_base[0] += th; s_base[1] += tc;
+    }
+    __syncthreads();
+  }
+  if (nonfinite) stat_flag(stats, FL_NONFINITE);
+  if (tid == 0) {
+    const int nh = s_base[0], ncl = s_base[1];
+    if (nh > ZMAX) stat_flag(stats, FL_HOP_OVERFLOW);
+    if (ncl > nc_max) stat_flag(stats, FL_CLUSTER_OVERFLOW);
+    hop_n[i] = nh < ZMAX ? nh : ZMAX;
+    clu_n[i] = ncl < nc_max ? ncl : nc_max;
+    stat_max(stats, ST_MAX_HOP, nh);
+    stat_max(stats, ST_MAX_CLUSTER, ncl);
+  }
+}
+
+__global__ void k_pairs(int n, Model M, const int* __restrict__ hop_n, const int* __restrict__ hop_j,
+                        const double* __restrict__ hop_d, double* __restrict__ pair64,
+                        float* __restrict__ pair32, int* __restrict__ hop_rev) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)n * ZMAX) return;
+  const int i = (int)(q / ZMAX), slot = (int)(q % ZMAX);
+  double hx = 0, hy = 0, hz = 0, s = 0;
+  int rev = -1;
+  if (slot < hop_n[i]) {
+    const double r = hop_d[4 * q + 3];
+    hx = hop_d[4 * q] / r; hy = hop_d[4 * q + 1] / r; hz = hop_d[4 * q + 2] / r;
+    double ds;
+    hop_scale(M, r, s, ds);
+    const int j = hop_j[q];
+    const int nj = hop_n[j];
+    for (int t = 0; t < nj; ++t)
+      if (hop_j[(int64_t)j * ZMAX + t] == i) { rev = t; break; }
+  }
+  pair64[4 * q] = hx; pair64[4 * q + 1] = hy; pair64[4 * q + 2] = hz; pair64[4 * q + 3] = s;
+  pair32[4 * q] = (float)hx; pair32[4 * q + 1] = (float)hy; pair32[4 * q + 2] = (float)hz;
+  pair32[4 * q + 3] = (float)s;
+  hop_rev[q] = rev;
+}
+
+// Local index of global atom g in the sphere list c (c[0] = target, c[1..n-1]
+// sorted increasingly), or -1.
+__device__ __forceinline__ int find_local(const int* c, int n, int g) {
+  if (g == c[0]) return 0;
+  int lo = 1, hi = n - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int v = c[mid];
+    if (v == g) return mid;
+    if (v < g) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+__global__ void __launch_bounds__(LIST_NT)
+k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_max, int64_t emax,
+        const int* __restrict__ hop_n, const int* __restrict__ hop_j, const double* __restrict__ hop_d,
+        const double* __restrict__ pair64, const int* __restrict__ clu_n, const int* __restrict__ clu_j,
+        int* __restrict__ loc_off, uint16_t* __restrict__ loc_ent, double* __restrict__ hnorm,
+        int* __restrict__ jloc, int64_t* stats) {
+  extern __shared__ unsigned char smem[];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int n = clu_n[i];
+  int* s_c = (int*)smem;                               // [nc_max]
+  int* s_cnt = s_c + nc_max;                           // [nc_max + 1]
+  double* s_x = (double*)(s_cnt + nc_max + 2);         // [nc_max][3] (8-byte aligned below)
+  s_x = (double*)(((uintptr_t)s_x + 7) & ~(uintptr_t)7);
+  __shared__ double s_red[LIST_NT / 64];
+  const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+  for (int a = tid; a < n; a += LIST_NT) {
+    const int g = clu_j[(int64_t)i * nc_max + a];
+    s_c[a] = g;
+    s_x[3 * a] = mic(pos[3 * g] - xi, box.L[0], box.per[0]);
+    s_x[3 * a + 1] = mic(pos[3 * g + 1] - yi, box.L[1], box.per[1]);
+    s_x[3 * a + 2] = mic(pos[3 * g + 2] - zi, box.L[2], box.per[2]);
+  }
+  __syncthreads();
+  const double rm2 = M.rm * M.rm;
+  const double kfro = M.v_sss * M.v_sss + 2 * M.v_sps * M.v_sps + M.v_pps * M.v_pps + 2 * M.v_ppp * M.v_ppp;
+  double fro = 0.0;
+  // pass 1: count couplings per local atom
+  for (int a = tid; a < n; a += LIST_NT) {
+    const int g = s_c[a];
+    const int nh = hop_n[g];
+    int cnt = 0;
+    fro += M.eps_s * M.eps_s + 3 * M.eps_p * M.eps_p;
+    for (int t = 0; t < nh; ++t) {
+      const int64_t q = (int64_t)g * ZMAX + t;
+      if (hop_d[4 * q + 3] >= M.rm) continue;
+      const int b = find_local(s_c, n, hop_j[q]);
+      if (b < 0) continue;
+      const double ex = s_x[3 * b] - s_x[3 * a], ey = s_x[3 * b + 1] - s_x[3 * a + 1],
+                   ez = s_x[3 * b + 2] - s_x[3 * a + 2];
+      if (ex * ex + ey * ey + ez * ez >= rm2) continue;   // wraps behind the target
+      ++cnt;
+      const double s = pair64[4 * q + 3];
+      fro += kfro * s * s;
+    }
+    s_cnt[a + 1] = cnt;
+  }
+  if (tid == 0) s_cnt[0] = 0;
+  fro = wave_sum(fro);
+  if ((tid & 63) == 0) s_red[tid >> 6] = fro;
+  __syncthreads();
+  if (tid == 0) {
+    double f = 0.0;
+    for (int w = 0; w < LIST_NT / 64; ++w) f += s_red[w];
+    hnorm[i] = sqrt(f);
+    for (int a = 0; a < n; ++a) s_cnt[a + 1] += s_cnt[a];   // inclusive offsets
+    if (s_cnt[n] > emax) stat_flag(stats, FL_COUPLING_OVERFLOW);
+    stat_max(stats, ST_MAX_COUPLINGS, s_cnt[n]);
+  }
+  __syncthreads();
+  for (int a = tid; a <= n; a += LIST_NT) loc_off[(int64_t)i * (nc_max + 1) + a] = s_cnt[a];
+  // pass 2: write couplings (b | slot << LOCAL_BITS) in hop-list order
+  for (int a = tid; a < n; a += LIST_NT) {
+    const int g = s_c[a];
+    const int nh = hop_n[g];
+    int64_t e = s_cnt[a];
+    for (int t = 0; t < nh; ++t) {
+      const int64_t q = (int64_t)g * ZMAX + t;
+      if (hop_d[4 * q + 3] >= M.rm) continue;
+      const int b = find_local(s_c, n, hop_j[q]);
+      if (b < 0) continue;
+      const double ex = s_x[3 * b] - s_x[3 * a], ey = s_x[3 * b + 1] - s_x[3 * a + 1],
+                   ez = s_x[3 * b + 2] - s_x[3 * a + 2];
+      if (ex * ex + ey * ey + ez * ez >= rm2) continue;
+      if (e < emax) loc_ent[(int64_t)i * emax + e] = (uint16_t)(b | (t << LOCAL_BITS));
+      ++e;
+    }
+  }
+  // rho row atoms: J[0] = target (local 0), then hop(i) in list order
+  if (tid == 0) {
+    int* jl = jloc + (int64_t)i * JMAX;
+    jl[0] = 0;
+    const int nh = hop_n[i];
+    for (int t = 0; t < nh; ++t) jl[1 + t] = find_local(s_c, n, hop_j[(int64_t)i * ZMAX + t]);
+    for (int t = nh + 1; t < JMAX; ++t) jl[t] = -1;
+  }
+}
+
+__global__ void k_rowptr(int n, const int* __restrict__ hop_n, const int* __restrict__ hop_j,
+                         int64_t* __restrict__ row_ptr, int* __restrict__ col_j) {
+  // single workgroup: sequential chunks with a workgroup scan
+  __shared__ int64_t s_part[LIST_NT];
+  __shared__ int64_t s_base;
+  const int tid = threadIdx.x;
+  if (tid == 0) { s_base = 0; row_ptr[0] = 0; }
+  __syncthreads();
+  for (int base = 0; base < n; base += LIST_NT) {
+    const int i = base + tid;
+    const int64_t v = (i < n) ? 1 + hop_n[i] : 0;
+    s_part[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < LIST_NT; off <<= 1) {
+      int64_t add = (tid >= off) ? s_part[tid - off] : 0;
+      __syncthreads();
+      s_part[tid] += add;
+      __syncthreads();
+    }
+    const int64_t start = s_base + s_part[tid] - v;
+    if (i < n) {
+      row_ptr[i + 1] = start + v;
+      col_j[start] = i;
+      for (int t = 0; t < hop_n[i]; ++t) col_j[start + 1 + t] = hop_j[(int64_t)i * ZMAX + t];
+    }
+    __syncthreads();
+    if (tid == LIST_NT - 1) s_base += s_part[tid];
+    __syncthreads();
+  }
+}
+
+void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st) {
+  const int n = (int)c->n_atoms;
+  hipLaunchKernelGGL(k_lists, dim3(n), dim3(LIST_NT), 0, st, n, pos, c->box, r_list, c->r_cluster, c->nc_max,
+                     c->hop_n, c->hop_j, c->hop_d, c->clu_n, c->clu_j, c->stats);
+  const int64_t np = (int64_t)n * ZMAX;
+  hipLaunchKernelGGL(k_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, n, c->model, c->hop_n,
+                     c->hop_j, c->hop_d, c->pair64, c->pair32, c->hop_rev);
+  const size_t lds_local = (size_t)c->nc_max * (4 + 4 + 24) + 64;
+  hipLaunchKernelGGL(k_local, dim3(n), dim3(LIST_NT), lds_local, st, n, c->model, pos, c->box, c->nc_max,
+                     c->emax, c->hop_n, c->hop_j, c->hop_d, c->pair64, c->clu_n, c->clu_j, c->loc_off,
+                     c->loc_ent, c->hnorm, c->jloc, c->stats);
+  hipLaunchKernelGGL(k_rowptr, dim3(1), dim3(LIST_NT), 0, st, n, c->hop_n, c->hop_j, c->row_ptr, c->col_j);
+}
+
+}  // namespace tbk

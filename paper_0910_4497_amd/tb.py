@@ -1,0 +1,188 @@
+"""Thin Python binding of libtbkrylov (ctypes): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; PyTorch provides the
+device memory and the stream. The library is loaded from this package's
+directory; if it is missing the import fails loudly (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtbkrylov.so")
+
+TB_FP64, TB_FP32 = 0, 1
+PRECISIONS = {"fp64": TB_FP64, "fp32": TB_FP32}
+ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4: "TB_EMU",
+          -5: "TB_EUNSUPPORTED", -6: "TB_EHIP", -7: "TB_ESTATE", -8: "TB_EDEVICE"}
+STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
+              "max_eig_iters", "memory_bytes", "reorth_second_pass")
+EXPORTS = ("tb_create", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
+           "tb_energy_forces", "tb_get_stats", "tb_last_error")
+
+
+class TBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class TBParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int64)] + [
+        (k, ctypes.c_double) for k in ("eps_s", "eps_p", "v_sss", "v_sps", "v_pps", "v_ppp",
+                                        "r0", "n", "nc", "rc", "r1", "rm")] + [
+        ("s_tail", ctypes.c_double * 4)] + [
+        (k, ctypes.c_double) for k in ("phi0", "d0", "m", "mc", "dc", "d1", "dm")] + [
+        ("phi_tail", ctypes.c_double * 4), ("frep", ctypes.c_double * 5)]
+
+    @classmethod
+    def from_dict(cls, p: dict) -> "TBParams":
+        s = cls()
+        s.struct_size = ctypes.sizeof(cls)
+        for k, _t in cls._fields_[1:]:
+            v = p[k]
+            if isinstance(v, (list, tuple)):
+                arr = getattr(s, k)
+                for q, x in enumerate(v):
+                    arr[q] = float(x)
+            else:
+                setattr(s, k, float(v))
+        return s
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libtbkrylov.so not built at {path}; run paper_0910_4497_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.tb_create.argtypes = [ctypes.POINTER(P), I, P, I64, I, I]
+    lib.tb_destroy.argtypes = [P]
+    lib.tb_build_local_H.argtypes = [P, I64, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I),
+                                     ctypes.POINTER(TBParams), ctypes.c_double, P]
+    lib.tb_krylov_rho.argtypes = [P, I, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I, P, P]
+    lib.tb_rho_layout.argtypes = [P, ctypes.POINTER(I64), P, P]
+    lib.tb_energy_forces.argtypes = [P, P, P]
+    lib.tb_get_stats.argtypes = [P, ctypes.POINTER(I64), I]
+    lib.tb_last_error.restype = ctypes.c_char_p
+    lib.tb_last_error.argtypes = []
+    for name in EXPORTS:
+        if name != "tb_last_error":
+            getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != 0:
+        raise TBError(code, _lib.tb_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class TBContext:
+    """Owns one library context on one device and stream."""
+
+    def __init__(self, n_atoms_max: int, n_cluster_max: int, r_max: int, device: int = 0,
+                 stream: torch.cuda.Stream | None = None):
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(self.lib.tb_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream),
+                                  n_atoms_max, n_cluster_max, r_max))
+        self.h = h
+        self.n_atoms = 0
+        self.nnz = None
+        self.rho = None
+        self.row_ptr = None
+        self.col_j = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_local_H(self, pos: torch.Tensor, cell, periodic, params: dict, r_cluster: float,
+                      want_sizes: bool = False):
+        assert pos.is_cuda and pos.dtype == torch.float64 and pos.is_contiguous() and pos.shape[1] == 3
+        cell = np.asarray(cell, dtype=np.float64)
+        if cell.shape == (3,):
+            cell = np.diag(cell)
+        cell = np.ascontiguousarray(cell.reshape(3, 3))
+        per = (ctypes.c_int * 3)(*[int(bool(x)) for x in periodic])
+        self._params = TBParams.from_dict(params)
+        n = pos.shape[0]
+        sizes = torch.empty(n, dtype=torch.int32, device=pos.device) if want_sizes else None
+        _check(self.lib.tb_build_local_H(self.h, n, _ptr(pos),
+                                         cell.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), per,
+                                         ctypes.byref(self._params), float(r_cluster), _ptr(sizes)))
+        if self.n_atoms != n or self.nnz is None:
+            self.n_atoms = n
+        self._pos = pos
+        self.nnz = None
+        return sizes
+
+    def rho_layout(self):
+        nnz = ctypes.c_int64()
+        rp = torch.empty(self.n_atoms + 1, dtype=torch.int64, device=self.device)
+        _check(self.lib.tb_rho_layout(self.h, ctypes.byref(nnz), None, None))
+        cj = torch.empty(max(1, nnz.value), dtype=torch.int32, device=self.device)
+        _check(self.lib.tb_rho_layout(self.h, ctypes.byref(nnz), _ptr(rp), _ptr(cj)))
+        self.nnz, self.row_ptr, self.col_j = nnz.value, rp, cj[:nnz.value]
+        return rp, self.col_j
+
+    def krylov_rho(self, r: int, kT: float, mu: float | None = None, n_electrons: float | None = None,
+                   precision: str = "fp64", r_per_atom: torch.Tensor | None = None,
+                   rho_out: torch.Tensor | None = None):
+        if self.nnz is None:
+            self.rho_layout()
+        if rho_out is None:
+            if self.rho is None or self.rho.shape[0] != self.nnz:
+                self.rho = torch.empty((self.nnz, 4, 4), dtype=torch.float64, device=self.device)
+            rho_out = self.rho
+        mu_t = torch.empty(1, dtype=torch.float64, device=self.device)
+        if r_per_atom is not None:
+            assert r_per_atom.dtype == torch.int32 and r_per_atom.is_cuda
+        mu_arg = math.nan if mu is None else float(mu)
+        ne = 0.0 if n_electrons is None else float(n_electrons)
+        _check(self.lib.tb_krylov_rho(self.h, int(r), _ptr(r_per_atom), float(kT), mu_arg, ne,
+                                      PRECISIONS[precision], _ptr(mu_t), _ptr(rho_out)))
+        self.rho = rho_out
+        return mu_t, rho_out
+
+    def energy_forces(self, forces: torch.Tensor | None = None, e_out: torch.Tensor | None = None):
+        if e_out is None:
+            e_out = torch.empty(4, dtype=torch.float64, device=self.device)
+        if forces is None:
+            forces = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.tb_energy_forces(self.h, _ptr(e_out), _ptr(forces)))
+        return e_out, forces
+
+    def stats(self, check: bool = True) -> dict:
+        arr = (ctypes.c_int64 * 16)()
+        code = self.lib.tb_get_stats(self.h, arr, 16)
+        out = {k: int(arr[q]) for q, k in enumerate(STAT_NAMES)}
+        if check:
+            _check(code)
+        out["status"] = code
+        return out
