@@ -148,6 +148,18 @@ int tb_energy_forces(tb_ctx *ctx, double *e_out, double *forces);
  * [8] re-orthogonalisation second passes. Synchronises the stream. */
 int tb_get_stats(tb_ctx *ctx, int64_t *stats_host, int n_stats);
 
+/* Per-phase timing with HIP events recorded on the context stream.
+ * tb_profile_enable(ctx, 1) starts recording start/end events around each
+ * phase (0: lists + local structure, 1: block Lanczos, 2: projected
+ * eigensolve, 3: chemical potential, 4: density-matrix assembly, 5: energy
+ * and forces); 0 stops. tb_profile_read synchronises the stream, adds the
+ * elapsed times of all recorded phases into ms_host[phase] and their launch
+ * counts into count_host[phase] (arrays of n >= 6), and clears the record.
+ * At most 4096 phase records are kept between reads; further ones are
+ * dropped and counted in count_host[6] if n > 6. */
+int tb_profile_enable(tb_ctx *ctx, int enable);
+int tb_profile_read(tb_ctx *ctx, double *ms_host, int64_t *count_host, int n);
+
 /* Message for the last nonzero status on this thread. */
 const char *tb_last_error(void);
 

@@ -134,6 +134,47 @@ def repulsion(pos, cell, periodic, p):
     return e_rep, -grad
 
 
+def _neighbours_of(k, pos, cell, periodic, cutoff):
+    d = geometry.displacements_from(k, pos, cell, periodic)
+    r = np.linalg.norm(d, axis=1)
+    sel = np.nonzero(r < cutoff)[0]
+    sel = sel[sel != k]
+    return sel, d[sel]
+
+
+def repulsion_forces_subset(pos, cell, periodic, p, atoms):
+    """-dE_rep/dR_k for the listed atoms only: the same sum as repulsion(),
+    F_k = sum_j (F'(x_k) + F'(x_j)) phi'(r_kj) d_kj / r_kj, evaluated from the
+    neighbourhoods of k and of its neighbours."""
+    xcache = {}
+
+    def x_of(a):
+        if a not in xcache:
+            _, d = _neighbours_of(a, pos, cell, periodic, p["dm"])
+            xcache[a] = float(np.sum(model.phi_pair(np.linalg.norm(d, axis=1), p))) if len(d) else 0.0
+        return xcache[a]
+
+    out = {}
+    for k in atoms:
+        nb, d = _neighbours_of(k, pos, cell, periodic, p["dm"])
+        f = np.zeros(3)
+        dFk = model.f_embed_deriv(x_of(k), p)
+        for j, dj in zip(nb, d):
+            r = np.linalg.norm(dj)
+            f += (dFk + model.f_embed_deriv(x_of(int(j)), p)) * model.phi_pair_deriv(r, p) / r * dj
+        out[int(k)] = f
+    return out
+
+
+def hop_closure(atoms, pos, cell, periodic, p):
+    """atoms together with their hopping neighbours (the seeds their forces need)."""
+    need = set(int(a) for a in atoms)
+    for k in atoms:
+        nb, _ = _neighbours_of(int(k), pos, cell, periodic, p["rm"])
+        need.update(int(j) for j in nb)
+    return sorted(need)
+
+
 # ---------------------------------------------------------- parallel map
 _G = {}
 
@@ -208,7 +249,7 @@ def run(pos, cell, periodic, p, r_cut, r, kT, n_electrons=None, mu=None,
     if full_column:
         out["rho_full"] = {s["i"]: rho_column_full(s, mu, kT) for s in sols}
     # forces
-    if all_atoms or force_atoms is not None:
+    if all_atoms:
         e_rep, f_rep = repulsion(pos, cell, periodic, p)
         grad = np.zeros((N, 3))
         for s in sols:
@@ -224,14 +265,25 @@ def run(pos, cell, periodic, p, r_cut, r, kT, n_electrons=None, mu=None,
         forces = -grad + f_rep
         out.update(e_rep=e_rep, forces=forces,
                    e_total=e_band - kT * ent + e_rep)
-        if force_atoms is not None:
-            need = set()
-            nb, _ = geometry.neighbour_lists(pos, cell, periodic, p["rm"])
-            for k in force_atoms:
-                need.add(k)
-                need.update(int(j) for j in nb[k])
-            missing = need - set(by_atom)
-            if missing:
-                raise ValueError(f"forces on {force_atoms} need solves of {sorted(missing)}")
-            out["forces_sampled"] = {int(k): forces[k] for k in force_atoms}
+    elif force_atoms is not None:
+        need = hop_closure(force_atoms, pos, cell, periodic, p)
+        missing = set(need) - set(by_atom)
+        if missing:
+            raise ValueError(f"forces on {list(force_atoms)} need solves of {sorted(missing)}")
+        f_rep = repulsion_forces_subset(pos, cell, periodic, p, force_atoms)
+        sampled = {}
+        for k in force_atoms:
+            k = int(k)
+            f = f_rep[k].copy()
+            sk = by_atom[k]
+            for row, j in enumerate(sk["J"][1:], start=1):
+                j = int(j)
+                d = geometry.min_image(pos[j] - pos[k], cell, periodic)
+                g_kj = np.einsum("cba,ab->c", model.sk_blocks_grad(d, p), rho[k][row])
+                sj = by_atom[j]
+                rowj = int(np.nonzero(sj["J"] == k)[0][0])
+                g_jk = np.einsum("cba,ab->c", model.sk_blocks_grad(-d, p), rho[j][rowj])
+                f += g_kj - g_jk            # F_k = -(grad_k): pair (k,j) gives -g_kj, pair (j,k) +g_jk
+            sampled[k] = f
+        out["forces_sampled"] = sampled
     return out

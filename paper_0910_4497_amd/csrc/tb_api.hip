@@ -43,6 +43,19 @@ static int fail(int code, const char* fmt, ...) {
 
 static const int MU_ITERS = 64;
 
+// phase timing: returns the slot of the start event, or -1 when disabled/full
+static int prof_begin(tb_ctx* c, int phase) {
+  if (!c->prof) return -1;
+  if (c->ev_used >= PROF_MAX) { ++c->ev_dropped; return -1; }
+  const int k = c->ev_used++;
+  c->ev_phase[k] = phase;
+  hipEventRecord(c->ev_pool[2 * k], c->stream);
+  return k;
+}
+static void prof_end(tb_ctx* c, int k) {
+  if (k >= 0) hipEventRecord(c->ev_pool[2 * k + 1], c->stream);
+}
+
 extern "C" const char* tb_last_error(void) { return g_err.c_str(); }
 
 template <typename T>
@@ -63,6 +76,11 @@ extern "C" int tb_destroy(tb_ctx* c) {
                   c->rot_n, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  if (c->ev_pool) {
+    for (int k = 0; k < 2 * PROF_MAX; ++k) hipEventDestroy(c->ev_pool[k]);
+    delete[] c->ev_pool;
+    delete[] c->ev_phase;
+  }
   hipSetDevice(dev_prev);
   delete c;
   return TB_OK;
@@ -220,8 +238,10 @@ extern "C" int tb_build_local_H(tb_ctx* c, int64_t n_atoms, const double* pos, c
   c->n_atoms = n_atoms;
   const int n = (int)n_atoms;
   hipStream_t st = c->stream;
+  const int pk = prof_begin(c, 0);
   hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, c->stats, ST_NSTATS);
   launch_build(c, pos, r_list, st);
+  prof_end(c, pk);
   if (n_cluster_out) HIP_TRY(hipMemcpyAsync(n_cluster_out, c->clu_n, n * sizeof(int), hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipGetLastError());
   c->stage = 1;
@@ -260,28 +280,36 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   la.vbuf = c->vbuf; la.tab = c->tab; la.kused = c->kused; la.vj = c->vj;
   la.counter = c->work_counter; la.stats = c->stats;
   const size_t lds = lanczos_lds_bytes(c->nc_max, c->r_max, fp32);
+  int pk = prof_begin(c, 1);
   launch_lanczos(la, fp32, c->n_wg_lanczos < n ? c->n_wg_lanczos : n, lds, st);
+  prof_end(c, pk);
   // K5: projected eigensolve
   EigArgs ea;
   ea.n_atoms = n; ea.r_max = c->r_max; ea.tab = c->tab; ea.kused = c->kused;
   ea.lam = c->lam; ea.wgt = c->wgt; ea.y1 = c->y1;
   ea.rot_cs = c->rot_cs; ea.rot_p = c->rot_p; ea.rot_n = c->rot_n; ea.rot_max = c->rot_max;
   ea.stats = c->stats;
+  pk = prof_begin(c, 2);
   launch_eig(ea, st);
+  prof_end(c, pk);
   // K6: chemical potential and spectral sums
   MuArgs ma;
   ma.n_pairs = (int64_t)n * 4 * c->r_max;
   ma.lam = c->lam; ma.wgt = c->wgt; ma.kT = kT; ma.n_e = n_electrons;
   ma.state = c->mu_state; ma.partial = c->partial; ma.counter = c->counter;
   ma.eparts = c->eparts; ma.mu_out = mu_out;
+  pk = prof_begin(c, 3);
   launch_mu(ma, mu, fixed, MU_ITERS, st);
+  prof_end(c, pk);
   // K7: density-matrix blocks
   RhoArgs ra;
   ra.n_atoms = n; ra.r_max = c->r_max; ra.kused = c->kused; ra.hop_n = c->hop_n; ra.clu_j = c->clu_j;
   ra.nc_max = c->nc_max; ra.lam = c->lam; ra.y1 = c->y1; ra.rot_cs = c->rot_cs; ra.rot_p = c->rot_p;
   ra.rot_n = c->rot_n; ra.rot_max = c->rot_max; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
   ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out;
+  pk = prof_begin(c, 4);
   launch_rho(ra, st);
+  prof_end(c, pk);
   HIP_TRY(hipGetLastError());
   c->rho_last = rho_out;
   c->stage = 2;
@@ -315,7 +343,9 @@ extern "C" int tb_energy_forces(tb_ctx* c, double* e_out, double* forces) {
   fa.hop_n = c->hop_n; fa.hop_j = c->hop_j; fa.hop_rev = c->hop_rev; fa.hop_d = c->hop_d;
   fa.row_ptr = c->row_ptr; fa.rho = c->rho_last; fa.xrep = c->xrep; fa.forces = forces;
   fa.eparts = c->eparts; fa.kT = c->kT; fa.e_out = e_out;
+  const int pk = prof_begin(c, 5);
   launch_forces(fa, c->stream);
+  prof_end(c, pk);
   HIP_TRY(hipGetLastError());
   return TB_OK;
 }
@@ -331,5 +361,33 @@ extern "C" int tb_get_stats(tb_ctx* c, int64_t* stats_host, int n_stats) {
   if (s[ST_FLAGS] & (FL_HOP_OVERFLOW | FL_CLUSTER_OVERFLOW | FL_COUPLING_OVERFLOW))
     return fail(TB_ECAPACITY, "device list overflow (flags 0x%llx)", (unsigned long long)s[ST_FLAGS]);
   if (s[ST_FLAGS]) return fail(TB_EDEVICE, "device error flags 0x%llx", (unsigned long long)s[ST_FLAGS]);
+  return TB_OK;
+}
+
+extern "C" int tb_profile_enable(tb_ctx* c, int enable) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  HIP_TRY(hipSetDevice(c->device));
+  if (enable && !c->ev_pool) {
+    c->ev_pool = new hipEvent_t[2 * PROF_MAX];
+    c->ev_phase = new int[PROF_MAX];
+    for (int k = 0; k < 2 * PROF_MAX; ++k) HIP_TRY(hipEventCreate(&c->ev_pool[k]));
+  }
+  c->prof = enable ? 1 : 0;
+  return TB_OK;
+}
+
+extern "C" int tb_profile_read(tb_ctx* c, double* ms_host, int64_t* count_host, int n) {
+  if (!c || !ms_host || !count_host || n < N_PHASES) return fail(TB_EINVAL, "null argument or n < 6");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < c->ev_used; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+    ms_host[c->ev_phase[k]] += ms;
+    count_host[c->ev_phase[k]] += 1;
+  }
+  if (n > N_PHASES) count_host[N_PHASES] += c->ev_dropped;
+  c->ev_used = 0;
+  c->ev_dropped = 0;
   return TB_OK;
 }

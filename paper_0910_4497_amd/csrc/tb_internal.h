@@ -16,6 +16,8 @@ constexpr int JMAX = ZMAX + 1;     // rho row atoms per target: itself + hop lis
 constexpr int LOCAL_BITS = 11;     // local atom index bits in a packed coupling
 constexpr int NCLUSTER_LIMIT = (1 << LOCAL_BITS) - 1;
 constexpr int RMAX_LIMIT = 256;
+constexpr int PROF_MAX = 4096;
+constexpr int N_PHASES = 6;
 
 // Device-side error / statistics words (int64 each).
 enum StatSlot {
@@ -198,4 +200,10 @@ struct tb_ctx {
   double* xrep;          // [N]: sum_j phi, then F'(x)
   double* eparts;        // [4] band, entropy, rep, count
   int64_t* stats;        // [ST_NSTATS]
+  // phase timing
+  int prof;
+  hipEvent_t* ev_pool;   // [2 * PROF_MAX]
+  int* ev_phase;         // host [PROF_MAX]
+  int ev_used;
+  int64_t ev_dropped;
 };

@@ -23,7 +23,9 @@ ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4:
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
               "max_eig_iters", "memory_bytes", "reorth_second_pass")
 EXPORTS = ("tb_create", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
-           "tb_energy_forces", "tb_get_stats", "tb_last_error")
+           "tb_energy_forces", "tb_get_stats", "tb_profile_enable", "tb_profile_read", "tb_last_error")
+PHASES = ("lists_local", "lanczos", "eig", "mu", "rho", "forces")
+RHO_ROWS_MAX = 25          # rho row atoms per target: itself + at most 24 neighbours
 
 
 class TBError(RuntimeError):
@@ -75,6 +77,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tb_rho_layout.argtypes = [P, ctypes.POINTER(I64), P, P]
     lib.tb_energy_forces.argtypes = [P, P, P]
     lib.tb_get_stats.argtypes = [P, ctypes.POINTER(I64), I]
+    lib.tb_profile_enable.argtypes = [P, I]
+    lib.tb_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I]
     lib.tb_last_error.restype = ctypes.c_char_p
     lib.tb_last_error.argtypes = []
     for name in EXPORTS:
@@ -136,8 +140,7 @@ class TBContext:
         _check(self.lib.tb_build_local_H(self.h, n, _ptr(pos),
                                          cell.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), per,
                                          ctypes.byref(self._params), float(r_cluster), _ptr(sizes)))
-        if self.n_atoms != n or self.nnz is None:
-            self.n_atoms = n
+        self.n_atoms = n
         self._pos = pos
         self.nnz = None
         return sizes
@@ -154,11 +157,12 @@ class TBContext:
     def krylov_rho(self, r: int, kT: float, mu: float | None = None, n_electrons: float | None = None,
                    precision: str = "fp64", r_per_atom: torch.Tensor | None = None,
                    rho_out: torch.Tensor | None = None):
-        if self.nnz is None:
-            self.rho_layout()
+        """rho_out defaults to a buffer of capacity n_atoms * RHO_ROWS_MAX blocks, so no
+        host synchronisation is needed; rho_layout() gives the used prefix."""
         if rho_out is None:
-            if self.rho is None or self.rho.shape[0] != self.nnz:
-                self.rho = torch.empty((self.nnz, 4, 4), dtype=torch.float64, device=self.device)
+            cap = self.n_atoms * RHO_ROWS_MAX
+            if self.rho is None or self.rho.shape[0] < cap:
+                self.rho = torch.empty((cap, 4, 4), dtype=torch.float64, device=self.device)
             rho_out = self.rho
         mu_t = torch.empty(1, dtype=torch.float64, device=self.device)
         if r_per_atom is not None:
@@ -177,6 +181,16 @@ class TBContext:
             forces = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=self.device)
         _check(self.lib.tb_energy_forces(self.h, _ptr(e_out), _ptr(forces)))
         return e_out, forces
+
+    def profile(self, enable: bool):
+        _check(self.lib.tb_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """Summed milliseconds and launch counts per phase since the last read."""
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        _check(self.lib.tb_profile_read(self.h, ms, cnt, 7))
+        return {name: (ms[q], int(cnt[q])) for q, name in enumerate(PHASES)}
 
     def stats(self, check: bool = True) -> dict:
         arr = (ctypes.c_int64 * 16)()

@@ -22,8 +22,9 @@ def gpu_run(ctx, pos_np, cell, periodic, r_cut, r, kT, n_electrons=None, mu=None
                                r_per_atom=rpa)
     e, f = ctx.energy_forces()
     torch.cuda.synchronize()
+    ctx.rho_layout()
     stats = ctx.stats()
-    return {"mu": float(mu_t.item()), "rho": rho.cpu().numpy(), "row_ptr": ctx.row_ptr.cpu().numpy(),
+    return {"mu": float(mu_t.item()), "rho": rho[:ctx.nnz].cpu().numpy(), "row_ptr": ctx.row_ptr.cpu().numpy(),
             "col_j": ctx.col_j.cpu().numpy(), "e": e.cpu().numpy(), "forces": f.cpu().numpy(),
             "stats": stats}
 

@@ -109,3 +109,49 @@ def test_parity_c60_240_fp32(torch_cuda, c60_240_oracle):
     print(f"  fp32: max force err {fe:.3e} eV/A, energy err {ee:.3e} eV/atom")
     assert fe <= 1e-3
     assert ee <= 1e-4
+
+
+def test_parity_c60_1920_full(torch_cuda):
+    """Precision workload at full size: every atom, mu by bisection."""
+    w = inputs.workload("c60_1920")
+    ora = otb.run(w.pos, w.cell, (1, 1, 1), P, w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                  processes=NPROC)
+    ctx = make_ctx(w.n_atoms, 240, w.r)
+    res = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons)
+    assert abs(res["mu"] - ora["mu"]) < 1e-9
+    check_against_oracle(res, ora, range(w.n_atoms))
+    r32 = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                  precision="fp32")
+    fe = float(np.abs(r32["forces"] - ora["forces"]).max())
+    print(f"  fp32 max force err {fe:.3e} eV/A")
+    assert fe <= 1e-3
+
+
+def sampled_parity(name, mu_fixed, n_sample, seed, n_cluster, precision="fp64"):
+    w = inputs.workload(name)
+    rng = np.random.default_rng(seed)
+    S = sorted(rng.choice(w.n_atoms, n_sample, replace=False).tolist())
+    need = otb.hop_closure(S, w.pos, w.cell, (1, 1, 1), P)
+    ora = otb.run(w.pos, w.cell, (1, 1, 1), P, w.r_cut, w.r, w.kT, mu=mu_fixed, atoms=need,
+                  force_atoms=S, r_per_atom=w.r_per_atom, processes=NPROC)
+    r_max = int(np.max(w.r_per_atom)) if w.r_per_atom is not None else w.r
+    ctx = make_ctx(w.n_atoms, n_cluster, r_max)
+    res = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, mu=mu_fixed,
+                  precision=precision, r_per_atom=w.r_per_atom)
+    return w, S, need, ora, res
+
+
+@pytest.mark.parametrize("name,n_cluster", [("c60_15360", 400), ("c60_6480_strained", 280)])
+def test_parity_large_sampled_fixed_mu(torch_cuda, name, n_cluster):
+    """Full-size launch, outputs sampled on seeded atoms the oracle solves one
+    by one (chemical potential fixed at 3.5 eV on both sides)."""
+    w, S, need, ora, res = sampled_parity(name, 3.5, 12, 99, n_cluster)
+    assert res["stats"]["max_cluster"] <= n_cluster
+    worst, scale = compare_rho(res, ora["rho"], ora["sols"], need)
+    print(f"  {name}: rho max abs err {worst:.3e} (scale {scale:.3e}) over {len(need)} seeds")
+    assert worst <= 1e-8 * scale
+    F = np.array([ora["forces_sampled"][k] for k in S])
+    G = res["forces"][S]
+    err = rel_inf(G, F)
+    print(f"  {name}: sampled force rel err {err:.3e}")
+    assert err <= 1e-8

@@ -179,3 +179,15 @@ def test_cfg1_translation_and_permutation(cfg1_run):
         assert np.array_equal(perm[b["J"]], a["J"]) or set(perm[b["J"]]) == set(a["J"])
         order = [list(perm[b["J"]]).index(j) for j in a["J"]]
         assert np.abs(ra - rb[order]).max() < 1e-11
+
+
+def test_subset_mode_matches_full(cfg1_run):
+    """The oracle's sampled-force path (used at sizes where only a subset of
+    seeds is solved) reproduces the all-atom forces."""
+    w, res = cfg1_run
+    S = [5, 77, 230]
+    need = tb.hop_closure(S, w.pos, w.cell, (1, 1, 1), P)
+    sub = tb.run(w.pos, w.cell, (1, 1, 1), P, w.r_cut, w.r, w.kT, mu=res["mu"], atoms=need,
+                 force_atoms=S, processes=1)
+    for k in S:
+        assert np.abs(sub["forces_sampled"][k] - res["forces"][k]).max() < 1e-12
