@@ -73,7 +73,7 @@ extern "C" int tb_destroy(tb_ctx* c) {
   void* ptrs[] = {c->hop_n, c->hop_j, c->hop_rev, c->hop_d, c->pair64, c->pair32, c->clu_n, c->clu_j,
                   c->loc_off, c->loc_ent, c->hnorm, c->jloc, c->row_ptr, c->col_j, c->vbuf, c->tab,
                   c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->rot_cs, c->rot_p,
-                  c->rot_n, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
+                  c->rot_n, c->seg, c->seg_n, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (c->ev_pool) {
@@ -124,6 +124,11 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
     delete c;
     return fail(TB_ECAPACITY, "LDS request of %zu B refused: %s", lds, hipGetErrorString(e));
   }
+  e = eig_set_lds(r_max);
+  if (e != hipSuccess || rho_lds_bytes(r_max) > 160 * 1024) {
+    delete c;
+    return fail(TB_ECAPACITY, "r_max=%d too large for the eigensolver LDS: %s", r_max, hipGetErrorString(e));
+  }
   int per_cu = (int)((160 * 1024) / (lds + 1024));
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 2) per_cu = 2;
@@ -157,6 +162,9 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(rot_cs, N * c->rot_max * 2);
   ALLOC(rot_p, N * c->rot_max);
   ALLOC(rot_n, N);
+  c->seg_max = (int)(16 * dmax + 64);
+  ALLOC(seg, N * c->seg_max);
+  ALLOC(seg_n, 2 * N);
   ALLOC(mu_state, 16);
   ALLOC(partial, 4096);
   ALLOC(counter, 16);
@@ -183,6 +191,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   HIP_TRY(hipMemset(c->mu_state, 0, 16 * sizeof(double)));
   HIP_TRY(hipMemset(c->kused, 0, N * sizeof(int)));
   HIP_TRY(hipMemset(c->rot_n, 0, N * sizeof(int)));
+  HIP_TRY(hipMemset(c->seg_n, 0, 2 * N * sizeof(int)));
   HIP_TRY(hipDeviceSynchronize());
   c->nnz_pairs = -1;
   *out = c;
@@ -288,6 +297,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   ea.n_atoms = n; ea.r_max = c->r_max; ea.tab = c->tab; ea.kused = c->kused;
   ea.lam = c->lam; ea.wgt = c->wgt; ea.y1 = c->y1;
   ea.rot_cs = c->rot_cs; ea.rot_p = c->rot_p; ea.rot_n = c->rot_n; ea.rot_max = c->rot_max;
+  ea.seg = c->seg; ea.seg_n = c->seg_n; ea.seg_max = c->seg_max;
   ea.stats = c->stats;
   pk = prof_begin(c, 2);
   launch_eig(ea, st);
@@ -305,7 +315,8 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   RhoArgs ra;
   ra.n_atoms = n; ra.r_max = c->r_max; ra.kused = c->kused; ra.hop_n = c->hop_n; ra.clu_j = c->clu_j;
   ra.nc_max = c->nc_max; ra.lam = c->lam; ra.y1 = c->y1; ra.rot_cs = c->rot_cs; ra.rot_p = c->rot_p;
-  ra.rot_n = c->rot_n; ra.rot_max = c->rot_max; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
+  ra.rot_n = c->rot_n; ra.rot_max = c->rot_max;
+  ra.seg = c->seg; ra.seg_n = c->seg_n; ra.seg_max = c->seg_max; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
   ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out;
   pk = prof_begin(c, 4);
   launch_rho(ra, st);

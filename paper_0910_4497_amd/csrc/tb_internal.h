@@ -27,7 +27,7 @@ enum StatSlot {
 };
 enum FlagBits {
   FL_HOP_OVERFLOW = 1, FL_CLUSTER_OVERFLOW = 2, FL_COUPLING_OVERFLOW = 4,
-  FL_NONFINITE = 8, FL_EIG_NOCONV = 16, FL_ROTLOG_OVERFLOW = 32
+  FL_NONFINITE = 8, FL_EIG_NOCONV = 16, FL_ROTLOG_OVERFLOW = 32, FL_SEG_OVERFLOW = 64
 };
 
 // Model parameters as the kernels see them (plain struct, passed by value).
@@ -108,6 +108,7 @@ struct EigArgs {
   const double* tab; const int* kused;
   double* lam; double* wgt; double* y1;
   double* rot_cs; uint16_t* rot_p; int* rot_n; int64_t rot_max;
+  int* seg; int* seg_n; int seg_max;   // [N][seg_max] segment starts; [N][2]: band steps, total
   int64_t* stats;
 };
 struct RhoArgs {
@@ -115,6 +116,7 @@ struct RhoArgs {
   const int* kused; const int* hop_n; const int* clu_j; int nc_max;
   const double* lam; const double* y1;
   const double* rot_cs; const uint16_t* rot_p; const int* rot_n; int64_t rot_max;
+  const int* seg; const int* seg_n; int seg_max;
   const void* vj; int vj_fp32;
   const int64_t* row_ptr;
   const double* mu_state; double kT;
@@ -122,6 +124,7 @@ struct RhoArgs {
 };
 size_t eig_lds_bytes(int r_max);
 size_t rho_lds_bytes(int r_max);
+hipError_t eig_set_lds(int r_max);
 void launch_eig(const EigArgs& a, hipStream_t st);
 void launch_rho(const RhoArgs& a, hipStream_t st);
 
@@ -193,6 +196,7 @@ struct tb_ctx {
   // eigen (K5/K7)
   double* lam; double* wgt; double* y1;                    // [N][D], [N][D], [N][4][D]
   double* rot_cs; uint16_t* rot_p; int* rot_n;             // [N][ROT][2], [N][ROT], [N]
+  int* seg; int* seg_n; int seg_max;                       // [N][SEG], [N][2]
   // mu / energies (K6/K8)
   double* mu_state;      // [8]: lo, hi, mu, done, N(mu) ...
   double* partial;       // [NPART][4]

@@ -111,45 +111,59 @@ __device__ __forceinline__ void store4(VT* p, const double (&v)[4]) {
   *(V4*)p = x;
 }
 
-// In-place Cholesky of the active submatrix of a 4x4 SPD Gram G = U^T U;
-// returns false if an active pivot is not safely positive.
-__device__ __forceinline__ bool chol4(const double* G, const bool* act, double (&U)[16],
-                                      double tol2) {
+// Register Cholesky of the active submatrix of a 4x4 SPD Gram G = U^T U;
+// false if an active pivot is not safely positive; ratio = min pivot^2 / G_cc.
+__device__ __forceinline__ bool chol4r(const double (&G)[16], const bool (&act)[4], double (&U)[16],
+                                       double tol2, double& ratio) {
+  bool ok = true;
+  ratio = 1.0;
+#pragma unroll
   for (int q = 0; q < 16; ++q) U[q] = 0.0;
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (!act[c]) continue;
     double d = G[c * 4 + c];
-    for (int p = 0; p < c; ++p) if (act[p]) d -= U[p * 4 + c] * U[p * 4 + c];
-    if (!(d > 1e-8 * G[c * 4 + c]) || !(d > tol2)) return false;
+#pragma unroll
+    for (int p = 0; p < c; ++p) d -= U[p * 4 + c] * U[p * 4 + c];
+    if (!(d > 1e-8 * G[c * 4 + c]) || !(d > tol2)) { ok = false; d = 1.0; }
+    const double rr = d / G[c * 4 + c];
+    ratio = rr < ratio ? rr : ratio;
     const double u = sqrt(d);
     U[c * 4 + c] = u;
+    const double iu = 1.0 / u;
+#pragma unroll
     for (int e = c + 1; e < 4; ++e) {
       if (!act[e]) continue;
-      double s = G[c * 4 + e];
-      for (int p = 0; p < c; ++p) if (act[p]) s -= U[p * 4 + c] * U[p * 4 + e];
-      U[c * 4 + e] = s / u;
+      double sm = G[c * 4 + e];
+#pragma unroll
+      for (int p = 0; p < c; ++p) sm -= U[p * 4 + c] * U[p * 4 + e];
+      U[c * 4 + e] = sm * iu;
     }
   }
-  return true;
+  return ok;
 }
 
-// Inverse of an upper-triangular 4x4 restricted to active columns (zero elsewhere).
-__device__ __forceinline__ void inv_upper4(const double (&U)[16], const bool* act, double (&X)[16]) {
+__device__ __forceinline__ void inv_upper4r(const double (&U)[16], const bool (&act)[4], double (&X)[16]) {
+#pragma unroll
   for (int q = 0; q < 16; ++q) X[q] = 0.0;
+#pragma unroll
   for (int c = 3; c >= 0; --c) {
     if (!act[c]) continue;
-    X[c * 4 + c] = 1.0 / U[c * 4 + c];
+    const double iu = 1.0 / U[c * 4 + c];
+    X[c * 4 + c] = iu;
+#pragma unroll
     for (int e = c + 1; e < 4; ++e) {
       if (!act[e]) continue;
-      double s = 0.0;
-      for (int p = c + 1; p <= e; ++p) if (act[p]) s += U[c * 4 + p] * X[p * 4 + e];
-      X[c * 4 + e] = -s / U[c * 4 + c];
+      double sm = 0.0;
+#pragma unroll
+      for (int p = c + 1; p <= e; ++p) sm += U[c * 4 + p] * X[p * 4 + e];
+      X[c * 4 + e] = -sm * iu;
     }
   }
 }
 
 template <typename VT>
-__global__ void __launch_bounds__(LZ_NT)
+__global__ void __launch_bounds__(LZ_NT, 4)
 k_lanczos(LanczosArgs g) {
   extern __shared__ unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -160,10 +174,10 @@ k_lanczos(LanczosArgs g) {
   double* s_C = (double*)(((uintptr_t)(s_W + (size_t)Rcap * 4) + 15) & ~(uintptr_t)15);
   // s_C: [max(r_max, LZ_NW)][16] projection coefficients / partials
   const int cslots = (g.r_max > 2 * LZ_NW ? g.r_max : 2 * LZ_NW);
-  double* s_Cp = s_C + (size_t)cslots * 16;                 // partials [2*LZ_NW][16]
-  double* s_red = s_Cp + (size_t)2 * LZ_NW * 16;            // [LZ_NW][16]
-  double* s_misc = s_red + LZ_NW * 16;                      // 128 doubles
-  int* s_off = (int*)(s_misc + 128);                        // [ncap+1]
+  double* s_Cp = s_C + (size_t)cslots * 16;                 // partials [4*LZ_NW][16]
+  double* s_red = s_Cp + (size_t)4 * LZ_NW * 16;            // [LZ_NW][16]
+  double* s_misc = s_red + LZ_NW * 16;                      // 192 doubles
+  int* s_off = (int*)(s_misc + 192);                        // [ncap+1]
   int* s_gid = s_off + ncap + 1;                            // [ncap]
   signed char* s_js = (signed char*)(s_gid + ncap);         // [ncap]
   __shared__ int s_atom;
@@ -174,6 +188,7 @@ k_lanczos(LanczosArgs g) {
   double* B = s_misc + 48;     // [16] new B
   double* X = s_misc + 64;     // [16] scratch
   int* s_flag = (int*)(s_misc + 96);     // [8]: active columns, ok, ...
+  double* s_Np = s_misc + 128;           // [16 parts][4] column-norm partials
 
   VT* vbase = (VT*)g.vbuf + (size_t)blockIdx.x * g.r_max * Rcap * 4;
   const VT* pairs = (const VT*)g.pair;
@@ -216,64 +231,86 @@ k_lanczos(LanczosArgs g) {
     int k_end = r_i;
     int ndefl = 0, n2 = 0;
     double* tab = g.tab + (size_t)atom * g.r_max * 32;
+    const int cq = tid & 3;                 // fixed column of this thread in the H.V items
 
     for (int k = 0; k < r_i; ++k) {
-      const VT* Vk = vbase + (size_t)k * Rcap * 4;
-      // ---- 1. W = H V_k
-      for (int item = tid; item < 4 * n; item += LZ_NT) {
-        const int a = item >> 2, c = item & 3;
-        const VT* va = s_V + 16 * a + c;
+      // ---- 1. W = H V_k, fused with the partial sums of A_k = V_k^T W
+      {
+        double accA[4] = {0.0, 0.0, 0.0, 0.0};     // A[c'][cq], c' = 0..3
         const VT es = (VT)g.eps_s, ep = (VT)g.eps_p, vsss = (VT)g.v_sss, vsps = (VT)g.v_sps,
                  vdif = (VT)(g.v_pps - g.v_ppp), vppp = (VT)g.v_ppp;
-        VT w0 = es * va[0], w1 = ep * va[4], w2 = ep * va[8], w3 = ep * va[12];
-        const int gid = s_gid[a];
-        int e1 = s_off[a + 1];
-        if (e1 > g.emax) e1 = (int)g.emax;
-        for (int e = s_off[a]; e < e1; ++e) {
-          const unsigned int pe = ent[e];
-          const int b = pe & NCLUSTER_LIMIT, slot = pe >> LOCAL_BITS;
-          typedef typename Vec4<VT>::T V4;
-          const V4 hp4 = *(const V4*)(pairs + ((size_t)gid * ZMAX + slot) * 4);
-          const VT hx = hp4.x, hy = hp4.y, hz = hp4.z, s = hp4.w;
-          const VT* vb = s_V + 16 * b + c;
-          const VT vs = vb[0], vx = vb[4], vy = vb[8], vz = vb[12];
-          const VT hp = hx * vx + hy * vy + hz * vz;
-          w0 += s * (vsss * vs + vsps * hp);
-          const VT t = s * (vdif * hp - vsps * vs);
-          const VT sp = s * vppp;
-          w1 += t * hx + sp * vx;
-          w2 += t * hy + sp * vy;
-          w3 += t * hz + sp * vz;
+        typedef typename Vec4<VT>::T V4;
+        for (int item = tid; item < 4 * n; item += LZ_NT) {
+          const int a = item >> 2, c = cq;
+          const VT* va = s_V + 16 * a + c;
+          VT w0 = es * va[0], w1 = ep * va[4], w2 = ep * va[8], w3 = ep * va[12];
+          const int gid = s_gid[a];
+          int e1 = s_off[a + 1];
+          if (e1 > g.emax) e1 = (int)g.emax;
+          for (int e0 = s_off[a]; e0 < e1; e0 += 4) {
+            unsigned int pe[4];
+            V4 hp4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pe[u] = (e0 + u < e1) ? ent[e0 + u] : 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int slot = pe[u] >> LOCAL_BITS;
+              hp4[u] = *(const V4*)(pairs + ((size_t)gid * ZMAX + slot) * 4);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (e0 + u >= e1) break;
+              const int b = pe[u] & NCLUSTER_LIMIT;
+              const VT hx = hp4[u].x, hy = hp4[u].y, hz = hp4[u].z, sv = hp4[u].w;
+              const VT* vb = s_V + 16 * b + c;
+              const VT vs = vb[0], vx = vb[4], vy = vb[8], vz = vb[12];
+              const VT hp = hx * vx + hy * vy + hz * vz;
+              w0 += sv * (vsss * vs + vsps * hp);
+              const VT t = sv * (vdif * hp - vsps * vs);
+              const VT sp = sv * vppp;
+              w1 += t * hx + sp * vx;
+              w2 += t * hy + sp * vy;
+              w3 += t * hz + sp * vz;
+            }
+          }
+          VT* wa = s_W + 16 * a + c;
+          wa[0] = w0; wa[4] = w1; wa[8] = w2; wa[12] = w3;
+          const VT wb[4] = {w0, w1, w2, w3};
+#pragma unroll
+          for (int beta = 0; beta < 4; ++beta) {
+            const V4 vr = *(const V4*)(s_V + 4 * (4 * a + beta));
+            accA[0] += (double)vr.x * (double)wb[beta];
+            accA[1] += (double)vr.y * (double)wb[beta];
+            accA[2] += (double)vr.z * (double)wb[beta];
+            accA[3] += (double)vr.w * (double)wb[beta];
+          }
         }
-        VT* wa = s_W + 16 * a + c;
-        wa[0] = w0; wa[4] = w1; wa[8] = w2; wa[12] = w3;
-      }
-      __syncthreads();
-      // ---- 2. A_k = V_k^T W
-      {
-        double acc[16];
+        // reduce over lanes with equal (lane & 3), then over waves
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-        for (int row = tid; row < R; row += LZ_NT) {
-          double v[4], w[4];
-          load4<VT>(s_V + 4 * row, v);
-          load4<VT>(s_W + 4 * row, w);
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
+          for (int off = 4; off < 64; off <<= 1) accA[q] += __shfl_xor(accA[q], off, 64);
+        if (lane < 4) {
 #pragma unroll
-            for (int d = 0; d < 4; ++d) acc[c * 4 + d] += v[c] * w[d];
+          for (int q = 0; q < 4; ++q) s_red[wave * 16 + q * 4 + lane] = accA[q];
         }
-        block_sum<16>(acc, s_red, X);
+        __syncthreads();
+        if (tid < 16) {
+          double sum = 0.0;
+          for (int w = 0; w < LZ_NW; ++w) sum += s_red[w * 16 + tid];
+          X[tid] = sum;
+        }
+        __syncthreads();
         if (tid < 16) {
           const int c = tid >> 2, d = tid & 3;
-          const double a = 0.5 * (X[c * 4 + d] + X[d * 4 + c]);
-          A[tid] = a;
-          tab[(size_t)k * 32 + tid] = a;
+          const double av = 0.5 * (X[c * 4 + d] + X[d * 4 + c]);
+          A[tid] = av;
+          tab[(size_t)k * 32 + tid] = av;
         }
         __syncthreads();
       }
       if (k == r_i - 1) break;
-      // ---- 3. three-term recursion
+      // ---- 2. three-term recursion: W -= V_k A_k + V_{k-1} B_{k-1}^T
       {
         const VT* Vprev = (k > 0) ? vbase + (size_t)(k - 1) * Rcap * 4 : nullptr;
         for (int row = tid; row < R; row += LZ_NT) {
@@ -292,11 +329,13 @@ k_lanczos(LanczosArgs g) {
         }
         __syncthreads();
       }
-      // ---- 4/5. full re-orthogonalisation against V_0..V_k (one pass, a
-      // second one if a column norm dropped by more than sqrt(2))
+      // ---- 3. full re-orthogonalisation against V_0..V_k: projection sweep
+      // (items with block k also give the column norms before the pass),
+      // then the update sweep with the Gram matrix of the result; a second
+      // pass when a column norm fell by more than sqrt(2).
       for (int pass = 0; pass < 2; ++pass) {
         const int nb = k + 1;
-        const int parts = (nb >= LZ_NW) ? 1 : (2 * LZ_NW) / nb;   // row splits per block
+        const int parts = (nb >= 2 * LZ_NW) ? 1 : (2 * LZ_NW + nb - 1) / nb;
         const int items = nb * parts;
         for (int it = wave; it < items; it += LZ_NW) {
           const int j = it / parts, part = it % parts;
@@ -304,8 +343,32 @@ k_lanczos(LanczosArgs g) {
           VT pacc[16];
 #pragma unroll
           for (int q = 0; q < 16; ++q) pacc[q] = (VT)0;
-          for (int row = part * 64 + lane; row < R; row += 64 * parts) {
-            typedef typename Vec4<VT>::T V4;
+          double nacc[4] = {0.0, 0.0, 0.0, 0.0};
+          const bool want_norm = (j == k);
+          typedef typename Vec4<VT>::T V4;
+          const int S = 64 * parts;
+          int row = part * 64 + lane;
+          constexpr int UP = sizeof(VT) == 8 ? 2 : 4;
+          for (; row + (UP - 1) * S < R; row += UP * S) {
+            V4 v[UP], w[UP];
+#pragma unroll
+            for (int u = 0; u < UP; ++u) v[u] = *(const V4*)(Vj + 4 * (row + u * S));
+#pragma unroll
+            for (int u = 0; u < UP; ++u) w[u] = *(const V4*)(s_W + 4 * (row + u * S));
+#pragma unroll
+            for (int u = 0; u < UP; ++u) {
+              const VT vv[4] = {v[u].x, v[u].y, v[u].z, v[u].w}, ww[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+#pragma unroll
+              for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int d = 0; d < 4; ++d) pacc[c * 4 + d] += vv[c] * ww[d];
+              if (want_norm) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) nacc[d] += (double)ww[d] * (double)ww[d];
+              }
+            }
+          }
+          for (; row < R; row += S) {
             const V4 v = *(const V4*)(Vj + 4 * row);
             const V4 w = *(const V4*)(s_W + 4 * row);
             const VT vv[4] = {v.x, v.y, v.z, v.w}, ww[4] = {w.x, w.y, w.z, w.w};
@@ -313,6 +376,10 @@ k_lanczos(LanczosArgs g) {
             for (int c = 0; c < 4; ++c)
 #pragma unroll
               for (int d = 0; d < 4; ++d) pacc[c * 4 + d] += vv[c] * ww[d];
+            if (want_norm) {
+#pragma unroll
+              for (int d = 0; d < 4; ++d) nacc[d] += (double)ww[d] * (double)ww[d];
+            }
           }
           double acc[16];
 #pragma unroll
@@ -323,43 +390,55 @@ k_lanczos(LanczosArgs g) {
             if (parts == 1) s_C[j * 16 + which] = sum;
             else s_Cp[it * 16 + which] = sum;
           }
+          if (want_norm) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) nacc[d] = wave_sum(nacc[d]);
+            if (lane < 4) s_Np[part * 4 + lane] = nacc[lane];
+          }
         }
         __syncthreads();
         if (parts > 1) {
           for (int q = tid; q < nb * 16; q += LZ_NT) {
             const int j = q >> 4, e = q & 15;
-            double s = 0.0;
-            for (int p = 0; p < parts; ++p) s += s_Cp[(j * parts + p) * 16 + e];
-            s_C[q] = s;
+            double sum = 0.0;
+            for (int p = 0; p < parts; ++p) sum += s_Cp[(j * parts + p) * 16 + e];
+            s_C[q] = sum;
           }
-          __syncthreads();
         }
-        // update sweep with Gram (10) and norms-before (4)
-        double acc[16];
+        if (tid < 4) {
+          double sum = 0.0;
+          for (int p = 0; p < parts; ++p) sum += s_Np[p * 4 + tid];
+          X[12 + tid] = sum;                        // norms before this pass
+        }
+        __syncthreads();
+        // update sweep with the Gram matrix (10 values) of the result
+        double acc[10];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+        for (int q = 0; q < 10; ++q) acc[q] = 0.0;
         for (int row = tid; row < R; row += LZ_NT) {
           typedef typename Vec4<VT>::T V4;
           const V4 w4 = *(const V4*)(s_W + 4 * row);
           VT w[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-          for (int d = 0; d < 4; ++d) acc[12 + d] += (double)w[d] * (double)w[d];
           int j = 0;
-          for (; j + 1 < nb; j += 2) {
-            const V4 a0 = *(const V4*)(vbase + (size_t)j * Rcap * 4 + 4 * row);
-            const V4 a1 = *(const V4*)(vbase + (size_t)(j + 1) * Rcap * 4 + 4 * row);
-            const VT v0[4] = {a0.x, a0.y, a0.z, a0.w}, v1[4] = {a1.x, a1.y, a1.z, a1.w};
-            const double* C0 = s_C + j * 16;
-            const double* C1 = s_C + (j + 1) * 16;
+          constexpr int UB = sizeof(VT) == 8 ? 2 : 4;
+          for (; j + UB - 1 < nb; j += UB) {
+            V4 av[UB];
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-              VT t = w[d];
+            for (int u = 0; u < UB; ++u) av[u] = *(const V4*)(vbase + (size_t)(j + u) * Rcap * 4 + 4 * row);
 #pragma unroll
-              for (int c = 0; c < 4; ++c) t -= v0[c] * (VT)C0[c * 4 + d] + v1[c] * (VT)C1[c * 4 + d];
-              w[d] = t;
+            for (int u = 0; u < UB; ++u) {
+              const VT v0[4] = {av[u].x, av[u].y, av[u].z, av[u].w};
+              const double* C0 = s_C + (j + u) * 16;
+#pragma unroll
+              for (int d = 0; d < 4; ++d) {
+                VT t = w[d];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) t -= v0[c] * (VT)C0[c * 4 + d];
+                w[d] = t;
+              }
             }
           }
-          if (j < nb) {
+          for (; j < nb; ++j) {
             const V4 a0 = *(const V4*)(vbase + (size_t)j * Rcap * 4 + 4 * row);
             const VT v0[4] = {a0.x, a0.y, a0.z, a0.w};
             const double* C0 = s_C + j * 16;
@@ -378,37 +457,46 @@ k_lanczos(LanczosArgs g) {
           acc[4] += w1 * w1; acc[5] += w1 * w2; acc[6] += w1 * w3;
           acc[7] += w2 * w2; acc[8] += w2 * w3; acc[9] += w3 * w3;
         }
-        block_sum<16>(acc, s_red, X);
-        if (tid == 0) {
-          const int map[16] = {0, 1, 2, 3, 1, 4, 5, 6, 2, 5, 7, 8, 3, 6, 8, 9};
-          for (int q = 0; q < 16; ++q) G[q] = X[map[q]];
-          int again = 0;
-          for (int d = 0; d < 4; ++d)
-            if (s_flag[d] && X[12 + d] > tol * tol && G[d * 4 + d] < 0.5 * X[12 + d]) again = 1;
-          s_flag[4] = again;
+        block_sum<10>(acc, s_red, G);              // G[0..9] packed Gram
+        bool again = false;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const int dd = d == 0 ? 0 : (d == 1 ? 4 : (d == 2 ? 7 : 9));
+          const double before = X[12 + d];
+          if (s_flag[d] && before > tol * tol && G[dd] < 0.5 * before) again = true;
         }
-        __syncthreads();
-        if (!s_flag[4] || pass == 1) break;
+        __syncthreads();                            // X, G read by all before reuse
+        if (!again || pass == 1) break;
         ++n2;
       }
-      // ---- 6. QR of W: Cholesky QR twice, or MGS with deflation
-      if (tid == 0) {
-        bool act[4];
-        for (int c = 0; c < 4; ++c) act[c] = s_flag[c] != 0;
-        double U[16], Ui[16];
-        const bool ok = chol4(G, act, U, tol * tol);
-        s_flag[5] = ok ? 1 : 0;
-        if (ok) {
-          inv_upper4(U, act, Ui);
-          for (int q = 0; q < 16; ++q) { B[q] = U[q]; X[q] = Ui[q]; }
-        }
-      }
-      __syncthreads();
-      if (s_flag[5]) {
-        // V = W U^-1, Gram of V, second Cholesky
-        double acc[16];
+      // ---- 4. QR of W. Every thread factors the 4x4 Gram itself (no serial
+      // section): one Cholesky QR when the factor is well conditioned
+      // (pivot ratio > 1e-4, so kappa^2 eps < 1e-12), twice otherwise, and
+      // modified Gram-Schmidt with deflation when a pivot is not safely > 0.
+      bool act[4];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+      for (int c = 0; c < 4; ++c) act[c] = s_flag[c] != 0;
+      const int map[16] = {0, 1, 2, 3, 1, 4, 5, 6, 2, 5, 7, 8, 3, 6, 8, 9};
+      {
+        double Gf[16], Ur[16], Xr[16], ratio;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Gf[q] = G[map[q]];
+        const bool ok = chol4r(Gf, act, Ur, tol * tol, ratio);
+        inv_upper4r(Ur, act, Xr);
+        __syncthreads();                              // every thread has read G
+        if (tid == 0) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q) { X[q] = Xr[q]; B[q] = Ur[q]; }
+          s_flag[5] = !ok ? 2 : (ratio > 1e-4 ? 0 : 1);
+        }
+        __syncthreads();
+      }
+      const int path = s_flag[5];
+      if (path == 1) {
+        // second Cholesky QR: V = W U^-1 in place, Gram of V, refactor
+        double acc[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) acc[q] = 0.0;
         for (int row = tid; row < R; row += LZ_NT) {
           double w[4], v[4];
           load4<VT>(s_W + 4 * row, w);
@@ -424,61 +512,54 @@ k_lanczos(LanczosArgs g) {
           acc[4] += v[1] * v[1]; acc[5] += v[1] * v[2]; acc[6] += v[1] * v[3];
           acc[7] += v[2] * v[2]; acc[8] += v[2] * v[3]; acc[9] += v[3] * v[3];
         }
-        block_sum<16>(acc, s_red, G);
-        if (tid == 0) {
-          const int map[16] = {0, 1, 2, 3, 1, 4, 5, 6, 2, 5, 7, 8, 3, 6, 8, 9};
-          double G2[16];
-          for (int q = 0; q < 16; ++q) G2[q] = G[map[q]];
-          bool act[4];
-          for (int c = 0; c < 4; ++c) act[c] = s_flag[c] != 0;
-          double U[16], Ui[16];
-          chol4(G2, act, U, 0.0);
-          inv_upper4(U, act, Ui);
-          double Bn[16];
-          for (int r0 = 0; r0 < 4; ++r0)
-            for (int c = 0; c < 4; ++c) {
-              double s = 0.0;
-              for (int p = 0; p < 4; ++p) s += U[r0 * 4 + p] * B[p * 4 + c];
-              Bn[r0 * 4 + c] = s;
-            }
-          for (int q = 0; q < 16; ++q) { B[q] = Bn[q]; X[q] = Ui[q]; }
-        }
-        __syncthreads();
-        for (int row = tid; row < R; row += LZ_NT) {
-          double w[4], v[4];
-          load4<VT>(s_W + 4 * row, w);
+        block_sum<10>(acc, s_red, G);
+        {
+          double Gf[16], U2[16], X2[16], r2;
 #pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            double t = 0.0;
+          for (int q = 0; q < 16; ++q) Gf[q] = G[map[q]];
+          chol4r(Gf, act, U2, 0.0, r2);
+          inv_upper4r(U2, act, X2);
+          __syncthreads();                            // G, X, B read by all
+          if (tid == 0) {
+            double Bn[16];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) t += w[c] * X[c * 4 + d];
-            v[d] = t;
+            for (int r0 = 0; r0 < 4; ++r0)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                double sum = 0.0;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) sum += U2[r0 * 4 + p] * B[p * 4 + c];
+                Bn[r0 * 4 + c] = sum;
+              }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) { B[q] = Bn[q]; X[q] = X2[q]; }
           }
-          store4<VT>(s_W + 4 * row, v);
+          __syncthreads();
         }
-      } else {
+        ++n2;
+      } else if (path == 2) {
         // modified Gram-Schmidt (twice) within the block, with deflation
         if (tid < 16) B[tid] = 0.0;
         __syncthreads();
         for (int c = 0; c < 4; ++c) {
-          for (int pass = 0; pass < 2; ++pass) {
+          for (int ps = 0; ps < 2; ++ps) {
             for (int p = 0; p < c; ++p) {
               if (!s_flag[p]) continue;          // uniform (LDS)
-              double acc[1] = {0.0};
+              double a1[1] = {0.0};
               for (int row = tid; row < R; row += LZ_NT)
-                acc[0] += (double)s_W[4 * row + p] * (double)s_W[4 * row + c];
-              block_sum<1>(acc, s_red, X);
-              const double dot = X[0];
+                a1[0] += (double)s_W[4 * row + p] * (double)s_W[4 * row + c];
+              block_sum<1>(a1, s_red, G);
+              const double dot = G[0];
               for (int row = tid; row < R; row += LZ_NT)
                 s_W[4 * row + c] = (VT)((double)s_W[4 * row + c] - dot * (double)s_W[4 * row + p]);
               if (tid == 0) B[p * 4 + c] += dot;
               __syncthreads();
             }
           }
-          double acc[1] = {0.0};
-          for (int row = tid; row < R; row += LZ_NT) acc[0] += (double)s_W[4 * row + c] * (double)s_W[4 * row + c];
-          block_sum<1>(acc, s_red, X);
-          const double nrm = sqrt(X[0]);
+          double a1[1] = {0.0};
+          for (int row = tid; row < R; row += LZ_NT) a1[0] += (double)s_W[4 * row + c] * (double)s_W[4 * row + c];
+          block_sum<1>(a1, s_red, G);
+          const double nrm = sqrt(G[0]);
           const bool keep = nrm > tol;
           const double sc = keep ? 1.0 / nrm : 0.0;
           for (int row = tid; row < R; row += LZ_NT) s_W[4 * row + c] = (VT)((double)s_W[4 * row + c] * sc);
@@ -490,14 +571,22 @@ k_lanczos(LanczosArgs g) {
           }
           __syncthreads();
         }
+        if (tid < 16) X[tid] = ((tid % 5) == 0) ? 1.0 : 0.0;
+        __syncthreads();
       }
-      __syncthreads();
-      // ---- store V_{k+1}: LDS current block, HBM basis, J rows; B_k
+      // ---- 5. V_{k+1} = W X: LDS current block, HBM basis, J rows; B_k
       {
         VT* Vn = vbase + (size_t)(k + 1) * Rcap * 4;
         for (int row = tid; row < R; row += LZ_NT) {
-          double v[4];
-          load4<VT>(s_W + 4 * row, v);
+          double w[4], v[4];
+          load4<VT>(s_W + 4 * row, w);
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) t += w[c] * X[c * 4 + d];
+            v[d] = t;
+          }
           store4<VT>(s_V + 4 * row, v);
           store4<VT>(Vn + 4 * row, v);
           const int js = s_js[row >> 2];
@@ -513,7 +602,6 @@ k_lanczos(LanczosArgs g) {
         }
         __syncthreads();
       }
-      (void)Vk;
       if (!(s_flag[0] | s_flag[1] | s_flag[2] | s_flag[3])) {   // invariant space
         k_end = k + 1;
         if (tid == 0) atomicAdd((unsigned long long*)&g.stats[ST_EARLY_STOP], 1ull);
@@ -534,7 +622,7 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32) {
   const size_t Rcap = 4 * (size_t)nc_max;
   size_t b = 2 * Rcap * 4 * vt + 16;
   const int cslots = r_max > 2 * LZ_NW ? r_max : 2 * LZ_NW;
-  b += (size_t)cslots * 16 * 8 + 2 * LZ_NW * 16 * 8 + LZ_NW * 16 * 8 + 128 * 8;
+  b += (size_t)cslots * 16 * 8 + 4 * LZ_NW * 16 * 8 + LZ_NW * 16 * 8 + 192 * 8;
   b += (size_t)(nc_max + 1) * 4 + (size_t)nc_max * 4 + (size_t)nc_max;
   return b + 64;
 }
