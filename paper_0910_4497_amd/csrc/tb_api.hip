@@ -73,7 +73,7 @@ extern "C" int tb_destroy(tb_ctx* c) {
   void* ptrs[] = {c->hop_n, c->hop_j, c->hop_rev, c->hop_d, c->pair64, c->pair32, c->clu_n, c->clu_j,
                   c->loc_off, c->loc_ent, c->hnorm, c->jloc, c->row_ptr, c->col_j, c->vbuf, c->tab,
                   c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->rot_cs, c->rot_p,
-                  c->rot_n, c->seg, c->seg_n, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
+                  c->rot_n, c->seg, c->seg_n, c->evec, c->eig_scratch, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (c->ev_pool) {
@@ -107,7 +107,8 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   c->r_max = r_max;
   c->emax = (int64_t)n_cluster_max * ZMAX;
   const int64_t dmax = 4 * (int64_t)r_max;
-  c->rot_max = 2 * dmax * dmax + 16 * dmax;
+  // band -> tridiagonal takes fewer than (1/8 + 1/6 + 1/4) d^2 + 3 d rotations
+  c->rot_max = (3 * dmax * dmax) / 4 + 16 * dmax;
   if (c->rot_max > 65535 * 16) c->rot_max = 65535 * 16;
 
   // persistent Krylov workgroups: as many as fit on the device at once
@@ -134,6 +135,8 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   if (per_cu > 2) per_cu = 2;
   c->n_wg_lanczos = prop.multiProcessorCount * per_cu;
   if (c->n_wg_lanczos > n_atoms_max) c->n_wg_lanczos = (int)n_atoms_max;
+  c->n_wg_eig = prop.multiProcessorCount * 4;
+  if (c->n_wg_eig > n_atoms_max) c->n_wg_eig = (int)n_atoms_max;
 
   const int64_t N = n_atoms_max, NC = n_cluster_max;
   hipError_t a = hipSuccess;
@@ -165,6 +168,8 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   c->seg_max = (int)(16 * dmax + 64);
   ALLOC(seg, N * c->seg_max);
   ALLOC(seg_n, 2 * N);
+  ALLOC(evec, N * dmax * dmax);
+  ALLOC(eig_scratch, (int64_t)c->n_wg_eig * dmax * 4 * eig_threads());
   ALLOC(mu_state, 16);
   ALLOC(partial, 4096);
   ALLOC(counter, 16);
@@ -298,9 +303,10 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   ea.lam = c->lam; ea.wgt = c->wgt; ea.y1 = c->y1;
   ea.rot_cs = c->rot_cs; ea.rot_p = c->rot_p; ea.rot_n = c->rot_n; ea.rot_max = c->rot_max;
   ea.seg = c->seg; ea.seg_n = c->seg_n; ea.seg_max = c->seg_max;
+  ea.counter = c->work_counter + 1; ea.scratch = c->eig_scratch; ea.evec = c->evec;
   ea.stats = c->stats;
   pk = prof_begin(c, 2);
-  launch_eig(ea, st);
+  launch_eig(ea, c->n_wg_eig < n ? c->n_wg_eig : n, st);
   prof_end(c, pk);
   // K6: chemical potential and spectral sums
   MuArgs ma;
@@ -316,7 +322,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   ra.n_atoms = n; ra.r_max = c->r_max; ra.kused = c->kused; ra.hop_n = c->hop_n; ra.clu_j = c->clu_j;
   ra.nc_max = c->nc_max; ra.lam = c->lam; ra.y1 = c->y1; ra.rot_cs = c->rot_cs; ra.rot_p = c->rot_p;
   ra.rot_n = c->rot_n; ra.rot_max = c->rot_max;
-  ra.seg = c->seg; ra.seg_n = c->seg_n; ra.seg_max = c->seg_max; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
+  ra.seg = c->seg; ra.seg_n = c->seg_n; ra.seg_max = c->seg_max; ra.evec = c->evec; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
   ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out;
   pk = prof_begin(c, 4);
   launch_rho(ra, st);

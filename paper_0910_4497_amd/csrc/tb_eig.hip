@@ -1,22 +1,34 @@
 // Projected eigenproblem and density-matrix assembly (Sec. 3: the small
 // projected matrix is diagonalised; Sec. 2, Eq. 2: rho = sum |m> f <m|).
 //
-// k_eig (one wave per atom, FP64): T (block tridiagonal, 4x4 blocks A_k,
-// upper-triangular B_k, so a symmetric band of half-width 4) is reduced to
-// tridiagonal form by Givens rotations that chase the fill-in ("bulge") down
-// the band, then diagonalised by the implicit QL iteration with Wilkinson
-// shifts (Bowdler, Martin, Reinsch & Wilkinson, 1968). Every plane rotation
-// is applied to the first four rows of the accumulated eigenvector matrix
-// (they give Y[0:4, :], hence the seed weights w_m) and logged (c, s, plane).
+// k_eig, one persistent 256-thread workgroup per atom at a time, FP64:
+//   1. T (block tridiagonal, 4x4 blocks A_k, upper-triangular B_k: a band of
+//      half-width 4) -> tridiagonal S = Z^T T Z by Givens rotations, one
+//      diagonal at a time (half-width bc -> bc-1 for bc = 4, 3, 2). The fill-in
+//      of each rotation is chased down the band; chase j starts at time j * I
+//      and advances one rotation per time step, and with I * bc - 1 >= bc + 3
+//      concurrent rotations touch disjoint entries, so each time step applies
+//      one rotation per active chase in parallel. Every rotation is applied to
+//      the first four rows of Z and logged (c, s, plane) with one segment per
+//      time step.
+//   2. eigenvalues of S by bisection on Sturm counts, one thread per
+//      eigenvalue index (all in parallel);
+//   3. eigenvectors of S by two steps of inverse iteration (tridiagonal LU
+//      with partial pivoting, deterministic pseudo-random start); inside a
+//      cluster of eigenvalues closer than max(1e-6 ||S||, 1e-5 eV) each member
+//      is then Gram-Schmidt orthogonalised against the earlier ones, iterated
+//      once more and orthogonalised again (Peters & Wilkinson; LAPACK's stein
+//      does the same). The eigenvector matrix U of S goes to HBM;
+//   4. Y[0:4, :] = Z[0:4, :] U, weights w_m = ||Y[0:4, m]||^2, Ritz values.
 //
-// k_rho (one wave per atom): after the chemical potential is known,
-// c = Y f(Lambda) Y[0:4, :]^T is obtained by replaying the logged rotations
-// in reverse on the 4r x 4 block f(Lambda) Y[0:4, :]^T (no eigenvector matrix
-// is ever stored), and rho_{J,i} = V_J c for the rho row atoms J.
+// k_rho (after the chemical potential is known): x = U (f(Lambda) Y[0:4,:]^T),
+// then c = Z x by replaying the logged band rotations in reverse (steps in
+// reverse order, the rotations of one step in parallel), and
+// rho_{J,i} = V_J c for the rho row atoms J.
 //
 // Rotation convention: a logged (c, s, p) acts on the column pair (p, p+1)
 // of a row vector set R as R_p <- c R_p + s R_{p+1}, R_{p+1} <- -s R_p + c R_{p+1}
-// (R <- R G^T); Y is the ordered product of all these, so Y x is the reverse
+// (R <- R G^T); Z is the ordered product of all these, so Z x is the reverse
 // replay x_p <- c x_p - s x_{p+1}, x_{p+1} <- s x_p + c x_{p+1}.
 #include <float.h>
 
@@ -24,10 +36,10 @@
 
 namespace tbk {
 
-constexpr int EIG_NT = 64;
+constexpr int EIG_NT = 256;
+constexpr int RHO_NT = 64;
 constexpr int BW = 4;              // half-bandwidth of T
 constexpr int LB = BW + 2;         // stored lower diagonals incl. the bulge
-
 
 __device__ __forceinline__ double t_entry(const double* tab, int row, int col) {
   // lower triangle (row >= col) of the block tridiagonal T
@@ -45,293 +57,373 @@ __device__ __forceinline__ void givens(double x, double y, double& c, double& s,
   c = x * inv; s = y * inv; r = q * inv;
 }
 
-// Band -> tridiagonal, one diagonal at a time (half-width bc -> bc - 1 for
-// bc = 4, 3, 2). For every column j the element at offset bc is zeroed by a
-// rotation in plane (j+bc-1, j+bc); the fill-in it creates at offset bc+1 is
-// chased down the band in steps of bc. Chase j starts at time j * I and moves
-// one rotation per time step; with I * bc - 1 >= bc + 3 the rotations of
-// concurrent chases touch disjoint entries, so every time step applies one
-// rotation per active chase (one thread each) and the result equals the
-// sequential column-by-column order.
+// Number of eigenvalues of the tridiagonal (D, E^2) below sigma.
+__device__ __forceinline__ int sturm_count(const double* D, const double* E2, int d, double sigma,
+                                           double pivmin) {
+  double q = D[0] - sigma;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int k = 1; k < d; ++k) {
+    q = (D[k] - sigma) - E2[k - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// Deterministic start vector component for eigenvalue t, row k: uniform in
+// (-1, 1) from an integer hash. Signs alone (+-1) are not enough: a
+// mirror-symmetric block of S has eigenvectors that are exactly orthogonal to
+// every symmetric +-1 pattern.
+__device__ __forceinline__ double start_val(int t, int k) {
+  unsigned int h = (unsigned int)k * 2654435761u ^ ((unsigned int)t * 40503u + 0x9e3779b9u);
+  h ^= h >> 15; h *= 0x2c1b3c6du; h ^= h >> 12; h *= 0x297a2d39u; h ^= h >> 15;
+  return ((double)(h >> 8) + 0.5) * (2.0 / 16777216.0) - 1.0;
+}
+
+// (S - lam I) x = small * b by LU with partial pivoting; b from start_val
+// (bcol == nullptr) or from the column bcol (stride ld). x is written to xcol
+// (stride ld; may alias bcol). The right-hand side is scaled by the pivot
+// floor so that a near-singular last pivot gives |x| of order one rather than
+// 1/eps. Scratch: 4 values per row at scr[(k * 4 + f) * EIG_NT] (coalesced
+// over the workgroup). Returns ||x||^2.
+__device__ double inv_solve(const double* D, const double* E, int d, double lam, double small, int t,
+                            const double* bcol, double* xcol, size_t ld, double* scr) {
+  double cd = D[0] - lam;
+  double cu = d > 1 ? E[0] : 0.0;
+  double cb = small * (bcol ? bcol[0] : start_val(t, 0));
+  for (int k = 0; k + 1 < d; ++k) {
+    const double sub = E[k];
+    const double nd = D[k + 1] - lam;
+    const double nu = (k + 2 < d) ? E[k + 1] : 0.0;
+    const double nb = small * (bcol ? bcol[(size_t)(k + 1) * ld] : start_val(t, k + 1));
+    double* sk = scr + (size_t)k * 4 * EIG_NT;
+    if (fabs(cd) >= fabs(sub)) {
+      const double piv = (cd != 0.0) ? cd : small;
+      const double l = sub / piv;
+      sk[0] = piv; sk[EIG_NT] = cu; sk[2 * EIG_NT] = 0.0; sk[3 * EIG_NT] = cb;
+      cd = nd - l * cu; cu = nu; cb = nb - l * cb;
+    } else {
+      const double l = cd / sub;
+      sk[0] = sub; sk[EIG_NT] = nd; sk[2 * EIG_NT] = nu; sk[3 * EIG_NT] = nb;
+      cd = cu - l * nd; cu = -l * nu; cb = cb - l * nb;
+    }
+  }
+  double* sl = scr + (size_t)(d - 1) * 4 * EIG_NT;
+  sl[0] = cd; sl[EIG_NT] = 0.0; sl[2 * EIG_NT] = 0.0; sl[3 * EIG_NT] = cb;
+  double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+  for (int k = d - 1; k >= 0; --k) {
+    const double* sk = scr + (size_t)k * 4 * EIG_NT;
+    double piv = sk[0];
+    if (fabs(piv) < small) piv = (piv < 0.0) ? -small : small;
+    const double x = (sk[3 * EIG_NT] - sk[EIG_NT] * x1 - sk[2 * EIG_NT] * x2) / piv;
+    xcol[(size_t)k * ld] = x;
+    nrm += x * x;
+    x2 = x1; x1 = x;
+  }
+  return nrm;
+}
+
 __global__ void __launch_bounds__(EIG_NT) k_eig(EigArgs g) {
   extern __shared__ double esm[];
-  const int atom = blockIdx.x, lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int dmax = 4 * g.r_max;
-  double* Lb = esm;                      // [dmax][LB]: Lb[j][t] = T[j+t][j]
-  double* R1 = esm + (size_t)dmax * LB;  // [4][d]
-  const int K = g.kused[atom];
-  const int d = 4 * K;
-  const double* tab = g.tab + (size_t)atom * g.r_max * 32;
-  for (int q = lane; q < d * LB; q += EIG_NT) {
-    const int j = q / LB, t = q % LB;
-    const int row = j + t;
-    Lb[q] = (t <= BW && row < d) ? t_entry(tab, row, j) : 0.0;
-  }
-  for (int q = lane; q < 4 * d; q += EIG_NT) {
-    const int c = q / d, m = q % d;
-    R1[q] = (m == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
-  uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
-  int64_t nrot = 0;
-  bool overflow = false;
-  int* seg = g.seg + (size_t)atom * g.seg_max;
-  int nseg = 0;
+  double* Lb = esm;                        // [dmax][LB]: Lb[j][t] = T[j+t][j]
+  double* R1 = Lb + (size_t)dmax * LB;     // [4][d]
+  double* Dg = R1 + (size_t)4 * dmax;      // [dmax] diagonal of S
+  double* Eg = Dg + dmax;                  // [dmax] off-diagonal of S (E[k]: k, k+1)
+  double* E2 = Eg + dmax;                  // [dmax] E^2
+  double* lam_s = E2 + dmax;               // [dmax] eigenvalues (ascending)
+  double* red = lam_s + dmax;              // [EIG_NT/64][4]
+  int* pos_s = (int*)(red + 4 * (EIG_NT / 64));   // [dmax] position inside a cluster
+  __shared__ int s_atom, s_maxpos;
+  __shared__ double s_lo, s_hi, s_e2max;
+  double* scr = g.scratch + (size_t)blockIdx.x * dmax * 4 * EIG_NT + tid;
 
-  // ---- band -> tridiagonal, pipelined chases (one thread per chase)
-  for (int bc = BW; bc >= 2; --bc) {
-    const int I = (bc + 4 + bc - 1) / bc;           // ceil((bc + 4) / bc): 2, 3, 3
-    const int nchase = d - bc;
-    if (nchase <= 0) continue;
-    const int last = nchase - 1;
-    const int t_end = last * I + (d - 1 - last - bc) / bc + 1;
-    for (int tau = 0; tau < t_end; ++tau) {
-      int jtop = tau / I;
-      if (jtop > last) jtop = last;
-      const int64_t step_start = nrot;
-      // chases jtop, jtop-1, ... in batches of 64 until one has finished
-      // (every smaller j started earlier and is finished too)
-      for (int jb = jtop; jb >= 0; jb -= EIG_NT) {
-        const int j = jb - lane;
-        bool act = false;
-        int p = 0, m0 = 0;
-        if (j >= 0) {
-          const int st = tau - j * I;
-          p = j + bc - 1 + st * bc;
-          act = (p + 1 <= d - 1);
-          m0 = (st == 0) ? p + 1 - bc : p - bc;
-        }
-        const bool batch_done = __ballot(act) == 0ull;
-        double x = 0.0, y = 0.0;
-        if (act) {
-          x = Lb[(size_t)m0 * LB + (p - m0)];
-          y = Lb[(size_t)m0 * LB + (p + 1 - m0)];
-          act = (y != 0.0);
-        }
-        double c = 1.0, s = 0.0, r = 0.0;
-        if (act) {
-          givens(x, y, c, s, r);
-          const int q = p + 1;
-          // left pairs (T[p][m], T[q][m]), m in [p - bc, p - 1]
-          for (int m = (p - bc > 0 ? p - bc : 0); m < p; ++m) {
-            double* up = Lb + (size_t)m * LB + (p - m);
-            double* uq = Lb + (size_t)m * LB + (q - m);
-            const double u = *up, v = *uq;
-            if (m == m0) { *up = r; *uq = 0.0; }
-            else { *up = c * u + s * v; *uq = -s * u + c * v; }
-          }
-          // right pairs (T[m][p], T[m][q]), m in [p + 2, p + 1 + bc]
-          const int mr = (p + 1 + bc < d - 1) ? p + 1 + bc : d - 1;
-          for (int m = p + 2; m <= mr; ++m) {
-            double* up = Lb + (size_t)p * LB + (m - p);
-            double* uq = Lb + (size_t)q * LB + (m - q);
-            const double u = *up, v = *uq;
-            *up = c * u + s * v; *uq = -s * u + c * v;
-          }
-          // 2x2 diagonal block
-          {
-            const double a = Lb[(size_t)p * LB], b = Lb[(size_t)p * LB + 1], e = Lb[(size_t)q * LB];
-            const double cc = c * c, ss = s * s, cs = c * s;
-            Lb[(size_t)p * LB] = cc * a + 2.0 * cs * b + ss * e;
-            Lb[(size_t)q * LB] = ss * a - 2.0 * cs * b + cc * e;
-            Lb[(size_t)p * LB + 1] = cs * (e - a) + (cc - ss) * b;
-          }
-          // first four rows of the accumulated transform
+  for (;;) {
+    if (tid == 0) s_atom = atomicAdd(g.counter, 1);
+    __syncthreads();
+    const int atom = s_atom;
+    if (atom >= g.n_atoms) break;
+    const int K = g.kused[atom];
+    const int d = 4 * K;
+    const double* tab = g.tab + (size_t)atom * g.r_max * 32;
+    for (int q = tid; q < d * LB; q += EIG_NT) {
+      const int j = q / LB, t = q % LB;
+      const int row = j + t;
+      Lb[q] = (t <= BW && row < d) ? t_entry(tab, row, j) : 0.0;
+    }
+    for (int q = tid; q < 4 * d; q += EIG_NT) {
+      const int c = q / d, m = q % d;
+      R1[q] = (m == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
+    uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
+    int* seg = g.seg + (size_t)atom * g.seg_max;
+    int64_t nrot = 0;
+    int nseg = 0;
+
+    // ---- 1. band -> tridiagonal, pipelined chases (wave 0, one lane per chase)
+    for (int bc = BW; bc >= 2; --bc) {
+      const int I = (2 * bc + 3) / bc;              // ceil((bc + 4) / bc): 2, 3, 3
+      const int nchase = d - bc;
+      if (nchase <= 0) continue;
+      const int last = nchase - 1;
+      const int t_end = last * I + (d - 1 - last - bc) / bc + 1;
+      for (int tau = 0; tau < t_end; ++tau) {
+        if (wave == 0) {
+          const int64_t step_start = nrot;
+          int jtop = tau / I;
+          if (jtop > last) jtop = last;
+          for (int jb = jtop; jb >= 0; jb -= 64) {
+            const int j = jb - lane;
+            bool act = false;
+            int p = 0, m0 = 0;
+            if (j >= 0) {
+              const int st = tau - j * I;
+              p = j + bc - 1 + st * bc;
+              act = (p + 1 <= d - 1);
+              m0 = (st == 0) ? p + 1 - bc : p - bc;
+            }
+            const bool batch_done = __ballot(act) == 0ull;
+            double x = 0.0, y = 0.0;
+            if (act) {
+              x = Lb[(size_t)m0 * LB + (p - m0)];
+              y = Lb[(size_t)m0 * LB + (p + 1 - m0)];
+              act = (y != 0.0);
+            }
+            double c = 1.0, s = 0.0;
+            if (act) {
+              double r;
+              givens(x, y, c, s, r);
+              const int q = p + 1;
+              // gather every entry of the rotation first (loads before stores)
+              const int mlo = (p - bc > 0 ? p - bc : 0);
+              const int mr = (p + 1 + bc < d - 1) ? p + 1 + bc : d - 1;
+              double lu[BW], lv[BW], ru[BW], rv[BW], r1u[4], r1v[4];
 #pragma unroll
-          for (int row = 0; row < 4; ++row) {
-            double* rr = R1 + (size_t)row * d;
-            const double u = rr[p], v = rr[q];
-            rr[p] = c * u + s * v; rr[q] = -s * u + c * v;
+              for (int u = 0; u < BW; ++u) {
+                const int m = mlo + u;
+                lu[u] = (m < p) ? Lb[(size_t)m * LB + (p - m)] : 0.0;
+                lv[u] = (m < p) ? Lb[(size_t)m * LB + (q - m)] : 0.0;
+                const int mm = p + 2 + u;
+                ru[u] = (mm <= mr) ? Lb[(size_t)p * LB + (mm - p)] : 0.0;
+                rv[u] = (mm <= mr) ? Lb[(size_t)q * LB + (mm - q)] : 0.0;
+              }
+              const double da = Lb[(size_t)p * LB], db = Lb[(size_t)p * LB + 1], de = Lb[(size_t)q * LB];
+#pragma unroll
+              for (int row = 0; row < 4; ++row) {
+                r1u[row] = R1[(size_t)row * d + p];
+                r1v[row] = R1[(size_t)row * d + q];
+              }
+#pragma unroll
+              for (int u = 0; u < BW; ++u) {
+                const int m = mlo + u;
+                if (m < p) {
+                  if (m == m0) {
+                    Lb[(size_t)m * LB + (p - m)] = r;
+                    Lb[(size_t)m * LB + (q - m)] = 0.0;
+                  } else {
+                    Lb[(size_t)m * LB + (p - m)] = c * lu[u] + s * lv[u];
+                    Lb[(size_t)m * LB + (q - m)] = -s * lu[u] + c * lv[u];
+                  }
+                }
+                const int mm = p + 2 + u;
+                if (mm <= mr) {
+                  Lb[(size_t)p * LB + (mm - p)] = c * ru[u] + s * rv[u];
+                  Lb[(size_t)q * LB + (mm - q)] = -s * ru[u] + c * rv[u];
+                }
+              }
+              const double cc = c * c, ss = s * s, cs = c * s;
+              Lb[(size_t)p * LB] = cc * da + 2.0 * cs * db + ss * de;
+              Lb[(size_t)q * LB] = ss * da - 2.0 * cs * db + cc * de;
+              Lb[(size_t)p * LB + 1] = cs * (de - da) + (cc - ss) * db;
+#pragma unroll
+              for (int row = 0; row < 4; ++row) {
+                R1[(size_t)row * d + p] = c * r1u[row] + s * r1v[row];
+                R1[(size_t)row * d + q] = -s * r1u[row] + c * r1v[row];
+              }
+            }
+            const uint64_t mask = __ballot(act);
+            const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            const int64_t slot = nrot + __popcll(mask & below);
+            if (act && slot < g.rot_max) { lcs[2 * slot] = c; lcs[2 * slot + 1] = s; lp[slot] = (uint16_t)p; }
+            nrot += __popcll(mask);
+            if (batch_done) break;
+          }
+          if (nrot > step_start) {                  // one segment per non-empty time step
+            if (lane == 0 && nseg < g.seg_max) seg[nseg] = (int)step_start;
+            ++nseg;
           }
         }
-        // log in lane order (rotations of one time step commute)
-        const uint64_t mask = __ballot(act);
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        const int64_t slot = nrot + __popcll(mask & below);
-        if (act && slot < g.rot_max) { lcs[2 * slot] = c; lcs[2 * slot + 1] = s; lp[slot] = (uint16_t)p; }
-        nrot += __popcll(mask);
-        if (batch_done) break;
+        __syncthreads();
       }
-      if (nrot > step_start) {                    // one segment per non-empty time step
-        if (lane == 0 && nseg < g.seg_max) seg[nseg] = (int)step_start;
-        ++nseg;
-      }
-      __syncthreads();
     }
-  }
-  const int nseg_band = nseg;
-  if (nrot > g.rot_max) { overflow = true; nrot = g.rot_max; }
+    if (tid == 0) {
+      g.rot_n[atom] = (int)(nrot < g.rot_max ? nrot : g.rot_max);
+      g.seg_n[2 * atom] = nseg < g.seg_max ? nseg : g.seg_max;
+      g.seg_n[2 * atom + 1] = nseg < g.seg_max ? nseg : g.seg_max;
+      if (nseg > g.seg_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_SEG_OVERFLOW);
+      if (nrot > g.rot_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
+    }
 
-  // ---- implicit QL on the tridiagonal: D[j] = Lb[j][0], E[j] = Lb[j][1]
-  // Every lane runs the scalar recursion; lanes 0..3 carry one row of R1,
-  // lane 4 writes the log. Within a sweep no entry is read after being
-  // written, so the sweep needs no barrier; the next entries are prefetched.
-  int max_it = 0;
-  bool noconv = false;
-  for (int l = 0; l < d; ++l) {
-    int it = 0;
-    for (;;) {
-      // first m >= l with a negligible E[m] (m = d-1 if none), 64 at a time
-      int m = d - 1;
-      for (int base = l; base < d - 1; base += EIG_NT) {
-        const int mm = base + lane;
-        bool neg = true;
-        if (mm < d - 1) {
-          const double dd = fabs(Lb[(size_t)mm * LB]) + fabs(Lb[(size_t)(mm + 1) * LB]);
-          neg = (fabs(Lb[(size_t)mm * LB + 1]) + dd == dd);
-        }
-        const uint64_t bm = __ballot(neg);
-        if (bm) { m = base + __ffsll((unsigned long long)bm) - 1; break; }
+    // ---- 2. tridiagonal S, Gershgorin interval, eigenvalues by bisection
+    double glo = 1e300, ghi = -1e300, e2m = 0.0;
+    for (int k = tid; k < d; k += EIG_NT) {
+      const double Dk = Lb[(size_t)k * LB];
+      const double Ek = (k + 1 < d) ? Lb[(size_t)k * LB + 1] : 0.0;
+      const double Em = (k > 0) ? Lb[(size_t)(k - 1) * LB + 1] : 0.0;
+      Dg[k] = Dk; Eg[k] = Ek; E2[k] = Ek * Ek;
+      const double rad = fabs(Ek) + fabs(Em);
+      glo = fmin(glo, Dk - rad); ghi = fmax(ghi, Dk + rad); e2m = fmax(e2m, Ek * Ek);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      glo = fmin(glo, __shfl_xor(glo, off, 64));
+      ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
+      e2m = fmax(e2m, __shfl_xor(e2m, off, 64));
+    }
+    if (lane == 0) { red[wave * 4] = glo; red[wave * 4 + 1] = ghi; red[wave * 4 + 2] = e2m; }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 1e300, b = -1e300, e = 0.0;
+      for (int w = 0; w < EIG_NT / 64; ++w) { a = fmin(a, red[w * 4]); b = fmax(b, red[w * 4 + 1]); e = fmax(e, red[w * 4 + 2]); }
+      const double pad = 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + 1e-300;
+      s_lo = a - pad; s_hi = b + pad; s_e2max = e;
+    }
+    __syncthreads();
+    const double lo0 = s_lo, hi0 = s_hi;
+    const double anorm = fmax(fabs(lo0), fabs(hi0));
+    const double pivmin = DBL_MIN * fmax(1.0, s_e2max);
+    for (int t = tid; t < d; t += EIG_NT) {
+      double l = lo0, h = hi0;
+      for (int it = 0; it < 128; ++it) {
+        const double m = 0.5 * (l + h);
+        if (sturm_count(Dg, E2, d, m, pivmin) <= t) l = m; else h = m;
+        if (h - l <= 4.0 * DBL_EPSILON * fmax(fabs(l), fabs(h)) + pivmin) break;
       }
-      if (m == l) break;
-      if (it == 60) { noconv = true; break; }
-      ++it;
-      if (lane == 0 && nseg < g.seg_max) seg[nseg] = (int)nrot;   // one segment per sweep
-      ++nseg;
-      const double Dl = Lb[(size_t)l * LB], El = Lb[(size_t)l * LB + 1];
-      double gg = (Lb[(size_t)(l + 1) * LB] - Dl) / (2.0 * El);
-      double rr = sqrt(gg * gg + 1.0);
-      gg = Lb[(size_t)m * LB] - Dl + El / (gg + copysign(rr, gg));
-      double s = 1.0, c = 1.0, p = 0.0;
-      int i = m - 1;
-      bool underflow = false;
-      const int row = lane < 4 ? lane : 0;
-      double carry = R1[(size_t)row * d + m];
-      double Ei = Lb[(size_t)i * LB + 1], Di = Lb[(size_t)i * LB], Di1 = Lb[(size_t)m * LB];
-      double Ri = R1[(size_t)row * d + i];
-      for (; i >= l; --i) {
-        // prefetch the next iteration's inputs (entries not written in this sweep)
-        const int in = i > l ? i - 1 : i;
-        const double En = Lb[(size_t)in * LB + 1], Dn = Lb[(size_t)in * LB];
-        const double Rn = R1[(size_t)row * d + in];
-        const double f = s * Ei, b = c * Ei;
-        const double q2 = f * f + gg * gg;
-        if (q2 == 0.0) {
-          if (lane == 0) { Lb[(size_t)(i + 1) * LB + 1] = 0.0; Lb[(size_t)(i + 1) * LB] = Di1 - p; Lb[(size_t)m * LB + 1] = 0.0; }
-          underflow = true;
-          break;
+      lam_s[t] = 0.5 * (l + h);
+    }
+    __syncthreads();
+    // ---- 3. clusters and inverse iteration
+    const double ctol = fmax(1e-6 * anorm, 1e-5);
+    const double small = DBL_EPSILON * anorm + 1e-300;
+    int mp = 0;
+    for (int t = tid; t < d; t += EIG_NT) {
+      int p = 0;
+      while (t - p - 1 >= 0 && lam_s[t - p] - lam_s[t - p - 1] < ctol) ++p;
+      pos_s[t] = p;
+      mp = p > mp ? p : mp;
+    }
+    for (int off = 32; off > 0; off >>= 1) { const int o = __shfl_xor(mp, off, 64); mp = o > mp ? o : mp; }
+    if (tid == 0) s_maxpos = 0;
+    __syncthreads();
+    if (lane == 0) atomicMax(&s_maxpos, mp);
+    __syncthreads();
+    const int maxpos = s_maxpos;
+    double* Ua = g.evec + (size_t)atom * dmax * dmax;       // U[k][t], row stride dmax
+    for (int round = 0; round <= maxpos; ++round) {
+      for (int t = tid; t < d; t += EIG_NT) {
+        if (pos_s[t] != round) continue;
+        double* xc = Ua + t;
+        // two steps of inverse iteration: the second one squares the
+        // contamination left by a start vector with a small target component
+        double nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, nullptr, xc, dmax, scr);
+        double sc = 1.0 / sqrt(nrm);
+        for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
+        nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, xc, xc, dmax, scr);
+        sc = 1.0 / sqrt(nrm);
+        for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
+        if (round > 0) {
+          for (int rep = 0; rep < 2; ++rep) {
+            for (int j = t - round; j < t; ++j) {
+              const double* uj = Ua + j;
+              double dot = 0.0;
+              for (int k = 0; k < d; ++k) dot += uj[(size_t)k * dmax] * xc[(size_t)k * dmax];
+              for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] -= dot * uj[(size_t)k * dmax];
+            }
+            nrm = 0.0;
+            for (int k = 0; k < d; ++k) nrm += xc[(size_t)k * dmax] * xc[(size_t)k * dmax];
+            sc = 1.0 / sqrt(nrm);
+            for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
+            if (rep == 0) {
+              nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, xc, xc, dmax, scr);
+              sc = 1.0 / sqrt(nrm);
+              for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
+            }
+          }
         }
-        const double inv = rsqrt(q2);
-        rr = q2 * inv;
-        s = f * inv; c = gg * inv;
-        gg = Di1 - p;
-        rr = (Di - gg) * s + 2.0 * c * b;
-        p = s * rr;
-        const double Dnew = gg + p;
-        gg = c * rr - b;
-        if (lane == 0) { Lb[(size_t)(i + 1) * LB + 1] = q2 * inv; Lb[(size_t)(i + 1) * LB] = Dnew; }
-        if (lane < 4) R1[(size_t)row * d + (i + 1)] = s * Ri + c * carry;
-        carry = c * Ri - s * carry;
-        if (lane == 4 && nrot < g.rot_max) { lcs[2 * nrot] = c; lcs[2 * nrot + 1] = -s; lp[nrot] = (uint16_t)i; }
-        if (nrot < g.rot_max) ++nrot; else overflow = true;
-        Ei = En; Di1 = Di; Di = Dn; Ri = Rn;
-      }
-      if (lane < 4) R1[(size_t)row * d + (i + 1)] = carry;
-      __syncthreads();
-      if (underflow && i >= l) continue;
-      if (lane == 0) {
-        Lb[(size_t)l * LB] -= p;
-        Lb[(size_t)l * LB + 1] = gg;
-        Lb[(size_t)m * LB + 1] = 0.0;
       }
       __syncthreads();
     }
-    if (it > max_it) max_it = it;
-  }
-  __syncthreads();
-  // ---- outputs (padding beyond d: lambda = 0, w = 0, Y1 = 0)
-  double* lam = g.lam + (size_t)atom * dmax;
-  double* wgt = g.wgt + (size_t)atom * dmax;
-  double* y1 = g.y1 + (size_t)atom * 4 * dmax;
-  for (int m = lane; m < dmax; m += EIG_NT) {
-    if (m < d) {
-      const double a0 = R1[m], a1 = R1[(size_t)d + m], a2 = R1[(size_t)2 * d + m], a3 = R1[(size_t)3 * d + m];
-      lam[m] = Lb[(size_t)m * LB];
-      wgt[m] = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
-      y1[m] = a0; y1[dmax + m] = a1; y1[2 * dmax + m] = a2; y1[3 * dmax + m] = a3;
-    } else {
-      lam[m] = 0.0; wgt[m] = 0.0;
-      y1[m] = 0.0; y1[dmax + m] = 0.0; y1[2 * dmax + m] = 0.0; y1[3 * dmax + m] = 0.0;
+    // ---- 4. Y[0:4, t] = Z[0:4, :] U[:, t], weights, outputs
+    double* lam = g.lam + (size_t)atom * dmax;
+    double* wgt = g.wgt + (size_t)atom * dmax;
+    double* y1 = g.y1 + (size_t)atom * 4 * dmax;
+    for (int t = tid; t < dmax; t += EIG_NT) {
+      if (t < d) {
+        const double* xc = Ua + t;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double x = xc[(size_t)k * dmax];
+          a0 += R1[k] * x; a1 += R1[(size_t)d + k] * x; a2 += R1[(size_t)2 * d + k] * x; a3 += R1[(size_t)3 * d + k] * x;
+        }
+        lam[t] = lam_s[t];
+        wgt[t] = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+        y1[t] = a0; y1[dmax + t] = a1; y1[2 * dmax + t] = a2; y1[3 * dmax + t] = a3;
+      } else {
+        lam[t] = 0.0; wgt[t] = 0.0;
+        y1[t] = 0.0; y1[dmax + t] = 0.0; y1[2 * dmax + t] = 0.0; y1[3 * dmax + t] = 0.0;
+      }
     }
-  }
-  if (lane == 0) {
-    g.rot_n[atom] = (int)(nrot < g.rot_max ? nrot : g.rot_max);
-    g.seg_n[2 * atom] = nseg_band;
-    g.seg_n[2 * atom + 1] = nseg < g.seg_max ? nseg : g.seg_max;
-    if (nseg > g.seg_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_SEG_OVERFLOW);
-    atomicMax((unsigned long long*)&g.stats[ST_MAX_EIG_ITERS], (unsigned long long)max_it);
-    if (noconv) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_EIG_NOCONV);
-    if (overflow) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
+    if (tid == 0) atomicMax((unsigned long long*)&g.stats[ST_MAX_EIG_ITERS], (unsigned long long)maxpos);
+    __syncthreads();
   }
 }
 
-// Reverse replay, one wave per atom, x = f(Lambda) Y[0:4,:]^T (4r x 4) in LDS.
-//  1. QL sweeps, last first. Sweep s logged planes m_s-1, ..., l_s (one chain);
-//     its replay runs l_s upward. Replayed sweep r starts at time 2r, so it
-//     trails the previous one by two planes: l never decreases from one forward
-//     sweep to the next, which keeps concurrent rotations on disjoint rows and
-//     every row's updates in the sequential reverse order.
-//  2. band steps, last first; rotations of one step commute (disjoint rows).
-__global__ void __launch_bounds__(EIG_NT) k_rho(RhoArgs g) {
+// One wave per atom.
+__global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   extern __shared__ double rsm[];
   const int lane = threadIdx.x;
   const int atom = blockIdx.x;
   const int dmax = 4 * g.r_max;
-  double* x = rsm;                       // [dmax][4]
+  double* v = rsm;                       // [dmax][4]: f(Lambda) Y[0:4,:]^T
+  double* x = rsm + (size_t)dmax * 4;    // [dmax][4]
   const double mu = g.mu_state[2];
   const int d = 4 * g.kused[atom];
   {
     const double* lam = g.lam + (size_t)atom * dmax;
     const double* y1 = g.y1 + (size_t)atom * 4 * dmax;
-    for (int q = lane; q < 4 * d; q += EIG_NT) {
+    for (int q = lane; q < 4 * d; q += RHO_NT) {
       const int m = q >> 2, col = q & 3;
       const double z = (lam[m] - mu) / g.kT;
       const double e = exp(-fabs(z));
       const double f = (z > 0.0) ? 2.0 * e / (1.0 + e) : 2.0 / (1.0 + e);
-      x[q] = f * y1[(size_t)col * dmax + m];
+      v[q] = f * y1[(size_t)col * dmax + m];
     }
   }
+  __syncthreads();
+  // x = U v (eigenvectors of the tridiagonal)
+  const double* Ua = g.evec + (size_t)atom * dmax * dmax;
+  for (int k = lane; k < d; k += RHO_NT) {
+    const double* ur = Ua + (size_t)k * dmax;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int m = 0; m < d; ++m) {
+      const double u = ur[m];
+      s0 += u * v[4 * m]; s1 += u * v[4 * m + 1]; s2 += u * v[4 * m + 2]; s3 += u * v[4 * m + 3];
+    }
+    x[4 * k] = s0; x[4 * k + 1] = s1; x[4 * k + 2] = s2; x[4 * k + 3] = s3;
+  }
+  __syncthreads();
+  // c = Z x: band steps in reverse; the rotations of one step commute
   const double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
   const uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
   const int* seg = g.seg + (size_t)atom * g.seg_max;
   const int nrot = g.rot_n[atom];
-  const int nb = g.seg_n[2 * atom], ns = g.seg_n[2 * atom + 1];
-  const int S = ns - nb;                           // QL sweeps
-  auto seg_end = [&](int k) { return k + 1 < ns ? seg[k + 1] : nrot; };
-  __syncthreads();
-  // ---- 1. QL sweeps, pipelined
-  int maxlen = 0;
-  for (int k = nb + lane; k < ns; k += EIG_NT) { const int len = seg_end(k) - seg[k]; maxlen = len > maxlen ? len : maxlen; }
-  for (int off = 32; off > 0; off >>= 1) { const int o = __shfl_xor(maxlen, off, 64); maxlen = o > maxlen ? o : maxlen; }
-  const int t_end = S > 0 ? 2 * (S - 1) + maxlen : 0;
-  for (int tau = 0; tau < t_end; ++tau) {
-    // replayed sweep r (forward sweep s = nb + S - 1 - r) is at rotation tau - 2r
-    int rhi = tau / 2;
-    if (rhi > S - 1) rhi = S - 1;
-    int rlo = (tau - maxlen + 2) / 2;
-    if (rlo < 0) rlo = 0;
-    for (int r = rhi - lane; r >= rlo; r -= EIG_NT) {
-      const int k = nb + S - 1 - r;
-      const int st = seg[k], en = seg_end(k);
-      const int t = tau - 2 * r;
-      if (t < en - st) {
-        const int e = en - 1 - t;
-        const double c = lcs[2 * e], s = lcs[2 * e + 1];
-        const int p = lp[e];
-        double* xp = x + 4 * p;
-        const double a0 = xp[0], a1 = xp[1], a2 = xp[2], a3 = xp[3];
-        const double b0 = xp[4], b1 = xp[5], b2 = xp[6], b3 = xp[7];
-        xp[0] = c * a0 - s * b0; xp[1] = c * a1 - s * b1; xp[2] = c * a2 - s * b2; xp[3] = c * a3 - s * b3;
-        xp[4] = s * a0 + c * b0; xp[5] = s * a1 + c * b1; xp[6] = s * a2 + c * b2; xp[7] = s * a3 + c * b3;
-      }
-    }
-    __syncthreads();
-  }
-  // ---- 2. band steps, last first
+  const int nb = g.seg_n[2 * atom];
   for (int k = nb - 1; k >= 0; --k) {
-    const int st = seg[k], en = seg_end(k);
-    for (int e = st + lane; e < en; e += EIG_NT) {
+    const int st = seg[k], en = (k + 1 < nb) ? seg[k + 1] : nrot;
+    for (int e = st + lane; e < en; e += RHO_NT) {
       const double c = lcs[2 * e], s = lcs[2 * e + 1];
       const int p = lp[e];
       double* xp = x + 4 * p;
@@ -342,24 +434,24 @@ __global__ void __launch_bounds__(EIG_NT) k_rho(RhoArgs g) {
     }
     __syncthreads();
   }
-  // ---- rho_{J,i}[4 js + a][col] = sum_m V_J[4 js + a][m] x[m][col]
+  // rho_{J,i}[4 js + a][col] = sum_m V_J[4 js + a][m] x[m][col]
   const int nJ = 1 + g.hop_n[atom];
   const int64_t p0 = g.row_ptr[atom];
   const int vld = 4 * g.r_max;
-  for (int q = lane; q < 4 * nJ; q += EIG_NT) {
+  for (int q = lane; q < 4 * nJ; q += RHO_NT) {
     const size_t row = (size_t)atom * (4 * JMAX) + q;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (g.vj_fp32) {
       const float* vr = (const float*)g.vj + row * vld;
       for (int m = 0; m < d; ++m) {
-        const double v = vr[m];
-        s0 += v * x[4 * m]; s1 += v * x[4 * m + 1]; s2 += v * x[4 * m + 2]; s3 += v * x[4 * m + 3];
+        const double vv = vr[m];
+        s0 += vv * x[4 * m]; s1 += vv * x[4 * m + 1]; s2 += vv * x[4 * m + 2]; s3 += vv * x[4 * m + 3];
       }
     } else {
       const double* vr = (const double*)g.vj + row * vld;
       for (int m = 0; m < d; ++m) {
-        const double v = vr[m];
-        s0 += v * x[4 * m]; s1 += v * x[4 * m + 1]; s2 += v * x[4 * m + 2]; s3 += v * x[4 * m + 3];
+        const double vv = vr[m];
+        s0 += vv * x[4 * m]; s1 += vv * x[4 * m + 1]; s2 += vv * x[4 * m + 2]; s3 += vv * x[4 * m + 3];
       }
     }
     double* out = g.rho + (size_t)(p0 + (q >> 2)) * 16 + (q & 3) * 4;
@@ -367,8 +459,13 @@ __global__ void __launch_bounds__(EIG_NT) k_rho(RhoArgs g) {
   }
 }
 
-size_t eig_lds_bytes(int r_max) { return (size_t)4 * r_max * (LB + 4) * sizeof(double); }
-size_t rho_lds_bytes(int r_max) { return (size_t)4 * r_max * 4 * sizeof(double); }
+size_t eig_lds_bytes(int r_max) {
+  const size_t dmax = 4 * (size_t)r_max;
+  return (dmax * LB + 4 * dmax + 4 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) +
+         dmax * sizeof(int) + 64;
+}
+size_t rho_lds_bytes(int r_max) { return (size_t)2 * 4 * r_max * 4 * sizeof(double); }
+int eig_threads() { return EIG_NT; }
 
 hipError_t eig_set_lds(int r_max) {
   hipError_t e = hipFuncSetAttribute((const void*)k_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -378,11 +475,11 @@ hipError_t eig_set_lds(int r_max) {
                              (int)rho_lds_bytes(r_max));
 }
 
-void launch_eig(const EigArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_eig, dim3(a.n_atoms), dim3(EIG_NT), eig_lds_bytes(a.r_max), st, a);
+void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
+  hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(EIG_NT), eig_lds_bytes(a.r_max), st, a);
 }
 void launch_rho(const RhoArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_rho, dim3(a.n_atoms), dim3(EIG_NT), rho_lds_bytes(a.r_max), st, a);
+  hipLaunchKernelGGL(k_rho, dim3(a.n_atoms), dim3(RHO_NT), rho_lds_bytes(a.r_max), st, a);
 }
 
 }  // namespace tbk

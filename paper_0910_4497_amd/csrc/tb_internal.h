@@ -109,6 +109,9 @@ struct EigArgs {
   double* lam; double* wgt; double* y1;
   double* rot_cs; uint16_t* rot_p; int* rot_n; int64_t rot_max;
   int* seg; int* seg_n; int seg_max;   // [N][seg_max] segment starts; [N][2]: band steps, total
+  int* counter;                        // persistent-kernel atom queue (zeroed before launch)
+  double* scratch;                     // [WG][4 r_max][4][threads]: LU factors of inverse iteration
+  double* evec;                        // [N][4 r_max][4 r_max]: eigenvectors of the tridiagonal, [k][t]
   int64_t* stats;
 };
 struct RhoArgs {
@@ -117,6 +120,7 @@ struct RhoArgs {
   const double* lam; const double* y1;
   const double* rot_cs; const uint16_t* rot_p; const int* rot_n; int64_t rot_max;
   const int* seg; const int* seg_n; int seg_max;
+  const double* evec;
   const void* vj; int vj_fp32;
   const int64_t* row_ptr;
   const double* mu_state; double kT;
@@ -125,7 +129,8 @@ struct RhoArgs {
 size_t eig_lds_bytes(int r_max);
 size_t rho_lds_bytes(int r_max);
 hipError_t eig_set_lds(int r_max);
-void launch_eig(const EigArgs& a, hipStream_t st);
+void launch_eig(const EigArgs& a, int n_wg, hipStream_t st);
+int eig_threads();
 void launch_rho(const RhoArgs& a, hipStream_t st);
 
 struct MuArgs {
@@ -197,6 +202,9 @@ struct tb_ctx {
   double* lam; double* wgt; double* y1;                    // [N][D], [N][D], [N][4][D]
   double* rot_cs; uint16_t* rot_p; int* rot_n;             // [N][ROT][2], [N][ROT], [N]
   int* seg; int* seg_n; int seg_max;                       // [N][SEG], [N][2]
+  double* evec;                                            // [N][D][D]
+  double* eig_scratch;                                     // [WG_EIG][D][4][EIG_NT]
+  int n_wg_eig;                                            // persistent workgroups of k_eig
   // mu / energies (K6/K8)
   double* mu_state;      // [8]: lo, hi, mu, done, N(mu) ...
   double* partial;       // [NPART][4]
