@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle atom-solves timed on host cores (0: about 20 s of CPU work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before the MD runs, launch one elementwise copy kernel of this many MiB "
+                         "(read once, written once) to calibrate HBM byte counters")
     return ap.parse_args()
 
 
@@ -45,14 +48,15 @@ def algorithmic_bytes_lanczos(n_cluster, k_steps, value_bytes):
     """Basis traffic of the block-Lanczos kernel for one launch: per atom with
     a sphere of n atoms (4n rows) and K block steps, the re-orthogonalisation
     reads blocks 0..k twice at step k, the recursion reads V_{k-1}, and every
-    new block is written once: K(K-1) + 2(K-1) blocks of 4n x 4 values."""
+    new block is written once: K(K-1) + 2(K-1) blocks of 4n x 4 values.
+    k_steps is a scalar or one K per atom."""
     import numpy as np
     n = np.asarray(n_cluster, dtype=np.float64)
-    K = float(k_steps)
+    K = np.asarray(k_steps, dtype=np.float64)
     return float(np.sum(16.0 * n * value_bytes * (K * (K - 1) + 2 * (K - 1))))
 
 
-def run_md(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, torch, inputs):
+def run_md(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, torch, inputs, rpa=None):
     """velocity-Verlet; returns timing, per-phase ms and the first-step forces."""
     dev = ctx.device
     pos = pos0.clone()
@@ -62,7 +66,7 @@ def run_md(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, torch, inpu
 
     def forces_at(p):
         ctx.build_local_H(p, w.cell, (1, 1, 1), params, w.r_cut)
-        ctx.krylov_rho(w.r, w.kT, n_electrons=w.n_electrons, precision=precision)
+        ctx.krylov_rho(w.r, w.kT, n_electrons=w.n_electrons, precision=precision, r_per_atom=rpa)
         return ctx.energy_forces()
 
     e, f = forces_at(pos)
@@ -116,19 +120,30 @@ def main():
     vel0 = torch.tensor(inputs.maxwell_velocities(N, args.temperature, seed=7), dtype=torch.float64,
                         device=dev)
     # size the sphere capacity from the geometry (plus a margin for the MD motion)
-    probe = TBContext(N, 480, 2)
+    probe = TBContext(N, 560, 1)
     sizes = probe.build_local_H(pos0, w.cell, (1, 1, 1), params, w.r_cut, want_sizes=True)
     n_max = int(sizes.max().item())
     n_cluster = sizes.cpu().numpy()
     probe.close()
     del probe
-    ctx = TBContext(N, n_max + 24, w.r)
+    rpa = None
+    r_atoms = np.full(N, w.r)
+    if w.r_per_atom is not None:
+        r_atoms = np.asarray(w.r_per_atom)
+        rpa = torch.tensor(r_atoms.astype(np.int32), device=dev)
+    ctx = TBContext(N, n_max + 24, int(r_atoms.max()))
+    if args.calib_copy_mb:
+        src = torch.ones(args.calib_copy_mb << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     results = {}
     precs = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
     for prec in precs:
         results[prec] = run_md(ctx, w, params, pos0, vel0, prec, args.steps, args.warmup, args.dt,
-                               torch, inputs)
+                               torch, inputs, rpa)
     ref = results.get("fp64")
     for prec, r in results.items():
         r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
@@ -142,7 +157,7 @@ def main():
     vt = 4 if head_prec == "fp32" else 8
     lz_ms, lz_n = head["phases"]["lanczos"]
     lz_avg_ms = lz_ms / max(lz_n, 1)
-    bytes_launch = algorithmic_bytes_lanczos(n_cluster, w.r, vt)
+    bytes_launch = algorithmic_bytes_lanczos(n_cluster, r_atoms, vt)
     achieved = bytes_launch / (lz_avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,

@@ -57,14 +57,21 @@ __device__ __forceinline__ void givens(double x, double y, double& c, double& s,
   c = x * inv; s = y * inv; r = q * inv;
 }
 
-// Number of eigenvalues of the tridiagonal (D, E^2) below sigma.
+// Number of eigenvalues of the tridiagonal (D, E^2) below sigma: the count of
+// negative pivots of the LDL^T factorisation of S - sigma I (Sylvester's law
+// of inertia), pivots of magnitude below pivmin replaced by -pivmin. The
+// quotient E^2 / q uses the hardware reciprocal refined by one Newton step
+// (relative error near the unit roundoff, which perturbs each pivot by a few
+// ulps; bisection only needs the counts of a nearby matrix).
 __device__ __forceinline__ int sturm_count(const double* D, const double* E2, int d, double sigma,
                                            double pivmin) {
   double q = D[0] - sigma;
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
   for (int k = 1; k < d; ++k) {
-    q = (D[k] - sigma) - E2[k - 1] / q;
+    double rq = __builtin_amdgcn_rcp(q);
+    rq = fma(rq, fma(-q, rq, 1.0), rq);
+    q = (D[k] - sigma) - E2[k - 1] * rq;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -124,7 +131,7 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
   return nrm;
 }
 
-__global__ void __launch_bounds__(EIG_NT) k_eig(EigArgs g) {
+__global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
   extern __shared__ double esm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int dmax = 4 * g.r_max;
@@ -164,7 +171,12 @@ __global__ void __launch_bounds__(EIG_NT) k_eig(EigArgs g) {
     int64_t nrot = 0;
     int nseg = 0;
 
-    // ---- 1. band -> tridiagonal, pipelined chases (wave 0, one lane per chase)
+    // ---- 1. band -> tridiagonal, pipelined chases (wave 0, one lane per chase).
+    // Only wave 0 works here, so the time steps are ordered by wave-scope
+    // fences: the LDS operations of one wave complete in issue order, and a
+    // workgroup barrier would also wait for the rotation-log stores to reach
+    // memory on every step.
+    if (wave == 0) {
     for (int bc = BW; bc >= 2; --bc) {
       const int I = (2 * bc + 3) / bc;              // ceil((bc + 4) / bc): 2, 3, 3
       const int nchase = d - bc;
@@ -172,7 +184,7 @@ __global__ void __launch_bounds__(EIG_NT) k_eig(EigArgs g) {
       const int last = nchase - 1;
       const int t_end = last * I + (d - 1 - last - bc) / bc + 1;
       for (int tau = 0; tau < t_end; ++tau) {
-        if (wave == 0) {
+        {
           const int64_t step_start = nrot;
           int jtop = tau / I;
           if (jtop > last) jtop = last;
@@ -257,9 +269,13 @@ __global__ void __launch_bounds__(EIG_NT) k_eig(EigArgs g) {
             ++nseg;
           }
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
+    }
+    __syncthreads();
     if (tid == 0) {
       g.rot_n[atom] = (int)(nrot < g.rot_max ? nrot : g.rot_max);
       g.seg_n[2 * atom] = nseg < g.seg_max ? nseg : g.seg_max;

@@ -1,0 +1,120 @@
+"""Energy/force evaluation as a PyTorch autograd Function, and velocity-Verlet
+molecular dynamics on top of it (argument marshalling only: every step of the
+evaluation runs in libtbkrylov's kernels).
+
+Sec. 2: the force on an atom is the trace of the density matrix with the
+derivative of the Hamiltonian, plus the repulsive pair term. TBEnergy returns
+the total energy A + E_rep (A = E_band - T S, the Mermin free energy whose
+exact-limit gradient the trace formula gives) and its backward hands back
+-F * grad_out. At finite Krylov order or cutoff the local density matrix is
+not variational, so -F is the method's force, not the exact derivative of the
+returned energy; the gap shrinks as r and the cutoff grow.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import inputs
+from .tb import TBContext
+
+PROBE_CLUSTER_CAP = 560        # FP64 Krylov kernel: two 4n x 4 blocks in 160 KB of LDS
+
+
+@dataclass
+class TBSettings:
+    """What one evaluation needs besides the positions."""
+    cell: tuple
+    periodic: tuple
+    params: dict
+    r_cluster: float
+    r: int
+    kT: float = 0.1
+    n_electrons: float | None = None      # None: keep mu fixed at `mu`
+    mu: float | None = None
+    precision: str = "fp64"
+    r_per_atom: torch.Tensor | None = None
+
+
+class TBForceField:
+    """One library context bound to fixed settings: pos -> (e[4], forces)."""
+
+    def __init__(self, n_atoms: int, n_cluster_max: int, settings: TBSettings, device: int = 0):
+        self.s = settings
+        r_max = settings.r if settings.r_per_atom is None else max(settings.r, int(settings.r_per_atom.max()))
+        self.ctx = TBContext(n_atoms, n_cluster_max, r_max, device=device)
+        self.mu = None
+
+    @classmethod
+    def for_geometry(cls, pos: torch.Tensor, settings: TBSettings, margin: int = 24) -> "TBForceField":
+        """Sizes the sphere capacity from the geometry itself (plus a margin for motion)."""
+        s = settings
+        cap = PROBE_CLUSTER_CAP
+        probe = TBContext(pos.shape[0], cap, 1, device=pos.device.index or 0)
+        sizes = probe.build_local_H(pos, s.cell, s.periodic, s.params, s.r_cluster, want_sizes=True)
+        n_max = int(sizes.max().item())
+        probe.close()
+        if n_max >= cap:
+            raise ValueError(f"a cutoff sphere holds {cap} or more atoms; the Krylov kernel keeps two "
+                             f"basis blocks of the sphere in LDS and supports fewer")
+        return cls(pos.shape[0], min(cap, n_max + margin), s, device=pos.device.index or 0)
+
+    def __call__(self, pos: torch.Tensor):
+        s = self.s
+        self.ctx.build_local_H(pos, s.cell, s.periodic, s.params, s.r_cluster)
+        self.mu, _ = self.ctx.krylov_rho(s.r, s.kT, mu=s.mu, n_electrons=s.n_electrons,
+                                         precision=s.precision, r_per_atom=s.r_per_atom)
+        return self.ctx.energy_forces()
+
+    def close(self):
+        self.ctx.close()
+
+
+class TBEnergy(torch.autograd.Function):
+    """E_tot = E_band - T S + E_rep as a 0-d tensor; backward returns -F * grad_out."""
+
+    @staticmethod
+    def forward(ctx, pos: torch.Tensor, ff: TBForceField):
+        e, f = ff(pos.detach().contiguous())
+        ctx.save_for_backward(f)
+        return e[3].clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (f,) = ctx.saved_tensors
+        return -f * grad_out, None
+
+
+def velocity_verlet(ff: TBForceField, pos: torch.Tensor, vel: torch.Tensor, dt: float, steps: int,
+                    mass: float = inputs.MASS_C, record_energy: bool = False):
+    """NVE velocity Verlet (positions in A, velocities in A/fs, dt in fs).
+    Positions are wrapped into the periodic cell on every step. Returns
+    (pos, vel, energies) where energies is a [steps + 1][3] device tensor of
+    (E_pot, E_kin, E_pot + E_kin) when record_energy is set, else None."""
+    cell = torch.tensor(np.diag(np.asarray(ff.s.cell, dtype=np.float64)) if np.ndim(ff.s.cell) == 2
+                        else np.asarray(ff.s.cell, dtype=np.float64), dtype=torch.float64, device=pos.device)
+    per = torch.tensor([bool(x) for x in ff.s.periodic], device=pos.device)
+    acc_unit = inputs.ACC_UNIT / mass
+    ke_unit = 0.5 * mass / inputs.ACC_UNIT          # amu A^2/fs^2 -> eV
+    e, f = ff(pos)
+    acc = f * acc_unit
+    rec = torch.empty((steps + 1, 3), dtype=torch.float64, device=pos.device) if record_energy else None
+
+    def log(k, e):
+        if rec is not None:
+            ke = ke_unit * (vel * vel).sum()
+            rec[k, 0] = e[3]
+            rec[k, 1] = ke
+            rec[k, 2] = e[3] + ke
+    log(0, e)
+    for k in range(steps):
+        pos = pos + vel * dt + 0.5 * acc * dt * dt
+        pos = torch.where(per, torch.remainder(pos, cell), pos)
+        e, f = ff(pos)
+        a_new = f * acc_unit
+        vel = vel + 0.5 * (acc + a_new) * dt
+        acc = a_new
+        log(k + 1, e)
+    return pos, vel, rec
