@@ -24,6 +24,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_lanczos_c60_1920_traffic.md")
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per k_lanczos launch from the committed FETCH_SIZE/WRITE_SIZE
+    record, if it was taken on this workload and precision with the current
+    kernel source (else None)."""
+    import hashlib
+    try:
+        rec = None
+        with open(TRAFFIC_RECORD) as fh:
+            for line in fh:
+                if line.startswith("traffic-record:"):
+                    rec = json.loads(line.split(":", 1)[1])
+        if rec is None or rec["workload"] != workload or rec["precision"] != precision:
+            return None
+        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+        return int(rec["bytes_per_launch"]) if sha == rec["source_sha256_16"] else None
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def parse():
@@ -36,7 +57,7 @@ def parse():
     ap.add_argument("--temperature", type=float, default=300.0, help="K, initial Maxwell velocities")
     ap.add_argument("--precision", choices=("both", "fp32", "fp64"), default="both")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="oracle atom-solves timed on host cores (0: about 20 s of CPU work)")
+                    help="oracle atom solves timed on host cores (0: one step's worth, at most 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the MD runs, launch one elementwise copy kernel of this many MiB "
@@ -160,7 +181,7 @@ def main():
     bytes_launch = algorithmic_bytes_lanczos(n_cluster, r_atoms, vt)
     achieved = bytes_launch / (lz_avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload, head_prec),
             "kernel": "k_lanczos", "avg_ms": round(lz_avg_ms, 4),
             "algorithmic_bytes_per_launch": bytes_launch}
 
@@ -168,7 +189,7 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import timing
         procs = min(16, len(os.sched_getaffinity(0)))
-        sample = args.cpu_sample or max(procs * 24, 64)
+        sample = args.cpu_sample or min(N, 2048)
         t = timing.time_atom_solves(w.pos, w.cell, (1, 1, 1), params, w.r_cut, w.r, sample,
                                     seed=11, processes=procs)
         cpu = {"value": round(t["steps_per_s"], 5), "unit": "MD steps/s", "cores": t["cores"],
