@@ -7,6 +7,8 @@
 
 #include <string>
 
+#include <float.h>
+
 #include "tb_internal.h"
 
 namespace tbk {
@@ -73,7 +75,7 @@ extern "C" int tb_destroy(tb_ctx* c) {
   void* ptrs[] = {c->hop_n, c->hop_j, c->hop_rev, c->hop_d, c->pair64, c->pair32, c->clu_n, c->clu_j,
                   c->loc_off, c->loc_ent, c->hnorm, c->jloc, c->row_ptr, c->col_j, c->vbuf, c->tab,
                   c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->rot_cs, c->rot_p,
-                  c->rot_n, c->seg, c->seg_n, c->evec, c->eig_scratch, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
+                  c->rot_n, c->seg, c->seg_n, c->evec, c->eig_scratch, c->omega, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (c->ev_pool) {
@@ -177,6 +179,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(eparts, 8);
   ALLOC(stats, ST_NSTATS);
 #undef ALLOC
+  if (a == hipSuccess) a = alloc(c, &c->omega, (size_t)c->n_wg_lanczos * 3 * r_max * 16);
   if (a == hipSuccess) {
     double* vb = nullptr;
     a = alloc(c, &vb, (size_t)c->n_wg_lanczos * r_max * 4 * NC * 4);
@@ -293,6 +296,12 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   la.v_sps = c->model.v_sps; la.v_pps = c->model.v_pps; la.v_ppp = c->model.v_ppp;
   la.vbuf = c->vbuf; la.tab = c->tab; la.kused = c->kused; la.vj = c->vj;
   la.counter = c->work_counter; la.stats = c->stats;
+  la.omega = c->omega;
+  // re-orthogonalisation threshold on the estimated |V_j^T V_{k+1}|: well
+  // below the parity bar in FP64; in FP32 at the level the FP32 recursion
+  // already carries
+  la.eta = fp32 ? 1e-4 : 1e-12;
+  la.eps_unit = fp32 ? (double)FLT_EPSILON : DBL_EPSILON;
   const size_t lds = lanczos_lds_bytes(c->nc_max, c->r_max, fp32);
   int pk = prof_begin(c, 1);
   launch_lanczos(la, fp32, c->n_wg_lanczos < n ? c->n_wg_lanczos : n, lds, st);

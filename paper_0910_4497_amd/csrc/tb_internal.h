@@ -23,7 +23,7 @@ constexpr int N_PHASES = 6;
 enum StatSlot {
   ST_FLAGS = 0, ST_MAX_CLUSTER = 1, ST_MAX_HOP = 2, ST_MAX_COUPLINGS = 3,
   ST_DEFLATED = 4, ST_EARLY_STOP = 5, ST_MAX_EIG_ITERS = 6, ST_MEMORY = 7,
-  ST_REORTH2 = 8, ST_NSTATS = 16
+  ST_REORTH2 = 8, ST_REORTH_STEPS = 9, ST_BASIS_BYTES = 10, ST_NSTATS = 16
 };
 enum FlagBits {
   FL_HOP_OVERFLOW = 1, FL_CLUSTER_OVERFLOW = 2, FL_COUPLING_OVERFLOW = 4,
@@ -80,6 +80,11 @@ __device__ __forceinline__ T wave_sum(T v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
 
 
 // ------------------------------------------------------------ kernel args
@@ -96,6 +101,8 @@ struct LanczosArgs {
   int* kused;
   void* vj;                    // [N][4*JMAX][4*r_max]
   int* counter;
+  double* omega;               // [WG][3][r_max][16] orthogonality estimates
+  double eta, eps_unit;        // re-orthogonalisation threshold, unit roundoff of VT
   int64_t* stats;
 };
 size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32);
@@ -194,6 +201,7 @@ struct tb_ctx {
   int* col_j;                                              // [N*JMAX] (pairs, compact)
   // Krylov (K4)
   void* vbuf;            // [WG][RMAX][4*NC][4] f64 or f32
+  double* omega;         // [WG][3][RMAX][16] orthogonality estimates
   double* tab;           // [N][RMAX][2][16]
   int* kused;            // [N]
   void* vj;              // [N][4*JMAX][4*RMAX] f64 or f32

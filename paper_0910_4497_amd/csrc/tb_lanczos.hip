@@ -176,8 +176,8 @@ k_lanczos(LanczosArgs g) {
   const int cslots = (g.r_max > 2 * LZ_NW ? g.r_max : 2 * LZ_NW);
   double* s_Cp = s_C + (size_t)cslots * 16;                 // partials [4*LZ_NW][16]
   double* s_red = s_Cp + (size_t)4 * LZ_NW * 16;            // [LZ_NW][16]
-  double* s_misc = s_red + LZ_NW * 16;                      // 192 doubles
-  int* s_off = (int*)(s_misc + 192);                        // [ncap+1]
+  double* s_misc = s_red + LZ_NW * 16;                      // 224 doubles
+  int* s_off = (int*)(s_misc + 224);                        // [ncap+1]
   int* s_gid = s_off + ncap + 1;                            // [ncap]
   signed char* s_js = (signed char*)(s_gid + ncap);         // [ncap]
   __shared__ int s_atom;
@@ -220,6 +220,7 @@ k_lanczos(LanczosArgs g) {
     }
     if (tid < 16) Bp[tid] = 0.0;
     if (tid < 4) s_flag[tid] = 1;
+    if (tid == 0) s_misc[208] = 0.0;             // running bound of ||T||
     __syncthreads();
     VT* vjrow = (VT*)g.vj + (size_t)atom * (4 * JMAX) * (4 * g.r_max);
     const int vjld = 4 * g.r_max;
@@ -229,7 +230,9 @@ k_lanczos(LanczosArgs g) {
       for (int c = 0; c < 4; ++c) vjrow[(size_t)row * vjld + c] = (VT)((row == c) ? 1.0 : 0.0);
     }
     int k_end = r_i;
-    int ndefl = 0, n2 = 0;
+    int ndefl = 0, n2 = 0, nreorth = 0;
+    int64_t bytes = (int64_t)R * 4 * (int64_t)sizeof(VT);    // V_0
+    bool force_next = false;
     double* tab = g.tab + (size_t)atom * g.r_max * 32;
     const int cq = tid & 3;                 // fixed column of this thread in the H.V items
 
@@ -310,9 +313,13 @@ k_lanczos(LanczosArgs g) {
         __syncthreads();
       }
       if (k == r_i - 1) break;
-      // ---- 2. three-term recursion: W -= V_k A_k + V_{k-1} B_{k-1}^T
+      // ---- 2. three-term recursion: W -= V_k A_k + V_{k-1} B_{k-1}^T, with
+      // the Gram matrix W^T W of the result
       {
         const VT* Vprev = (k > 0) ? vbase + (size_t)(k - 1) * Rcap * 4 : nullptr;
+        double acc[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) acc[q] = 0.0;
         for (int row = tid; row < R; row += LZ_NT) {
           double v[4], w[4], vp[4] = {0, 0, 0, 0};
           load4<VT>(s_V + 4 * row, v);
@@ -326,15 +333,122 @@ k_lanczos(LanczosArgs g) {
             w[d] = t;
           }
           store4<VT>(s_W + 4 * row, w);
+          load4<VT>(s_W + 4 * row, w);           // the stored (rounded) values
+          acc[0] += w[0] * w[0]; acc[1] += w[0] * w[1]; acc[2] += w[0] * w[2]; acc[3] += w[0] * w[3];
+          acc[4] += w[1] * w[1]; acc[5] += w[1] * w[2]; acc[6] += w[1] * w[3];
+          acc[7] += w[2] * w[2]; acc[8] += w[2] * w[3]; acc[9] += w[3] * w[3];
+        }
+        block_sum<10>(acc, s_red, G);
+        bytes += (int64_t)R * 4 * (int64_t)sizeof(VT) * (k > 0 ? 2 : 1);   // V_{k-1} read, V_{k+1} written
+      }
+      // ---- 3a. orthogonality estimate. With Omega_{j,k} = V_j^T V_k, the
+      // recursion H V_j = V_{j+1} B_j + V_j A_j + V_{j-1} B_{j-1}^T and the
+      // symmetry of H give, for j < k,
+      //   Omega_{j,k+1} B_k = B_j^T Omega_{j+1,k} + A_j Omega_{j,k} + B_{j-1} Omega_{j-1,k}
+      //                       - Omega_{j,k} A_k - Omega_{j,k-1} B_{k-1}^T  (+ rounding),
+      // and Omega_{k,k+1} is of order eps ||H|| / B_k (block form of Simon's
+      // recurrence). Rounding is modelled by eps ||T|| added with the sign of
+      // each entry; ||T|| is bounded by the running block-Gershgorin row sum.
+      // B_k comes from the Cholesky factor of the Gram matrix just formed.
+      bool reorth;
+      {
+        double* Xe = s_misc + 192;               // [16] B_k^-1 estimate
+        if (tid == 0) {
+          double Gf[16], Ur[16], Xr[16], ratio;
+          const int map[16] = {0, 1, 2, 3, 1, 4, 5, 6, 2, 5, 7, 8, 3, 6, 8, 9};
+          bool actk[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) actk[c] = s_flag[c] != 0;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) Gf[q] = G[map[q]];
+          const bool ok = chol4r(Gf, actk, Ur, tol * tol, ratio);
+          inv_upper4r(Ur, actk, Xr);
+          double tn = s_misc[208];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            double rs = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rs += fabs(A[a * 4 + c]) + fabs(Ur[c * 4 + a]) + fabs(Bp[a * 4 + c]);
+            tn = rs > tn ? rs : tn;
+          }
+#pragma unroll
+          for (int q = 0; q < 16; ++q) Xe[q] = Xr[q];
+          s_misc[208] = tn;
+          s_flag[6] = ok ? 1 : 0;
+        }
+        __syncthreads();
+        const double rnd = 2.0 * g.eps_unit * s_misc[208];
+        double* om = g.omega + (size_t)blockIdx.x * 3 * g.r_max * 16;
+        const double* Ok = om + (size_t)(k % 3) * g.r_max * 16;          // Omega_{j,k}, j < k
+        const double* Okm = om + (size_t)((k + 2) % 3) * g.r_max * 16;   // Omega_{j,k-1}, j < k-1
+        double* Okp = om + (size_t)((k + 1) % 3) * g.r_max * 16;         // Omega_{j,k+1}, j <= k
+        double lmax = 0.0;
+        for (int t = tid; t < 4 * (k + 1); t += LZ_NT) {
+          const int j = t >> 2, a = t & 3;
+          double M[4];
+          if (j == k) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) M[b] = rnd;
+          } else {
+            const double* Aj = tab + (size_t)j * 32;
+            const double* Bj = Aj + 16;
+            const double* Ojk = Ok + j * 16;
+            const double* Ojp = Ok + (j + 1) * 16;
+            const double* Ojm = Ok + (j - 1) * 16;
+            const double* Oold = Okm + j * 16;
+            double aj[4], bj[4], bjm[4], oa[4], ol[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              aj[c] = Aj[a * 4 + c];                                      // row a of A_j
+              bj[c] = Bj[c * 4 + a];                                      // column a of B_j
+              bjm[c] = (j > 0) ? Aj[-16 + a * 4 + c] : 0.0;               // row a of B_{j-1}
+              oa[c] = Ojk[a * 4 + c];                                     // row a of Omega_{j,k}
+              ol[c] = (j == k - 1) ? (a == c ? 1.0 : 0.0) : Oold[a * 4 + c];   // row a of Omega_{j,k-1}
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              double m = 0.0;
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                const double op = (j + 1 == k) ? (c == b ? 1.0 : 0.0) : Ojp[c * 4 + b];
+                m += aj[c] * Ojk[c * 4 + b] - oa[c] * A[c * 4 + b] + bj[c] * op - ol[c] * Bp[b * 4 + c];
+                if (j > 0) m += bjm[c] * Ojm[c * 4 + b];
+              }
+              M[b] = m + copysign(rnd, m);
+            }
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            double o = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o += M[c] * Xe[c * 4 + b];
+            Okp[j * 16 + a * 4 + b] = o;
+            lmax = fmax(lmax, fabs(o));
+          }
+        }
+        lmax = wave_max(lmax);
+        if (lane == 0) s_red[wave] = lmax;
+        __syncthreads();
+        double gmax = 0.0;
+        for (int w2 = 0; w2 < LZ_NW; ++w2) gmax = fmax(gmax, s_red[w2]);
+        const bool trig = !(gmax <= g.eta) || s_flag[6] == 0;
+        reorth = trig || force_next;
+        force_next = trig && !force_next;        // a triggered pass also covers the next block
+        if (reorth) {
+          // the pass restores orthogonality to rounding level
+          for (int t = tid; t < 16 * (k + 1); t += LZ_NT) Okp[t] = g.eps_unit;
+          ++nreorth;
         }
         __syncthreads();
       }
-      // ---- 3. full re-orthogonalisation against V_0..V_k: projection sweep
-      // (items with block k also give the column norms before the pass),
-      // then the update sweep with the Gram matrix of the result; a second
-      // pass when a column norm fell by more than sqrt(2).
-      for (int pass = 0; pass < 2; ++pass) {
+      // ---- 3b. when the estimate exceeds eta: full re-orthogonalisation
+      // against V_0..V_k: projection sweep (items with block k also give the
+      // column norms before the pass), then the update sweep with the Gram
+      // matrix of the result; a second pass when a column norm fell by more
+      // than sqrt(2).
+      for (int pass = 0; reorth && pass < 2; ++pass) {
         const int nb = k + 1;
+        bytes += 2 * (int64_t)nb * R * 4 * (int64_t)sizeof(VT);
         const int parts = (nb >= 2 * LZ_NW) ? 1 : (2 * LZ_NW + nb - 1) / nb;
         const int items = nb * parts;
         for (int it = wave; it < items; it += LZ_NW) {
@@ -612,6 +726,8 @@ k_lanczos(LanczosArgs g) {
       g.kused[atom] = k_end;
       if (ndefl) atomicAdd((unsigned long long*)&g.stats[ST_DEFLATED], (unsigned long long)ndefl);
       if (n2) atomicAdd((unsigned long long*)&g.stats[ST_REORTH2], (unsigned long long)n2);
+      atomicAdd((unsigned long long*)&g.stats[ST_REORTH_STEPS], (unsigned long long)nreorth);
+      atomicAdd((unsigned long long*)&g.stats[ST_BASIS_BYTES], (unsigned long long)bytes);
     }
     __syncthreads();
   }
@@ -622,7 +738,7 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32) {
   const size_t Rcap = 4 * (size_t)nc_max;
   size_t b = 2 * Rcap * 4 * vt + 16;
   const int cslots = r_max > 2 * LZ_NW ? r_max : 2 * LZ_NW;
-  b += (size_t)cslots * 16 * 8 + 4 * LZ_NW * 16 * 8 + LZ_NW * 16 * 8 + 192 * 8;
+  b += (size_t)cslots * 16 * 8 + 4 * LZ_NW * 16 * 8 + LZ_NW * 16 * 8 + 224 * 8;
   b += (size_t)(nc_max + 1) * 4 + (size_t)nc_max * 4 + (size_t)nc_max;
   return b + 64;
 }
