@@ -114,7 +114,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   if (c->rot_max > 65535 * 16) c->rot_max = 65535 * 16;
 
   // persistent Krylov workgroups: as many as fit on the device at once
-  const size_t lds = lanczos_lds_bytes(n_cluster_max, r_max, false);
+  const size_t lds = lanczos_lds_bytes(n_cluster_max, r_max, false, false, false);
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
   if (lds > prop.sharedMemPerBlock && lds > 160 * 1024) {
@@ -122,7 +122,12 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
     return fail(TB_ECAPACITY, "n_cluster_max=%d, r_max=%d need %zu B of LDS per workgroup", n_cluster_max,
                 r_max, lds);
   }
-  hipError_t e = lanczos_set_lds(lds);
+  size_t lds_attr = lds;
+  for (int v = 1; v <= 2; ++v) {
+    const size_t l = lanczos_lds_bytes(n_cluster_max, r_max, false, true, v == 2);
+    if (l <= 160 * 1024) lds_attr = l;
+  }
+  hipError_t e = lanczos_set_lds(lds_attr);
   if (e != hipSuccess) {
     delete c;
     return fail(TB_ECAPACITY, "LDS request of %zu B refused: %s", lds, hipGetErrorString(e));
@@ -135,6 +140,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   int per_cu = (int)((160 * 1024) / (lds + 1024));
   if (per_cu < 1) per_cu = 1;
   if (per_cu > 2) per_cu = 2;
+  c->lz_per_cu = per_cu;
   c->n_wg_lanczos = prop.multiProcessorCount * per_cu;
   if (c->n_wg_lanczos > n_atoms_max) c->n_wg_lanczos = (int)n_atoms_max;
   c->n_wg_eig = prop.multiProcessorCount * 4;
@@ -302,7 +308,17 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   // already carries
   la.eta = fp32 ? 1e-4 : 1e-12;
   la.eps_unit = fp32 ? (double)FLT_EPSILON : DBL_EPSILON;
-  const size_t lds = lanczos_lds_bytes(c->nc_max, c->r_max, fp32);
+  // orthogonality estimates in LDS when that keeps the workgroups per CU
+  // (and the FP32 copies of A_j, B_j beside them) when that keeps the
+  // workgroups per CU
+  auto fits = [&](size_t l) { return l <= 160 * 1024 && (160 * 1024) / (l + 1024) >= (size_t)c->lz_per_cu; };
+  const size_t lds0 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, false, false);
+  const size_t lds1 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, false);
+  const size_t lds2 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, true);
+  const bool om_lds = fits(lds1), ab_lds = fits(lds2);
+  const size_t lds = ab_lds ? lds2 : (om_lds ? lds1 : lds0);
+  la.om_lds = om_lds ? 1 : 0;
+  la.ab_lds = ab_lds ? 1 : 0;
   int pk = prof_begin(c, 1);
   launch_lanczos(la, fp32, c->n_wg_lanczos < n ? c->n_wg_lanczos : n, lds, st);
   prof_end(c, pk);

@@ -80,6 +80,15 @@ __device__ __forceinline__ T wave_sum(T v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+// Workgroup barrier that orders LDS only. Unlike __syncthreads() it does not
+// wait for the thread's outstanding global stores; use it where no other
+// thread of the workgroup reads those stores before a later full barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -101,11 +110,13 @@ struct LanczosArgs {
   int* kused;
   void* vj;                    // [N][4*JMAX][4*r_max]
   int* counter;
-  double* omega;               // [WG][3][r_max][16] orthogonality estimates
+  double* omega;               // [WG][3][r_max][16] float orthogonality estimates (when not in LDS)
+  int om_lds;                  // estimates kept in LDS
+  int ab_lds;                  // FP32 copies of A_j, B_j kept in LDS (needs om_lds)
   double eta, eps_unit;        // re-orthogonalisation threshold, unit roundoff of VT
   int64_t* stats;
 };
-size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32);
+size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_lds);
 void launch_lanczos(const LanczosArgs& a, bool fp32, int n_wg, size_t lds, hipStream_t st);
 hipError_t lanczos_set_lds(size_t lds);
 int lanczos_threads();
@@ -177,6 +188,7 @@ struct tb_ctx {
   int64_t emax;          // couplings per sphere
   int64_t rot_max;       // rotation-log entries per atom
   int n_wg_lanczos;      // persistent workgroups of the Krylov kernel
+  int lz_per_cu;         // of them per compute unit (FP64 LDS sizing)
   size_t bytes;
 
   // state

@@ -36,7 +36,9 @@ template <> struct Vec4<float> { typedef float4 T; };
 
 
 // Sum m values (m <= 16) over the workgroup; result in out[0..m-1] (LDS).
-template <int M>
+// FULL: the first barrier is a full one (global stores become visible to the
+// workgroup); otherwise both order LDS only.
+template <int M, bool FULL = false>
 __device__ __forceinline__ void block_sum(double (&v)[M], double* red, double* out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
@@ -45,13 +47,13 @@ __device__ __forceinline__ void block_sum(double (&v)[M], double* red, double* o
 #pragma unroll
     for (int q = 0; q < M; ++q) red[wave * 16 + q] = v[q];
   }
-  __syncthreads();
+  if (FULL) __syncthreads(); else lds_barrier();
   if (tid < M) {
     double s = 0.0;
     for (int w = 0; w < LZ_NW; ++w) s += red[w * 16 + tid];
     out[tid] = s;
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Butterfly reduce-scatter of 16 values over a wave; lanes with (lane & 3) == 0
@@ -174,12 +176,13 @@ k_lanczos(LanczosArgs g) {
   double* s_C = (double*)(((uintptr_t)(s_W + (size_t)Rcap * 4) + 15) & ~(uintptr_t)15);
   // s_C: [max(r_max, LZ_NW)][16] projection coefficients / partials
   const int cslots = (g.r_max > 2 * LZ_NW ? g.r_max : 2 * LZ_NW);
-  double* s_Cp = s_C + (size_t)cslots * 16;                 // partials [4*LZ_NW][16]
-  double* s_red = s_Cp + (size_t)4 * LZ_NW * 16;            // [LZ_NW][16]
+  double* s_red = s_C + (size_t)cslots * 16;                // [LZ_NW][16]
   double* s_misc = s_red + LZ_NW * 16;                      // 224 doubles
   int* s_off = (int*)(s_misc + 224);                        // [ncap+1]
   int* s_gid = s_off + ncap + 1;                            // [ncap]
   signed char* s_js = (signed char*)(s_gid + ncap);         // [ncap]
+  float* s_om = (float*)(((uintptr_t)(s_js + ncap) + 15) & ~(uintptr_t)15);   // [3][r_max][16] if om_lds
+  float* s_ab = s_om + (g.om_lds ? (size_t)3 * g.r_max * 16 : 0);                 // [r_max][32] if ab_lds
   __shared__ int s_atom;
 
   double* A = s_misc;          // [16]
@@ -297,20 +300,21 @@ k_lanczos(LanczosArgs g) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) s_red[wave * 16 + q * 4 + lane] = accA[q];
         }
-        __syncthreads();
+        lds_barrier();
         if (tid < 16) {
           double sum = 0.0;
           for (int w = 0; w < LZ_NW; ++w) sum += s_red[w * 16 + tid];
           X[tid] = sum;
         }
-        __syncthreads();
+        lds_barrier();
         if (tid < 16) {
           const int c = tid >> 2, d = tid & 3;
           const double av = 0.5 * (X[c * 4 + d] + X[d * 4 + c]);
           A[tid] = av;
           tab[(size_t)k * 32 + tid] = av;
+          if (g.ab_lds) s_ab[k * 32 + tid] = (float)av;
         }
-        __syncthreads();
+        lds_barrier();
       }
       if (k == r_i - 1) break;
       // ---- 2. three-term recursion: W -= V_k A_k + V_{k-1} B_{k-1}^T, with
@@ -338,7 +342,9 @@ k_lanczos(LanczosArgs g) {
           acc[4] += w[1] * w[1]; acc[5] += w[1] * w[2]; acc[6] += w[1] * w[3];
           acc[7] += w[2] * w[2]; acc[8] += w[2] * w[3]; acc[9] += w[3] * w[3];
         }
-        block_sum<10>(acc, s_red, G);
+        // the one full barrier of the step: the global stores of the previous
+        // step (V_k, rho rows, A, B, Omega) are visible to the workgroup after it
+        block_sum<10, true>(acc, s_red, G);
         bytes += (int64_t)R * 4 * (int64_t)sizeof(VT) * (k > 0 ? 2 : 1);   // V_{k-1} read, V_{k+1} written
       }
       // ---- 3a. orthogonality estimate. With Omega_{j,k} = V_j^T V_k, the
@@ -352,6 +358,7 @@ k_lanczos(LanczosArgs g) {
       // B_k comes from the Cholesky factor of the Gram matrix just formed.
       bool reorth;
       {
+        // thread 0: Cholesky factor of the Gram matrix, B_k^-1, ||T|| bound
         double* Xe = s_misc + 192;               // [16] B_k^-1 estimate
         if (tid == 0) {
           double Gf[16], Ur[16], Xr[16], ratio;
@@ -376,70 +383,71 @@ k_lanczos(LanczosArgs g) {
           s_misc[208] = tn;
           s_flag[6] = ok ? 1 : 0;
         }
-        __syncthreads();
+        lds_barrier();
         const double rnd = 2.0 * g.eps_unit * s_misc[208];
-        double* om = g.omega + (size_t)blockIdx.x * 3 * g.r_max * 16;
-        const double* Ok = om + (size_t)(k % 3) * g.r_max * 16;          // Omega_{j,k}, j < k
-        const double* Okm = om + (size_t)((k + 2) % 3) * g.r_max * 16;   // Omega_{j,k-1}, j < k-1
-        double* Okp = om + (size_t)((k + 1) % 3) * g.r_max * 16;         // Omega_{j,k+1}, j <= k
+        float* om = g.om_lds ? s_om : (float*)g.omega + (size_t)blockIdx.x * 3 * g.r_max * 16;
+        const float* Ok = om + (size_t)(k % 3) * g.r_max * 16;          // Omega_{j,k}, j < k
+        const float* Okm = om + (size_t)((k + 2) % 3) * g.r_max * 16;   // Omega_{j,k-1}, j < k-1
+        float* Okp = om + (size_t)((k + 1) % 3) * g.r_max * 16;         // Omega_{j,k+1}, j <= k
+        // one entry (j, a, b) of Omega_{j,k+1} per thread, in FP32 (an
+        // estimate); the four lanes holding row (j, a) exchange M by shuffles
+        const float rndf = (float)rnd;
         double lmax = 0.0;
-        for (int t = tid; t < 4 * (k + 1); t += LZ_NT) {
-          const int j = t >> 2, a = t & 3;
-          double M[4];
-          if (j == k) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) M[b] = rnd;
-          } else {
-            const double* Aj = tab + (size_t)j * 32;
-            const double* Bj = Aj + 16;
-            const double* Ojk = Ok + j * 16;
-            const double* Ojp = Ok + (j + 1) * 16;
-            const double* Ojm = Ok + (j - 1) * 16;
-            const double* Oold = Okm + j * 16;
-            double aj[4], bj[4], bjm[4], oa[4], ol[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              aj[c] = Aj[a * 4 + c];                                      // row a of A_j
-              bj[c] = Bj[c * 4 + a];                                      // column a of B_j
-              bjm[c] = (j > 0) ? Aj[-16 + a * 4 + c] : 0.0;               // row a of B_{j-1}
-              oa[c] = Ojk[a * 4 + c];                                     // row a of Omega_{j,k}
-              ol[c] = (j == k - 1) ? (a == c ? 1.0 : 0.0) : Oold[a * 4 + c];   // row a of Omega_{j,k-1}
-            }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              double m = 0.0;
+        for (int t = tid; t < 16 * (k + 1); t += LZ_NT) {
+          const int j = t >> 4, a = (t >> 2) & 3, b = t & 3;
+          float m = rndf;
+          if (j < k) {
+            // row a of A_j, column a of B_j, row a of B_{j-1}
+            float aj[4], bj[4], bjm[4];
+            if (g.ab_lds) {
+              const float* ABj = s_ab + j * 32;
 #pragma unroll
               for (int c = 0; c < 4; ++c) {
-                const double op = (j + 1 == k) ? (c == b ? 1.0 : 0.0) : Ojp[c * 4 + b];
-                m += aj[c] * Ojk[c * 4 + b] - oa[c] * A[c * 4 + b] + bj[c] * op - ol[c] * Bp[b * 4 + c];
-                if (j > 0) m += bjm[c] * Ojm[c * 4 + b];
+                aj[c] = ABj[a * 4 + c]; bj[c] = ABj[16 + c * 4 + a];
+                bjm[c] = (j > 0) ? ABj[-16 + a * 4 + c] : 0.0f;
               }
-              M[b] = m + copysign(rnd, m);
+            } else {
+              const double* ABj = tab + (size_t)j * 32;
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                aj[c] = (float)ABj[a * 4 + c]; bj[c] = (float)ABj[16 + c * 4 + a];
+                bjm[c] = (j > 0) ? (float)ABj[-16 + a * 4 + c] : 0.0f;
+              }
             }
-          }
+            const float* Ojk = Ok + j * 16;
+            float acc = 0.0f;
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            double o = 0.0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) o += M[c] * Xe[c * 4 + b];
-            Okp[j * 16 + a * 4 + b] = o;
-            lmax = fmax(lmax, fabs(o));
+            for (int c = 0; c < 4; ++c) {
+              const float ojp = (j + 1 == k) ? (c == b ? 1.0f : 0.0f) : Ojk[16 + c * 4 + b];
+              const float ol = (j == k - 1) ? (a == c ? 1.0f : 0.0f) : Okm[j * 16 + a * 4 + c];
+              acc += aj[c] * Ojk[c * 4 + b] - Ojk[a * 4 + c] * (float)A[c * 4 + b]
+                   + bj[c] * ojp - ol * (float)Bp[b * 4 + c];
+              if (j > 0) acc += bjm[c] * Ojk[-16 + c * 4 + b];
+            }
+            m = acc + copysignf(rndf, acc);
           }
+          float o = 0.0f;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) o += __shfl(m, (lane & ~3) | c, 64) * (float)Xe[c * 4 + b];
+          Okp[j * 16 + a * 4 + b] = o;
+          lmax = fmax(lmax, (double)fabsf(o));
         }
         lmax = wave_max(lmax);
         if (lane == 0) s_red[wave] = lmax;
-        __syncthreads();
+        lds_barrier();
         double gmax = 0.0;
         for (int w2 = 0; w2 < LZ_NW; ++w2) gmax = fmax(gmax, s_red[w2]);
         const bool trig = !(gmax <= g.eta) || s_flag[6] == 0;
         reorth = trig || force_next;
         force_next = trig && !force_next;        // a triggered pass also covers the next block
         if (reorth) {
-          // the pass restores orthogonality to rounding level
-          for (int t = tid; t < 16 * (k + 1); t += LZ_NT) Okp[t] = g.eps_unit;
+          // the pass restores orthogonality to rounding level (each thread
+          // overwrites the entries it stored: the step's barriers order LDS
+          // only, and the buffer may be in global memory)
+          for (int t = tid; t < 16 * (k + 1); t += LZ_NT) Okp[t] = (float)g.eps_unit;
           ++nreorth;
         }
-        __syncthreads();
+        lds_barrier();
       }
       // ---- 3b. when the estimate exceeds eta: full re-orthogonalisation
       // against V_0..V_k: projection sweep (items with block k also give the
@@ -449,8 +457,13 @@ k_lanczos(LanczosArgs g) {
       for (int pass = 0; reorth && pass < 2; ++pass) {
         const int nb = k + 1;
         bytes += 2 * (int64_t)nb * R * 4 * (int64_t)sizeof(VT);
-        const int parts = (nb >= 2 * LZ_NW) ? 1 : (2 * LZ_NW + nb - 1) / nb;
+        // short bases are split over the waves by rows; the partial sums go
+        // to the free slots of s_C behind the nb coefficient blocks
+        int parts = (nb >= 2 * LZ_NW) ? 1 : (2 * LZ_NW + nb - 1) / nb;
+        const int pmax = (cslots - nb) / nb;
+        parts = parts <= pmax ? parts : (pmax > 1 ? pmax : 1);
         const int items = nb * parts;
+        double* s_Cp = s_C + nb * 16;
         for (int it = wave; it < items; it += LZ_NW) {
           const int j = it / parts, part = it % parts;
           const VT* Vj = vbase + (size_t)j * Rcap * 4;
@@ -510,7 +523,7 @@ k_lanczos(LanczosArgs g) {
             if (lane < 4) s_Np[part * 4 + lane] = nacc[lane];
           }
         }
-        __syncthreads();
+        lds_barrier();
         if (parts > 1) {
           for (int q = tid; q < nb * 16; q += LZ_NT) {
             const int j = q >> 4, e = q & 15;
@@ -524,7 +537,7 @@ k_lanczos(LanczosArgs g) {
           for (int p = 0; p < parts; ++p) sum += s_Np[p * 4 + tid];
           X[12 + tid] = sum;                        // norms before this pass
         }
-        __syncthreads();
+        lds_barrier();
         // update sweep with the Gram matrix (10 values) of the result
         double acc[10];
 #pragma unroll
@@ -579,7 +592,7 @@ k_lanczos(LanczosArgs g) {
           const double before = X[12 + d];
           if (s_flag[d] && before > tol * tol && G[dd] < 0.5 * before) again = true;
         }
-        __syncthreads();                            // X, G read by all before reuse
+        lds_barrier();                            // X, G read by all before reuse
         if (!again || pass == 1) break;
         ++n2;
       }
@@ -597,13 +610,13 @@ k_lanczos(LanczosArgs g) {
         for (int q = 0; q < 16; ++q) Gf[q] = G[map[q]];
         const bool ok = chol4r(Gf, act, Ur, tol * tol, ratio);
         inv_upper4r(Ur, act, Xr);
-        __syncthreads();                              // every thread has read G
+        lds_barrier();                              // every thread has read G
         if (tid == 0) {
 #pragma unroll
           for (int q = 0; q < 16; ++q) { X[q] = Xr[q]; B[q] = Ur[q]; }
           s_flag[5] = !ok ? 2 : (ratio > 1e-4 ? 0 : 1);
         }
-        __syncthreads();
+        lds_barrier();
       }
       const int path = s_flag[5];
       if (path == 1) {
@@ -633,7 +646,7 @@ k_lanczos(LanczosArgs g) {
           for (int q = 0; q < 16; ++q) Gf[q] = G[map[q]];
           chol4r(Gf, act, U2, 0.0, r2);
           inv_upper4r(U2, act, X2);
-          __syncthreads();                            // G, X, B read by all
+          lds_barrier();                            // G, X, B read by all
           if (tid == 0) {
             double Bn[16];
 #pragma unroll
@@ -648,13 +661,13 @@ k_lanczos(LanczosArgs g) {
 #pragma unroll
             for (int q = 0; q < 16; ++q) { B[q] = Bn[q]; X[q] = X2[q]; }
           }
-          __syncthreads();
+          lds_barrier();
         }
         ++n2;
       } else if (path == 2) {
         // modified Gram-Schmidt (twice) within the block, with deflation
         if (tid < 16) B[tid] = 0.0;
-        __syncthreads();
+        lds_barrier();
         for (int c = 0; c < 4; ++c) {
           for (int ps = 0; ps < 2; ++ps) {
             for (int p = 0; p < c; ++p) {
@@ -667,7 +680,7 @@ k_lanczos(LanczosArgs g) {
               for (int row = tid; row < R; row += LZ_NT)
                 s_W[4 * row + c] = (VT)((double)s_W[4 * row + c] - dot * (double)s_W[4 * row + p]);
               if (tid == 0) B[p * 4 + c] += dot;
-              __syncthreads();
+              lds_barrier();
             }
           }
           double a1[1] = {0.0};
@@ -683,10 +696,10 @@ k_lanczos(LanczosArgs g) {
             if (s_flag[c] && !keep) ++ndefl;
             s_flag[c] = keep ? 1 : 0;
           }
-          __syncthreads();
+          lds_barrier();
         }
         if (tid < 16) X[tid] = ((tid % 5) == 0) ? 1.0 : 0.0;
-        __syncthreads();
+        lds_barrier();
       }
       // ---- 5. V_{k+1} = W X: LDS current block, HBM basis, J rows; B_k
       {
@@ -712,9 +725,10 @@ k_lanczos(LanczosArgs g) {
         }
         if (tid < 16) {
           tab[(size_t)k * 32 + 16 + tid] = B[tid];
+          if (g.ab_lds) s_ab[k * 32 + 16 + tid] = (float)B[tid];
           Bp[tid] = B[tid];
         }
-        __syncthreads();
+        lds_barrier();
       }
       if (!(s_flag[0] | s_flag[1] | s_flag[2] | s_flag[3])) {   // invariant space
         k_end = k + 1;
@@ -733,13 +747,15 @@ k_lanczos(LanczosArgs g) {
   }
 }
 
-size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32) {
+size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_lds) {
   const size_t vt = fp32 ? 4 : 8;
   const size_t Rcap = 4 * (size_t)nc_max;
   size_t b = 2 * Rcap * 4 * vt + 16;
   const int cslots = r_max > 2 * LZ_NW ? r_max : 2 * LZ_NW;
-  b += (size_t)cslots * 16 * 8 + 4 * LZ_NW * 16 * 8 + LZ_NW * 16 * 8 + 224 * 8;
-  b += (size_t)(nc_max + 1) * 4 + (size_t)nc_max * 4 + (size_t)nc_max;
+  b += (size_t)cslots * 16 * 8 + LZ_NW * 16 * 8 + 224 * 8;
+  b += (size_t)(nc_max + 1) * 4 + (size_t)nc_max * 4 + (size_t)nc_max + 16;
+  if (om_lds) b += (size_t)3 * r_max * 16 * 4;
+  if (ab_lds) b += (size_t)r_max * 32 * 4;
   return b + 64;
 }
 
