@@ -75,7 +75,7 @@ extern "C" int tb_destroy(tb_ctx* c) {
   void* ptrs[] = {c->hop_n, c->hop_j, c->hop_rev, c->hop_d, c->pair64, c->pair32, c->clu_n, c->clu_j,
                   c->loc_off, c->loc_ent, c->hnorm, c->jloc, c->row_ptr, c->col_j, c->vbuf, c->tab,
                   c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->rot_cs, c->rot_p,
-                  c->rot_n, c->seg, c->seg_n, c->evec, c->eig_scratch, c->omega, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
+                  c->rot_n, c->seg, c->seg_n, c->evec, c->tri, c->eig_scratch, c->omega, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (c->ev_pool) {
@@ -177,6 +177,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(seg, N * c->seg_max);
   ALLOC(seg_n, 2 * N);
   ALLOC(evec, N * dmax * dmax);
+  ALLOC(tri, N * 2 * dmax);
   ALLOC(eig_scratch, (int64_t)c->n_wg_eig * dmax * 4 * eig_threads());
   ALLOC(mu_state, 16);
   ALLOC(partial, 4096);
@@ -328,7 +329,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   ea.lam = c->lam; ea.wgt = c->wgt; ea.y1 = c->y1;
   ea.rot_cs = c->rot_cs; ea.rot_p = c->rot_p; ea.rot_n = c->rot_n; ea.rot_max = c->rot_max;
   ea.seg = c->seg; ea.seg_n = c->seg_n; ea.seg_max = c->seg_max;
-  ea.counter = c->work_counter + 1; ea.scratch = c->eig_scratch; ea.evec = c->evec;
+  ea.counter = c->work_counter + 1; ea.scratch = c->eig_scratch; ea.evec = c->evec; ea.tri = c->tri;
   ea.stats = c->stats;
   pk = prof_begin(c, 2);
   launch_eig(ea, c->n_wg_eig < n ? c->n_wg_eig : n, st);

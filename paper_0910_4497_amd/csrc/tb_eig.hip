@@ -1,8 +1,9 @@
 // Projected eigenproblem and density-matrix assembly (Sec. 3: the small
 // projected matrix is diagonalised; Sec. 2, Eq. 2: rho = sum |m> f <m|).
 //
-// k_eig, one persistent 256-thread workgroup per atom at a time, FP64:
-//   1. T (block tridiagonal, 4x4 blocks A_k, upper-triangular B_k: a band of
+// k_band (one wave per atom) and k_eig (one persistent 256-thread workgroup
+// per atom at a time), FP64:
+//   1. k_band: T (block tridiagonal, 4x4 blocks A_k, upper-triangular B_k: a band of
 //      half-width 4) -> tridiagonal S = Z^T T Z by Givens rotations, one
 //      diagonal at a time (half-width bc -> bc-1 for bc = 4, 3, 2). The fill-in
 //      of each rotation is chased down the band; chase j starts at time j * I
@@ -10,8 +11,8 @@
 //      concurrent rotations touch disjoint entries, so each time step applies
 //      one rotation per active chase in parallel. Every rotation is applied to
 //      the first four rows of Z and logged (c, s, plane) with one segment per
-//      time step.
-//   2. eigenvalues of S by bisection on Sturm counts, one thread per
+//      time step. D, E of S and Z[0:4, :] go to HBM.
+//   2. k_eig: eigenvalues of S by bisection on Sturm counts, one thread per
 //      eigenvalue index (all in parallel);
 //   3. eigenvectors of S by two steps of inverse iteration (tridiagonal LU
 //      with partial pivoting, deterministic pseudo-random start); inside a
@@ -37,6 +38,7 @@
 namespace tbk {
 
 constexpr int EIG_NT = 256;
+constexpr int BAND_NT = 64;
 constexpr int RHO_NT = 64;
 constexpr int BW = 4;              // half-bandwidth of T
 constexpr int LB = BW + 2;         // stored lower diagonals incl. the bulge
@@ -131,12 +133,155 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
   return nrm;
 }
 
+// One time step of the chases that reduce the half-bandwidth from BC to BC-1.
+// Lb points at row 0 of the band storage; row -1 exists and is zero, and the
+// entries of rows p past the matrix end are zero, so the rotation needs no
+// bounds tests (rotating zeros gives zeros). Lane l takes chase jtop - l, then
+// jtop - 64 - l, ... until a batch has no active chase.
+template <int BC>
+__device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau, int lane, double* lcs,
+                                          uint16_t* lp, int64_t rot_max, int64_t& nrot) {
+  constexpr int I = (2 * BC + 3) / BC;       // ceil((BC + 4) / BC): 2, 3, 3
+  const int last = d - BC - 1;
+  int jtop = tau / I;
+  if (jtop > last) jtop = last;
+  for (int jb = jtop; jb >= 0; jb -= 64) {
+    const int j = jb - lane;
+    bool act = false;
+    int p = 0, u0 = 0;
+    if (j >= 0) {
+      const int st = tau - j * I;
+      p = j + BC - 1 + st * BC;
+      act = (p + 1 <= d - 1);
+      u0 = (st == 0) ? 1 : 0;               // the annihilated entry is T[q][p - BC + u0]
+    }
+    const bool batch_done = __ballot(act) == 0ull;
+    double c = 1.0, s = 0.0;
+    if (act) {
+      const int q = p + 1, ml = p - BC;
+      double lu[BC], lv[BC], ru[BC], rv[BC], r1u[4], r1v[4];
+#pragma unroll
+      for (int u = 0; u < BC; ++u) {
+        lu[u] = Lb[(ml + u) * LB + (BC - u)];         // T[p][m], m = ml + u
+        lv[u] = Lb[(ml + u) * LB + (BC + 1 - u)];     // T[q][m]
+        ru[u] = Lb[p * LB + 2 + u];                   // T[p + 2 + u][p]
+        rv[u] = Lb[q * LB + 1 + u];                   // T[p + 2 + u][q]
+      }
+      const double da = Lb[p * LB], db = Lb[p * LB + 1], de = Lb[q * LB];
+#pragma unroll
+      for (int row = 0; row < 4; ++row) { r1u[row] = R1[row * d + p]; r1v[row] = R1[row * d + q]; }
+      const double x = u0 ? lu[1] : lu[0], y = u0 ? lv[1] : lv[0];
+      act = (y != 0.0);
+      if (act) {
+        double r;
+        givens(x, y, c, s, r);
+#pragma unroll
+        for (int u = 0; u < BC; ++u) {
+          const int m = ml + u;
+          Lb[m * LB + (BC - u)] = (u == u0) ? r : c * lu[u] + s * lv[u];
+          Lb[m * LB + (BC + 1 - u)] = (u == u0) ? 0.0 : -s * lu[u] + c * lv[u];
+          Lb[p * LB + 2 + u] = c * ru[u] + s * rv[u];
+          Lb[q * LB + 1 + u] = -s * ru[u] + c * rv[u];
+        }
+        const double cc = c * c, ss = s * s, cs = c * s;
+        Lb[p * LB] = cc * da + 2.0 * cs * db + ss * de;
+        Lb[q * LB] = ss * da - 2.0 * cs * db + cc * de;
+        Lb[p * LB + 1] = cs * (de - da) + (cc - ss) * db;
+#pragma unroll
+        for (int row = 0; row < 4; ++row) {
+          R1[row * d + p] = c * r1u[row] + s * r1v[row];
+          R1[row * d + q] = -s * r1u[row] + c * r1v[row];
+        }
+      }
+    }
+    // log in lane order (the rotations of one time step commute)
+    const uint64_t mask = __ballot(act);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t slot = nrot + __popcll(mask & below);
+    if (act && slot < rot_max) { lcs[2 * slot] = c; lcs[2 * slot + 1] = s; lp[slot] = (uint16_t)p; }
+    nrot += __popcll(mask);
+    if (batch_done) break;
+  }
+}
+
+template <int BC>
+__device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int lane, double* lcs, uint16_t* lp,
+                                           int64_t rot_max, int64_t& nrot, int* seg, int seg_max, int& nseg) {
+  constexpr int I = (2 * BC + 3) / BC;
+  const int nchase = d - BC;
+  if (nchase <= 0) return;
+  const int last = nchase - 1;
+  const int t_end = last * I + (d - 1 - last - BC) / BC + 1;
+  for (int tau = 0; tau < t_end; ++tau) {
+    const int64_t step_start = nrot;
+    band_step<BC>(Lb, R1, d, tau, lane, lcs, lp, rot_max, nrot);
+    if (nrot > step_start) {                  // one segment per non-empty time step
+      if (lane == 0 && nseg < seg_max) seg[nseg] = (int)step_start;
+      ++nseg;
+    }
+    // the LDS operations of one wave complete in issue order: a wave-scope
+    // fence orders the time steps
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Band -> tridiagonal reduction: one wave per atom, one lane per chase.
+__global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
+  extern __shared__ double bsm[];
+  const int lane = threadIdx.x;
+  const int atom = blockIdx.x;
+  const int dmax = 4 * g.r_max;
+  const int K = g.kused[atom];
+  const int d = 4 * K;
+  double* Lb = bsm + LB;                   // [-1 .. d-1][LB]: Lb[j][t] = T[j+t][j]; row -1 zero
+  double* R1 = Lb + (size_t)dmax * LB;     // [4][d] first rows of the transform
+  const double* tab = g.tab + (size_t)atom * g.r_max * 32;
+  for (int q = lane; q < (d + 1) * LB; q += BAND_NT) {
+    const int j = q / LB - 1, t = q % LB;
+    const int row = j + t;
+    bsm[q] = (j >= 0 && t <= BW && row < d) ? t_entry(tab, row, j) : 0.0;
+  }
+  for (int q = lane; q < 4 * d; q += BAND_NT) {
+    const int c = q / d, m = q % d;
+    R1[q] = (m == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
+  uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
+  int* seg = g.seg + (size_t)atom * g.seg_max;
+  int64_t nrot = 0;
+  int nseg = 0;
+  band_stage<4>(Lb, R1, d, lane, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
+  band_stage<3>(Lb, R1, d, lane, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
+  band_stage<2>(Lb, R1, d, lane, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
+  if (lane == 0) {
+    g.rot_n[atom] = (int)(nrot < g.rot_max ? nrot : g.rot_max);
+    g.seg_n[2 * atom] = nseg < g.seg_max ? nseg : g.seg_max;
+    g.seg_n[2 * atom + 1] = nseg < g.seg_max ? nseg : g.seg_max;
+    if (nseg > g.seg_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_SEG_OVERFLOW);
+    if (nrot > g.rot_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
+  }
+  __syncthreads();
+  // tridiagonal S (D, E) and Z[0:4, :]
+  double* tri = g.tri + (size_t)atom * 2 * dmax;
+  double* r1 = g.y1 + (size_t)atom * 4 * dmax;
+  for (int k = lane; k < d; k += BAND_NT) {
+    tri[k] = Lb[(size_t)k * LB];
+    tri[dmax + k] = (k + 1 < d) ? Lb[(size_t)k * LB + 1] : 0.0;
+  }
+  for (int q = lane; q < 4 * d; q += BAND_NT) {
+    const int c = q / d, m = q % d;
+    r1[(size_t)c * dmax + m] = R1[q];
+  }
+}
+
 __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
   extern __shared__ double esm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int dmax = 4 * g.r_max;
-  double* Lb = esm;                        // [dmax][LB]: Lb[j][t] = T[j+t][j]
-  double* R1 = Lb + (size_t)dmax * LB;     // [4][d]
+  double* R1 = esm;                        // [4][d] first rows of Z
   double* Dg = R1 + (size_t)4 * dmax;      // [dmax] diagonal of S
   double* Eg = Dg + dmax;                  // [dmax] off-diagonal of S (E[k]: k, k+1)
   double* E2 = Eg + dmax;                  // [dmax] E^2
@@ -154,142 +299,19 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     if (atom >= g.n_atoms) break;
     const int K = g.kused[atom];
     const int d = 4 * K;
-    const double* tab = g.tab + (size_t)atom * g.r_max * 32;
-    for (int q = tid; q < d * LB; q += EIG_NT) {
-      const int j = q / LB, t = q % LB;
-      const int row = j + t;
-      Lb[q] = (t <= BW && row < d) ? t_entry(tab, row, j) : 0.0;
-    }
+    const double* tri = g.tri + (size_t)atom * 2 * dmax;
+    const double* r1 = g.y1 + (size_t)atom * 4 * dmax;
     for (int q = tid; q < 4 * d; q += EIG_NT) {
       const int c = q / d, m = q % d;
-      R1[q] = (m == c) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
-    uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
-    int* seg = g.seg + (size_t)atom * g.seg_max;
-    int64_t nrot = 0;
-    int nseg = 0;
-
-    // ---- 1. band -> tridiagonal, pipelined chases (wave 0, one lane per chase).
-    // Only wave 0 works here, so the time steps are ordered by wave-scope
-    // fences: the LDS operations of one wave complete in issue order, and a
-    // workgroup barrier would also wait for the rotation-log stores to reach
-    // memory on every step.
-    if (wave == 0) {
-    for (int bc = BW; bc >= 2; --bc) {
-      const int I = (2 * bc + 3) / bc;              // ceil((bc + 4) / bc): 2, 3, 3
-      const int nchase = d - bc;
-      if (nchase <= 0) continue;
-      const int last = nchase - 1;
-      const int t_end = last * I + (d - 1 - last - bc) / bc + 1;
-      for (int tau = 0; tau < t_end; ++tau) {
-        {
-          const int64_t step_start = nrot;
-          int jtop = tau / I;
-          if (jtop > last) jtop = last;
-          for (int jb = jtop; jb >= 0; jb -= 64) {
-            const int j = jb - lane;
-            bool act = false;
-            int p = 0, m0 = 0;
-            if (j >= 0) {
-              const int st = tau - j * I;
-              p = j + bc - 1 + st * bc;
-              act = (p + 1 <= d - 1);
-              m0 = (st == 0) ? p + 1 - bc : p - bc;
-            }
-            const bool batch_done = __ballot(act) == 0ull;
-            double x = 0.0, y = 0.0;
-            if (act) {
-              x = Lb[(size_t)m0 * LB + (p - m0)];
-              y = Lb[(size_t)m0 * LB + (p + 1 - m0)];
-              act = (y != 0.0);
-            }
-            double c = 1.0, s = 0.0;
-            if (act) {
-              double r;
-              givens(x, y, c, s, r);
-              const int q = p + 1;
-              // gather every entry of the rotation first (loads before stores)
-              const int mlo = (p - bc > 0 ? p - bc : 0);
-              const int mr = (p + 1 + bc < d - 1) ? p + 1 + bc : d - 1;
-              double lu[BW], lv[BW], ru[BW], rv[BW], r1u[4], r1v[4];
-#pragma unroll
-              for (int u = 0; u < BW; ++u) {
-                const int m = mlo + u;
-                lu[u] = (m < p) ? Lb[(size_t)m * LB + (p - m)] : 0.0;
-                lv[u] = (m < p) ? Lb[(size_t)m * LB + (q - m)] : 0.0;
-                const int mm = p + 2 + u;
-                ru[u] = (mm <= mr) ? Lb[(size_t)p * LB + (mm - p)] : 0.0;
-                rv[u] = (mm <= mr) ? Lb[(size_t)q * LB + (mm - q)] : 0.0;
-              }
-              const double da = Lb[(size_t)p * LB], db = Lb[(size_t)p * LB + 1], de = Lb[(size_t)q * LB];
-#pragma unroll
-              for (int row = 0; row < 4; ++row) {
-                r1u[row] = R1[(size_t)row * d + p];
-                r1v[row] = R1[(size_t)row * d + q];
-              }
-#pragma unroll
-              for (int u = 0; u < BW; ++u) {
-                const int m = mlo + u;
-                if (m < p) {
-                  if (m == m0) {
-                    Lb[(size_t)m * LB + (p - m)] = r;
-                    Lb[(size_t)m * LB + (q - m)] = 0.0;
-                  } else {
-                    Lb[(size_t)m * LB + (p - m)] = c * lu[u] + s * lv[u];
-                    Lb[(size_t)m * LB + (q - m)] = -s * lu[u] + c * lv[u];
-                  }
-                }
-                const int mm = p + 2 + u;
-                if (mm <= mr) {
-                  Lb[(size_t)p * LB + (mm - p)] = c * ru[u] + s * rv[u];
-                  Lb[(size_t)q * LB + (mm - q)] = -s * ru[u] + c * rv[u];
-                }
-              }
-              const double cc = c * c, ss = s * s, cs = c * s;
-              Lb[(size_t)p * LB] = cc * da + 2.0 * cs * db + ss * de;
-              Lb[(size_t)q * LB] = ss * da - 2.0 * cs * db + cc * de;
-              Lb[(size_t)p * LB + 1] = cs * (de - da) + (cc - ss) * db;
-#pragma unroll
-              for (int row = 0; row < 4; ++row) {
-                R1[(size_t)row * d + p] = c * r1u[row] + s * r1v[row];
-                R1[(size_t)row * d + q] = -s * r1u[row] + c * r1v[row];
-              }
-            }
-            const uint64_t mask = __ballot(act);
-            const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-            const int64_t slot = nrot + __popcll(mask & below);
-            if (act && slot < g.rot_max) { lcs[2 * slot] = c; lcs[2 * slot + 1] = s; lp[slot] = (uint16_t)p; }
-            nrot += __popcll(mask);
-            if (batch_done) break;
-          }
-          if (nrot > step_start) {                  // one segment per non-empty time step
-            if (lane == 0 && nseg < g.seg_max) seg[nseg] = (int)step_start;
-            ++nseg;
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-    }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      g.rot_n[atom] = (int)(nrot < g.rot_max ? nrot : g.rot_max);
-      g.seg_n[2 * atom] = nseg < g.seg_max ? nseg : g.seg_max;
-      g.seg_n[2 * atom + 1] = nseg < g.seg_max ? nseg : g.seg_max;
-      if (nseg > g.seg_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_SEG_OVERFLOW);
-      if (nrot > g.rot_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
+      R1[q] = r1[(size_t)c * dmax + m];
     }
 
     // ---- 2. tridiagonal S, Gershgorin interval, eigenvalues by bisection
     double glo = 1e300, ghi = -1e300, e2m = 0.0;
     for (int k = tid; k < d; k += EIG_NT) {
-      const double Dk = Lb[(size_t)k * LB];
-      const double Ek = (k + 1 < d) ? Lb[(size_t)k * LB + 1] : 0.0;
-      const double Em = (k > 0) ? Lb[(size_t)(k - 1) * LB + 1] : 0.0;
+      const double Dk = tri[k];
+      const double Ek = (k + 1 < d) ? tri[dmax + k] : 0.0;
+      const double Em = (k > 0) ? tri[dmax + k - 1] : 0.0;
       Dg[k] = Dk; Eg[k] = Ek; E2[k] = Ek * Ek;
       const double rad = fabs(Ek) + fabs(Em);
       glo = fmin(glo, Dk - rad); ghi = fmax(ghi, Dk + rad); e2m = fmax(e2m, Ek * Ek);
@@ -477,8 +499,11 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
 
 size_t eig_lds_bytes(int r_max) {
   const size_t dmax = 4 * (size_t)r_max;
-  return (dmax * LB + 4 * dmax + 4 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) +
-         dmax * sizeof(int) + 64;
+  return (4 * dmax + 4 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) + dmax * sizeof(int) + 64;
+}
+size_t band_lds_bytes(int r_max) {
+  const size_t dmax = 4 * (size_t)r_max;
+  return ((dmax + 1) * LB + 4 * dmax) * sizeof(double) + 64;
 }
 size_t rho_lds_bytes(int r_max) { return (size_t)2 * 4 * r_max * 4 * sizeof(double); }
 int eig_threads() { return EIG_NT; }
@@ -487,11 +512,15 @@ hipError_t eig_set_lds(int r_max) {
   hipError_t e = hipFuncSetAttribute((const void*)k_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)eig_lds_bytes(r_max));
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_band, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)band_lds_bytes(r_max));
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_rho, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)rho_lds_bytes(r_max));
 }
 
 void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
+  hipLaunchKernelGGL(k_band, dim3(a.n_atoms), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
   hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(EIG_NT), eig_lds_bytes(a.r_max), st, a);
 }
 void launch_rho(const RhoArgs& a, hipStream_t st) {

@@ -130,6 +130,7 @@ struct EigArgs {
   int* counter;                        // persistent-kernel atom queue (zeroed before launch)
   double* scratch;                     // [WG][4 r_max][4][threads]: LU factors of inverse iteration
   double* evec;                        // [N][4 r_max][4 r_max]: eigenvectors of the tridiagonal, [k][t]
+  double* tri;                         // [N][2][4 r_max]: diagonal and off-diagonal of the tridiagonal
   int64_t* stats;
 };
 struct RhoArgs {
@@ -223,6 +224,7 @@ struct tb_ctx {
   double* rot_cs; uint16_t* rot_p; int* rot_n;             // [N][ROT][2], [N][ROT], [N]
   int* seg; int* seg_n; int seg_max;                       // [N][SEG], [N][2]
   double* evec;                                            // [N][D][D]
+  double* tri;                                             // [N][2][D]
   double* eig_scratch;                                     // [WG_EIG][D][4][EIG_NT]
   int n_wg_eig;                                            // persistent workgroups of k_eig
   // mu / energies (K6/K8)
