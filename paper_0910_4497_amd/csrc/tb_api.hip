@@ -43,7 +43,7 @@ static int fail(int code, const char* fmt, ...) {
     if (_e != hipSuccess) return fail(TB_EHIP, "%s: %s", #expr, hipGetErrorString(_e));   \
   } while (0)
 
-static const int MU_ITERS = 64;
+static const int MU_ITERS = 13;   // multisection steps (5 bits each)
 
 // phase timing: returns the slot of the start event, or -1 when disabled/full
 static int prof_begin(tb_ctx* c, int phase) {
@@ -180,7 +180,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(tri, N * 2 * dmax);
   ALLOC(eig_scratch, (int64_t)c->n_wg_eig * dmax * 4 * eig_threads());
   ALLOC(mu_state, 16);
-  ALLOC(partial, 4096);
+  ALLOC(partial, 16384);             // [blocks][points] of the mu reductions
   ALLOC(counter, 16);
   ALLOC(xrep, 2 * N);
   ALLOC(eparts, 8);

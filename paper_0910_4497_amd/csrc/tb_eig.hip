@@ -441,16 +441,24 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     }
   }
   __syncthreads();
-  // x = U v (eigenvectors of the tridiagonal)
+  // x = U v (eigenvectors of the tridiagonal): four rows of U at a time,
+  // read along the row by the lanes (coalesced), 16 sums reduced over the wave
   const double* Ua = g.evec + (size_t)atom * dmax * dmax;
-  for (int k = lane; k < d; k += RHO_NT) {
-    const double* ur = Ua + (size_t)k * dmax;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (int m = 0; m < d; ++m) {
-      const double u = ur[m];
-      s0 += u * v[4 * m]; s1 += u * v[4 * m + 1]; s2 += u * v[4 * m + 2]; s3 += u * v[4 * m + 3];
+  for (int k0 = 0; k0 < d; k0 += 4) {
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int m = lane; m < d; m += RHO_NT) {
+      const double v0 = v[4 * m], v1 = v[4 * m + 1], v2 = v[4 * m + 2], v3 = v[4 * m + 3];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double u = Ua[(size_t)(k0 + r) * dmax + m];
+        acc[r * 4] += u * v0; acc[r * 4 + 1] += u * v1; acc[r * 4 + 2] += u * v2; acc[r * 4 + 3] += u * v3;
+      }
     }
-    x[4 * k] = s0; x[4 * k + 1] = s1; x[4 * k + 2] = s2; x[4 * k + 3] = s3;
+    int which;
+    const double sum = wave_sum16(acc, lane, which);
+    if ((lane & 3) == 0) x[4 * k0 + which] = sum;
   }
   __syncthreads();
   // c = Z x: band steps in reverse; the rotations of one step commute

@@ -56,49 +56,6 @@ __device__ __forceinline__ void block_sum(double (&v)[M], double* red, double* o
   lds_barrier();
 }
 
-// Butterfly reduce-scatter of 16 values over a wave; lanes with (lane & 3) == 0
-// end with the full sum of value index 8*b5 + 4*b4 + 2*b3 + b2 (bits of lane).
-__device__ __forceinline__ double wave_sum16(double (&a)[16], int lane, int& which) {
-  double b8[8], b4[4], b2[2], b1;
-  {
-    const bool h = lane & 32;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const double send = h ? a[q] : a[q + 8];
-      const double keep = h ? a[q + 8] : a[q];
-      b8[q] = keep + __shfl_xor(send, 32, 64);
-    }
-  }
-  {
-    const bool h = lane & 16;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double send = h ? b8[q] : b8[q + 4];
-      const double keep = h ? b8[q + 4] : b8[q];
-      b4[q] = keep + __shfl_xor(send, 16, 64);
-    }
-  }
-  {
-    const bool h = lane & 8;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const double send = h ? b4[q] : b4[q + 2];
-      const double keep = h ? b4[q + 2] : b4[q];
-      b2[q] = keep + __shfl_xor(send, 8, 64);
-    }
-  }
-  {
-    const bool h = lane & 4;
-    const double send = h ? b2[0] : b2[1];
-    const double keep = h ? b2[1] : b2[0];
-    b1 = keep + __shfl_xor(send, 4, 64);
-  }
-  b1 += __shfl_xor(b1, 2, 64);
-  b1 += __shfl_xor(b1, 1, 64);
-  which = 8 * ((lane >> 5) & 1) + 4 * ((lane >> 4) & 1) + 2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);
-  return b1;
-}
-
 template <typename VT>
 __device__ __forceinline__ void load4(const VT* p, double (&v)[4]) {
   typedef typename Vec4<VT>::T V4;

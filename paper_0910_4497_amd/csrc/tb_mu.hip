@@ -3,12 +3,11 @@
 //
 //   N(mu) = sum_i sum_m f(lambda_m^i) w_m^i,  f(e) = 2 / (1 + exp((e - mu)/kT)),
 // solved for N(mu) = N_e. N is increasing in mu; every launch of k_mu_iter
-// evaluates N and dN/dmu at the current trial point over all Ritz pairs,
-// tightens the bracket [lo, hi] and proposes the next point (Newton step
-// when it stays inside the bracket and at least halves the previous step,
-// else bisection). A fixed number of launches is enqueued; once the bracket
-// has collapsed to rounding level, later launches return at once, so the
-// sequence is capturable in a graph. Reductions are two-level and in a
+// evaluates N at 31 points that split the bracket [lo, hi] into 32 equal
+// parts and keeps the part where N crosses N_e (multisection: 5 bits per
+// launch, 13 launches take a 300 eV bracket to rounding level). A fixed number
+// of launches is enqueued; once the bracket has collapsed to rounding level,
+// later launches return at once, so the sequence is capturable in a graph. Reductions are two-level and in a
 // fixed order (per-block partials summed by the last block to finish), so
 // the result is bitwise reproducible run to run.
 #include <float.h>
@@ -19,43 +18,63 @@ namespace tbk {
 
 constexpr int MU_NT = 256;
 constexpr int MU_NB = 512;         // blocks of the reduction kernels
+constexpr int MU_P = 31;           // points per multisection step
 
 enum { MS_LO = 0, MS_HI = 1, MS_MU = 2, MS_DONE = 3, MS_N = 4, MS_STEP = 5, MS_IT = 6 };
 
 
-__device__ __forceinline__ void fermi_and_deriv(double lam, double mu, double kT, double& f, double& df) {
-  const double z = (lam - mu) / kT;
-  const double e = exp(-fabs(z));
-  f = (z > 0.0) ? 2.0 * e / (1.0 + e) : 2.0 / (1.0 + e);
-  df = f * (1.0 - 0.5 * f) / kT;     // d f / d mu
-}
-
-// Block-level sum of M values into partial[blockIdx][M]; returns true in the
-// last block to finish (after which partials of every block are visible).
-template <int M>
-__device__ bool reduce_partials(double (&v)[M], double* partial, unsigned int* counter) {
+// Sum M values over the grid. Every block stores its M block sums (fixed
+// order: waves, then the waves' results) in partial[block][M]; the last block
+// to finish sums the blocks in a fixed tree (thread t takes blocks t, t +
+// MU_NT, ..., then the wave and workgroup reductions) and returns true with
+// the totals in tot[0..M-1] (shared memory of that block). OP 0 sums, OP 1
+// takes minima.
+template <int M, int OP>
+__device__ bool grid_reduce(double (&v)[M], double* partial, unsigned int* counter, double* tot) {
   __shared__ double red[MU_NT / 64][M];
   __shared__ bool last;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto comb = [](double a, double b) { return OP == 0 ? a + b : fmin(a, b); };
+  const double ident = OP == 0 ? 0.0 : 1e300;
 #pragma unroll
-  for (int q = 0; q < M; ++q) v[q] = wave_sum(v[q]);
-  if ((tid & 63) == 0)
+  for (int q = 0; q < M; ++q)
+    for (int off = 32; off > 0; off >>= 1) v[q] = comb(v[q], __shfl_xor(v[q], off, 64));
+  if (lane == 0)
 #pragma unroll
-    for (int q = 0; q < M; ++q) red[tid >> 6][q] = v[q];
+    for (int q = 0; q < M; ++q) red[wave][q] = v[q];
   __syncthreads();
-  if (tid == 0) {
-    for (int q = 0; q < M; ++q) {
-      double s = 0.0;
-      for (int w = 0; w < MU_NT / 64; ++w) s += red[w][q];
-      partial[(size_t)blockIdx.x * M + q] = s;
-    }
-    __threadfence();
-    const unsigned int t = atomicAdd(counter, 1u);
-    last = (t == gridDim.x - 1);
+  if (tid < M) {
+    double sm = ident;
+    for (int w = 0; w < MU_NT / 64; ++w) sm = comb(sm, red[w][tid]);
+    partial[(size_t)blockIdx.x * M + tid] = sm;
     __threadfence();
   }
   __syncthreads();
-  return last;
+  if (tid == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double acc[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) acc[q] = ident;
+  for (unsigned int bk = tid; bk < gridDim.x; bk += MU_NT)
+#pragma unroll
+    for (int q = 0; q < M; ++q) acc[q] = comb(acc[q], partial[(size_t)bk * M + q]);
+#pragma unroll
+  for (int q = 0; q < M; ++q)
+    for (int off = 32; off > 0; off >>= 1) acc[q] = comb(acc[q], __shfl_xor(acc[q], off, 64));
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < M; ++q) red[wave][q] = acc[q];
+  __syncthreads();
+  if (tid < M) {
+    double sm = ident;
+    for (int w = 0; w < MU_NT / 64; ++w) sm = comb(sm, red[w][tid]);
+    tot[tid] = sm;
+  }
+  if (tid == 0) *counter = 0u;
+  __syncthreads();
+  return true;
 }
 
 __global__ void __launch_bounds__(MU_NT) k_mu_bracket(MuArgs g, double mu_fixed, int fixed) {
@@ -65,73 +84,66 @@ __global__ void __launch_bounds__(MU_NT) k_mu_bracket(MuArgs g, double mu_fixed,
     v[0] = fmin(v[0], l);
     v[1] = fmin(v[1], -l);
   }
-  __shared__ double red[MU_NT / 64][2];
-  __shared__ bool last;
-  const int tid = threadIdx.x;
-  for (int off = 32; off > 0; off >>= 1) {
-    v[0] = fmin(v[0], __shfl_xor(v[0], off, 64));
-    v[1] = fmin(v[1], __shfl_xor(v[1], off, 64));
-  }
-  if ((tid & 63) == 0) { red[tid >> 6][0] = v[0]; red[tid >> 6][1] = v[1]; }
-  __syncthreads();
-  if (tid == 0) {
-    double a = 1e300, b = 1e300;
-    for (int w = 0; w < MU_NT / 64; ++w) { a = fmin(a, red[w][0]); b = fmin(b, red[w][1]); }
-    g.partial[2 * blockIdx.x] = a;
-    g.partial[2 * blockIdx.x + 1] = b;
-    __threadfence();
-    last = (atomicAdd(g.counter, 1u) == gridDim.x - 1);
-    __threadfence();
-  }
-  __syncthreads();
-  if (last && tid == 0) {
-    double a = 1e300, b = 1e300;
-    for (unsigned int w = 0; w < gridDim.x; ++w) { a = fmin(a, g.partial[2 * w]); b = fmin(b, g.partial[2 * w + 1]); }
+  __shared__ double tot[2];
+  if (grid_reduce<2, 1>(v, g.partial, g.counter, tot) && threadIdx.x == 0) {
     double* s = g.state;
-    s[MS_LO] = a - 50.0 * g.kT;
-    s[MS_HI] = -b + 50.0 * g.kT;
+    s[MS_LO] = tot[0] - 50.0 * g.kT;
+    s[MS_HI] = -tot[1] + 50.0 * g.kT;
     s[MS_MU] = fixed ? mu_fixed : 0.5 * (s[MS_LO] + s[MS_HI]);
     s[MS_DONE] = fixed ? 1.0 : 0.0;
     s[MS_STEP] = s[MS_HI] - s[MS_LO];
     s[MS_IT] = 0.0;
-    *g.counter = 0u;
   }
 }
 
+// One multisection step: N(mu) at the MU_P interior points of [lo, hi] that
+// split it into MU_P + 1 equal parts; the bracket becomes the part where N
+// crosses N_e (MU_P + 1 = 32: five bits per launch). Sums are per block in a
+// fixed order, then per point over the blocks in a fixed order by the last
+// block, so the result is reproducible bit for bit.
 __global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g) {
   if (g.state[MS_DONE] != 0.0) return;
-  const double mu = g.state[MS_MU];
-  double v[2] = {0.0, 0.0};
+  const double lo = g.state[MS_LO], hi = g.state[MS_HI];
+  const double h = (hi - lo) / (MU_P + 1);
+  const double cut = 40.0 * g.kT;                 // f = 0 or 2 to rounding beyond this
+  double v[MU_P];
+#pragma unroll
+  for (int p = 0; p < MU_P; ++p) v[p] = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * MU_NT + threadIdx.x; q < g.n_pairs; q += (int64_t)gridDim.x * MU_NT) {
     const double w = g.wgt[q];
-    double f, df;
-    fermi_and_deriv(g.lam[q], mu, g.kT, f, df);
-    v[0] += f * w;
-    v[1] += df * w;
+    if (w == 0.0) continue;
+    const double l = g.lam[q];
+    if (l < lo - cut) {
+#pragma unroll
+      for (int p = 0; p < MU_P; ++p) v[p] += 2.0 * w;
+    } else if (l <= hi + cut) {
+#pragma unroll
+      for (int p = 0; p < MU_P; ++p) {
+        const double z = (l - (lo + (p + 1) * h)) / g.kT;
+        const double e = exp(-fabs(z));
+        const double f = (z > 0.0) ? 2.0 * e / (1.0 + e) : 2.0 / (1.0 + e);
+        v[p] += f * w;
+      }
+    }
   }
-  const bool last = reduce_partials<2>(v, g.partial, g.counter);
-  if (last && threadIdx.x == 0) {
-    double N = 0.0, dN = 0.0;
-    for (unsigned int b = 0; b < gridDim.x; ++b) { N += g.partial[2 * b]; dN += g.partial[2 * b + 1]; }
+  __shared__ double Np[MU_P];
+  if (!grid_reduce<MU_P, 0>(v, g.partial, g.counter, Np)) return;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
     double* s = g.state;
-    double lo = s[MS_LO], hi = s[MS_HI];
-    if (N < g.n_e) lo = mu; else hi = mu;
-    double next = 0.5 * (lo + hi);
-    if (dN > 0.0) {
-      const double newton = mu - (N - g.n_e) / dN;
-      if (newton > lo && newton < hi && fabs(newton - mu) < 0.5 * s[MS_STEP]) next = newton;
+    int below = 0;                               // points with N < N_e (N is increasing in mu)
+    int exact = -1;
+    for (int p = 0; p < MU_P; ++p) {
+      if (Np[p] < g.n_e) below = p + 1;
+      if (Np[p] == g.n_e && exact < 0) exact = p;
     }
-    const double step = fabs(next - mu);
-    s[MS_LO] = lo; s[MS_HI] = hi; s[MS_N] = N; s[MS_IT] += 1.0;
-    const double scale = fmax(1.0, fabs(mu));
-    if (N == g.n_e || step <= 4.0 * DBL_EPSILON * scale || hi - lo <= 4.0 * DBL_EPSILON * scale) {
-      s[MS_DONE] = 1.0;
-      if (N != g.n_e && step > 0.0) s[MS_MU] = next; else s[MS_MU] = mu;
-    } else {
-      s[MS_MU] = next;
-      s[MS_STEP] = step;
-    }
-    *g.counter = 0u;
+    double nlo = below == 0 ? lo : lo + below * h;
+    double nhi = below == MU_P ? hi : lo + (below + 1) * h;
+    if (exact >= 0) nlo = nhi = lo + (exact + 1) * h;
+    s[MS_LO] = nlo; s[MS_HI] = nhi; s[MS_IT] += 1.0;
+    s[MS_MU] = 0.5 * (nlo + nhi);
+    const double scale = fmax(1.0, fabs(s[MS_MU]));
+    if (nhi - nlo <= 4.0 * DBL_EPSILON * scale) s[MS_DONE] = 1.0;
   }
 }
 
@@ -150,17 +162,12 @@ __global__ void __launch_bounds__(MU_NT) k_mu_final(MuArgs g) {
     v[1] += l * f * w;
     v[2] += w * 2.0 * (log1p(e) + a * e / (1.0 + e));
   }
-  const bool last = reduce_partials<3>(v, g.partial, g.counter);
-  if (last && threadIdx.x == 0) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (unsigned int b = 0; b < gridDim.x; ++b) {
-      s0 += g.partial[3 * b]; s1 += g.partial[3 * b + 1]; s2 += g.partial[3 * b + 2];
-    }
-    g.eparts[0] = s1;      // E_band
-    g.eparts[1] = s2;      // S / k_B
-    g.eparts[3] = s0;      // electron count at mu
+  __shared__ double tot[3];
+  if (grid_reduce<3, 0>(v, g.partial, g.counter, tot) && threadIdx.x == 0) {
+    g.eparts[0] = tot[1];      // E_band
+    g.eparts[1] = tot[2];      // S / k_B
+    g.eparts[3] = tot[0];      // electron count at mu
     if (g.mu_out) *g.mu_out = mu;
-    *g.counter = 0u;
   }
 }
 
