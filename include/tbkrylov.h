@@ -103,9 +103,14 @@ int tb_build_local_H(tb_ctx *ctx, int64_t n_atoms, const double *pos,
 
 /* Sec. 3: for every target atom, r block steps of the block Lanczos
  * recursion (Eqs. 6-9 with 4x4 blocks A_k, B_k, seed = the atom's four
- * orbitals) with full re-orthogonalisation, the eigensolve of the projected
- * block-tridiagonal T, the global chemical potential and the density-matrix
- * blocks of Eq. (2) restricted to the Krylov space:
+ * orbitals), the eigensolve of the projected block-tridiagonal T, the global
+ * chemical potential and the density-matrix blocks of Eq. (2) restricted to
+ * the Krylov space. The basis is kept orthogonal by partial
+ * re-orthogonalisation: a running estimate of |V_j^T V_{k+1}| (the block form
+ * of Simon's recurrence) triggers a full Gram-Schmidt pass against all
+ * earlier blocks, for that block and the next, whenever it exceeds 1e-12
+ * (TB_FP64) or 1e-4 (TB_FP32), so the result is the projection on K_r to
+ * that level:
  *     rho[:, i] = Q Y f(Lambda) Y[0:4, :]^T,  f(e) = 2 / (1 + exp((e - mu)/kT)).
  *   r           block steps (1 <= r <= r_max) unless r_per_atom is given.
  *   r_per_atom  [n_atoms] device int, nullable: per-atom r.
@@ -122,8 +127,8 @@ int tb_krylov_rho(tb_ctx *ctx, int r, const int *r_per_atom, double kT,
                   double *mu_out, double *rho_out);
 
 /* Pair list of rho_out: for target atom i, the rows row_ptr[i] ..
- * row_ptr[i+1]-1 hold j = i first, then the atoms within rm of i in
- * increasing index. nnz_pairs_host receives the count (host). row_ptr
+ * row_ptr[i+1]-1 hold j = i first, then the atoms closer than max(rm, dm)
+ * to i (the hop list) in increasing index. nnz_pairs_host receives the count (host). row_ptr
  * [n_atoms+1] and col_j [nnz] are device arrays (nullable: count only).
  * Synchronises the stream. Valid after tb_build_local_H. */
 int tb_rho_layout(tb_ctx *ctx, int64_t *nnz_pairs_host, int64_t *row_ptr,
@@ -140,12 +145,15 @@ int tb_rho_layout(tb_ctx *ctx, int64_t *nnz_pairs_host, int64_t *row_ptr,
  * Errors: TB_ESTATE, TB_EHIP. */
 int tb_energy_forces(tb_ctx *ctx, double *e_out, double *forces);
 
-/* Diagnostics (host): counters of the last calls. stats_host receives
- * up to n_stats values: [0] device error flags, [1] max cluster size,
- * [2] max hop count, [3] max local couplings per sphere, [4] total
+/* Diagnostics (host): counters since the last tb_build_local_H. stats_host
+ * receives up to n_stats values: [0] device error flags, [1] max cluster
+ * size, [2] max hop count, [3] max local couplings per sphere, [4] total
  * deflated columns, [5] atoms whose recursion stopped early (invariant
- * space), [6] max eigen-iteration count, [7] work memory bytes,
- * [8] re-orthogonalisation second passes. Synchronises the stream. */
+ * space), [6] largest eigenvalue-cluster position (0: no clusters), [7] work
+ * memory bytes, [8] re-orthogonalisation second passes, [9] block steps
+ * with a re-orthogonalisation pass, [10] basis bytes the Krylov kernel
+ * moved (blocks written, read by the recursion and by the passes).
+ * Synchronises the stream. */
 int tb_get_stats(tb_ctx *ctx, int64_t *stats_host, int n_stats);
 
 /* Per-phase timing with HIP events recorded on the context stream.

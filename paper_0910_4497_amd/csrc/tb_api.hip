@@ -143,7 +143,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   c->lz_per_cu = per_cu;
   c->n_wg_lanczos = prop.multiProcessorCount * per_cu;
   if (c->n_wg_lanczos > n_atoms_max) c->n_wg_lanczos = (int)n_atoms_max;
-  c->n_wg_eig = prop.multiProcessorCount * 4;
+  c->n_wg_eig = prop.multiProcessorCount * (eig_threads(r_max) <= 192 ? 6 : 4);
   if (c->n_wg_eig > n_atoms_max) c->n_wg_eig = (int)n_atoms_max;
 
   const int64_t N = n_atoms_max, NC = n_cluster_max;
@@ -178,7 +178,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(seg_n, 2 * N);
   ALLOC(evec, N * dmax * dmax);
   ALLOC(tri, N * 2 * dmax);
-  ALLOC(eig_scratch, (int64_t)c->n_wg_eig * dmax * 4 * eig_threads());
+  ALLOC(eig_scratch, (int64_t)c->n_wg_eig * dmax * 4 * eig_threads(r_max));
   ALLOC(mu_state, 16);
   ALLOC(partial, 16384);             // [blocks][points] of the mu reductions
   ALLOC(counter, 16);
@@ -349,7 +349,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   ra.nc_max = c->nc_max; ra.lam = c->lam; ra.y1 = c->y1; ra.rot_cs = c->rot_cs; ra.rot_p = c->rot_p;
   ra.rot_n = c->rot_n; ra.rot_max = c->rot_max;
   ra.seg = c->seg; ra.seg_n = c->seg_n; ra.seg_max = c->seg_max; ra.evec = c->evec; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
-  ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out;
+  ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out; ra.stats = c->stats;
   pk = prof_begin(c, 4);
   launch_rho(ra, st);
   prof_end(c, pk);

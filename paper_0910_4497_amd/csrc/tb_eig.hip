@@ -14,12 +14,13 @@
 //      time step. D, E of S and Z[0:4, :] go to HBM.
 //   2. k_eig: eigenvalues of S by bisection on Sturm counts, one thread per
 //      eigenvalue index (all in parallel);
-//   3. eigenvectors of S by two steps of inverse iteration (tridiagonal LU
-//      with partial pivoting, deterministic pseudo-random start); inside a
-//      cluster of eigenvalues closer than max(1e-6 ||S||, 1e-5 eV) each member
-//      is then Gram-Schmidt orthogonalised against the earlier ones, iterated
-//      once more and orthogonalised again (Peters & Wilkinson; LAPACK's stein
-//      does the same). The eigenvector matrix U of S goes to HBM;
+//   3. eigenvectors of S: for an eigenvalue with no neighbour closer than
+//      max(1e-6 ||S||, 1e-5 eV), a twisted factorisation of S - lambda I;
+//      inside such a cluster, two steps of inverse iteration (tridiagonal LU
+//      with partial pivoting, deterministic pseudo-random start), then
+//      Gram-Schmidt against the earlier members, one more step and
+//      Gram-Schmidt again (Peters & Wilkinson; LAPACK's stein does the same).
+//      The eigenvector matrix U of S goes to HBM;
 //   4. Y[0:4, :] = Z[0:4, :] U, weights w_m = ||Y[0:4, m]||^2, Ritz values.
 //
 // k_rho (after the chemical potential is known): x = U (f(Lambda) Y[0:4,:]^T),
@@ -40,6 +41,9 @@ namespace tbk {
 constexpr int EIG_NT = 256;
 constexpr int BAND_NT = 64;
 constexpr int RHO_NT = 64;
+constexpr int RHO_SEGW = 256;      // segment-table window of k_rho
+constexpr int RHO_ROTW = 512;      // rotation-log window of k_rho (>= rotations of any one segment)
+constexpr int XS = 5;              // row stride (doubles) of the 4-column vectors in k_rho's LDS
 constexpr int BW = 4;              // half-bandwidth of T
 constexpr int LB = BW + 2;         // stored lower diagonals incl. the bulge
 
@@ -94,10 +98,10 @@ __device__ __forceinline__ double start_val(int t, int k) {
 // (bcol == nullptr) or from the column bcol (stride ld). x is written to xcol
 // (stride ld; may alias bcol). The right-hand side is scaled by the pivot
 // floor so that a near-singular last pivot gives |x| of order one rather than
-// 1/eps. Scratch: 4 values per row at scr[(k * 4 + f) * EIG_NT] (coalesced
+// 1/eps. Scratch: 4 values per row at scr[(k * 4 + f) * ns] (coalesced
 // over the workgroup). Returns ||x||^2.
 __device__ double inv_solve(const double* D, const double* E, int d, double lam, double small, int t,
-                            const double* bcol, double* xcol, size_t ld, double* scr) {
+                            const double* bcol, double* xcol, size_t ld, double* scr, int ns) {
   double cd = D[0] - lam;
   double cu = d > 1 ? E[0] : 0.0;
   double cb = small * (bcol ? bcol[0] : start_val(t, 0));
@@ -106,31 +110,80 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
     const double nd = D[k + 1] - lam;
     const double nu = (k + 2 < d) ? E[k + 1] : 0.0;
     const double nb = small * (bcol ? bcol[(size_t)(k + 1) * ld] : start_val(t, k + 1));
-    double* sk = scr + (size_t)k * 4 * EIG_NT;
+    double* sk = scr + (size_t)k * 4 * ns;
     if (fabs(cd) >= fabs(sub)) {
       const double piv = (cd != 0.0) ? cd : small;
       const double l = sub / piv;
-      sk[0] = piv; sk[EIG_NT] = cu; sk[2 * EIG_NT] = 0.0; sk[3 * EIG_NT] = cb;
+      sk[0] = piv; sk[ns] = cu; sk[2 * ns] = 0.0; sk[3 * ns] = cb;
       cd = nd - l * cu; cu = nu; cb = nb - l * cb;
     } else {
       const double l = cd / sub;
-      sk[0] = sub; sk[EIG_NT] = nd; sk[2 * EIG_NT] = nu; sk[3 * EIG_NT] = nb;
+      sk[0] = sub; sk[ns] = nd; sk[2 * ns] = nu; sk[3 * ns] = nb;
       cd = cu - l * nd; cu = -l * nu; cb = cb - l * nb;
     }
   }
-  double* sl = scr + (size_t)(d - 1) * 4 * EIG_NT;
-  sl[0] = cd; sl[EIG_NT] = 0.0; sl[2 * EIG_NT] = 0.0; sl[3 * EIG_NT] = cb;
+  double* sl = scr + (size_t)(d - 1) * 4 * ns;
+  sl[0] = cd; sl[ns] = 0.0; sl[2 * ns] = 0.0; sl[3 * ns] = cb;
   double x1 = 0.0, x2 = 0.0, nrm = 0.0;
   for (int k = d - 1; k >= 0; --k) {
-    const double* sk = scr + (size_t)k * 4 * EIG_NT;
+    const double* sk = scr + (size_t)k * 4 * ns;
     double piv = sk[0];
     if (fabs(piv) < small) piv = (piv < 0.0) ? -small : small;
-    const double x = (sk[3 * EIG_NT] - sk[EIG_NT] * x1 - sk[2 * EIG_NT] * x2) / piv;
+    const double x = (sk[3 * ns] - sk[ns] * x1 - sk[2 * ns] * x2) / piv;
     xcol[(size_t)k * ld] = x;
     nrm += x * x;
     x2 = x1; x1 = x;
   }
   return nrm;
+}
+
+// Eigenvector of the tridiagonal (D, E; E2 = E^2) for an eigenvalue lam that
+// is not in a cluster, by a twisted factorisation of S - lam I (Godunov;
+// Fernando; Parlett & Dhillon): forward pivots d+_k of L D L^T, backward
+// pivots d-_k of U D U^T, the twist index r where
+// |gamma_r| = |d+_r + d-_r - (D_r - lam)| is smallest, then z_r = 1 and
+// z_k = -E_k z_{k+1} / d+_k (k < r), z_k = -E_{k-1} z_{k-1} / d-_k (k > r).
+// Pivots of magnitude below `small` are replaced by +-small. Scratch: 2
+// values per row at scr[(2 k + f) * ns]. The normalised vector goes to
+// xcol (stride ld).
+__device__ void twisted_vec(const double* D, const double* E, const double* E2, int d, double lam, double small,
+                            double* xcol, size_t ld, double* scr, int ns) {
+  double q = D[0] - lam;
+  if (fabs(q) < small) q = q < 0.0 ? -small : small;
+  scr[0] = q;
+  for (int k = 1; k < d; ++k) {
+    q = (D[k] - lam) - E2[k - 1] / q;
+    if (fabs(q) < small) q = q < 0.0 ? -small : small;
+    scr[(size_t)2 * k * ns] = q;
+  }
+  double m = D[d - 1] - lam;
+  if (fabs(m) < small) m = m < 0.0 ? -small : small;
+  scr[(size_t)(2 * (d - 1) + 1) * ns] = m;
+  int r = d - 1;
+  double best = fabs(q);                       // gamma_{d-1} = d+_{d-1}
+  for (int k = d - 2; k >= 0; --k) {
+    const double a = D[k] - lam;
+    m = a - E2[k] / m;
+    if (fabs(m) < small) m = m < 0.0 ? -small : small;
+    scr[(size_t)(2 * k + 1) * ns] = m;
+    const double gam = fabs(scr[(size_t)2 * k * ns] + m - a);
+    if (gam < best) { best = gam; r = k; }
+  }
+  double z = 1.0, nrm = 1.0;
+  xcol[(size_t)r * ld] = 1.0;
+  for (int k = r - 1; k >= 0; --k) {
+    z = -E[k] * z / scr[(size_t)2 * k * ns];
+    xcol[(size_t)k * ld] = z;
+    nrm += z * z;
+  }
+  z = 1.0;
+  for (int k = r + 1; k < d; ++k) {
+    z = -E[k - 1] * z / scr[(size_t)(2 * k + 1) * ns];
+    xcol[(size_t)k * ld] = z;
+    nrm += z * z;
+  }
+  const double sc = 1.0 / sqrt(nrm);
+  for (int k = 0; k < d; ++k) xcol[(size_t)k * ld] *= sc;
 }
 
 // One time step of the chases that reduce the half-bandwidth from BC to BC-1.
@@ -204,19 +257,26 @@ __device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau
   }
 }
 
+// A stage of chases. The rotations of MS consecutive time steps act on
+// pairwise disjoint planes (chase j is at plane 3 + 4 tau - 7 j for BC = 4,
+// 2 + 3 tau - 8 j for BC = 3, 1 + 2 tau - 5 j for BC = 2: within MS = 2, 3, 2
+// steps no two planes are closer than 2), so they commute and the reverse
+// replay takes them as one segment.
 template <int BC>
 __device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int lane, double* lcs, uint16_t* lp,
                                            int64_t rot_max, int64_t& nrot, int* seg, int seg_max, int& nseg) {
   constexpr int I = (2 * BC + 3) / BC;
+  constexpr int MS = BC == 3 ? 3 : 2;
   const int nchase = d - BC;
   if (nchase <= 0) return;
   const int last = nchase - 1;
   const int t_end = last * I + (d - 1 - last - BC) / BC + 1;
+  int64_t group_start = nrot;
   for (int tau = 0; tau < t_end; ++tau) {
-    const int64_t step_start = nrot;
+    if (tau % MS == 0) group_start = nrot;
     band_step<BC>(Lb, R1, d, tau, lane, lcs, lp, rot_max, nrot);
-    if (nrot > step_start) {                  // one segment per non-empty time step
-      if (lane == 0 && nseg < seg_max) seg[nseg] = (int)step_start;
+    if ((tau % MS == MS - 1 || tau == t_end - 1) && nrot > group_start) {   // one segment per group
+      if (lane == 0 && nseg < seg_max) seg[nseg] = (int)group_start;
       ++nseg;
     }
     // the LDS operations of one wave complete in issue order: a wave-scope
@@ -280,6 +340,7 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
 __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
   extern __shared__ double esm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = blockDim.x, nw = nt / 64;        // threads: 64 ceil(4 r_max / 64), at most EIG_NT
   const int dmax = 4 * g.r_max;
   double* R1 = esm;                        // [4][d] first rows of Z
   double* Dg = R1 + (size_t)4 * dmax;      // [dmax] diagonal of S
@@ -290,7 +351,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
   int* pos_s = (int*)(red + 4 * (EIG_NT / 64));   // [dmax] position inside a cluster
   __shared__ int s_atom, s_maxpos;
   __shared__ double s_lo, s_hi, s_e2max;
-  double* scr = g.scratch + (size_t)blockIdx.x * dmax * 4 * EIG_NT + tid;
+  double* scr = g.scratch + (size_t)blockIdx.x * dmax * 4 * nt + tid;
 
   for (;;) {
     if (tid == 0) s_atom = atomicAdd(g.counter, 1);
@@ -301,14 +362,14 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     const int d = 4 * K;
     const double* tri = g.tri + (size_t)atom * 2 * dmax;
     const double* r1 = g.y1 + (size_t)atom * 4 * dmax;
-    for (int q = tid; q < 4 * d; q += EIG_NT) {
+    for (int q = tid; q < 4 * d; q += nt) {
       const int c = q / d, m = q % d;
       R1[q] = r1[(size_t)c * dmax + m];
     }
 
     // ---- 2. tridiagonal S, Gershgorin interval, eigenvalues by bisection
     double glo = 1e300, ghi = -1e300, e2m = 0.0;
-    for (int k = tid; k < d; k += EIG_NT) {
+    for (int k = tid; k < d; k += nt) {
       const double Dk = tri[k];
       const double Ek = (k + 1 < d) ? tri[dmax + k] : 0.0;
       const double Em = (k > 0) ? tri[dmax + k - 1] : 0.0;
@@ -325,7 +386,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     __syncthreads();
     if (tid == 0) {
       double a = 1e300, b = -1e300, e = 0.0;
-      for (int w = 0; w < EIG_NT / 64; ++w) { a = fmin(a, red[w * 4]); b = fmax(b, red[w * 4 + 1]); e = fmax(e, red[w * 4 + 2]); }
+      for (int w = 0; w < nw; ++w) { a = fmin(a, red[w * 4]); b = fmax(b, red[w * 4 + 1]); e = fmax(e, red[w * 4 + 2]); }
       const double pad = 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + 1e-300;
       s_lo = a - pad; s_hi = b + pad; s_e2max = e;
     }
@@ -333,7 +394,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     const double lo0 = s_lo, hi0 = s_hi;
     const double anorm = fmax(fabs(lo0), fabs(hi0));
     const double pivmin = DBL_MIN * fmax(1.0, s_e2max);
-    for (int t = tid; t < d; t += EIG_NT) {
+    for (int t = tid; t < d; t += nt) {
       double l = lo0, h = hi0;
       for (int it = 0; it < 128; ++it) {
         const double m = 0.5 * (l + h);
@@ -347,7 +408,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     const double ctol = fmax(1e-6 * anorm, 1e-5);
     const double small = DBL_EPSILON * anorm + 1e-300;
     int mp = 0;
-    for (int t = tid; t < d; t += EIG_NT) {
+    for (int t = tid; t < d; t += nt) {
       int p = 0;
       while (t - p - 1 >= 0 && lam_s[t - p] - lam_s[t - p - 1] < ctol) ++p;
       pos_s[t] = p;
@@ -361,15 +422,21 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     const int maxpos = s_maxpos;
     double* Ua = g.evec + (size_t)atom * dmax * dmax;       // U[k][t], row stride dmax
     for (int round = 0; round <= maxpos; ++round) {
-      for (int t = tid; t < d; t += EIG_NT) {
+      for (int t = tid; t < d; t += nt) {
         if (pos_s[t] != round) continue;
         double* xc = Ua + t;
-        // two steps of inverse iteration: the second one squares the
-        // contamination left by a start vector with a small target component
-        double nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, nullptr, xc, dmax, scr);
+        if (round == 0 && (t + 1 >= d || pos_s[t + 1] == 0)) {
+          // not in a cluster: twisted factorisation
+          twisted_vec(Dg, Eg, E2, d, lam_s[t], small, xc, dmax, scr, nt);
+          continue;
+        }
+        // cluster members: two steps of inverse iteration (the second one
+        // squares the contamination left by a start vector with a small
+        // target component), then Gram-Schmidt against the earlier members
+        double nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, nullptr, xc, dmax, scr, nt);
         double sc = 1.0 / sqrt(nrm);
         for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
-        nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, xc, xc, dmax, scr);
+        nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, xc, xc, dmax, scr, nt);
         sc = 1.0 / sqrt(nrm);
         for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
         if (round > 0) {
@@ -385,7 +452,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
             sc = 1.0 / sqrt(nrm);
             for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
             if (rep == 0) {
-              nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, xc, xc, dmax, scr);
+              nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, xc, xc, dmax, scr, nt);
               sc = 1.0 / sqrt(nrm);
               for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
             }
@@ -398,7 +465,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     double* lam = g.lam + (size_t)atom * dmax;
     double* wgt = g.wgt + (size_t)atom * dmax;
     double* y1 = g.y1 + (size_t)atom * 4 * dmax;
-    for (int t = tid; t < dmax; t += EIG_NT) {
+    for (int t = tid; t < dmax; t += nt) {
       if (t < d) {
         const double* xc = Ua + t;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -414,7 +481,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
         y1[t] = 0.0; y1[dmax + t] = 0.0; y1[2 * dmax + t] = 0.0; y1[3 * dmax + t] = 0.0;
       }
     }
-    if (tid == 0) atomicMax((unsigned long long*)&g.stats[ST_MAX_EIG_ITERS], (unsigned long long)maxpos);
+    if (tid == 0) atomicMax((unsigned long long*)&g.stats[ST_MAX_CLUSTER_POS], (unsigned long long)maxpos);
     __syncthreads();
   }
 }
@@ -426,7 +493,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   const int atom = blockIdx.x;
   const int dmax = 4 * g.r_max;
   double* v = rsm;                       // [dmax][4]: f(Lambda) Y[0:4,:]^T
-  double* x = rsm + (size_t)dmax * 4;    // [dmax][4]
+  double* x = rsm + (size_t)dmax * 4;    // [dmax][XS]: rows padded against LDS bank conflicts
   const double mu = g.mu_state[2];
   const int d = 4 * g.kused[atom];
   {
@@ -458,50 +525,97 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     }
     int which;
     const double sum = wave_sum16(acc, lane, which);
-    if ((lane & 3) == 0) x[4 * k0 + which] = sum;
+    if ((lane & 3) == 0) x[XS * (k0 + (which >> 2)) + (which & 3)] = sum;
   }
   __syncthreads();
-  // c = Z x: band steps in reverse; the rotations of one step commute
+  // c = Z x: band steps in reverse; the rotations of one step commute. The
+  // segment table and the rotation log are staged through LDS in windows
+  // (coalesced loads), and the steps are ordered by wave-scope fences.
   const double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
   const uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
   const int* seg = g.seg + (size_t)atom * g.seg_max;
   const int nrot = g.rot_n[atom];
   const int nb = g.seg_n[2 * atom];
-  for (int k = nb - 1; k >= 0; --k) {
-    const int st = seg[k], en = (k + 1 < nb) ? seg[k + 1] : nrot;
-    for (int e = st + lane; e < en; e += RHO_NT) {
-      const double c = lcs[2 * e], s = lcs[2 * e + 1];
-      const int p = lp[e];
-      double* xp = x + 4 * p;
-      const double a0 = xp[0], a1 = xp[1], a2 = xp[2], a3 = xp[3];
-      const double b0 = xp[4], b1 = xp[5], b2 = xp[6], b3 = xp[7];
-      xp[0] = c * a0 - s * b0; xp[1] = c * a1 - s * b1; xp[2] = c * a2 - s * b2; xp[3] = c * a3 - s * b3;
-      xp[4] = s * a0 + c * b0; xp[5] = s * a1 + c * b1; xp[6] = s * a2 + c * b2; xp[7] = s * a3 + c * b3;
+  int* s_seg = (int*)(x + (size_t)dmax * XS);                // [RHO_SEGW]
+  double* s_cs = (double*)(s_seg + RHO_SEGW);                // [RHO_ROTW][2]
+  uint16_t* s_p = (uint16_t*)(s_cs + 2 * RHO_ROTW);          // [RHO_ROTW]
+  int k = nb - 1;
+  while (k >= 0) {
+    // segment starts seg[k0 .. k]
+    const int k0 = k - RHO_SEGW + 1 > 0 ? k - RHO_SEGW + 1 : 0;
+    for (int q = k0 + lane; q <= k; q += RHO_NT) s_seg[q - k0] = seg[q];
+    const int en = (k + 1 < nb) ? seg[k + 1] : nrot;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the window: segments kw .. k whose rotations fit in RHO_ROTW (at least one)
+    int kw = k;
+    for (int base = k; base >= k0; base -= RHO_NT) {
+      const int q = base - lane;
+      const bool fits = q >= k0 && en - s_seg[q - k0] <= RHO_ROTW;
+      const uint64_t m = __ballot(fits);
+      // lanes are ordered by decreasing q; the fitting ones form a prefix
+      const int nfit = __popcll(m);
+      if (nfit > 0) kw = base - nfit + 1;
+      if (nfit < RHO_NT) break;
     }
-    __syncthreads();
+    const int w0 = s_seg[kw - k0];
+    if (en - w0 > RHO_ROTW) {         // one segment with more rotations than the window: not
+      if (lane == 0)                  // reached for d <= 1024 (at most 341 rotations per segment)
+        atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
+      break;
+    }
+    for (int e = w0 + lane; e < en; e += RHO_NT) {
+      const double2 cs = *(const double2*)(lcs + 2 * (size_t)e);
+      s_cs[2 * (e - w0)] = cs.x;
+      s_cs[2 * (e - w0) + 1] = cs.y;
+      s_p[e - w0] = lp[e];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int kk = k; kk >= kw; --kk) {
+      const int st = s_seg[kk - k0] - w0;
+      const int se = (kk == k ? en : s_seg[kk + 1 - k0]) - w0;
+      for (int e = st + lane; e < se; e += RHO_NT) {
+        const double c = s_cs[2 * e], s = s_cs[2 * e + 1];
+        const int p = s_p[e];
+        double* xp = x + XS * p;
+        double* xq = xp + XS;
+        const double a0 = xp[0], a1 = xp[1], a2 = xp[2], a3 = xp[3];
+        const double b0 = xq[0], b1 = xq[1], b2 = xq[2], b3 = xq[3];
+        xp[0] = c * a0 - s * b0; xp[1] = c * a1 - s * b1; xp[2] = c * a2 - s * b2; xp[3] = c * a3 - s * b3;
+        xq[0] = s * a0 + c * b0; xq[1] = s * a1 + c * b1; xq[2] = s * a2 + c * b2; xq[3] = s * a3 + c * b3;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    k = kw - 1;
   }
-  // rho_{J,i}[4 js + a][col] = sum_m V_J[4 js + a][m] x[m][col]
+  // rho_{J,i}[4 js + a][col] = sum_m V_J[4 js + a][m] x[m][col]: four rows of
+  // V_J at a time, read along the row by the lanes, reduced over the wave
   const int nJ = 1 + g.hop_n[atom];
   const int64_t p0 = g.row_ptr[atom];
   const int vld = 4 * g.r_max;
-  for (int q = lane; q < 4 * nJ; q += RHO_NT) {
-    const size_t row = (size_t)atom * (4 * JMAX) + q;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (g.vj_fp32) {
-      const float* vr = (const float*)g.vj + row * vld;
-      for (int m = 0; m < d; ++m) {
-        const double vv = vr[m];
-        s0 += vv * x[4 * m]; s1 += vv * x[4 * m + 1]; s2 += vv * x[4 * m + 2]; s3 += vv * x[4 * m + 3];
-      }
-    } else {
-      const double* vr = (const double*)g.vj + row * vld;
-      for (int m = 0; m < d; ++m) {
-        const double vv = vr[m];
-        s0 += vv * x[4 * m]; s1 += vv * x[4 * m + 1]; s2 += vv * x[4 * m + 2]; s3 += vv * x[4 * m + 3];
+  for (int q0 = 0; q0 < 4 * nJ; q0 += 4) {
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    const size_t row0 = (size_t)atom * (4 * JMAX) + q0;
+    for (int m = lane; m < d; m += RHO_NT) {
+      const double x0 = x[XS * m], x1 = x[XS * m + 1], x2 = x[XS * m + 2], x3 = x[XS * m + 3];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double vv = g.vj_fp32 ? (double)((const float*)g.vj)[(row0 + r) * vld + m]
+                                    : ((const double*)g.vj)[(row0 + r) * vld + m];
+        acc[r * 4] += vv * x0; acc[r * 4 + 1] += vv * x1; acc[r * 4 + 2] += vv * x2; acc[r * 4 + 3] += vv * x3;
       }
     }
-    double* out = g.rho + (size_t)(p0 + (q >> 2)) * 16 + (q & 3) * 4;
-    out[0] = s0; out[1] = s1; out[2] = s2; out[3] = s3;
+    int which;
+    const double sum = wave_sum16(acc, lane, which);
+    // rows q0 .. q0+3 are the four orbital rows of row atom q0 / 4
+    if ((lane & 3) == 0) g.rho[(size_t)(p0 + (q0 >> 2)) * 16 + which] = sum;
   }
 }
 
@@ -513,8 +627,14 @@ size_t band_lds_bytes(int r_max) {
   const size_t dmax = 4 * (size_t)r_max;
   return ((dmax + 1) * LB + 4 * dmax) * sizeof(double) + 64;
 }
-size_t rho_lds_bytes(int r_max) { return (size_t)2 * 4 * r_max * 4 * sizeof(double); }
-int eig_threads() { return EIG_NT; }
+size_t rho_lds_bytes(int r_max) {
+  return (size_t)4 * r_max * (4 + XS) * sizeof(double) + RHO_SEGW * sizeof(int) + RHO_ROTW * (2 * sizeof(double) + 2) + 64;
+}
+// Threads of a k_eig workgroup: one per eigenvalue of the largest T.
+int eig_threads(int r_max) {
+  const int t = 64 * ((4 * r_max + 63) / 64);
+  return t < EIG_NT ? t : EIG_NT;
+}
 
 hipError_t eig_set_lds(int r_max) {
   hipError_t e = hipFuncSetAttribute((const void*)k_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -529,7 +649,7 @@ hipError_t eig_set_lds(int r_max) {
 
 void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
   hipLaunchKernelGGL(k_band, dim3(a.n_atoms), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
-  hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(EIG_NT), eig_lds_bytes(a.r_max), st, a);
+  hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
 }
 void launch_rho(const RhoArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_rho, dim3(a.n_atoms), dim3(RHO_NT), rho_lds_bytes(a.r_max), st, a);

@@ -22,7 +22,7 @@ constexpr int N_PHASES = 6;
 // Device-side error / statistics words (int64 each).
 enum StatSlot {
   ST_FLAGS = 0, ST_MAX_CLUSTER = 1, ST_MAX_HOP = 2, ST_MAX_COUPLINGS = 3,
-  ST_DEFLATED = 4, ST_EARLY_STOP = 5, ST_MAX_EIG_ITERS = 6, ST_MEMORY = 7,
+  ST_DEFLATED = 4, ST_EARLY_STOP = 5, ST_MAX_CLUSTER_POS = 6, ST_MEMORY = 7,
   ST_REORTH2 = 8, ST_REORTH_STEPS = 9, ST_BASIS_BYTES = 10, ST_NSTATS = 16
 };
 enum FlagBits {
@@ -187,12 +187,13 @@ struct RhoArgs {
   const int64_t* row_ptr;
   const double* mu_state; double kT;
   double* rho;
+  int64_t* stats;
 };
 size_t eig_lds_bytes(int r_max);
 size_t rho_lds_bytes(int r_max);
 hipError_t eig_set_lds(int r_max);
 void launch_eig(const EigArgs& a, int n_wg, hipStream_t st);
-int eig_threads();
+int eig_threads(int r_max);
 void launch_rho(const RhoArgs& a, hipStream_t st);
 
 struct MuArgs {

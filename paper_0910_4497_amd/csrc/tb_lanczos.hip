@@ -203,38 +203,67 @@ k_lanczos(LanczosArgs g) {
         const VT es = (VT)g.eps_s, ep = (VT)g.eps_p, vsss = (VT)g.v_sss, vsps = (VT)g.v_sps,
                  vdif = (VT)(g.v_pps - g.v_ppp), vppp = (VT)g.v_ppp;
         typedef typename Vec4<VT>::T V4;
+        // item (a, part): the four lanes of atom a take every fourth coupling
+        // and compute all four columns; a reduce-scatter over the four lanes
+        // leaves lane `part` with column c = part
         for (int item = tid; item < 4 * n; item += LZ_NT) {
           const int a = item >> 2, c = cq;
-          const VT* va = s_V + 16 * a + c;
-          VT w0 = es * va[0], w1 = ep * va[4], w2 = ep * va[8], w3 = ep * va[12];
+          VT w[16];                                   // [orbital][column]
+          if (c == 0) {
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+              const V4 va = *(const V4*)(s_V + 16 * a + 4 * o);
+              const VT eo = o == 0 ? es : ep;
+              w[o * 4] = eo * va.x; w[o * 4 + 1] = eo * va.y; w[o * 4 + 2] = eo * va.z; w[o * 4 + 3] = eo * va.w;
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) w[q] = (VT)0;
+          }
           const int gid = s_gid[a];
           int e1 = s_off[a + 1];
           if (e1 > g.emax) e1 = (int)g.emax;
-          for (int e0 = s_off[a]; e0 < e1; e0 += 4) {
-            unsigned int pe[4];
-            V4 hp4[4];
+#pragma unroll 2
+          for (int e = s_off[a] + c; e < e1; e += 4) {
+            const unsigned int pe = ent[e];
+            const int slot = pe >> LOCAL_BITS, b = pe & NCLUSTER_LIMIT;
+            const V4 hp4 = *(const V4*)(pairs + ((size_t)gid * ZMAX + slot) * 4);
+            const VT hx = hp4.x, hy = hp4.y, hz = hp4.z, sv = hp4.w;
+            const V4 vs4 = *(const V4*)(s_V + 16 * b), vx4 = *(const V4*)(s_V + 16 * b + 4),
+                     vy4 = *(const V4*)(s_V + 16 * b + 8), vz4 = *(const V4*)(s_V + 16 * b + 12);
+            const VT vs[4] = {vs4.x, vs4.y, vs4.z, vs4.w}, vx[4] = {vx4.x, vx4.y, vx4.z, vx4.w},
+                     vy[4] = {vy4.x, vy4.y, vy4.z, vy4.w}, vz[4] = {vz4.x, vz4.y, vz4.z, vz4.w};
+            const VT sp = sv * vppp;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) pe[u] = (e0 + u < e1) ? ent[e0 + u] : 0u;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int slot = pe[u] >> LOCAL_BITS;
-              hp4[u] = *(const V4*)(pairs + ((size_t)gid * ZMAX + slot) * 4);
+            for (int cc = 0; cc < 4; ++cc) {
+              const VT hp = hx * vx[cc] + hy * vy[cc] + hz * vz[cc];
+              w[cc] += sv * (vsss * vs[cc] + vsps * hp);
+              const VT t = sv * (vdif * hp - vsps * vs[cc]);
+              w[4 + cc] += t * hx + sp * vx[cc];
+              w[8 + cc] += t * hy + sp * vy[cc];
+              w[12 + cc] += t * hz + sp * vz[cc];
             }
+          }
+          VT w0, w1, w2, w3;
+          {
+            const bool hi = c & 2, lo = c & 1;
+            VT h[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              if (e0 + u >= e1) break;
-              const int b = pe[u] & NCLUSTER_LIMIT;
-              const VT hx = hp4[u].x, hy = hp4[u].y, hz = hp4[u].z, sv = hp4[u].w;
-              const VT* vb = s_V + 16 * b + c;
-              const VT vs = vb[0], vx = vb[4], vy = vb[8], vz = vb[12];
-              const VT hp = hx * vx + hy * vy + hz * vz;
-              w0 += sv * (vsss * vs + vsps * hp);
-              const VT t = sv * (vdif * hp - vsps * vs);
-              const VT sp = sv * vppp;
-              w1 += t * hx + sp * vx;
-              w2 += t * hy + sp * vy;
-              w3 += t * hz + sp * vz;
+            for (int o = 0; o < 4; ++o)
+#pragma unroll
+              for (int cc = 0; cc < 2; ++cc) {
+                const VT keep = hi ? w[o * 4 + 2 + cc] : w[o * 4 + cc];
+                const VT send = hi ? w[o * 4 + cc] : w[o * 4 + 2 + cc];
+                h[o * 2 + cc] = keep + __shfl_xor(send, 2, 64);
+              }
+            VT r[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+              const VT keep = lo ? h[o * 2 + 1] : h[o * 2];
+              const VT send = lo ? h[o * 2] : h[o * 2 + 1];
+              r[o] = keep + __shfl_xor(send, 1, 64);
             }
+            w0 = r[0]; w1 = r[1]; w2 = r[2]; w3 = r[3];
           }
           VT* wa = s_W + 16 * a + c;
           wa[0] = w0; wa[4] = w1; wa[8] = w2; wa[12] = w3;

@@ -21,7 +21,7 @@ PRECISIONS = {"fp64": TB_FP64, "fp32": TB_FP32}
 ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4: "TB_EMU",
           -5: "TB_EUNSUPPORTED", -6: "TB_EHIP", -7: "TB_ESTATE", -8: "TB_EDEVICE"}
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
-              "max_eig_iters", "memory_bytes", "reorth_second_pass", "reorth_steps", "basis_bytes")
+              "max_cluster_pos", "memory_bytes", "reorth_second_pass", "reorth_steps", "basis_bytes")
 EXPORTS = ("tb_create", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
            "tb_energy_forces", "tb_get_stats", "tb_profile_enable", "tb_profile_read", "tb_last_error")
 PHASES = ("lists_local", "lanczos", "eig", "mu", "rho", "forces")
