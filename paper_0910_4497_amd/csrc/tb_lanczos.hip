@@ -203,11 +203,16 @@ k_lanczos(LanczosArgs g) {
         const VT es = (VT)g.eps_s, ep = (VT)g.eps_p, vsss = (VT)g.v_sss, vsps = (VT)g.v_sps,
                  vdif = (VT)(g.v_pps - g.v_ppp), vppp = (VT)g.v_ppp;
         typedef typename Vec4<VT>::T V4;
-        // item (a, part): the four lanes of atom a take every fourth coupling
-        // and compute all four columns; a reduce-scatter over the four lanes
-        // leaves lane `part` with column c = part
+        // FP64: item (a, part) -- the four lanes of atom a take every fourth
+        // coupling and compute all four columns, then a reduce-scatter over the
+        // four lanes leaves lane `part` with column c = part (fewer dependent
+        // load rounds). FP32: item (a, c) -- one column per lane over all the
+        // couplings of atom a (fewer registers).
         for (int item = tid; item < 4 * n; item += LZ_NT) {
+          VT w0, w1, w2, w3;
           const int a = item >> 2, c = cq;
+          if constexpr (sizeof(VT) == 8) {
+
           VT w[16];                                   // [orbital][column]
           if (c == 0) {
 #pragma unroll
@@ -244,7 +249,6 @@ k_lanczos(LanczosArgs g) {
               w[12 + cc] += t * hz + sp * vz[cc];
             }
           }
-          VT w0, w1, w2, w3;
           {
             const bool hi = c & 2, lo = c & 1;
             VT h[8];
@@ -264,6 +268,40 @@ k_lanczos(LanczosArgs g) {
               r[o] = keep + __shfl_xor(send, 1, 64);
             }
             w0 = r[0]; w1 = r[1]; w2 = r[2]; w3 = r[3];
+          }
+          } else {
+
+          const VT* va = s_V + 16 * a + c;
+          w0 = es * va[0]; w1 = ep * va[4]; w2 = ep * va[8]; w3 = ep * va[12];
+          const int gid = s_gid[a];
+          int e1 = s_off[a + 1];
+          if (e1 > g.emax) e1 = (int)g.emax;
+          for (int e0 = s_off[a]; e0 < e1; e0 += 4) {
+            unsigned int pe[4];
+            V4 hp4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pe[u] = (e0 + u < e1) ? ent[e0 + u] : 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int slot = pe[u] >> LOCAL_BITS;
+              hp4[u] = *(const V4*)(pairs + ((size_t)gid * ZMAX + slot) * 4);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (e0 + u >= e1) break;
+              const int b = pe[u] & NCLUSTER_LIMIT;
+              const VT hx = hp4[u].x, hy = hp4[u].y, hz = hp4[u].z, sv = hp4[u].w;
+              const VT* vb = s_V + 16 * b + c;
+              const VT vs = vb[0], vx = vb[4], vy = vb[8], vz = vb[12];
+              const VT hp = hx * vx + hy * vy + hz * vz;
+              w0 += sv * (vsss * vs + vsps * hp);
+              const VT t = sv * (vdif * hp - vsps * vs);
+              const VT sp = sv * vppp;
+              w1 += t * hx + sp * vx;
+              w2 += t * hy + sp * vy;
+              w3 += t * hz + sp * vz;
+            }
+          }
           }
           VT* wa = s_W + 16 * a + c;
           wa[0] = w0; wa[4] = w1; wa[8] = w2; wa[12] = w3;
