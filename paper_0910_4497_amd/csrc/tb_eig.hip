@@ -84,6 +84,13 @@ __device__ __forceinline__ int sturm_count(const double* D, const double* E2, in
   return cnt;
 }
 
+// 1 / q from the hardware reciprocal refined by one Newton step (relative
+// error near the unit roundoff).
+__device__ __forceinline__ double rcp_nr(double q) {
+  const double r = __builtin_amdgcn_rcp(q);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
 // Deterministic start vector component for eigenvalue t, row k: uniform in
 // (-1, 1) from an integer hash. Signs alone (+-1) are not enough: a
 // mirror-symmetric block of S has eigenvectors that are exactly orthogonal to
@@ -152,7 +159,7 @@ __device__ void twisted_vec(const double* D, const double* E, const double* E2, 
   if (fabs(q) < small) q = q < 0.0 ? -small : small;
   scr[0] = q;
   for (int k = 1; k < d; ++k) {
-    q = (D[k] - lam) - E2[k - 1] / q;
+    q = (D[k] - lam) - E2[k - 1] * rcp_nr(q);
     if (fabs(q) < small) q = q < 0.0 ? -small : small;
     scr[(size_t)2 * k * ns] = q;
   }
@@ -163,7 +170,7 @@ __device__ void twisted_vec(const double* D, const double* E, const double* E2, 
   double best = fabs(q);                       // gamma_{d-1} = d+_{d-1}
   for (int k = d - 2; k >= 0; --k) {
     const double a = D[k] - lam;
-    m = a - E2[k] / m;
+    m = a - E2[k] * rcp_nr(m);
     if (fabs(m) < small) m = m < 0.0 ? -small : small;
     scr[(size_t)(2 * k + 1) * ns] = m;
     const double gam = fabs(scr[(size_t)2 * k * ns] + m - a);
@@ -172,13 +179,13 @@ __device__ void twisted_vec(const double* D, const double* E, const double* E2, 
   double z = 1.0, nrm = 1.0;
   xcol[(size_t)r * ld] = 1.0;
   for (int k = r - 1; k >= 0; --k) {
-    z = -E[k] * z / scr[(size_t)2 * k * ns];
+    z = -E[k] * z * rcp_nr(scr[(size_t)2 * k * ns]);
     xcol[(size_t)k * ld] = z;
     nrm += z * z;
   }
   z = 1.0;
   for (int k = r + 1; k < d; ++k) {
-    z = -E[k - 1] * z / scr[(size_t)(2 * k + 1) * ns];
+    z = -E[k - 1] * z * rcp_nr(scr[(size_t)(2 * k + 1) * ns]);
     xcol[(size_t)k * ld] = z;
     nrm += z * z;
   }
@@ -394,8 +401,20 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     const double lo0 = s_lo, hi0 = s_hi;
     const double anorm = fmax(fabs(lo0), fabs(hi0));
     const double pivmin = DBL_MIN * fmax(1.0, s_e2max);
+    // one multisection round on a grid of nt points (one Sturm count per
+    // thread), then each eigenvalue is bisected from its grid cell
+    int* cnt_s = pos_s + dmax;                     // [nt]
+    const double hg = (hi0 - lo0) / (nt + 1);
+    cnt_s[tid] = sturm_count(Dg, E2, d, lo0 + (tid + 1) * hg, pivmin);
+    __syncthreads();
     for (int t = tid; t < d; t += nt) {
-      double l = lo0, h = hi0;
+      // cells with count(left) <= t < count(right); the ends count 0 and d
+      int il = -1, ih = nt;
+      while (ih - il > 1) {
+        const int im = (il + ih) >> 1;
+        if (cnt_s[im] <= t) il = im; else ih = im;
+      }
+      double l = il < 0 ? lo0 : lo0 + (il + 1) * hg, h = ih >= nt ? hi0 : lo0 + (ih + 1) * hg;
       for (int it = 0; it < 128; ++it) {
         const double m = 0.5 * (l + h);
         if (sturm_count(Dg, E2, d, m, pivmin) <= t) l = m; else h = m;
@@ -621,7 +640,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
 
 size_t eig_lds_bytes(int r_max) {
   const size_t dmax = 4 * (size_t)r_max;
-  return (4 * dmax + 4 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) + dmax * sizeof(int) + 64;
+  return (4 * dmax + 4 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) + (dmax + EIG_NT) * sizeof(int) + 64;
 }
 size_t band_lds_bytes(int r_max) {
   const size_t dmax = 4 * (size_t)r_max;
