@@ -114,7 +114,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   if (c->rot_max > 65535 * 16) c->rot_max = 65535 * 16;
 
   // persistent Krylov workgroups: as many as fit on the device at once
-  const size_t lds = lanczos_lds_bytes(n_cluster_max, r_max, false, false, false);
+  const size_t lds = lanczos_lds_bytes(n_cluster_max, r_max, false, false, false, false);
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
   if (lds > prop.sharedMemPerBlock && lds > 160 * 1024) {
@@ -123,8 +123,8 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
                 r_max, lds);
   }
   size_t lds_attr = lds;
-  for (int v = 1; v <= 2; ++v) {
-    const size_t l = lanczos_lds_bytes(n_cluster_max, r_max, false, true, v == 2);
+  for (int v = 1; v <= 3; ++v) {
+    const size_t l = lanczos_lds_bytes(n_cluster_max, r_max, false, true, v >= 2, v == 3);
     if (l <= 160 * 1024) lds_attr = l;
   }
   hipError_t e = lanczos_set_lds(lds_attr);
@@ -313,13 +313,15 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   // (and the FP32 copies of A_j, B_j beside them) when that keeps the
   // workgroups per CU
   auto fits = [&](size_t l) { return l <= 160 * 1024 && (160 * 1024) / (l + 1024) >= (size_t)c->lz_per_cu; };
-  const size_t lds0 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, false, false);
-  const size_t lds1 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, false);
-  const size_t lds2 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, true);
-  const bool om_lds = fits(lds1), ab_lds = fits(lds2);
-  const size_t lds = ab_lds ? lds2 : (om_lds ? lds1 : lds0);
+  const size_t lds0 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, false, false, false);
+  const size_t lds1 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, false, false);
+  const size_t lds2 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, true, false);
+  const size_t lds3 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, true, true);
+  const bool om_lds = fits(lds1), ab_lds = fits(lds2), vprev_lds = fits(lds3);
+  const size_t lds = vprev_lds ? lds3 : (ab_lds ? lds2 : (om_lds ? lds1 : lds0));
   la.om_lds = om_lds ? 1 : 0;
   la.ab_lds = ab_lds ? 1 : 0;
+  la.vprev_lds = vprev_lds ? 1 : 0;
   int pk = prof_begin(c, 1);
   launch_lanczos(la, fp32, c->n_wg_lanczos < n ? c->n_wg_lanczos : n, lds, st);
   prof_end(c, pk);

@@ -156,10 +156,11 @@ struct LanczosArgs {
   double* omega;               // [WG][3][r_max][16] float orthogonality estimates (when not in LDS)
   int om_lds;                  // estimates kept in LDS
   int ab_lds;                  // FP32 copies of A_j, B_j kept in LDS (needs om_lds)
+  int vprev_lds;               // V_{k-1} kept in a second LDS block buffer
   double eta, eps_unit;        // re-orthogonalisation threshold, unit roundoff of VT
   int64_t* stats;
 };
-size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_lds);
+size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_lds, bool vprev_lds);
 void launch_lanczos(const LanczosArgs& a, bool fp32, int n_wg, size_t lds, hipStream_t st);
 hipError_t lanczos_set_lds(size_t lds);
 int lanczos_threads();

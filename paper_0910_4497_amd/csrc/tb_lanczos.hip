@@ -128,8 +128,8 @@ k_lanczos(LanczosArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ncap = g.nc_max, Rcap = 4 * ncap;
   // LDS layout
-  VT* s_V = (VT*)smem;                                      // [Rcap][4] current V_k
-  VT* s_W = s_V + (size_t)Rcap * 4;                         // [Rcap][4]
+  VT* s_Va = (VT*)smem;                                     // [Rcap][4] current V_k
+  VT* s_W = s_Va + (size_t)Rcap * 4;                        // [Rcap][4]
   double* s_C = (double*)(((uintptr_t)(s_W + (size_t)Rcap * 4) + 15) & ~(uintptr_t)15);
   // s_C: [max(r_max, LZ_NW)][16] projection coefficients / partials
   const int cslots = (g.r_max > 2 * LZ_NW ? g.r_max : 2 * LZ_NW);
@@ -140,6 +140,10 @@ k_lanczos(LanczosArgs g) {
   signed char* s_js = (signed char*)(s_gid + ncap);         // [ncap]
   float* s_om = (float*)(((uintptr_t)(s_js + ncap) + 15) & ~(uintptr_t)15);   // [3][r_max][16] if om_lds
   float* s_ab = s_om + (g.om_lds ? (size_t)3 * g.r_max * 16 : 0);                 // [r_max][32] if ab_lds
+  // second block buffer (vprev_lds): V_k and V_{k+1} alternate, so the
+  // three-term update reads V_{k-1} from LDS instead of HBM
+  VT* s_Vb = g.vprev_lds ? (VT*)(((uintptr_t)(s_ab + (g.ab_lds ? (size_t)g.r_max * 32 : 0)) + 15) & ~(uintptr_t)15)
+                         : s_Va;
   __shared__ int s_atom;
 
   double* A = s_misc;          // [16]
@@ -175,7 +179,7 @@ k_lanczos(LanczosArgs g) {
       double v[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) v[c] = (row == c) ? 1.0 : 0.0;
-      store4<VT>(s_V + 4 * row, v);
+      store4<VT>(s_Va + 4 * row, v);
       store4<VT>(vbase + 4 * row, v);
     }
     if (tid < 16) Bp[tid] = 0.0;
@@ -197,6 +201,8 @@ k_lanczos(LanczosArgs g) {
     const int cq = tid & 3;                 // fixed column of this thread in the H.V items
 
     for (int k = 0; k < r_i; ++k) {
+      VT* s_V = (k & 1) ? s_Vb : s_Va;           // V_k
+      VT* s_Vo = (k & 1) ? s_Va : s_Vb;          // V_{k-1}, then V_{k+1} (vprev_lds)
       // ---- 1. W = H V_k, fused with the partial sums of A_k = V_k^T W
       {
         double accA[4] = {0.0, 0.0, 0.0, 0.0};     // A[c'][cq], c' = 0..3
@@ -344,7 +350,7 @@ k_lanczos(LanczosArgs g) {
       // ---- 2. three-term recursion: W -= V_k A_k + V_{k-1} B_{k-1}^T, with
       // the Gram matrix W^T W of the result
       {
-        const VT* Vprev = (k > 0) ? vbase + (size_t)(k - 1) * Rcap * 4 : nullptr;
+        const VT* Vprev = (k == 0) ? nullptr : (g.vprev_lds ? s_Vo : vbase + (size_t)(k - 1) * Rcap * 4);
         double acc[10];
 #pragma unroll
         for (int q = 0; q < 10; ++q) acc[q] = 0.0;
@@ -369,7 +375,8 @@ k_lanczos(LanczosArgs g) {
         // the one full barrier of the step: the global stores of the previous
         // step (V_k, rho rows, A, B, Omega) are visible to the workgroup after it
         block_sum<10, true>(acc, s_red, G);
-        bytes += (int64_t)R * 4 * (int64_t)sizeof(VT) * (k > 0 ? 2 : 1);   // V_{k-1} read, V_{k+1} written
+        // V_{k+1} written; V_{k-1} read unless it is in LDS
+        bytes += (int64_t)R * 4 * (int64_t)sizeof(VT) * (k > 0 && !g.vprev_lds ? 2 : 1);
       }
       // ---- 3a. orthogonality estimate. With Omega_{j,k} = V_j^T V_k, the
       // recursion H V_j = V_{j+1} B_j + V_j A_j + V_{j-1} B_{j-1}^T and the
@@ -738,7 +745,7 @@ k_lanczos(LanczosArgs g) {
             for (int c = 0; c < 4; ++c) t += w[c] * X[c * 4 + d];
             v[d] = t;
           }
-          store4<VT>(s_V + 4 * row, v);
+          store4<VT>(s_Vo + 4 * row, v);             // V_{k+1}: the buffer of the next step
           store4<VT>(Vn + 4 * row, v);
           const int js = s_js[row >> 2];
           if (js >= 0) {
@@ -771,7 +778,7 @@ k_lanczos(LanczosArgs g) {
   }
 }
 
-size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_lds) {
+size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_lds, bool vprev_lds) {
   const size_t vt = fp32 ? 4 : 8;
   const size_t Rcap = 4 * (size_t)nc_max;
   size_t b = 2 * Rcap * 4 * vt + 16;
@@ -780,6 +787,7 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_
   b += (size_t)(nc_max + 1) * 4 + (size_t)nc_max * 4 + (size_t)nc_max + 16;
   if (om_lds) b += (size_t)3 * r_max * 16 * 4;
   if (ab_lds) b += (size_t)r_max * 32 * 4;
+  if (vprev_lds) b += Rcap * 4 * vt + 16;
   return b + 64;
 }
 
