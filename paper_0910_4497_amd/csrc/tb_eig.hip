@@ -3,7 +3,7 @@
 //
 // k_band (one wave per atom) and k_eig (one persistent 256-thread workgroup
 // per atom at a time), FP64:
-//   1. k_band: T (block tridiagonal, 4x4 blocks A_k, upper-triangular B_k: a band of
+//   1. k_band (two atoms per wave): T (block tridiagonal, 4x4 blocks A_k, upper-triangular B_k: a band of
 //      half-width 4) -> tridiagonal S = Z^T T Z by Givens rotations, one
 //      diagonal at a time (half-width bc -> bc-1 for bc = 4, 3, 2). The fill-in
 //      of each rotation is chased down the band; chase j starts at time j * I
@@ -46,6 +46,12 @@ constexpr int RHO_ROTW = 512;      // rotation-log window of k_rho (>= rotations
 constexpr int XS = 5;              // row stride (doubles) of the 4-column vectors in k_rho's LDS
 constexpr int BW = 4;              // half-bandwidth of T
 constexpr int LB = BW + 2;         // stored lower diagonals incl. the bulge
+
+// LDS doubles of one atom in k_band: band rows -1 .. dmax-1 and Z[0:4, :].
+__host__ __device__ inline size_t band_atom_doubles(int r_max) {
+  const size_t dmax = 4 * (size_t)r_max;
+  return (dmax + 1) * LB + 4 * dmax;
+}
 
 __device__ __forceinline__ double t_entry(const double* tab, int row, int col) {
   // lower triangle (row >= col) of the block tridiagonal T
@@ -193,20 +199,23 @@ __device__ void twisted_vec(const double* D, const double* E, const double* E2, 
   for (int k = 0; k < d; ++k) xcol[(size_t)k * ld] *= sc;
 }
 
-// One time step of the chases that reduce the half-bandwidth from BC to BC-1.
-// Lb points at row 0 of the band storage; row -1 exists and is zero, and the
-// entries of rows p past the matrix end are zero, so the rotation needs no
-// bounds tests (rotating zeros gives zeros). Lane l takes chase jtop - l, then
-// jtop - 64 - l, ... until a batch has no active chase.
+// One time step of the chases that reduce the half-bandwidth from BC to BC-1,
+// for the atom of one half-wave (32 lanes; hl = lane within the half, hm =
+// the half's lane mask). Lb points at row 0 of the band storage; row -1
+// exists and is zero, and the entries of rows p past the matrix end are zero,
+// so the rotation needs no bounds tests (rotating zeros gives zeros). Lane hl
+// takes chase jtop - hl, then jtop - 32 - hl, ... until a batch has no active
+// chase.
 template <int BC>
-__device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau, int lane, double* lcs,
-                                          uint16_t* lp, int64_t rot_max, int64_t& nrot) {
+__device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau, int hl, uint64_t hm,
+                                          uint64_t below, double* lcs, uint16_t* lp, int64_t rot_max,
+                                          int64_t& nrot) {
   constexpr int I = (2 * BC + 3) / BC;       // ceil((BC + 4) / BC): 2, 3, 3
   const int last = d - BC - 1;
   int jtop = tau / I;
   if (jtop > last) jtop = last;
-  for (int jb = jtop; jb >= 0; jb -= 64) {
-    const int j = jb - lane;
+  for (int jb = jtop; jb >= 0; jb -= 32) {
+    const int j = jb - hl;
     bool act = false;
     int p = 0, u0 = 0;
     if (j >= 0) {
@@ -215,7 +224,7 @@ __device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau
       act = (p + 1 <= d - 1);
       u0 = (st == 0) ? 1 : 0;               // the annihilated entry is T[q][p - BC + u0]
     }
-    const bool batch_done = __ballot(act) == 0ull;
+    const bool batch_done = (__ballot(act) & hm) == 0ull;
     double c = 1.0, s = 0.0;
     if (act) {
       const int q = p + 1, ml = p - BC;
@@ -255,8 +264,7 @@ __device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau
       }
     }
     // log in lane order (the rotations of one time step commute)
-    const uint64_t mask = __ballot(act);
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t mask = __ballot(act) & hm;
     const int64_t slot = nrot + __popcll(mask & below);
     if (act && slot < rot_max) { lcs[2 * slot] = c; lcs[2 * slot + 1] = s; lp[slot] = (uint16_t)p; }
     nrot += __popcll(mask);
@@ -270,8 +278,9 @@ __device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau
 // steps no two planes are closer than 2), so they commute and the reverse
 // replay takes them as one segment.
 template <int BC>
-__device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int lane, double* lcs, uint16_t* lp,
-                                           int64_t rot_max, int64_t& nrot, int* seg, int seg_max, int& nseg) {
+__device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int hl, uint64_t hm, uint64_t below,
+                                           double* lcs, uint16_t* lp, int64_t rot_max, int64_t& nrot, int* seg,
+                                           int seg_max, int& nseg) {
   constexpr int I = (2 * BC + 3) / BC;
   constexpr int MS = BC == 3 ? 3 : 2;
   const int nchase = d - BC;
@@ -281,9 +290,9 @@ __device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int la
   int64_t group_start = nrot;
   for (int tau = 0; tau < t_end; ++tau) {
     if (tau % MS == 0) group_start = nrot;
-    band_step<BC>(Lb, R1, d, tau, lane, lcs, lp, rot_max, nrot);
+    band_step<BC>(Lb, R1, d, tau, hl, hm, below, lcs, lp, rot_max, nrot);
     if ((tau % MS == MS - 1 || tau == t_end - 1) && nrot > group_start) {   // one segment per group
-      if (lane == 0 && nseg < seg_max) seg[nseg] = (int)group_start;
+      if (hl == 0 && nseg < seg_max) seg[nseg] = (int)group_start;
       ++nseg;
     }
     // the LDS operations of one wave complete in issue order: a wave-scope
@@ -294,53 +303,63 @@ __device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int la
   }
 }
 
-// Band -> tridiagonal reduction: one wave per atom, one lane per chase.
+// Band -> tridiagonal reduction: one half-wave (32 lanes) per atom, one lane
+// per chase; two atoms per wave share the instruction stream.
 __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
   extern __shared__ double bsm[];
-  const int lane = threadIdx.x;
-  const int atom = blockIdx.x;
+  const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
+  const int atom = 2 * blockIdx.x + half;
+  const bool valid = atom < g.n_atoms;
   const int dmax = 4 * g.r_max;
-  const int K = g.kused[atom];
-  const int d = 4 * K;
-  double* Lb = bsm + LB;                   // [-1 .. d-1][LB]: Lb[j][t] = T[j+t][j]; row -1 zero
+  const int d = valid ? 4 * g.kused[atom] : 0;
+  const uint64_t hm = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
+  const uint64_t below = ((1ull << lane) - 1ull) & hm;
+  double* base = bsm + (size_t)half * band_atom_doubles(g.r_max);
+  double* Lb = base + LB;                  // [-1 .. d-1][LB]: Lb[j][t] = T[j+t][j]; row -1 zero
   double* R1 = Lb + (size_t)dmax * LB;     // [4][d] first rows of the transform
-  const double* tab = g.tab + (size_t)atom * g.r_max * 32;
-  for (int q = lane; q < (d + 1) * LB; q += BAND_NT) {
-    const int j = q / LB - 1, t = q % LB;
-    const int row = j + t;
-    bsm[q] = (j >= 0 && t <= BW && row < d) ? t_entry(tab, row, j) : 0.0;
-  }
-  for (int q = lane; q < 4 * d; q += BAND_NT) {
-    const int c = q / d, m = q % d;
-    R1[q] = (m == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
-  uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
-  int* seg = g.seg + (size_t)atom * g.seg_max;
-  int64_t nrot = 0;
-  int nseg = 0;
-  band_stage<4>(Lb, R1, d, lane, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
-  band_stage<3>(Lb, R1, d, lane, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
-  band_stage<2>(Lb, R1, d, lane, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
-  if (lane == 0) {
-    g.rot_n[atom] = (int)(nrot < g.rot_max ? nrot : g.rot_max);
-    g.seg_n[2 * atom] = nseg < g.seg_max ? nseg : g.seg_max;
-    g.seg_n[2 * atom + 1] = nseg < g.seg_max ? nseg : g.seg_max;
-    if (nseg > g.seg_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_SEG_OVERFLOW);
-    if (nrot > g.rot_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
+  if (valid) {
+    const double* tab = g.tab + (size_t)atom * g.r_max * 32;
+    for (int q = hl; q < (d + 1) * LB; q += 32) {
+      const int j = q / LB - 1, t = q % LB;
+      const int row = j + t;
+      base[q] = (j >= 0 && t <= BW && row < d) ? t_entry(tab, row, j) : 0.0;
+    }
+    for (int q = hl; q < 4 * d; q += 32) {
+      const int c = q / d, m = q % d;
+      R1[q] = (m == c) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
-  // tridiagonal S (D, E) and Z[0:4, :]
-  double* tri = g.tri + (size_t)atom * 2 * dmax;
-  double* r1 = g.y1 + (size_t)atom * 4 * dmax;
-  for (int k = lane; k < d; k += BAND_NT) {
-    tri[k] = Lb[(size_t)k * LB];
-    tri[dmax + k] = (k + 1 < d) ? Lb[(size_t)k * LB + 1] : 0.0;
+  if (valid) {
+    double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
+    uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
+    int* seg = g.seg + (size_t)atom * g.seg_max;
+    int64_t nrot = 0;
+    int nseg = 0;
+    band_stage<4>(Lb, R1, d, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
+    band_stage<3>(Lb, R1, d, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
+    band_stage<2>(Lb, R1, d, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
+    if (hl == 0) {
+      g.rot_n[atom] = (int)(nrot < g.rot_max ? nrot : g.rot_max);
+      g.seg_n[2 * atom] = nseg < g.seg_max ? nseg : g.seg_max;
+      g.seg_n[2 * atom + 1] = nseg < g.seg_max ? nseg : g.seg_max;
+      if (nseg > g.seg_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_SEG_OVERFLOW);
+      if (nrot > g.rot_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
+    }
   }
-  for (int q = lane; q < 4 * d; q += BAND_NT) {
-    const int c = q / d, m = q % d;
-    r1[(size_t)c * dmax + m] = R1[q];
+  __syncthreads();
+  if (valid) {
+    // tridiagonal S (D, E) and Z[0:4, :]
+    double* tri = g.tri + (size_t)atom * 2 * dmax;
+    double* r1 = g.y1 + (size_t)atom * 4 * dmax;
+    for (int k = hl; k < d; k += 32) {
+      tri[k] = Lb[(size_t)k * LB];
+      tri[dmax + k] = (k + 1 < d) ? Lb[(size_t)k * LB + 1] : 0.0;
+    }
+    for (int q = hl; q < 4 * d; q += 32) {
+      const int c = q / d, m = q % d;
+      r1[(size_t)c * dmax + m] = R1[q];
+    }
   }
 }
 
@@ -642,10 +661,7 @@ size_t eig_lds_bytes(int r_max) {
   const size_t dmax = 4 * (size_t)r_max;
   return (4 * dmax + 4 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) + (dmax + EIG_NT) * sizeof(int) + 64;
 }
-size_t band_lds_bytes(int r_max) {
-  const size_t dmax = 4 * (size_t)r_max;
-  return ((dmax + 1) * LB + 4 * dmax) * sizeof(double) + 64;
-}
+size_t band_lds_bytes(int r_max) { return 2 * band_atom_doubles(r_max) * sizeof(double) + 64; }
 size_t rho_lds_bytes(int r_max) {
   return (size_t)4 * r_max * (4 + XS) * sizeof(double) + RHO_SEGW * sizeof(int) + RHO_ROTW * (2 * sizeof(double) + 2) + 64;
 }
@@ -667,7 +683,7 @@ hipError_t eig_set_lds(int r_max) {
 }
 
 void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
-  hipLaunchKernelGGL(k_band, dim3(a.n_atoms), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
+  hipLaunchKernelGGL(k_band, dim3((a.n_atoms + 1) / 2), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
   hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
 }
 void launch_rho(const RhoArgs& a, hipStream_t st) {
