@@ -74,18 +74,25 @@ __device__ __forceinline__ void givens(double x, double y, double& c, double& s,
 // of inertia), pivots of magnitude below pivmin replaced by -pivmin. The
 // quotient E^2 / q uses the hardware reciprocal refined by one Newton step
 // (relative error near the unit roundoff, which perturbs each pivot by a few
-// ulps; bisection only needs the counts of a nearby matrix).
-__device__ __forceinline__ int sturm_count(const double* D, const double* E2, int d, double sigma,
+// ulps; bisection only needs the counts of a nearby matrix). E2s holds E^2
+// shifted by one (E2s[k] = E[k-1]^2, E2s[0] = 0) and d is a multiple of 4, so
+// four steps take two 16-byte loads of each array.
+__device__ __forceinline__ int sturm_count(const double* D, const double* E2s, int d, double sigma,
                                            double pivmin) {
-  double q = D[0] - sigma;
-  if (fabs(q) < pivmin) q = -pivmin;
-  int cnt = q < 0.0;
-  for (int k = 1; k < d; ++k) {
-    double rq = __builtin_amdgcn_rcp(q);
-    rq = fma(rq, fma(-q, rq, 1.0), rq);
-    q = (D[k] - sigma) - E2[k - 1] * rq;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
+  double q = 1.0;
+  int cnt = 0;
+  for (int k = 0; k < d; k += 4) {
+    const double2 d01 = *(const double2*)(D + k), d23 = *(const double2*)(D + k + 2);
+    const double2 e01 = *(const double2*)(E2s + k), e23 = *(const double2*)(E2s + k + 2);
+    const double dv[4] = {d01.x, d01.y, d23.x, d23.y}, ev[4] = {e01.x, e01.y, e23.x, e23.y};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double rq = __builtin_amdgcn_rcp(q);
+      rq = fma(rq, fma(-q, rq, 1.0), rq);
+      q = (dv[u] - sigma) - ev[u] * rq;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
   }
   return cnt;
 }
@@ -156,44 +163,71 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
 // pivots d-_k of U D U^T, the twist index r where
 // |gamma_r| = |d+_r + d-_r - (D_r - lam)| is smallest, then z_r = 1 and
 // z_k = -E_k z_{k+1} / d+_k (k < r), z_k = -E_{k-1} z_{k-1} / d-_k (k > r).
-// Pivots of magnitude below `small` are replaced by +-small. Scratch: 2
-// values per row at scr[(2 k + f) * ns]. The normalised vector goes to
-// xcol (stride ld).
+// Pivots of magnitude below `small` are replaced by +-small. Scratch: d+ at
+// scr[k * ns], d- at scr[(d + k) * ns], read back in chunks so that the loads
+// do not wait one by one. The normalised vector goes to xcol (stride ld).
 __device__ void twisted_vec(const double* D, const double* E, const double* E2, int d, double lam, double small,
                             double* xcol, size_t ld, double* scr, int ns) {
+  constexpr int CH = 8;                        // scratch values prefetched per chunk
+  double* sp = scr;                            // d+_k at sp[k * ns]
+  double* sm = scr + (size_t)d * ns;           // d-_k at sm[k * ns]
   double q = D[0] - lam;
   if (fabs(q) < small) q = q < 0.0 ? -small : small;
-  scr[0] = q;
+  sp[0] = q;
   for (int k = 1; k < d; ++k) {
     q = (D[k] - lam) - E2[k - 1] * rcp_nr(q);
     if (fabs(q) < small) q = q < 0.0 ? -small : small;
-    scr[(size_t)2 * k * ns] = q;
+    sp[(size_t)k * ns] = q;
   }
   double m = D[d - 1] - lam;
   if (fabs(m) < small) m = m < 0.0 ? -small : small;
-  scr[(size_t)(2 * (d - 1) + 1) * ns] = m;
+  sm[(size_t)(d - 1) * ns] = m;
   int r = d - 1;
   double best = fabs(q);                       // gamma_{d-1} = d+_{d-1}
-  for (int k = d - 2; k >= 0; --k) {
-    const double a = D[k] - lam;
-    m = a - E2[k] * rcp_nr(m);
-    if (fabs(m) < small) m = m < 0.0 ? -small : small;
-    scr[(size_t)(2 * k + 1) * ns] = m;
-    const double gam = fabs(scr[(size_t)2 * k * ns] + m - a);
-    if (gam < best) { best = gam; r = k; }
+  for (int k0 = d - 2; k0 >= 0; k0 -= CH) {
+    double pv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) pv[u] = (k0 - u >= 0) ? sp[(size_t)(k0 - u) * ns] : 0.0;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int k = k0 - u;
+      if (k < 0) break;
+      const double a = D[k] - lam;
+      m = a - E2[k] * rcp_nr(m);
+      if (fabs(m) < small) m = m < 0.0 ? -small : small;
+      sm[(size_t)k * ns] = m;
+      const double gam = fabs(pv[u] + m - a);
+      if (gam < best) { best = gam; r = k; }
+    }
   }
   double z = 1.0, nrm = 1.0;
   xcol[(size_t)r * ld] = 1.0;
-  for (int k = r - 1; k >= 0; --k) {
-    z = -E[k] * z * rcp_nr(scr[(size_t)2 * k * ns]);
-    xcol[(size_t)k * ld] = z;
-    nrm += z * z;
+  for (int k0 = r - 1; k0 >= 0; k0 -= CH) {
+    double pv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) pv[u] = (k0 - u >= 0) ? sp[(size_t)(k0 - u) * ns] : 1.0;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int k = k0 - u;
+      if (k < 0) break;
+      z = -E[k] * z * rcp_nr(pv[u]);
+      xcol[(size_t)k * ld] = z;
+      nrm += z * z;
+    }
   }
   z = 1.0;
-  for (int k = r + 1; k < d; ++k) {
-    z = -E[k - 1] * z * rcp_nr(scr[(size_t)(2 * k + 1) * ns]);
-    xcol[(size_t)k * ld] = z;
-    nrm += z * z;
+  for (int k0 = r + 1; k0 < d; k0 += CH) {
+    double mv[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) mv[u] = (k0 + u < d) ? sm[(size_t)(k0 + u) * ns] : 1.0;
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int k = k0 + u;
+      if (k >= d) break;
+      z = -E[k - 1] * z * rcp_nr(mv[u]);
+      xcol[(size_t)k * ld] = z;
+      nrm += z * z;
+    }
   }
   const double sc = 1.0 / sqrt(nrm);
   for (int k = 0; k < d; ++k) xcol[(size_t)k * ld] *= sc;
@@ -373,7 +407,8 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
   double* Eg = Dg + dmax;                  // [dmax] off-diagonal of S (E[k]: k, k+1)
   double* E2 = Eg + dmax;                  // [dmax] E^2
   double* lam_s = E2 + dmax;               // [dmax] eigenvalues (ascending)
-  double* red = lam_s + dmax;              // [EIG_NT/64][4]
+  double* E2s = lam_s + dmax;              // [dmax] E^2 shifted by one (E2s[k] = E[k-1]^2)
+  double* red = E2s + dmax;                // [EIG_NT/64][4]
   int* pos_s = (int*)(red + 4 * (EIG_NT / 64));   // [dmax] position inside a cluster
   __shared__ int s_atom, s_maxpos;
   __shared__ double s_lo, s_hi, s_e2max;
@@ -399,7 +434,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
       const double Dk = tri[k];
       const double Ek = (k + 1 < d) ? tri[dmax + k] : 0.0;
       const double Em = (k > 0) ? tri[dmax + k - 1] : 0.0;
-      Dg[k] = Dk; Eg[k] = Ek; E2[k] = Ek * Ek;
+      Dg[k] = Dk; Eg[k] = Ek; E2[k] = Ek * Ek; E2s[k] = Em * Em;
       const double rad = fabs(Ek) + fabs(Em);
       glo = fmin(glo, Dk - rad); ghi = fmax(ghi, Dk + rad); e2m = fmax(e2m, Ek * Ek);
     }
@@ -424,7 +459,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     // thread), then each eigenvalue is bisected from its grid cell
     int* cnt_s = pos_s + dmax;                     // [nt]
     const double hg = (hi0 - lo0) / (nt + 1);
-    cnt_s[tid] = sturm_count(Dg, E2, d, lo0 + (tid + 1) * hg, pivmin);
+    cnt_s[tid] = sturm_count(Dg, E2s, d, lo0 + (tid + 1) * hg, pivmin);
     __syncthreads();
     for (int t = tid; t < d; t += nt) {
       // cells with count(left) <= t < count(right); the ends count 0 and d
@@ -436,7 +471,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
       double l = il < 0 ? lo0 : lo0 + (il + 1) * hg, h = ih >= nt ? hi0 : lo0 + (ih + 1) * hg;
       for (int it = 0; it < 128; ++it) {
         const double m = 0.5 * (l + h);
-        if (sturm_count(Dg, E2, d, m, pivmin) <= t) l = m; else h = m;
+        if (sturm_count(Dg, E2s, d, m, pivmin) <= t) l = m; else h = m;
         if (h - l <= 4.0 * DBL_EPSILON * fmax(fabs(l), fabs(h)) + pivmin) break;
       }
       lam_s[t] = 0.5 * (l + h);
@@ -659,7 +694,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
 
 size_t eig_lds_bytes(int r_max) {
   const size_t dmax = 4 * (size_t)r_max;
-  return (4 * dmax + 4 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) + (dmax + EIG_NT) * sizeof(int) + 64;
+  return (4 * dmax + 5 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) + (dmax + EIG_NT) * sizeof(int) + 64;
 }
 size_t band_lds_bytes(int r_max) { return 2 * band_atom_doubles(r_max) * sizeof(double) + 64; }
 size_t rho_lds_bytes(int r_max) {
