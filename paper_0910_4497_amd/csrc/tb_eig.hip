@@ -230,6 +230,7 @@ __device__ void twisted_vec(const double* D, const double* E, const double* E2, 
     }
   }
   const double sc = 1.0 / sqrt(nrm);
+#pragma unroll 8
   for (int k = 0; k < d; ++k) xcol[(size_t)k * ld] *= sc;
 }
 
@@ -542,6 +543,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
       if (t < d) {
         const double* xc = Ua + t;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 8
         for (int k = 0; k < d; ++k) {
           const double x = xc[(size_t)k * dmax];
           a0 += R1[k] * x; a1 += R1[(size_t)d + k] * x; a2 += R1[(size_t)2 * d + k] * x; a3 += R1[(size_t)3 * d + k] * x;

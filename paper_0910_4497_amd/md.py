@@ -48,6 +48,13 @@ class TBForceField:
         self.mu = None
 
     @classmethod
+    def from_context(cls, ctx: TBContext, settings: TBSettings) -> "TBForceField":
+        """Wraps an existing context (its stream, capacities and buffers)."""
+        ff = cls.__new__(cls)
+        ff.s, ff.ctx, ff.mu = settings, ctx, None
+        return ff
+
+    @classmethod
     def for_geometry(cls, pos: torch.Tensor, settings: TBSettings, margin: int = 24) -> "TBForceField":
         """Sizes the sphere capacity from the geometry itself (plus a margin for motion)."""
         s = settings
@@ -118,3 +125,73 @@ def velocity_verlet(ff: TBForceField, pos: torch.Tensor, vel: torch.Tensor, dt: 
         acc = a_new
         log(k + 1, e)
     return pos, vel, rec
+
+
+class GraphedVerlet:
+    """Velocity-Verlet MD with one whole step (position update, lists, Krylov
+    solve, eigensolve, chemical potential, density matrix, forces, velocity
+    update) captured in a HIP graph and replayed per step.
+
+    The force field's context must enqueue on `stream` (a non-default stream
+    of default priority): the library then launches into the capture. State
+    lives in static device buffers (pos, vel, acc, e, forces) updated in place.
+    """
+
+    def __init__(self, ff: TBForceField, pos: torch.Tensor, vel: torch.Tensor, dt: float,
+                 stream: torch.cuda.Stream, mass: float = inputs.MASS_C, warmup: int = 2):
+        self.ff, self.dt, self.stream = ff, dt, stream
+        s = ff.s
+        cell = np.asarray(s.cell, dtype=np.float64)
+        cell = np.diag(cell) if cell.ndim == 2 else cell
+        with torch.cuda.stream(stream):
+            self.L = torch.tensor(cell, dtype=torch.float64, device=pos.device)
+            self.per = torch.tensor([bool(x) for x in s.periodic], device=pos.device)
+            self.pos = pos.clone()
+            self.vel = vel.clone()
+            self.e = torch.empty(4, dtype=torch.float64, device=pos.device)
+            self.f = torch.empty_like(self.pos)
+            self.acc_unit = inputs.ACC_UNIT / mass
+            self._forces()
+            self.acc = self.f * self.acc_unit
+            for _ in range(warmup):
+                self._step()
+        stream.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=stream):
+            self._step()
+        stream.synchronize()
+
+    def _forces(self):
+        s = self.ff.s
+        ctx = self.ff.ctx
+        ctx.build_local_H(self.pos, s.cell, s.periodic, s.params, s.r_cluster)
+        ctx.krylov_rho(s.r, s.kT, mu=s.mu, n_electrons=s.n_electrons, precision=s.precision,
+                       r_per_atom=s.r_per_atom)
+        ctx.energy_forces(forces=self.f, e_out=self.e)
+
+    def _step(self):
+        dt = self.dt
+        self.pos.add_(self.vel * dt + 0.5 * self.acc * dt * dt)
+        self.pos.copy_(torch.where(self.per, torch.remainder(self.pos, self.L), self.pos))
+        self._forces()
+        a_new = self.f * self.acc_unit
+        self.vel.add_(0.5 * (self.acc + a_new) * dt)
+        self.acc.copy_(a_new)
+
+    def init_state(self, pos: torch.Tensor, vel: torch.Tensor):
+        """Set positions and velocities; forces and accelerations are evaluated
+        eagerly on the context's stream."""
+        with torch.cuda.stream(self.stream):
+            self.pos.copy_(pos)
+            self.vel.copy_(vel)
+            self._forces()
+            self.acc.copy_(self.f * self.acc_unit)
+
+    def eager_step(self):
+        """The same step as the graph, launched eagerly (reference for tests)."""
+        with torch.cuda.stream(self.stream):
+            self._step()
+
+    def step(self):
+        """One MD step: a replay of the captured graph (asynchronous)."""
+        self.graph.replay()
