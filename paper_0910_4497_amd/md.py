@@ -135,11 +135,17 @@ class GraphedVerlet:
     The force field's context must enqueue on `stream` (a non-default stream
     of default priority): the library then launches into the capture. State
     lives in static device buffers (pos, vel, acc, e, forces) updated in place.
+
+    fixed_start: every replay advances the state set by init_state() by one
+    step instead of the previous replay's state (a throughput measurement on
+    starts whose trajectory leaves the model's valid range; all work of the
+    step is still done).
     """
 
     def __init__(self, ff: TBForceField, pos: torch.Tensor, vel: torch.Tensor, dt: float,
-                 stream: torch.cuda.Stream, mass: float = inputs.MASS_C, warmup: int = 2):
-        self.ff, self.dt, self.stream = ff, dt, stream
+                 stream: torch.cuda.Stream, mass: float = inputs.MASS_C, warmup: int = 2,
+                 fixed_start: bool = False):
+        self.ff, self.dt, self.stream, self.fixed_start = ff, dt, stream, fixed_start
         s = ff.s
         cell = np.asarray(s.cell, dtype=np.float64)
         cell = np.diag(cell) if cell.ndim == 2 else cell
@@ -153,6 +159,7 @@ class GraphedVerlet:
             self.acc_unit = inputs.ACC_UNIT / mass
             self._forces()
             self.acc = self.f * self.acc_unit
+            self.start = (self.pos.clone(), self.vel.clone(), self.acc.clone())
             for _ in range(warmup):
                 self._step()
         stream.synchronize()
@@ -171,6 +178,10 @@ class GraphedVerlet:
 
     def _step(self):
         dt = self.dt
+        if self.fixed_start:
+            self.pos.copy_(self.start[0])
+            self.vel.copy_(self.start[1])
+            self.acc.copy_(self.start[2])
         self.pos.add_(self.vel * dt + 0.5 * self.acc * dt * dt)
         self.pos.copy_(torch.where(self.per, torch.remainder(self.pos, self.L), self.pos))
         self._forces()
@@ -186,6 +197,8 @@ class GraphedVerlet:
             self.vel.copy_(vel)
             self._forces()
             self.acc.copy_(self.f * self.acc_unit)
+            for buf, src in zip(self.start, (self.pos, self.vel, self.acc)):
+                buf.copy_(src)
 
     def eager_step(self):
         """The same step as the graph, launched eagerly (reference for tests)."""

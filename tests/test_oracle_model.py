@@ -154,3 +154,50 @@ def test_fermi_and_entropy_closed_forms():
     mask = np.abs(x) < 30
     assert np.allclose(tb.entropy_per_level(x, 0.0, 1.0)[mask], 2 * s[mask], rtol=1e-12)
     assert abs(tb.entropy_per_level(0.0, 0.0, 1.0) - 2 * np.log(2)) < 1e-15
+
+
+
+def _embedding_argument(k, pos, L):
+    """x_k = sum_j phi(r_kj) by brute force over minimum-image pairs."""
+    d = pos - pos[k]
+    d -= L * np.round(d / L)
+    r = np.linalg.norm(d, axis=1)
+    return float(np.sum(model.phi_pair(r[(r < P["dm"]) & (r > 0)], P)))
+
+
+def _close_contact_atoms(pos, L, r_close, chunk=64):
+    """Atoms with another atom closer than r_close (brute force, chunked)."""
+    hit = np.zeros(len(pos), dtype=bool)
+    for i in range(0, len(pos), chunk):
+        d = pos[None, :, :] - pos[i:i + chunk, None, :]
+        d -= L * np.round(d / L)
+        r = np.linalg.norm(d, axis=2)
+        r[np.arange(r.shape[0]), np.arange(i, i + r.shape[0])] = np.inf
+        hit[i:i + chunk] = (r < r_close).any(axis=1)
+    return np.nonzero(hit)[0]
+
+
+def test_embedding_polynomial_turnover_and_workload_starts():
+    """The quartic F(x) of the Xu-form repulsion has one real stationary point,
+    a maximum near x = 146.5: past it the pair repulsion reverses sign. Every
+    240- and 1920-atom start stays far below it; the sigma = 0.10 A start of
+    the 15360-atom cell holds atoms past it (closest contacts near 0.9 A), so
+    no trajectory from it stays in the model's valid range and its throughput
+    runs advance one fixed start state per step."""
+    c = np.asarray(P["frep"], dtype=np.float64)
+    roots = np.roots(np.polyder(c[::-1]))
+    real = sorted(float(z.real) for z in roots if abs(z.imag) < 1e-9)
+    assert len(real) == 1 and 146.0 < real[0] < 147.0
+    xs = real[0]
+    assert model.f_embed_deriv(xs - 1.0, P) > 0 > model.f_embed_deriv(xs + 1.0, P)
+    for name in ("c60_240", "c60_1920", "c60_1920_hot"):
+        w = inputs.workload(name)
+        L = np.asarray(w.cell, dtype=np.float64)
+        x = [_embedding_argument(k, w.pos, L) for k in range(w.n_atoms)]
+        assert max(x) < 0.7 * xs, name
+    w = inputs.workload("c60_15360")
+    L = np.asarray(w.cell, dtype=np.float64)
+    pos = np.mod(w.pos, L)
+    near = _close_contact_atoms(pos, L, 0.95)
+    assert 0 < len(near) < 64
+    assert max(_embedding_argument(k, pos, L) for k in near) > xs
