@@ -63,6 +63,11 @@ def parse():
                     help="chain: a velocity-Verlet trajectory; fixed: every timed step advances the "
                          "same start state by one step (auto: fixed for the workloads whose start has "
                          "atoms past the maximum of the repulsive embedding polynomial)")
+    ap.add_argument("--plain-steps", type=int, default=1,
+                    help="MD steps timed on the plain FP64 path with one launch per atom for each "
+                         "per-atom phase (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of timing the candidates first")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the run with each MD step captured in one HIP graph")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -72,9 +77,11 @@ def parse():
 
 
 def run_md(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, torch, inputs, rpa=None,
-           fixed=False):
+           fixed=False, atoms_per_launch=0):
     """velocity-Verlet; returns timing, per-phase ms and the first-step forces.
-    fixed: each step starts again from (pos0, vel0, a0)."""
+    fixed: each step starts again from (pos0, vel0, a0). atoms_per_launch: launch
+    granularity of the per-atom phases in the timed steps (results are bitwise
+    those of the batched launches, so the untimed start runs batched)."""
     dev = ctx.device
     pos = pos0.clone()
     vel = vel0.clone()
@@ -106,6 +113,7 @@ def run_md(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, torch, inpu
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    ctx.set_launch(atoms_per_launch)
     ctx.profile(True)
     ctx.profile_read()
     torch.cuda.synchronize()
@@ -116,6 +124,7 @@ def run_md(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, torch, inpu
     t1 = time.perf_counter()
     phases = ctx.profile_read()
     ctx.profile(False)
+    ctx.set_launch(0)
     stats = ctx.stats()
     return {"seconds": t1 - t0, "phases": phases, "f_first": f_first, "e_first": e_first,
             "e_last": e, "stats": stats}
@@ -194,13 +203,24 @@ def main():
                                         ("c60_6480_strained", "c60_15360"))
     results = {}
     precs = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
+    shapes = {}
     for prec in precs:
+        if not args.no_autotune:
+            # untimed: pick the launch shapes on the start geometry (results unchanged)
+            ctx.build_local_H(pos0, w.cell, (1, 1, 1), params, w.r_cut)
+            shapes[prec] = ctx.autotune(w.r, prec, r_per_atom=rpa)
         results[prec] = run_md(ctx, w, params, pos0, vel0, prec, args.steps, args.warmup, args.dt,
                                torch, inputs, rpa, fixed)
         if not args.no_graph:
             g = run_graph(ctx, w, params, pos0, vel0, prec, args.steps, args.warmup, args.dt, stream,
                           torch, rpa, fixed)
             results[prec]["graph"] = g
+    plain = None
+    if args.plain_steps > 0:
+        plain = run_md(ctx, w, params, pos0, vel0, "fp64", args.plain_steps, 0, args.dt, torch, inputs, rpa,
+                       fixed, atoms_per_launch=1)
+        plain["ms_per_step"] = 1e3 * plain["seconds"] / args.plain_steps
+        plain["steps_per_s"] = args.plain_steps / plain["seconds"]
     ref = results.get("fp64")
     for prec, r in results.items():
         r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
@@ -247,10 +267,17 @@ def main():
                        "reorth_second_passes": r["stats"]["reorth_second_pass"],
                        "reorth_steps_per_atom": round(r["stats"]["reorth_steps"] / N, 2),
                        "lanczos_basis_bytes_per_launch": r["stats"]["basis_bytes"]}
+        if prec in shapes:
+            extra[prec]["launch_shape"] = shapes[prec]
         if "graph" in r:
             g = r["graph"]
             extra[prec]["graph_ms_per_step"] = round(1e3 * g["seconds"] / args.steps, 3)
             extra[prec]["graph_steps_per_s"] = round(args.steps / g["seconds"], 3)
+    if plain is not None:
+        extra["plain_fp64_one_launch_per_atom"] = {
+            "steps": args.plain_steps, "steps_per_s": round(plain["steps_per_s"], 5),
+            "ms_per_step": round(plain["ms_per_step"], 1),
+            "phase_ms_per_step": {k: round(v[0] / args.plain_steps, 1) for k, v in plain["phases"].items()}}
     line = {
         "metric": "MD steps/s (E+F) at 1920/15360 atoms, mixed vs FP64, force err <=1e-3 eV/A",
         "value": round(head["steps_per_s"], 3),
@@ -275,6 +302,8 @@ def main():
     }
     if "fp32" in results and "fp64" in results:
         line["mixed_over_fp64"] = round(results["fp32"]["steps_per_s"] / results["fp64"]["steps_per_s"], 3)
+    if plain is not None:
+        line["headline_over_plain_fp64"] = round(head["steps_per_s"] / plain["steps_per_s"], 1)
     print(json.dumps(line))
 
 

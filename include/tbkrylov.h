@@ -145,6 +145,38 @@ int tb_rho_layout(tb_ctx *ctx, int64_t *nnz_pairs_host, int64_t *row_ptr,
  * Errors: TB_ESTATE, TB_EHIP. */
 int tb_energy_forces(tb_ctx *ctx, double *e_out, double *forces);
 
+/* Launch granularity of the per-atom phases of tb_krylov_rho (block Lanczos,
+ * projected eigensolve, density-matrix assembly). Every target atom's local
+ * solve is independent once the couplings are built (Sec. 2, the cutoff
+ * sphere): atoms_per_launch = 0 (the default) runs each phase as one launch
+ * over all atoms; k >= 1 runs it as consecutive launches over groups of k
+ * atoms (k = 1: one launch per atom), each with at most k workgroups. The
+ * results are bitwise the same in every mode; only the launch count and the
+ * device occupancy change. Host-side setting, no device work.
+ * Errors: TB_EINVAL (ctx null or atoms_per_launch < 0). */
+int tb_set_launch(tb_ctx *ctx, int atoms_per_launch);
+
+/* Launch-shape autotuner for tb_krylov_rho at this precision. On the spheres
+ * of the last tb_build_local_H (required first), it times the block-Lanczos
+ * kernel for every launch shape that fits the device (256 or 512 threads per
+ * workgroup x a register budget of 128 or 256 VGPRs x 1..4 persistent
+ * workgroups per compute unit that stay co-resident, with as many of the
+ * recursion's side buffers in LDS as that occupancy leaves room for), and
+ * then the projected eigensolver for 2..8 persistent workgroups per compute
+ * unit; every candidate runs twice, the faster run counts, and the fastest
+ * shapes are kept in the context for later calls at this precision. Shapes
+ * change launch geometry, registers and LDS residency, and with the thread
+ * count the order of the workgroup reductions: later results agree with
+ * those of the default shape to rounding (FP64: ~1e-15 relative). r, r_per_atom: as for
+ * tb_krylov_rho. shape_out (host, nullable) [5]: Krylov threads per
+ * workgroup, Krylov workgroups per compute unit, eigensolver workgroups per
+ * compute unit, candidates timed, Krylov waves per SIMD of the register
+ * budget (4: 128 VGPRs, 2: 256). Synchronises the stream (not for graph
+ * capture); tb_krylov_rho must run again before tb_energy_forces, and the
+ * counters of tb_get_stats are those of before the call.
+ * Errors: TB_EINVAL, TB_ESTATE, TB_ECAPACITY (r > r_max), TB_EHIP. */
+int tb_autotune(tb_ctx *ctx, int r, const int *r_per_atom, int precision, int *shape_out);
+
 /* Diagnostics (host): counters since the last tb_build_local_H. stats_host
  * receives up to n_stats values: [0] device error flags, [1] max cluster
  * size, [2] max hop count, [3] max local couplings per sphere, [4] total

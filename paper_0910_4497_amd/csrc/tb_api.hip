@@ -114,37 +114,46 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   if (c->rot_max > 65535 * 16) c->rot_max = 65535 * 16;
 
   // persistent Krylov workgroups: as many as fit on the device at once
-  const size_t lds = lanczos_lds_bytes(n_cluster_max, r_max, false, false, false, false);
+  const size_t lds = lanczos_lds_bytes(n_cluster_max, r_max, false, 512, false, false, false);
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
-  if (lds > prop.sharedMemPerBlock && lds > 160 * 1024) {
+  if (lds + LDS_RESERVE > LDS_CU) {
     delete c;
     return fail(TB_ECAPACITY, "n_cluster_max=%d, r_max=%d need %zu B of LDS per workgroup", n_cluster_max,
                 r_max, lds);
   }
-  size_t lds_attr = lds;
-  for (int v = 1; v <= 3; ++v) {
-    const size_t l = lanczos_lds_bytes(n_cluster_max, r_max, false, true, v >= 2, v == 3);
-    if (l <= 160 * 1024) lds_attr = l;
-  }
-  hipError_t e = lanczos_set_lds(lds_attr);
+  hipError_t e = lanczos_set_lds(LDS_CU - LDS_RESERVE);
   if (e != hipSuccess) {
     delete c;
-    return fail(TB_ECAPACITY, "LDS request of %zu B refused: %s", lds, hipGetErrorString(e));
+    return fail(TB_ECAPACITY, "LDS request of %zu B refused: %s", (size_t)(LDS_CU - LDS_RESERVE),
+                hipGetErrorString(e));
   }
   e = eig_set_lds(r_max);
-  if (e != hipSuccess || rho_lds_bytes(r_max) > 160 * 1024) {
+  if (e != hipSuccess || rho_lds_bytes(r_max) > LDS_CU) {
     delete c;
     return fail(TB_ECAPACITY, "r_max=%d too large for the eigensolver LDS: %s", r_max, hipGetErrorString(e));
   }
-  int per_cu = (int)((160 * 1024) / (lds + 1024));
-  if (per_cu < 1) per_cu = 1;
-  if (per_cu > 2) per_cu = 2;
-  c->lz_per_cu = per_cu;
-  c->n_wg_lanczos = prop.multiProcessorCount * per_cu;
-  if (c->n_wg_lanczos > n_atoms_max) c->n_wg_lanczos = (int)n_atoms_max;
-  c->n_wg_eig = prop.multiProcessorCount * (eig_threads(r_max) <= 192 ? 6 : 4);
-  if (c->n_wg_eig > n_atoms_max) c->n_wg_eig = (int)n_atoms_max;
+  c->n_cu = prop.multiProcessorCount;
+  // default shape: 512 threads, workgroups per CU from the FP64 footprint
+  // (at most 2), for both precisions; tb_autotune may change it
+  int per_cu = (int)(LDS_CU / (lds + LDS_RESERVE));
+  per_cu = per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu);
+  for (int q = 0; q < 2; ++q) { c->lz_nt[q] = 512; c->lz_minw[q] = 4; c->lz_per_cu[q] = per_cu; }
+  // workspace for the largest shape the tuner may pick: the smallest (FP32,
+  // 256-thread) footprint, at most LZ_PER_CU_MAX per compute unit
+  const size_t lds_min = lanczos_lds_bytes(n_cluster_max, r_max, true, 256, false, false, false);
+  int pmax = (int)(LDS_CU / (lds_min + LDS_RESERVE));
+  c->lz_per_cu_max = pmax < per_cu ? per_cu : (pmax > LZ_PER_CU_MAX ? LZ_PER_CU_MAX : pmax);
+  c->eig_per_cu = eig_threads(r_max) <= 192 ? 6 : 4;
+  int emx = (int)(LDS_CU / (eig_lds_bytes(r_max) + LDS_RESERVE));
+  const int ewv = 2048 / eig_threads(r_max);            // 32 waves per CU
+  emx = emx < ewv ? emx : ewv;
+  emx = emx > EIG_PER_CU_MAX ? EIG_PER_CU_MAX : emx;
+  c->eig_per_cu_max = emx < c->eig_per_cu ? c->eig_per_cu : emx;
+  const int64_t n_wg_lz_max = (int64_t)c->n_cu * c->lz_per_cu_max < n_atoms_max
+                                  ? (int64_t)c->n_cu * c->lz_per_cu_max : n_atoms_max;
+  const int64_t n_wg_eig_max = (int64_t)c->n_cu * c->eig_per_cu_max < n_atoms_max
+                                   ? (int64_t)c->n_cu * c->eig_per_cu_max : n_atoms_max;
 
   const int64_t N = n_atoms_max, NC = n_cluster_max;
   hipError_t a = hipSuccess;
@@ -178,7 +187,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(seg_n, 2 * N);
   ALLOC(evec, N * dmax * dmax);
   ALLOC(tri, N * 2 * dmax);
-  ALLOC(eig_scratch, (int64_t)c->n_wg_eig * dmax * 4 * eig_threads(r_max));
+  ALLOC(eig_scratch, n_wg_eig_max * dmax * 4 * eig_threads(r_max));
   ALLOC(mu_state, 16);
   ALLOC(partial, 16384);             // [blocks][points] of the mu reductions
   ALLOC(counter, 16);
@@ -186,10 +195,10 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(eparts, 8);
   ALLOC(stats, ST_NSTATS);
 #undef ALLOC
-  if (a == hipSuccess) a = alloc(c, &c->omega, (size_t)c->n_wg_lanczos * 3 * r_max * 16);
+  if (a == hipSuccess) a = alloc(c, &c->omega, (size_t)n_wg_lz_max * 3 * r_max * 16);
   if (a == hipSuccess) {
     double* vb = nullptr;
-    a = alloc(c, &vb, (size_t)c->n_wg_lanczos * r_max * 4 * NC * 4);
+    a = alloc(c, &vb, (size_t)n_wg_lz_max * r_max * 4 * NC * 4);
     c->vbuf = vb;
   }
   if (a == hipSuccess) {
@@ -273,28 +282,27 @@ extern "C" int tb_build_local_H(tb_ctx* c, int64_t n_atoms, const double* pos, c
   return TB_OK;
 }
 
-extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT, double mu, double n_electrons,
-                             int precision, double* mu_out, double* rho_out) {
-  if (!c) return fail(TB_EINVAL, "ctx is null");
-  if (c->stage < 1) return fail(TB_ESTATE, "tb_build_local_H must be called first");
-  if (!rho_out) return fail(TB_EINVAL, "rho_out is null");
-  if (r < 1 || r > c->r_max) return fail(TB_ECAPACITY, "r=%d outside [1, %d]", r, c->r_max);
-  if (!(isfinite(kT) && kT > 0)) return fail(TB_EINVAL, "kT must be positive and finite");
-  if (precision != TB_FP64 && precision != TB_FP32) return fail(TB_EINVAL, "unknown precision %d", precision);
-  const bool fixed = !isnan(mu);
-  if (fixed && !isfinite(mu)) return fail(TB_EINVAL, "mu must be finite or NaN");
-  const int n = (int)c->n_atoms;
-  if (!fixed && !(isfinite(n_electrons) && n_electrons > 0 && n_electrons < 8.0 * n))
-    return fail(TB_EMU, "n_electrons=%g outside (0, %d)", n_electrons, 8 * n);
-  HIP_TRY(hipSetDevice(c->device));
-  hipStream_t st = c->stream;
-  c->kT = kT;
-  c->precision = precision;
-  const bool fp32 = precision == TB_FP32;
-  // K4: block Lanczos
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 16);
+// LDS residency of the Krylov kernel for a launch shape: the orthogonality
+// estimates, then FP32 copies of A_j, B_j, then a second block buffer (V_{k-1}
+// read from LDS), each taken while the footprint still lets `per_cu`
+// workgroups share a compute unit. lds = 0 when even the base footprint does not.
+struct LzPlan { int nt, minw, per_cu, n_wg; size_t lds; int om_lds, ab_lds, vprev_lds; };
+static LzPlan lanczos_plan(const tb_ctx* c, bool fp32, int nt, int minw, int per_cu) {
+  LzPlan p{nt, minw, per_cu, c->n_cu * per_cu, 0, 0, 0, 0};
+  auto fits = [&](size_t l) { return (l + LDS_RESERVE) * per_cu <= LDS_CU; };
+  const size_t l0 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, nt, false, false, false);
+  const size_t l1 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, nt, true, false, false);
+  const size_t l2 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, nt, true, true, false);
+  const size_t l3 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, nt, true, true, true);
+  if (!fits(l0) && per_cu > 1) return p;
+  p.om_lds = fits(l1); p.ab_lds = p.om_lds && fits(l2); p.vprev_lds = p.ab_lds && fits(l3);
+  p.lds = p.vprev_lds ? l3 : (p.ab_lds ? l2 : (p.om_lds ? l1 : l0));
+  return p;
+}
+
+static LanczosArgs lanczos_args(const tb_ctx* c, int n, int r, const int* r_per_atom, bool fp32) {
   LanczosArgs la;
-  la.n_atoms = n; la.r_default = r; la.r_per_atom = r_per_atom;
+  la.atom0 = 0; la.n_atoms = n; la.r_default = r; la.r_per_atom = r_per_atom;
   la.clu_n = c->clu_n; la.clu_j = c->clu_j; la.loc_off = c->loc_off; la.loc_ent = c->loc_ent;
   la.hnorm = c->hnorm; la.jloc = c->jloc; la.hop_n = c->hop_n;
   la.pair = fp32 ? (const void*)c->pair32 : (const void*)c->pair64;
@@ -309,32 +317,72 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   // already carries
   la.eta = fp32 ? 1e-4 : 1e-12;
   la.eps_unit = fp32 ? (double)FLT_EPSILON : DBL_EPSILON;
-  // orthogonality estimates in LDS when that keeps the workgroups per CU
-  // (and the FP32 copies of A_j, B_j beside them) when that keeps the
-  // workgroups per CU
-  auto fits = [&](size_t l) { return l <= 160 * 1024 && (160 * 1024) / (l + 1024) >= (size_t)c->lz_per_cu; };
-  const size_t lds0 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, false, false, false);
-  const size_t lds1 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, false, false);
-  const size_t lds2 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, true, false);
-  const size_t lds3 = lanczos_lds_bytes(c->nc_max, c->r_max, fp32, true, true, true);
-  const bool om_lds = fits(lds1), ab_lds = fits(lds2), vprev_lds = fits(lds3);
-  const size_t lds = vprev_lds ? lds3 : (ab_lds ? lds2 : (om_lds ? lds1 : lds0));
-  la.om_lds = om_lds ? 1 : 0;
-  la.ab_lds = ab_lds ? 1 : 0;
-  la.vprev_lds = vprev_lds ? 1 : 0;
-  int pk = prof_begin(c, 1);
-  launch_lanczos(la, fp32, c->n_wg_lanczos < n ? c->n_wg_lanczos : n, lds, st);
-  prof_end(c, pk);
-  // K5: projected eigensolve
+  la.om_lds = la.ab_lds = la.vprev_lds = 0;
+  return la;
+}
+
+static EigArgs eig_args(const tb_ctx* c, int n) {
   EigArgs ea;
-  ea.n_atoms = n; ea.r_max = c->r_max; ea.tab = c->tab; ea.kused = c->kused;
+  ea.atom0 = 0; ea.n_atoms = n; ea.r_max = c->r_max; ea.tab = c->tab; ea.kused = c->kused;
   ea.lam = c->lam; ea.wgt = c->wgt; ea.y1 = c->y1;
   ea.rot_cs = c->rot_cs; ea.rot_p = c->rot_p; ea.rot_n = c->rot_n; ea.rot_max = c->rot_max;
   ea.seg = c->seg; ea.seg_n = c->seg_n; ea.seg_max = c->seg_max;
   ea.counter = c->work_counter + 1; ea.scratch = c->eig_scratch; ea.evec = c->evec; ea.tri = c->tri;
   ea.stats = c->stats;
+  return ea;
+}
+
+static int check_krylov_args(const tb_ctx* c, int r, int precision) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (c->stage < 1) return fail(TB_ESTATE, "tb_build_local_H must be called first");
+  if (r < 1 || r > c->r_max) return fail(TB_ECAPACITY, "r=%d outside [1, %d]", r, c->r_max);
+  if (precision != TB_FP64 && precision != TB_FP32) return fail(TB_EINVAL, "unknown precision %d", precision);
+  return TB_OK;
+}
+
+extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT, double mu, double n_electrons,
+                             int precision, double* mu_out, double* rho_out) {
+  const int bad = check_krylov_args(c, r, precision);
+  if (bad) return bad;
+  if (!rho_out) return fail(TB_EINVAL, "rho_out is null");
+  if (!(isfinite(kT) && kT > 0)) return fail(TB_EINVAL, "kT must be positive and finite");
+  const bool fixed = !isnan(mu);
+  if (fixed && !isfinite(mu)) return fail(TB_EINVAL, "mu must be finite or NaN");
+  const int n = (int)c->n_atoms;
+  if (!fixed && !(isfinite(n_electrons) && n_electrons > 0 && n_electrons < 8.0 * n))
+    return fail(TB_EMU, "n_electrons=%g outside (0, %d)", n_electrons, 8 * n);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  c->kT = kT;
+  c->precision = precision;
+  const bool fp32 = precision == TB_FP32;
+  // K4: block Lanczos
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 16);
+  LanczosArgs la = lanczos_args(c, n, r, r_per_atom, fp32);
+  const LzPlan plan = lanczos_plan(c, fp32, c->lz_nt[fp32], c->lz_minw[fp32], c->lz_per_cu[fp32]);
+  la.om_lds = plan.om_lds; la.ab_lds = plan.ab_lds; la.vprev_lds = plan.vprev_lds;
+  // per-atom phases run over consecutive groups of `chunk` target atoms, one
+  // launch per group (a single group by default); persistent kernels take a
+  // freshly zeroed queue counter per launch
+  const int chunk = c->atoms_per_launch > 0 && c->atoms_per_launch < n ? c->atoms_per_launch : n;
+  int pk = prof_begin(c, 1);
+  for (int a0 = 0; a0 < n; a0 += chunk) {
+    const int a1 = n - a0 > chunk ? a0 + chunk : n;
+    if (a0 > 0) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 1);
+    la.atom0 = a0; la.n_atoms = a1;
+    launch_lanczos(la, fp32, plan.nt, plan.minw, plan.n_wg < a1 - a0 ? plan.n_wg : a1 - a0, plan.lds, st);
+  }
+  prof_end(c, pk);
+  // K5: projected eigensolve
+  EigArgs ea = eig_args(c, n);
   pk = prof_begin(c, 2);
-  launch_eig(ea, c->n_wg_eig < n ? c->n_wg_eig : n, st);
+  for (int a0 = 0; a0 < n; a0 += chunk) {
+    const int a1 = n - a0 > chunk ? a0 + chunk : n;
+    if (a0 > 0) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter + 1, 1);
+    ea.atom0 = a0; ea.n_atoms = a1;
+    const int n_wg_eig = c->n_cu * c->eig_per_cu;
+    launch_eig(ea, n_wg_eig < a1 - a0 ? n_wg_eig : a1 - a0, st);
+  }
   prof_end(c, pk);
   // K6: chemical potential and spectral sums
   MuArgs ma;
@@ -353,11 +401,108 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   ra.seg = c->seg; ra.seg_n = c->seg_n; ra.seg_max = c->seg_max; ra.evec = c->evec; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
   ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out; ra.stats = c->stats;
   pk = prof_begin(c, 4);
-  launch_rho(ra, st);
+  for (int a0 = 0; a0 < n; a0 += chunk) {
+    ra.atom0 = a0; ra.n_atoms = n - a0 > chunk ? a0 + chunk : n;
+    launch_rho(ra, st);
+  }
   prof_end(c, pk);
   HIP_TRY(hipGetLastError());
   c->rho_last = rho_out;
   c->stage = 2;
+  return TB_OK;
+}
+
+// Launch-shape tuner: times the Krylov kernel for every shape that fits
+// (threads per workgroup x persistent workgroups per compute unit) and then
+// k_band + k_eig for every k_eig occupancy, on this context's current spheres;
+// each candidate runs twice and its faster run counts. The choice changes
+// launch geometry, registers and LDS residency; the thread count also sets
+// the order of the workgroup reductions, so results move at rounding level.
+extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precision, int* shape_out) {
+  const int bad = check_krylov_args(c, r, precision);
+  if (bad) return bad;
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  const bool fp32 = precision == TB_FP32;
+  const int n = (int)c->n_atoms;
+  int64_t saved[ST_NSTATS];
+  HIP_TRY(hipMemcpyAsync(saved, c->stats, sizeof saved, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto timed = [&](auto&& launch, float& best_ms) -> hipError_t {
+    for (int rep = 0; rep < 2; ++rep) {
+      hipEventRecord(e0, st);
+      launch();
+      hipEventRecord(e1, st);
+      hipError_t e = hipEventSynchronize(e1);
+      if (e != hipSuccess) return e;
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) return e;
+      if (ms < best_ms) best_ms = ms;
+    }
+    return hipGetLastError();
+  };
+  LanczosArgs la = lanczos_args(c, n, r, r_per_atom, fp32);
+  int best_nt = c->lz_nt[fp32], best_mw = c->lz_minw[fp32], best_pc = c->lz_per_cu[fp32], tried = 0;
+  float best = 3.0e38f;
+  hipError_t err = hipSuccess;
+  const int nts[2] = {256, 512}, mws[2] = {4, 2};
+  for (int m = 0; m < 2 && err == hipSuccess; ++m) {
+    for (int q = 0; q < 2 && err == hipSuccess; ++q) {
+      for (int pc = 1; pc <= c->lz_per_cu_max && err == hipSuccess; ++pc) {
+        // co-resident only: waves per SIMD within the register budget
+        if (pc * nts[q] / 64 > 4 * mws[m]) continue;
+        const LzPlan p = lanczos_plan(c, fp32, nts[q], mws[m], pc);
+        if (!p.lds) continue;
+        la.om_lds = p.om_lds; la.ab_lds = p.ab_lds; la.vprev_lds = p.vprev_lds;
+        float t = 3.0e38f;
+        err = timed([&] {
+          hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 16);
+          launch_lanczos(la, fp32, p.nt, p.minw, p.n_wg < n ? p.n_wg : n, p.lds, st);
+        }, t);
+        ++tried;
+        if (t < best) { best = t; best_nt = p.nt; best_mw = p.minw; best_pc = pc; }
+      }
+    }
+  }
+  int best_e = c->eig_per_cu;
+  if (err == hipSuccess) {
+    c->lz_nt[fp32] = best_nt;
+    c->lz_minw[fp32] = best_mw;
+    c->lz_per_cu[fp32] = best_pc;
+    // k_eig consumes the recursion of the last Krylov run (identical for every shape)
+    EigArgs ea = eig_args(c, n);
+    const int cand[5] = {2, 3, 4, 6, 8};
+    float beste = 3.0e38f;
+    for (int q = 0; q < 5 && err == hipSuccess; ++q) {
+      if (cand[q] > c->eig_per_cu_max) continue;
+      const int nw = c->n_cu * cand[q];
+      float t = 3.0e38f;
+      err = timed([&] {
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 16);
+        launch_eig(ea, nw < n ? nw : n, st);
+      }, t);
+      ++tried;
+      if (t < beste) { beste = t; best_e = cand[q]; }
+    }
+    if (err == hipSuccess) c->eig_per_cu = best_e;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(TB_EHIP, "autotune: %s", hipGetErrorString(err));
+  HIP_TRY(hipMemcpyAsync(c->stats, saved, sizeof saved, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  c->stage = 1;                      // the tuning runs replaced the recursion outputs
+  if (shape_out) {
+    shape_out[0] = c->lz_nt[fp32];
+    shape_out[1] = c->lz_per_cu[fp32];
+    shape_out[2] = c->eig_per_cu;
+    shape_out[3] = tried;
+    shape_out[4] = c->lz_minw[fp32];
+  }
   return TB_OK;
 }
 
@@ -406,6 +551,13 @@ extern "C" int tb_get_stats(tb_ctx* c, int64_t* stats_host, int n_stats) {
   if (s[ST_FLAGS] & (FL_HOP_OVERFLOW | FL_CLUSTER_OVERFLOW | FL_COUPLING_OVERFLOW))
     return fail(TB_ECAPACITY, "device list overflow (flags 0x%llx)", (unsigned long long)s[ST_FLAGS]);
   if (s[ST_FLAGS]) return fail(TB_EDEVICE, "device error flags 0x%llx", (unsigned long long)s[ST_FLAGS]);
+  return TB_OK;
+}
+
+extern "C" int tb_set_launch(tb_ctx* c, int atoms_per_launch) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (atoms_per_launch < 0) return fail(TB_EINVAL, "atoms_per_launch=%d < 0", atoms_per_launch);
+  c->atoms_per_launch = atoms_per_launch;
   return TB_OK;
 }
 

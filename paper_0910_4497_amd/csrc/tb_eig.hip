@@ -343,7 +343,7 @@ __device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int hl
 __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
   extern __shared__ double bsm[];
   const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
-  const int atom = 2 * blockIdx.x + half;
+  const int atom = g.atom0 + 2 * blockIdx.x + half;
   const bool valid = atom < g.n_atoms;
   const int dmax = 4 * g.r_max;
   const int d = valid ? 4 * g.kused[atom] : 0;
@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
   for (;;) {
     if (tid == 0) s_atom = atomicAdd(g.counter, 1);
     __syncthreads();
-    const int atom = s_atom;
+    const int atom = g.atom0 + s_atom;
     if (atom >= g.n_atoms) break;
     const int K = g.kused[atom];
     const int d = 4 * K;
@@ -565,7 +565,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
 __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   extern __shared__ double rsm[];
   const int lane = threadIdx.x;
-  const int atom = blockIdx.x;
+  const int atom = g.atom0 + blockIdx.x;
   const int dmax = 4 * g.r_max;
   double* v = rsm;                       // [dmax][4]: f(Lambda) Y[0:4,:]^T
   double* x = rsm + (size_t)dmax * 4;    // [dmax][XS]: rows padded against LDS bank conflicts
@@ -720,11 +720,11 @@ hipError_t eig_set_lds(int r_max) {
 }
 
 void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
-  hipLaunchKernelGGL(k_band, dim3((a.n_atoms + 1) / 2), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
+  hipLaunchKernelGGL(k_band, dim3((a.n_atoms - a.atom0 + 1) / 2), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
   hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
 }
 void launch_rho(const RhoArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_rho, dim3(a.n_atoms), dim3(RHO_NT), rho_lds_bytes(a.r_max), st, a);
+  hipLaunchKernelGGL(k_rho, dim3(a.n_atoms - a.atom0), dim3(RHO_NT), rho_lds_bytes(a.r_max), st, a);
 }
 
 }  // namespace tbk

@@ -18,6 +18,10 @@ constexpr int NCLUSTER_LIMIT = (1 << LOCAL_BITS) - 1;
 constexpr int RMAX_LIMIT = 256;
 constexpr int PROF_MAX = 4096;
 constexpr int N_PHASES = 6;
+constexpr size_t LDS_CU = 160 * 1024;   // LDS per compute unit (gfx950)
+constexpr size_t LDS_RESERVE = 1024;    // per workgroup: static LDS and allocation granularity
+constexpr int LZ_PER_CU_MAX = 4;   // Krylov workgroups per compute unit the tuner may pick
+constexpr int EIG_PER_CU_MAX = 8;  // k_eig workgroups per compute unit the tuner may pick
 
 // Device-side error / statistics words (int64 each).
 enum StatSlot {
@@ -141,7 +145,7 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // ------------------------------------------------------------ kernel args
 struct LanczosArgs {
-  int n_atoms, r_default;
+  int atom0, n_atoms, r_default;       // target atoms [atom0, n_atoms) of this launch
   const int* r_per_atom;
   const int* clu_n; const int* clu_j; const int* loc_off; const uint16_t* loc_ent;
   const double* hnorm; const int* jloc; const int* hop_n;
@@ -160,13 +164,13 @@ struct LanczosArgs {
   double eta, eps_unit;        // re-orthogonalisation threshold, unit roundoff of VT
   int64_t* stats;
 };
-size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_lds, bool vprev_lds);
-void launch_lanczos(const LanczosArgs& a, bool fp32, int n_wg, size_t lds, hipStream_t st);
+size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, bool ab_lds, bool vprev_lds);
+// nt: 256 or 512 threads; minw: 2 or 4 waves per SIMD (register budget)
+void launch_lanczos(const LanczosArgs& a, bool fp32, int nt, int minw, int n_wg, size_t lds, hipStream_t st);
 hipError_t lanczos_set_lds(size_t lds);
-int lanczos_threads();
 
 struct EigArgs {
-  int n_atoms, r_max;
+  int atom0, n_atoms, r_max;           // target atoms [atom0, n_atoms) of this launch
   const double* tab; const int* kused;
   double* lam; double* wgt; double* y1;
   double* rot_cs; uint16_t* rot_p; int* rot_n; int64_t rot_max;
@@ -178,7 +182,7 @@ struct EigArgs {
   int64_t* stats;
 };
 struct RhoArgs {
-  int n_atoms, r_max;
+  int atom0, n_atoms, r_max;           // target atoms [atom0, n_atoms) of this launch
   const int* kused; const int* hop_n; const int* clu_j; int nc_max;
   const double* lam; const double* y1;
   const double* rot_cs; const uint16_t* rot_p; const int* rot_n; int64_t rot_max;
@@ -233,8 +237,14 @@ struct tb_ctx {
   int nc_max, r_max;
   int64_t emax;          // couplings per sphere
   int64_t rot_max;       // rotation-log entries per atom
-  int n_wg_lanczos;      // persistent workgroups of the Krylov kernel
-  int lz_per_cu;         // of them per compute unit (FP64 LDS sizing)
+  int n_cu;              // compute units of the device
+  // launch shape of the Krylov kernel per precision ([0] FP64, [1] FP32):
+  // threads per workgroup, register budget (waves per SIMD) and persistent
+  // workgroups per compute unit
+  int lz_nt[2], lz_minw[2], lz_per_cu[2];
+  int lz_per_cu_max;     // workspace is sized for this many per compute unit
+  int eig_per_cu, eig_per_cu_max;   // persistent k_eig workgroups per compute unit
+  int atoms_per_launch;  // 0: one launch per phase; k: per-atom phases in launches of k atoms
   size_t bytes;
 
   // state
@@ -271,7 +281,6 @@ struct tb_ctx {
   double* evec;                                            // [N][D][D]
   double* tri;                                             // [N][2][D]
   double* eig_scratch;                                     // [WG_EIG][D][4][EIG_NT]
-  int n_wg_eig;                                            // persistent workgroups of k_eig
   // mu / energies (K6/K8)
   double* mu_state;      // [8]: lo, hi, mu, done, N(mu) ...
   double* partial;       // [NPART][4]

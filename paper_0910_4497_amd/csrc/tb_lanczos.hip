@@ -27,8 +27,6 @@
 
 namespace tbk {
 
-constexpr int LZ_NT = 512;
-constexpr int LZ_NW = LZ_NT / 64;
 
 template <typename VT> struct Vec4;
 template <> struct Vec4<double> { typedef double4 T; };
@@ -38,7 +36,7 @@ template <> struct Vec4<float> { typedef float4 T; };
 // Sum m values (m <= 16) over the workgroup; result in out[0..m-1] (LDS).
 // FULL: the first barrier is a full one (global stores become visible to the
 // workgroup); otherwise both order LDS only.
-template <int M, bool FULL = false>
+template <int M, int NW, bool FULL = false>
 __device__ __forceinline__ void block_sum(double (&v)[M], double* red, double* out) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
@@ -50,7 +48,7 @@ __device__ __forceinline__ void block_sum(double (&v)[M], double* red, double* o
   if (FULL) __syncthreads(); else lds_barrier();
   if (tid < M) {
     double s = 0.0;
-    for (int w = 0; w < LZ_NW; ++w) s += red[w * 16 + tid];
+    for (int w = 0; w < NW; ++w) s += red[w * 16 + tid];
     out[tid] = s;
   }
   lds_barrier();
@@ -121,9 +119,12 @@ __device__ __forceinline__ void inv_upper4r(const double (&U)[16], const bool (&
   }
 }
 
-template <typename VT>
-__global__ void __launch_bounds__(LZ_NT, 4)
+// LZ_NT threads per workgroup; MINW waves per SIMD the register allocation
+// must allow (4: 128 VGPRs, some spilled; 2: 256 VGPRs, none spilled)
+template <typename VT, int LZ_NT, int MINW>
+__global__ void __launch_bounds__(LZ_NT, MINW)
 k_lanczos(LanczosArgs g) {
+  constexpr int LZ_NW = LZ_NT / 64;
   extern __shared__ unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ncap = g.nc_max, Rcap = 4 * ncap;
@@ -160,7 +161,7 @@ k_lanczos(LanczosArgs g) {
   for (;;) {
     if (tid == 0) s_atom = atomicAdd(g.counter, 1);
     __syncthreads();
-    const int atom = s_atom;
+    const int atom = g.atom0 + s_atom;
     if (atom >= g.n_atoms) break;
     const int n = g.clu_n[atom];
     const int R = 4 * n;
@@ -374,7 +375,7 @@ k_lanczos(LanczosArgs g) {
         }
         // the one full barrier of the step: the global stores of the previous
         // step (V_k, rho rows, A, B, Omega) are visible to the workgroup after it
-        block_sum<10, true>(acc, s_red, G);
+        block_sum<10, LZ_NW, true>(acc, s_red, G);
         // V_{k+1} written; V_{k-1} read unless it is in LDS
         bytes += (int64_t)R * 4 * (int64_t)sizeof(VT) * (k > 0 && !g.vprev_lds ? 2 : 1);
       }
@@ -615,7 +616,7 @@ k_lanczos(LanczosArgs g) {
           acc[4] += w1 * w1; acc[5] += w1 * w2; acc[6] += w1 * w3;
           acc[7] += w2 * w2; acc[8] += w2 * w3; acc[9] += w3 * w3;
         }
-        block_sum<10>(acc, s_red, G);              // G[0..9] packed Gram
+        block_sum<10, LZ_NW>(acc, s_red, G);              // G[0..9] packed Gram
         bool again = false;
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
@@ -670,7 +671,7 @@ k_lanczos(LanczosArgs g) {
           acc[4] += v[1] * v[1]; acc[5] += v[1] * v[2]; acc[6] += v[1] * v[3];
           acc[7] += v[2] * v[2]; acc[8] += v[2] * v[3]; acc[9] += v[3] * v[3];
         }
-        block_sum<10>(acc, s_red, G);
+        block_sum<10, LZ_NW>(acc, s_red, G);
         {
           double Gf[16], U2[16], X2[16], r2;
 #pragma unroll
@@ -706,7 +707,7 @@ k_lanczos(LanczosArgs g) {
               double a1[1] = {0.0};
               for (int row = tid; row < R; row += LZ_NT)
                 a1[0] += (double)s_W[4 * row + p] * (double)s_W[4 * row + c];
-              block_sum<1>(a1, s_red, G);
+              block_sum<1, LZ_NW>(a1, s_red, G);
               const double dot = G[0];
               for (int row = tid; row < R; row += LZ_NT)
                 s_W[4 * row + c] = (VT)((double)s_W[4 * row + c] - dot * (double)s_W[4 * row + p]);
@@ -716,7 +717,7 @@ k_lanczos(LanczosArgs g) {
           }
           double a1[1] = {0.0};
           for (int row = tid; row < R; row += LZ_NT) a1[0] += (double)s_W[4 * row + c] * (double)s_W[4 * row + c];
-          block_sum<1>(a1, s_red, G);
+          block_sum<1, LZ_NW>(a1, s_red, G);
           const double nrm = sqrt(G[0]);
           const bool keep = nrm > tol;
           const double sc = keep ? 1.0 / nrm : 0.0;
@@ -778,12 +779,13 @@ k_lanczos(LanczosArgs g) {
   }
 }
 
-size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_lds, bool vprev_lds) {
+size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, bool ab_lds, bool vprev_lds) {
   const size_t vt = fp32 ? 4 : 8;
   const size_t Rcap = 4 * (size_t)nc_max;
+  const int nw = nt / 64;
   size_t b = 2 * Rcap * 4 * vt + 16;
-  const int cslots = r_max > 2 * LZ_NW ? r_max : 2 * LZ_NW;
-  b += (size_t)cslots * 16 * 8 + LZ_NW * 16 * 8 + 224 * 8;
+  const int cslots = r_max > 2 * nw ? r_max : 2 * nw;
+  b += (size_t)cslots * 16 * 8 + nw * 16 * 8 + 224 * 8;
   b += (size_t)(nc_max + 1) * 4 + (size_t)nc_max * 4 + (size_t)nc_max + 16;
   if (om_lds) b += (size_t)3 * r_max * 16 * 4;
   if (ab_lds) b += (size_t)r_max * 32 * 4;
@@ -791,21 +793,32 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, bool om_lds, bool ab_
   return b + 64;
 }
 
-void launch_lanczos(const LanczosArgs& a, bool fp32, int n_wg, size_t lds, hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_lanczos<float>, dim3(n_wg), dim3(LZ_NT), lds, st, a);
-  else
-    hipLaunchKernelGGL(k_lanczos<double>, dim3(n_wg), dim3(LZ_NT), lds, st, a);
+template <typename VT>
+static void launch_lz(const LanczosArgs& a, int nt, int minw, int n_wg, size_t lds, hipStream_t st) {
+  if (minw == 2) {
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 2>), dim3(n_wg), dim3(512), lds, st, a);
+  } else {
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 4>), dim3(n_wg), dim3(512), lds, st, a);
+  }
+}
+
+void launch_lanczos(const LanczosArgs& a, bool fp32, int nt, int minw, int n_wg, size_t lds, hipStream_t st) {
+  if (fp32) launch_lz<float>(a, nt, minw, n_wg, lds, st);
+  else launch_lz<double>(a, nt, minw, n_wg, lds, st);
 }
 
 hipError_t lanczos_set_lds(size_t lds) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_lanczos<double>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_lanczos<float>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* fn[8] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
+                       (const void*)k_lanczos<float, 256, 4>, (const void*)k_lanczos<float, 512, 4>,
+                       (const void*)k_lanczos<double, 256, 2>, (const void*)k_lanczos<double, 512, 2>,
+                       (const void*)k_lanczos<float, 256, 2>, (const void*)k_lanczos<float, 512, 2>};
+  for (int q = 0; q < 8; ++q) {
+    hipError_t e = hipFuncSetAttribute(fn[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
-
-int lanczos_threads() { return LZ_NT; }
 
 }  // namespace tbk

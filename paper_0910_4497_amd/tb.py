@@ -23,7 +23,8 @@ ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4:
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
               "max_cluster_pos", "memory_bytes", "reorth_second_pass", "reorth_steps", "basis_bytes")
 EXPORTS = ("tb_create", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
-           "tb_energy_forces", "tb_get_stats", "tb_profile_enable", "tb_profile_read", "tb_last_error")
+           "tb_energy_forces", "tb_get_stats", "tb_set_launch", "tb_autotune", "tb_profile_enable", "tb_profile_read",
+           "tb_last_error")
 PHASES = ("lists_local", "lanczos", "eig", "mu", "rho", "forces")
 RHO_ROWS_MAX = 25          # rho row atoms per target: itself + at most 24 neighbours
 
@@ -77,6 +78,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tb_rho_layout.argtypes = [P, ctypes.POINTER(I64), P, P]
     lib.tb_energy_forces.argtypes = [P, P, P]
     lib.tb_get_stats.argtypes = [P, ctypes.POINTER(I64), I]
+    lib.tb_set_launch.argtypes = [P, I]
+    lib.tb_autotune.argtypes = [P, I, P, I, ctypes.POINTER(I)]
     lib.tb_profile_enable.argtypes = [P, I]
     lib.tb_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I]
     lib.tb_last_error.restype = ctypes.c_char_p
@@ -181,6 +184,19 @@ class TBContext:
             forces = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=self.device)
         _check(self.lib.tb_energy_forces(self.h, _ptr(e_out), _ptr(forces)))
         return e_out, forces
+
+    def autotune(self, r: int, precision: str = "fp64", r_per_atom: torch.Tensor | None = None) -> dict:
+        """Times the launch shapes of the Krylov kernel and the eigensolver on
+        the current spheres and keeps the fastest for this precision (later
+        results agree with the default shape's to rounding)."""
+        out = (ctypes.c_int * 5)()
+        _check(self.lib.tb_autotune(self.h, int(r), _ptr(r_per_atom), PRECISIONS[precision], out))
+        return {"lanczos_threads": out[0], "lanczos_wg_per_cu": out[1], "lanczos_waves_per_simd": out[4],
+                "eig_wg_per_cu": out[2], "candidates": out[3]}
+
+    def set_launch(self, atoms_per_launch: int):
+        """0: one launch per per-atom phase; k: launches over groups of k atoms."""
+        _check(self.lib.tb_set_launch(self.h, int(atoms_per_launch)))
 
     def profile(self, enable: bool):
         _check(self.lib.tb_profile_enable(self.h, 1 if enable else 0))

@@ -50,3 +50,5 @@ def test_last_error_callable_without_device():
     code = lib.tb_krylov_rho(None, 10, None, 0.1, float("nan"), 4.0, 0, None, None)
     assert code == -1
     assert b"null" in lib.tb_last_error()
+    assert lib.tb_set_launch(None, 1) == -1
+    assert lib.tb_autotune(None, 10, None, 0, None) == -1

@@ -1,0 +1,83 @@
+"""Launch granularity of the per-atom phases: one launch per phase over all
+atoms, one launch per atom, and launches over groups of 7 atoms (a ragged last
+group) give bitwise the same density matrix, energies, forces and chemical
+potential; the per-atom Krylov orders are mixed (10, 20, 30) so that atoms of
+different cost share and split launches."""
+import numpy as np
+import pytest
+
+from paper_0910_4497_amd import inputs
+from parity_util import gpu_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_launch_granularity_is_bitwise_neutral(torch_cuda, precision):
+    from paper_0910_4497_amd.tb import TBContext
+    w = inputs.workload("c60_240")
+    r_atoms = np.random.default_rng(4242).choice([10, 20, 30], w.n_atoms).astype(np.int32)
+    ctx = TBContext(w.n_atoms, 130, 30)
+    runs = {}
+    for k in (0, 1, 7):
+        ctx.set_launch(k)
+        runs[k] = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, 30, w.kT, n_electrons=w.n_electrons,
+                          precision=precision, r_per_atom=r_atoms)
+    ctx.close()
+    ref = runs[0]
+    assert ref["stats"]["flags"] == 0
+    for k in (1, 7):
+        got = runs[k]
+        assert got["mu"] == ref["mu"], k
+        for key in ("rho", "row_ptr", "col_j", "e", "forces"):
+            assert np.array_equal(got[key], ref[key]), (k, key)
+        for key in ("reorth_steps", "basis_bytes", "deflated", "early_stop"):
+            assert got["stats"][key] == ref["stats"][key], (k, key)
+    print(f"  {precision}: launch modes 0/1/7 bitwise equal; E_tot {ref['e'][3]:.9f} eV, mu {ref['mu']:.12f}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotuned_shape_agrees_to_rounding(torch_cuda, precision):
+    """The tuner times every fitting launch shape on the current spheres and
+    keeps the fastest. The thread count of a shape sets the order of the
+    workgroup reductions, so later results agree with those of the default
+    shape to rounding: FP64 to 1e-12 relative; FP32 within 1e-4 eV/A in the
+    forces (the mixed-mode bar is 1e-3). The diagnostic counters of the step
+    before the tuning are kept."""
+    import torch
+    from paper_0910_4497_amd.tb import TBContext
+    w = inputs.workload("c60_240")
+    r_atoms = np.random.default_rng(4243).choice([10, 20, 30], w.n_atoms).astype(np.int32)
+    ctx = TBContext(w.n_atoms, 130, 30)
+    ref = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, 30, w.kT, n_electrons=w.n_electrons,
+                  precision=precision, r_per_atom=r_atoms)
+    rpa = torch.tensor(r_atoms, device="cuda:0")
+    shape = ctx.autotune(30, precision, r_per_atom=rpa)
+    after = ctx.stats()
+    for key in ("reorth_steps", "basis_bytes", "max_cluster", "flags"):
+        assert after[key] == ref["stats"][key], key
+    assert shape["lanczos_threads"] in (256, 512) and shape["lanczos_waves_per_simd"] in (2, 4)
+    assert 1 <= shape["lanczos_wg_per_cu"] <= 4 and 2 <= shape["eig_wg_per_cu"] <= 8
+    assert shape["candidates"] >= 3
+    got = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, 30, w.kT, n_electrons=w.n_electrons,
+                  precision=precision, r_per_atom=r_atoms)
+    ctx.close()
+    assert np.array_equal(got["row_ptr"], ref["row_ptr"]) and np.array_equal(got["col_j"], ref["col_j"])
+    df = float(np.abs(got["forces"] - ref["forces"]).max())
+    dr = float(np.abs(got["rho"] - ref["rho"]).max())
+    de = float(np.abs(got["e"] - ref["e"]).max() / np.abs(ref["e"]).max())
+    print(f"  {precision}: tuned shape {shape}; vs default: force {df:.2e} eV/A, rho {dr:.2e}, "
+          f"energies {de:.2e} rel, mu {abs(got['mu'] - ref['mu']):.2e} eV")
+    if precision == "fp64":
+        fs = float(np.abs(ref["forces"]).max())
+        assert df <= 1e-12 * fs and dr <= 1e-12 and de <= 1e-12 and abs(got["mu"] - ref["mu"]) <= 1e-12
+    else:
+        assert df <= 1e-4 and dr <= 1e-5 and de <= 1e-7 and abs(got["mu"] - ref["mu"]) <= 1e-6
