@@ -8,9 +8,10 @@ cutoff sphere, projected eigensolve, global chemical potential, density-matrix
 blocks, band energy + forces Tr[rho dH/dR] + repulsion. Positions and
 velocities stay in HBM; the timed region contains no host transfers.
 
-Prints one JSON line. The headline value is the mixed-precision path (Krylov
-recursion in FP32, everything else FP64) when its force error against the
-FP64 path stays within 1e-3 eV/A; the FP64 path is measured beside it.
+Prints one JSON line. The headline value is the fastest reduced-precision
+path (Krylov recursion in FP32, or FP32 with BF16 operands in H.V; everything
+else FP64) whose force error against the FP64 path stays within 1e-3 eV/A,
+else the FP64 path; every path is measured and reported in `modes`.
 """
 from __future__ import annotations
 
@@ -55,7 +56,8 @@ def parse():
     ap.add_argument("--workload", default="c60_1920")
     ap.add_argument("--dt", type=float, default=0.5, help="fs")
     ap.add_argument("--temperature", type=float, default=300.0, help="K, initial Maxwell velocities")
-    ap.add_argument("--precision", choices=("both", "fp32", "fp64"), default="both")
+    ap.add_argument("--precision", choices=("all", "both", "fp32", "bf16", "fp64"), default="all",
+                    help="all: FP32, BF16-operand and FP64 recursions; both: FP32 and FP64")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle atom solves timed on host cores (0: one step's worth, at most 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -202,7 +204,7 @@ def main():
     fixed = args.start == "fixed" or (args.start == "auto" and args.workload in
                                         ("c60_6480_strained", "c60_15360"))
     results = {}
-    precs = ["fp32", "fp64"] if args.precision == "both" else [args.precision]
+    precs = {"all": ["fp32", "bf16", "fp64"], "both": ["fp32", "fp64"]}.get(args.precision, [args.precision])
     shapes = {}
     for prec in precs:
         if not args.no_autotune:
@@ -229,9 +231,11 @@ def main():
             r["force_err"] = float((r["f_first"] - ref["f_first"]).abs().max().item())
             r["energy_err_per_atom"] = float(abs(r["e_first"][3] - ref["e_first"][3]).item()) / N
 
-    head_prec = "fp32" if ("fp32" in results and results["fp32"].get("force_err", 0.0) <= 1e-3) else "fp64"
+    # headline: the fastest reduced-precision mode whose first-step force error
+    # against the FP64 path is within 1e-3 eV/A, else FP64
+    ok = [p for p in ("fp32", "bf16") if p in results and results[p].get("force_err", 1.0) <= 1e-3]
+    head_prec = max(ok, key=lambda p: results[p]["steps_per_s"]) if ok else "fp64"
     head = results[head_prec]
-    vt = 4 if head_prec == "fp32" else 8
     lz_ms, lz_n = head["phases"]["lanczos"]
     lz_avg_ms = lz_ms / max(lz_n, 1)
     # algorithmic basis bytes of the last launch, counted by the kernel: V_0 and
@@ -289,7 +293,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if head_prec == "fp32" else "f64",
+        "dtype": {"fp32": "f32+f64", "bf16": "bf16+f32+f64"}.get(head_prec, "f64"),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {N} C atoms, fcc C60 crystal, periodic",
                    "n_atoms": N, "r_cluster_A": w.r_cut, "krylov_block_steps": w.r, "kT_eV": w.kT,
@@ -300,8 +304,8 @@ def main():
         "cpu_baseline": cpu,
         "modes": extra,
     }
-    if "fp32" in results and "fp64" in results:
-        line["mixed_over_fp64"] = round(results["fp32"]["steps_per_s"] / results["fp64"]["steps_per_s"], 3)
+    if head_prec != "fp64" and "fp64" in results:
+        line["mixed_over_fp64"] = round(head["steps_per_s"] / results["fp64"]["steps_per_s"], 3)
     if plain is not None:
         line["headline_over_plain_fp64"] = round(head["steps_per_s"] / plain["steps_per_s"], 1)
     print(json.dumps(line))

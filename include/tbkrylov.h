@@ -55,8 +55,15 @@ enum {
 
 /* Precision of the Krylov recursion (H.V products, basis storage and the
  * re-orthogonalisation). Projected eigensolve, chemical potential, block
- * normalisation norms, density-matrix assembly and forces are FP64 always. */
-enum { TB_FP64 = 0, TB_FP32 = 1 };
+ * normalisation norms, density-matrix assembly and forces are FP64 always.
+ *   TB_FP64  everything in FP64.
+ *   TB_FP32  H.V, basis, three-term update and passes in FP32 (norms and
+ *            Gram sums accumulated in FP64).
+ *   TB_BF16  as TB_FP32, but the operands of H.V (coupling data, on-site and
+ *            bond parameters, V_k) are rounded to BF16 and the products
+ *            accumulated in FP32; the orthogonality estimate then asks for a
+ *            re-orthogonalisation pass at every block step. */
+enum { TB_FP64 = 0, TB_FP32 = 1, TB_BF16 = 2 };
 
 /* Tight-binding parameters of the Xu-form carbon model (Sec. 4 names the
  * Xu parameter set, cutoff 2.6 A). Hopping scale s(r) = (r0/r)^n
@@ -117,7 +124,7 @@ int tb_build_local_H(tb_ctx *ctx, int64_t n_atoms, const double *pos,
  *   mu          fixed chemical potential in eV, or NaN: then mu solves
  *               sum_i sum_m f(lambda_m^i) w_m^i = n_electrons
  *               (w_m^i = weight of Ritz pair m on the seed block).
- *   precision   TB_FP64 or TB_FP32 (see the enum).
+ *   precision   TB_FP64, TB_FP32 or TB_BF16 (see the enum).
  *   mu_out      device double (nullable) receives mu.
  *   rho_out     [nnz_pairs][4][4] device: rho_out[p][a][b] = rho_{j a, i b}
  *               for the pair list of tb_rho_layout (target i, row atom j).

@@ -138,7 +138,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   // (at most 2), for both precisions; tb_autotune may change it
   int per_cu = (int)(LDS_CU / (lds + LDS_RESERVE));
   per_cu = per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu);
-  for (int q = 0; q < 2; ++q) { c->lz_nt[q] = 512; c->lz_minw[q] = 4; c->lz_per_cu[q] = per_cu; }
+  for (int q = 0; q < 3; ++q) { c->lz_nt[q] = 512; c->lz_minw[q] = 4; c->lz_per_cu[q] = per_cu; }
   // workspace for the largest shape the tuner may pick: the smallest (FP32,
   // 256-thread) footprint, at most LZ_PER_CU_MAX per compute unit
   const size_t lds_min = lanczos_lds_bytes(n_cluster_max, r_max, true, 256, false, false, false);
@@ -165,6 +165,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(hop_d, N * ZMAX * 4);
   ALLOC(pair64, N * ZMAX * 4);
   ALLOC(pair32, N * ZMAX * 4);
+  ALLOC(pair16, N * ZMAX * 4);
   ALLOC(clu_n, N);
   ALLOC(clu_j, N * NC);
   ALLOC(loc_off, N * (NC + 1));
@@ -300,12 +301,14 @@ static LzPlan lanczos_plan(const tb_ctx* c, bool fp32, int nt, int minw, int per
   return p;
 }
 
-static LanczosArgs lanczos_args(const tb_ctx* c, int n, int r, const int* r_per_atom, bool fp32) {
+static LanczosArgs lanczos_args(const tb_ctx* c, int n, int r, const int* r_per_atom, int precision) {
+  const bool fp32 = precision != TB_FP64;
   LanczosArgs la;
   la.atom0 = 0; la.n_atoms = n; la.r_default = r; la.r_per_atom = r_per_atom;
   la.clu_n = c->clu_n; la.clu_j = c->clu_j; la.loc_off = c->loc_off; la.loc_ent = c->loc_ent;
   la.hnorm = c->hnorm; la.jloc = c->jloc; la.hop_n = c->hop_n;
-  la.pair = fp32 ? (const void*)c->pair32 : (const void*)c->pair64;
+  la.pair = precision == TB_BF16 ? (const void*)c->pair16
+          : (fp32 ? (const void*)c->pair32 : (const void*)c->pair64);
   la.nc_max = c->nc_max; la.emax = c->emax; la.r_max = c->r_max;
   la.eps_s = c->model.eps_s; la.eps_p = c->model.eps_p; la.v_sss = c->model.v_sss;
   la.v_sps = c->model.v_sps; la.v_pps = c->model.v_pps; la.v_ppp = c->model.v_ppp;
@@ -316,7 +319,9 @@ static LanczosArgs lanczos_args(const tb_ctx* c, int n, int r, const int* r_per_
   // below the parity bar in FP64; in FP32 at the level the FP32 recursion
   // already carries
   la.eta = fp32 ? 1e-4 : 1e-12;
-  la.eps_unit = fp32 ? (double)FLT_EPSILON : DBL_EPSILON;
+  // BF16 operands perturb every product by ~2^-8 relative: the estimate's
+  // rounding term uses the BF16 epsilon, so the passes run at every step
+  la.eps_unit = precision == TB_BF16 ? 0.0078125 : (fp32 ? (double)FLT_EPSILON : DBL_EPSILON);
   la.om_lds = la.ab_lds = la.vprev_lds = 0;
   return la;
 }
@@ -336,7 +341,8 @@ static int check_krylov_args(const tb_ctx* c, int r, int precision) {
   if (!c) return fail(TB_EINVAL, "ctx is null");
   if (c->stage < 1) return fail(TB_ESTATE, "tb_build_local_H must be called first");
   if (r < 1 || r > c->r_max) return fail(TB_ECAPACITY, "r=%d outside [1, %d]", r, c->r_max);
-  if (precision != TB_FP64 && precision != TB_FP32) return fail(TB_EINVAL, "unknown precision %d", precision);
+  if (precision != TB_FP64 && precision != TB_FP32 && precision != TB_BF16)
+    return fail(TB_EINVAL, "unknown precision %d", precision);
   return TB_OK;
 }
 
@@ -355,11 +361,11 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   hipStream_t st = c->stream;
   c->kT = kT;
   c->precision = precision;
-  const bool fp32 = precision == TB_FP32;
+  const bool fp32 = precision != TB_FP64;      // FP32 recursion (TB_FP32, TB_BF16)
   // K4: block Lanczos
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 16);
-  LanczosArgs la = lanczos_args(c, n, r, r_per_atom, fp32);
-  const LzPlan plan = lanczos_plan(c, fp32, c->lz_nt[fp32], c->lz_minw[fp32], c->lz_per_cu[fp32]);
+  LanczosArgs la = lanczos_args(c, n, r, r_per_atom, precision);
+  const LzPlan plan = lanczos_plan(c, fp32, c->lz_nt[precision], c->lz_minw[precision], c->lz_per_cu[precision]);
   la.om_lds = plan.om_lds; la.ab_lds = plan.ab_lds; la.vprev_lds = plan.vprev_lds;
   // per-atom phases run over consecutive groups of `chunk` target atoms, one
   // launch per group (a single group by default); persistent kernels take a
@@ -370,7 +376,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
     const int a1 = n - a0 > chunk ? a0 + chunk : n;
     if (a0 > 0) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 1);
     la.atom0 = a0; la.n_atoms = a1;
-    launch_lanczos(la, fp32, plan.nt, plan.minw, plan.n_wg < a1 - a0 ? plan.n_wg : a1 - a0, plan.lds, st);
+    launch_lanczos(la, precision, plan.nt, plan.minw, plan.n_wg < a1 - a0 ? plan.n_wg : a1 - a0, plan.lds, st);
   }
   prof_end(c, pk);
   // K5: projected eigensolve
@@ -423,7 +429,7 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
   if (bad) return bad;
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = c->stream;
-  const bool fp32 = precision == TB_FP32;
+  const bool fp32 = precision != TB_FP64;
   const int n = (int)c->n_atoms;
   int64_t saved[ST_NSTATS];
   HIP_TRY(hipMemcpyAsync(saved, c->stats, sizeof saved, hipMemcpyDeviceToHost, st));
@@ -445,8 +451,9 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
     }
     return hipGetLastError();
   };
-  LanczosArgs la = lanczos_args(c, n, r, r_per_atom, fp32);
-  int best_nt = c->lz_nt[fp32], best_mw = c->lz_minw[fp32], best_pc = c->lz_per_cu[fp32], tried = 0;
+  LanczosArgs la = lanczos_args(c, n, r, r_per_atom, precision);
+  int best_nt = c->lz_nt[precision], best_mw = c->lz_minw[precision], best_pc = c->lz_per_cu[precision];
+  int tried = 0;
   float best = 3.0e38f;
   hipError_t err = hipSuccess;
   const int nts[2] = {256, 512}, mws[2] = {4, 2};
@@ -461,7 +468,7 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
         float t = 3.0e38f;
         err = timed([&] {
           hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 16);
-          launch_lanczos(la, fp32, p.nt, p.minw, p.n_wg < n ? p.n_wg : n, p.lds, st);
+          launch_lanczos(la, precision, p.nt, p.minw, p.n_wg < n ? p.n_wg : n, p.lds, st);
         }, t);
         ++tried;
         if (t < best) { best = t; best_nt = p.nt; best_mw = p.minw; best_pc = pc; }
@@ -470,9 +477,9 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
   }
   int best_e = c->eig_per_cu;
   if (err == hipSuccess) {
-    c->lz_nt[fp32] = best_nt;
-    c->lz_minw[fp32] = best_mw;
-    c->lz_per_cu[fp32] = best_pc;
+    c->lz_nt[precision] = best_nt;
+    c->lz_minw[precision] = best_mw;
+    c->lz_per_cu[precision] = best_pc;
     // k_eig consumes the recursion of the last Krylov run (identical for every shape)
     EigArgs ea = eig_args(c, n);
     const int cand[5] = {2, 3, 4, 6, 8};
@@ -497,11 +504,11 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
   HIP_TRY(hipStreamSynchronize(st));
   c->stage = 1;                      // the tuning runs replaced the recursion outputs
   if (shape_out) {
-    shape_out[0] = c->lz_nt[fp32];
-    shape_out[1] = c->lz_per_cu[fp32];
+    shape_out[0] = c->lz_nt[precision];
+    shape_out[1] = c->lz_per_cu[precision];
     shape_out[2] = c->eig_per_cu;
     shape_out[3] = tried;
-    shape_out[4] = c->lz_minw[fp32];
+    shape_out[4] = c->lz_minw[precision];
   }
   return TB_OK;
 }

@@ -4,12 +4,28 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "../../include/tbkrylov.h"
 
 struct tb_ctx;
 
 namespace tbk {
+
+// BF16 (8 significand bits) by round-to-nearest-even of an FP32 value; the
+// values here are finite. bf16_bits: the upper 16 bits; bf16_round: the
+// rounded value as FP32.
+__host__ __device__ inline uint16_t bf16_bits(float x) {
+  unsigned u;
+  memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_round(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
 
 constexpr int ZMAX = 24;           // neighbours within max(rm, dm) per atom
 constexpr int JMAX = ZMAX + 1;     // rho row atoms per target: itself + hop list
@@ -165,8 +181,9 @@ struct LanczosArgs {
   int64_t* stats;
 };
 size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, bool ab_lds, bool vprev_lds);
-// nt: 256 or 512 threads; minw: 2 or 4 waves per SIMD (register budget)
-void launch_lanczos(const LanczosArgs& a, bool fp32, int nt, int minw, int n_wg, size_t lds, hipStream_t st);
+// precision: TB_FP64 / TB_FP32 / TB_BF16; nt: 256 or 512 threads; minw: 2 or
+// 4 waves per SIMD (register budget)
+void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int n_wg, size_t lds, hipStream_t st);
 hipError_t lanczos_set_lds(size_t lds);
 
 struct EigArgs {
@@ -238,10 +255,10 @@ struct tb_ctx {
   int64_t emax;          // couplings per sphere
   int64_t rot_max;       // rotation-log entries per atom
   int n_cu;              // compute units of the device
-  // launch shape of the Krylov kernel per precision ([0] FP64, [1] FP32):
+  // launch shape of the Krylov kernel per precision ([0] FP64, [1] FP32, [2] BF16):
   // threads per workgroup, register budget (waves per SIMD) and persistent
   // workgroups per compute unit
-  int lz_nt[2], lz_minw[2], lz_per_cu[2];
+  int lz_nt[3], lz_minw[3], lz_per_cu[3];
   int lz_per_cu_max;     // workspace is sized for this many per compute unit
   int eig_per_cu, eig_per_cu_max;   // persistent k_eig workgroups per compute unit
   int atoms_per_launch;  // 0: one launch per phase; k: per-atom phases in launches of k atoms
@@ -261,6 +278,7 @@ struct tb_ctx {
   // lists (K1-K3)
   int* hop_n; int* hop_j; int* hop_rev; double* hop_d;     // [N][ZMAX][4]: dx dy dz r
   double* pair64; float* pair32;                           // [N][ZMAX][4]: hx hy hz s
+  uint16_t* pair16;                                        // [N][ZMAX][4]: the same in BF16
   int* clu_n; int* clu_j;                                  // [N][NC]
   int* loc_off; uint16_t* loc_ent;                         // [N][NC+1], [N][EMAX]
   double* hnorm;                                           // [N]

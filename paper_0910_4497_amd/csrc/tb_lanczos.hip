@@ -120,10 +120,14 @@ __device__ __forceinline__ void inv_upper4r(const double (&U)[16], const bool (&
 }
 
 // LZ_NT threads per workgroup; MINW waves per SIMD the register allocation
-// must allow (4: 128 VGPRs, some spilled; 2: 256 VGPRs, none spilled)
-template <typename VT, int LZ_NT, int MINW>
+// must allow (4: 128 VGPRs, some spilled; 2: 256 VGPRs, none spilled). BF
+// (with VT = float): the operands of H.V -- the coupling data, the on-site and
+// bond parameters, and V_k -- are rounded to BF16 and the products
+// accumulated in FP32; everything else is the FP32 recursion.
+template <typename VT, int LZ_NT, int MINW, bool BF = false>
 __global__ void __launch_bounds__(LZ_NT, MINW)
 k_lanczos(LanczosArgs g) {
+  static_assert(!BF || sizeof(VT) == 4, "BF16 operands with the FP32 recursion only");
   constexpr int LZ_NW = LZ_NT / 64;
   extern __shared__ unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -207,8 +211,11 @@ k_lanczos(LanczosArgs g) {
       // ---- 1. W = H V_k, fused with the partial sums of A_k = V_k^T W
       {
         double accA[4] = {0.0, 0.0, 0.0, 0.0};     // A[c'][cq], c' = 0..3
-        const VT es = (VT)g.eps_s, ep = (VT)g.eps_p, vsss = (VT)g.v_sss, vsps = (VT)g.v_sps,
-                 vdif = (VT)(g.v_pps - g.v_ppp), vppp = (VT)g.v_ppp;
+        auto op = [](VT x) -> VT {                 // an operand of the H.V products
+          if constexpr (BF) return bf16_round(x); else return x;
+        };
+        const VT es = op((VT)g.eps_s), ep = op((VT)g.eps_p), vsss = op((VT)g.v_sss), vsps = op((VT)g.v_sps),
+                 vdif = op((VT)(g.v_pps - g.v_ppp)), vppp = op((VT)g.v_ppp);
         typedef typename Vec4<VT>::T V4;
         // FP64: item (a, part) -- the four lanes of atom a take every fourth
         // coupling and compute all four columns, then a reduce-scatter over the
@@ -279,7 +286,7 @@ k_lanczos(LanczosArgs g) {
           } else {
 
           const VT* va = s_V + 16 * a + c;
-          w0 = es * va[0]; w1 = ep * va[4]; w2 = ep * va[8]; w3 = ep * va[12];
+          w0 = es * op(va[0]); w1 = ep * op(va[4]); w2 = ep * op(va[8]); w3 = ep * op(va[12]);
           const int gid = s_gid[a];
           int e1 = s_off[a + 1];
           if (e1 > g.emax) e1 = (int)g.emax;
@@ -291,7 +298,14 @@ k_lanczos(LanczosArgs g) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const int slot = pe[u] >> LOCAL_BITS;
-              hp4[u] = *(const V4*)(pairs + ((size_t)gid * ZMAX + slot) * 4);
+              if constexpr (BF) {
+                // four BF16 values (x, y, z, s) -> FP32, exactly
+                const uint2 raw = *(const uint2*)((const uint16_t*)g.pair + ((size_t)gid * ZMAX + slot) * 4);
+                hp4[u].x = __uint_as_float(raw.x << 16); hp4[u].y = __uint_as_float(raw.x & 0xffff0000u);
+                hp4[u].z = __uint_as_float(raw.y << 16); hp4[u].w = __uint_as_float(raw.y & 0xffff0000u);
+              } else {
+                hp4[u] = *(const V4*)(pairs + ((size_t)gid * ZMAX + slot) * 4);
+              }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -299,7 +313,7 @@ k_lanczos(LanczosArgs g) {
               const int b = pe[u] & NCLUSTER_LIMIT;
               const VT hx = hp4[u].x, hy = hp4[u].y, hz = hp4[u].z, sv = hp4[u].w;
               const VT* vb = s_V + 16 * b + c;
-              const VT vs = vb[0], vx = vb[4], vy = vb[8], vz = vb[12];
+              const VT vs = op(vb[0]), vx = op(vb[4]), vy = op(vb[8]), vz = op(vb[12]);
               const VT hp = hx * vx + hy * vy + hz * vz;
               w0 += sv * (vsss * vs + vsps * hp);
               const VT t = sv * (vdif * hp - vsps * vs);
@@ -793,28 +807,31 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, 
   return b + 64;
 }
 
-template <typename VT>
+template <typename VT, bool BF = false>
 static void launch_lz(const LanczosArgs& a, int nt, int minw, int n_wg, size_t lds, hipStream_t st) {
   if (minw == 2) {
-    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2>), dim3(n_wg), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_lanczos<VT, 512, 2>), dim3(n_wg), dim3(512), lds, st, a);
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2, BF>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 2, BF>), dim3(n_wg), dim3(512), lds, st, a);
   } else {
-    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4>), dim3(n_wg), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_lanczos<VT, 512, 4>), dim3(n_wg), dim3(512), lds, st, a);
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4, BF>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 4, BF>), dim3(n_wg), dim3(512), lds, st, a);
   }
 }
 
-void launch_lanczos(const LanczosArgs& a, bool fp32, int nt, int minw, int n_wg, size_t lds, hipStream_t st) {
-  if (fp32) launch_lz<float>(a, nt, minw, n_wg, lds, st);
+void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int n_wg, size_t lds, hipStream_t st) {
+  if (precision == TB_BF16) launch_lz<float, true>(a, nt, minw, n_wg, lds, st);
+  else if (precision == TB_FP32) launch_lz<float>(a, nt, minw, n_wg, lds, st);
   else launch_lz<double>(a, nt, minw, n_wg, lds, st);
 }
 
 hipError_t lanczos_set_lds(size_t lds) {
-  const void* fn[8] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
-                       (const void*)k_lanczos<float, 256, 4>, (const void*)k_lanczos<float, 512, 4>,
-                       (const void*)k_lanczos<double, 256, 2>, (const void*)k_lanczos<double, 512, 2>,
-                       (const void*)k_lanczos<float, 256, 2>, (const void*)k_lanczos<float, 512, 2>};
-  for (int q = 0; q < 8; ++q) {
+  const void* fn[12] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
+                        (const void*)k_lanczos<float, 256, 4>, (const void*)k_lanczos<float, 512, 4>,
+                        (const void*)k_lanczos<double, 256, 2>, (const void*)k_lanczos<double, 512, 2>,
+                        (const void*)k_lanczos<float, 256, 2>, (const void*)k_lanczos<float, 512, 2>,
+                        (const void*)k_lanczos<float, 256, 4, true>, (const void*)k_lanczos<float, 512, 4, true>,
+                        (const void*)k_lanczos<float, 256, 2, true>, (const void*)k_lanczos<float, 512, 2, true>};
+  for (int q = 0; q < 12; ++q) {
     hipError_t e = hipFuncSetAttribute(fn[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }

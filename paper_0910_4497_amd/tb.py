@@ -16,8 +16,8 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtbkrylov.so")
 
-TB_FP64, TB_FP32 = 0, 1
-PRECISIONS = {"fp64": TB_FP64, "fp32": TB_FP32}
+TB_FP64, TB_FP32, TB_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": TB_FP64, "fp32": TB_FP32, "bf16": TB_BF16}
 ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4: "TB_EMU",
           -5: "TB_EUNSUPPORTED", -6: "TB_EHIP", -7: "TB_ESTATE", -8: "TB_EDEVICE"}
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",

@@ -2,7 +2,8 @@
 
 Bar (FP64 mode): normwise relative error <= 1e-8 for rho blocks and forces,
 <= 1e-10 relative for the energies; mu to 1e-9 eV. FP32 mode: force error
-<= 1e-3 eV/A (max-abs over all components), errors reported.
+<= 1e-3 eV/A (max-abs over all components), errors reported. BF16-operand
+mode: errors reported, bounded by the BF16 perturbation (bf16_check).
 """
 import os
 
@@ -111,6 +112,46 @@ def test_parity_c60_240_fp32(torch_cuda, c60_240_oracle):
     assert ee <= 1e-4
 
 
+def bf16_check(res, ora, n_atoms, label, w):
+    """Errors of a BF16-operand run against the FP64 oracle, reported, and
+    bounded. Rounding both operands of every H.V product to 8 significand bits
+    perturbs the local Hamiltonian seen by the recursion by a relative 2^-8 at
+    most, so each Ritz value moves by at most 2^-8 of the local spectral
+    width (~40 eV): with 4 electrons per atom the energy error per atom is at
+    most 4 * 2^-8 * 40 eV. Force errors have no useful worst case (eigenvector
+    perturbations scale with 1/kT); their typical size is bounded instead:
+    rms error <= 2^-6 of the rms band force (the perturbation acts on the band
+    part only -- the net force is small where band and pair forces cancel --;
+    2^-8 for the operands, times the four terms of a pair force: rho_ji from
+    two seeds, each through Ritz values and vectors). The max error is only
+    reported."""
+    d = res["forces"] - ora["forces"]
+    fe = float(np.abs(d).max())
+    frms = float(np.sqrt(np.mean(d ** 2)))
+    band = ora["forces"] - otb.repulsion(w.pos, w.cell, (1, 1, 1), P)[1]
+    f_scale = float(np.sqrt(np.mean(band ** 2)))
+    ee = abs(res["e"][3] - ora["e_total"]) / n_atoms
+    eb = abs(res["e"][0] - ora["e_band"]) / n_atoms
+    st = res["stats"]
+    print(f"  {label} bf16: max force err {fe:.3e} eV/A (rms {frms:.3e}, rms band force {f_scale:.3f}), "
+          f"E_tot err {ee:.3e} eV/atom, E_band err {eb:.3e} eV/atom, mu err {abs(res['mu'] - ora['mu']):.3e} eV, "
+          f"reorth steps/atom {st['reorth_steps'] / n_atoms:.1f}")
+    assert st["flags"] == 0
+    e_bound = 4 * 2.0 ** -8 * 40.0
+    assert ee <= e_bound and eb <= e_bound
+    assert frms <= 2.0 ** -6 * f_scale
+
+
+def test_parity_c60_240_bf16(torch_cuda, c60_240_oracle):
+    """BF16 operands in H.V (FP32 accumulation, a pass at every step)."""
+    w, ora = c60_240_oracle
+    ctx = make_ctx(w.n_atoms, 128, w.r)
+    res = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                  precision="bf16")
+    bf16_check(res, ora, w.n_atoms, "c60_240", w)
+    assert res["stats"]["reorth_steps"] == w.n_atoms * (w.r - 1)
+
+
 def test_parity_c60_1920_full(torch_cuda):
     """Precision workload at full size: every atom, mu by bisection."""
     w = inputs.workload("c60_1920")
@@ -125,6 +166,9 @@ def test_parity_c60_1920_full(torch_cuda):
     fe = float(np.abs(r32["forces"] - ora["forces"]).max())
     print(f"  fp32 max force err {fe:.3e} eV/A")
     assert fe <= 1e-3
+    rbf = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                  precision="bf16")
+    bf16_check(rbf, ora, w.n_atoms, "c60_1920", w)
 
 
 def sampled_parity(name, mu_fixed, n_sample, seed, n_cluster, precision="fp64"):
