@@ -152,6 +152,20 @@ int tb_rho_layout(tb_ctx *ctx, int64_t *nnz_pairs_host, int64_t *row_ptr,
  * Errors: TB_ESTATE, TB_EHIP. */
 int tb_energy_forces(tb_ctx *ctx, double *e_out, double *forces);
 
+/* Virial of the last tb_energy_forces (Sec. 5 times the pressure of a diamond
+ * cell; Sec. 4 compresses the C60 crystal). With d_ij = R_j - R_i (minimum
+ * image) and g_ij the derivative with respect to d_ij of the pair's energy
+ * terms that the forces sum (Tr[H_ij rho_ji] of seed i, and the embedding
+ * term F'(x_i) phi'(r_ij) d_ij / r_ij):
+ *   W[a][b] = sum over ordered pairs (i, j) of (d_ij)_a (g_ij)_b  (eV).
+ * Stress sigma = W / V, pressure P = -(W[0][0] + W[1][1] + W[2][2]) / (3 V);
+ * for an isolated system W = -sum_k R_k (x) F_k. Like the forces, at finite r
+ * and cutoff this is the method's virial, not the exact strain derivative of
+ * E_tot. virial_out: device [3][3] row-major. Enqueued on the stream (no
+ * synchronisation); the sums run in a fixed order (bitwise reproducible).
+ * Errors: TB_EINVAL, TB_ESTATE (tb_energy_forces not called on this rho). */
+int tb_virial(tb_ctx *ctx, double *virial_out);
+
 /* Launch granularity of the per-atom phases of tb_krylov_rho (block Lanczos,
  * projected eigensolve, density-matrix assembly). Every target atom's local
  * solve is independent once the couplings are built (Sec. 2, the cutoff

@@ -20,7 +20,14 @@ Following the paper (Secs. 2-3):
     S/k_B = sum_i sum_m w_m 2 s(f_m/2), s(q) = -q ln q - (1-q) ln(1-q);
     A = E_band - kT S/k_B;  E_rep = sum_i F(sum_j phi(r_ij));  E = A + E_rep;
   * force (Sec. 2: <F_i> = Tr[rho F_i], F_i = -dH/dR_i):
-        F_k = - sum_i sum_{j in hop(i)} Tr[(dH_ij/dR_k) rho_ji] - dE_rep/dR_k.
+        F_k = - sum_i sum_{j in hop(i)} Tr[(dH_ij/dR_k) rho_ji] - dE_rep/dR_k;
+  * virial (Sec. 5 times the pressure of a diamond cell; the pair form is the
+    standard one for energies of pair vectors d_ij = R_j - R_i, minimum
+    image): with g_ij the derivative of the pair's energy terms with respect
+    to d_ij (the same terms the forces sum),
+        W_ab = sum over ordered pairs (i, j) of (d_ij)_a (g_ij)_b,
+    stress sigma = W / V and pressure P = -tr(W) / (3 V); for an isolated
+    system W = -sum_k R_k (x) F_k.
 """
 from __future__ import annotations
 
@@ -132,6 +139,30 @@ def repulsion(pos, cell, periodic, p):
         grad[nb[i]] += g
         grad[i] -= g.sum(axis=0)
     return e_rep, -grad
+
+
+def repulsion_virial(pos, cell, periodic, p):
+    """W_rep = sum over ordered pairs (i, j) of d_ij (x) dF(x_i)/d d_ij, with
+    dF(x_i)/d d_ij = F'(x_i) phi'(r_ij) d_ij / r_ij (each unordered pair
+    appears twice, once for each embedding term)."""
+    nb, dv = geometry.neighbour_lists(pos, cell, periodic, p["dm"])
+    xs = np.array([np.sum(model.phi_pair(np.linalg.norm(d, axis=1), p)) if len(d) else 0.0
+                   for d in dv])
+    dF = model.f_embed_deriv(xs, p)
+    W = np.zeros((3, 3))
+    for i in range(pos.shape[0]):
+        if len(nb[i]) == 0:
+            continue
+        rr = np.linalg.norm(dv[i], axis=1)
+        g = (dF[i] * model.phi_pair_deriv(rr, p) / rr)[:, None] * dv[i]
+        W += dv[i].T @ g
+    return W
+
+
+def pressure(virial, cell):
+    """P = -tr(W) / (3 V) in eV/A^3 for an orthorhombic cell (lengths)."""
+    V = float(np.prod(np.asarray(cell, dtype=np.float64)))
+    return -float(np.trace(virial)) / (3.0 * V)
 
 
 def _neighbours_of(k, pos, cell, periodic, cutoff):
@@ -252,6 +283,7 @@ def run(pos, cell, periodic, p, r_cut, r, kT, n_electrons=None, mu=None,
     if all_atoms:
         e_rep, f_rep = repulsion(pos, cell, periodic, p)
         grad = np.zeros((N, 3))
+        w_band = np.zeros((3, 3))
         for s in sols:
             i = s["i"]
             J = s["J"][1:]
@@ -262,8 +294,10 @@ def run(pos, cell, periodic, p, r_cut, r, kT, n_electrons=None, mu=None,
             g = np.einsum("pcba,pab->pc", dH, rho[i][1:])   # d Tr[H_ij rho_ji] / d d_c
             grad[J] += g
             grad[i] -= g.sum(axis=0)
+            w_band += d.T @ g                                 # sum_p d_p (x) g_p
         forces = -grad + f_rep
-        out.update(e_rep=e_rep, forces=forces,
+        virial = w_band + repulsion_virial(pos, cell, periodic, p)
+        out.update(e_rep=e_rep, forces=forces, virial=virial, virial_band=w_band,
                    e_total=e_band - kT * ent + e_rep)
     elif force_atoms is not None:
         need = hop_closure(force_atoms, pos, cell, periodic, p)

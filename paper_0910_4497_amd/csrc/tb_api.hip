@@ -194,6 +194,8 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(counter, 16);
   ALLOC(xrep, 2 * N);
   ALLOC(eparts, 8);
+  ALLOC(wpart, ((N + 255) / 256) * 9);
+  ALLOC(virial, 9);
   ALLOC(stats, ST_NSTATS);
 #undef ALLOC
   if (a == hipSuccess) a = alloc(c, &c->omega, (size_t)n_wg_lz_max * 3 * r_max * 16);
@@ -279,6 +281,7 @@ extern "C" int tb_build_local_H(tb_ctx* c, int64_t n_atoms, const double* pos, c
   if (n_cluster_out) HIP_TRY(hipMemcpyAsync(n_cluster_out, c->clu_n, n * sizeof(int), hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipGetLastError());
   c->stage = 1;
+  c->have_virial = 0;
   c->nnz_pairs = -1;
   return TB_OK;
 }
@@ -415,6 +418,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   HIP_TRY(hipGetLastError());
   c->rho_last = rho_out;
   c->stage = 2;
+  c->have_virial = 0;
   return TB_OK;
 }
 
@@ -503,6 +507,7 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
   HIP_TRY(hipMemcpyAsync(c->stats, saved, sizeof saved, hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   c->stage = 1;                      // the tuning runs replaced the recursion outputs
+  c->have_virial = 0;
   if (shape_out) {
     shape_out[0] = c->lz_nt[precision];
     shape_out[1] = c->lz_per_cu[precision];
@@ -540,9 +545,21 @@ extern "C" int tb_energy_forces(tb_ctx* c, double* e_out, double* forces) {
   fa.hop_n = c->hop_n; fa.hop_j = c->hop_j; fa.hop_rev = c->hop_rev; fa.hop_d = c->hop_d;
   fa.row_ptr = c->row_ptr; fa.rho = c->rho_last; fa.xrep = c->xrep; fa.forces = forces;
   fa.eparts = c->eparts; fa.kT = c->kT; fa.e_out = e_out;
+  fa.wpart = c->wpart; fa.virial = c->virial;
   const int pk = prof_begin(c, 5);
   launch_forces(fa, c->stream);
   prof_end(c, pk);
+  HIP_TRY(hipGetLastError());
+  c->have_virial = 1;
+  return TB_OK;
+}
+
+extern "C" int tb_virial(tb_ctx* c, double* virial_out) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (!virial_out) return fail(TB_EINVAL, "virial_out is null");
+  if (c->stage < 2 || !c->have_virial) return fail(TB_ESTATE, "tb_energy_forces must be called first");
+  HIP_TRY(hipSetDevice(c->device));
+  launch_virial_copy(c->virial, virial_out, c->stream);
   HIP_TRY(hipGetLastError());
   return TB_OK;
 }

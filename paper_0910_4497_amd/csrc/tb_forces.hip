@@ -12,6 +12,10 @@
 // gathered per atom (no atomics, fixed order). Repulsion
 // E_rep = sum_i F(x_i), x_i = sum_j phi(r_ij), gives
 //   F_k += sum_j (F'(x_k) + F'(x_j)) phi'(r_kj) d_kj / r_kj.
+// Virial (pressure of the diamond cell, Sec. 5): with the same pair terms,
+//   W_ab = sum over ordered pairs (k, j) of (d_kj)_a [g_kj + F'(x_k) phi'(r) d_kj / r]_b,
+// each atom summing its own ordered pairs; per-block sums in a fixed order,
+// then over blocks in k_energy (bitwise reproducible).
 #include "tb_internal.h"
 
 namespace tbk {
@@ -71,40 +75,70 @@ __global__ void __launch_bounds__(F_NT) k_rep_x(ForceArgs g) {
 }
 
 __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
+  __shared__ double s_w[F_NT / 64][9];
   const int k = blockIdx.x * F_NT + threadIdx.x;
-  if (k >= g.n_atoms || !g.forces) return;
-  double F[3] = {0.0, 0.0, 0.0};
-  const int nh = g.hop_n[k];
-  const int64_t pk = g.row_ptr[k];
-  const double dFk = g.xrep[2 * k];
-  for (int t = 0; t < nh; ++t) {
-    const size_t q = (size_t)k * ZMAX + t;
-    const int j = g.hop_j[q];
-    const double* dv = g.hop_d + 4 * q;
-    double gkj[3], gjk[3];
-    pair_grad(g.M, dv, g.rho + (size_t)(pk + 1 + t) * 16, gkj);
-    const int rt = g.hop_rev[q];
-    if (rt >= 0) {
-      const size_t qj = (size_t)j * ZMAX + rt;
-      pair_grad(g.M, g.hop_d + 4 * qj, g.rho + (size_t)(g.row_ptr[j] + 1 + rt) * 16, gjk);
-    } else {
-      gjk[0] = gjk[1] = gjk[2] = 0.0;     // only after a list overflow (flagged)
-    }
-    double phi, dphi;
-    pair_term(g.M, dv[3], phi, dphi);
-    const double rep = (dFk + g.xrep[2 * j]) * dphi / dv[3];
+  double W[9];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) F[c] += gkj[c] - gjk[c] + rep * dv[c];
+  for (int q = 0; q < 9; ++q) W[q] = 0.0;
+  if (k < g.n_atoms) {
+    double F[3] = {0.0, 0.0, 0.0};
+    const int nh = g.hop_n[k];
+    const int64_t pk = g.row_ptr[k];
+    const double dFk = g.xrep[2 * k];
+    for (int t = 0; t < nh; ++t) {
+      const size_t q = (size_t)k * ZMAX + t;
+      const int j = g.hop_j[q];
+      const double* dv = g.hop_d + 4 * q;
+      double gkj[3], gjk[3];
+      pair_grad(g.M, dv, g.rho + (size_t)(pk + 1 + t) * 16, gkj);
+      const int rt = g.hop_rev[q];
+      if (rt >= 0) {
+        const size_t qj = (size_t)j * ZMAX + rt;
+        pair_grad(g.M, g.hop_d + 4 * qj, g.rho + (size_t)(g.row_ptr[j] + 1 + rt) * 16, gjk);
+      } else {
+        gjk[0] = gjk[1] = gjk[2] = 0.0;     // only after a list overflow (flagged)
+      }
+      double phi, dphi;
+      pair_term(g.M, dv[3], phi, dphi);
+      const double rep = (dFk + g.xrep[2 * j]) * dphi / dv[3];
+      const double rep_k = dFk * dphi / dv[3];      // this atom's embedding term of the pair
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[c] += gkj[c] - gjk[c] + rep * dv[c];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) W[a * 3 + b] += dv[a] * (gkj[b] + rep_k * dv[b]);
+    }
+    if (g.forces) {
+      g.forces[3 * k] = F[0];
+      g.forces[3 * k + 1] = F[1];
+      g.forces[3 * k + 2] = F[2];
+    }
   }
-  g.forces[3 * k] = F[0];
-  g.forces[3 * k + 1] = F[1];
-  g.forces[3 * k + 2] = F[2];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) W[q] = wave_sum(W[q]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s_w[threadIdx.x >> 6][q] = W[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double t = 0.0;
+    for (int w = 0; w < F_NT / 64; ++w) t += s_w[w][threadIdx.x];
+    g.wpart[(size_t)blockIdx.x * 9 + threadIdx.x] = t;
+  }
 }
 
-// Single block: fixed-order sum of the per-atom repulsive energies, then the
-// energy record.
+// Single block: fixed-order sums of the per-atom repulsive energies and of
+// the per-block virials, then the energy record.
 __global__ void __launch_bounds__(F_NT) k_energy(ForceArgs g) {
   __shared__ double red[F_NT / 64];
+  if (threadIdx.x < 9) {                    // virial: blocks in a fixed order
+    const int nb = (g.n_atoms + F_NT - 1) / F_NT;
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += g.wpart[(size_t)b * 9 + threadIdx.x];
+    g.virial[threadIdx.x] = t;
+  }
   double s = 0.0;
   for (int i = threadIdx.x; i < g.n_atoms; i += F_NT) s += g.xrep[2 * i + 1];
   s = wave_sum(s);
@@ -127,6 +161,14 @@ void launch_forces(const ForceArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_rep_x, dim3(nb), dim3(F_NT), 0, st, a);
   hipLaunchKernelGGL(k_forces, dim3(nb), dim3(F_NT), 0, st, a);
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(F_NT), 0, st, a);
+}
+
+__global__ void k_copy9(const double* __restrict__ src, double* __restrict__ dst) {
+  if (threadIdx.x < 9) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+void launch_virial_copy(const double* src, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy9, dim3(1), dim3(64), 0, st, src, dst);
 }
 
 }  // namespace tbk

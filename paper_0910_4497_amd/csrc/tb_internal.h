@@ -238,8 +238,11 @@ struct ForceArgs {
   double* forces;             // [N][3] (nullable)
   double* eparts; double kT;
   double* e_out;
+  double* wpart;              // [blocks][9] per-block virial sums
+  double* virial;             // [9] W[a][b] = sum over ordered pairs of d_a g_b
 };
 void launch_forces(const ForceArgs& a, hipStream_t st);
+void launch_virial_copy(const double* src, double* dst, hipStream_t st);
 
 // K1-K3 and the rho pair layout for the geometry in pos (device).
 void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st);
@@ -305,6 +308,9 @@ struct tb_ctx {
   unsigned int* counter; // last-block counters
   double* xrep;          // [N]: sum_j phi, then F'(x)
   double* eparts;        // [4] band, entropy, rep, count
+  double* wpart;         // [ceil(N/256)][9] per-block virial sums
+  double* virial;        // [9] virial of the last tb_energy_forces
+  int have_virial;       // tb_energy_forces ran on the current rho
   int64_t* stats;        // [ST_NSTATS]
   // phase timing
   int prof;

@@ -106,6 +106,24 @@ def fcc_c60(k: int, a: float, sigma: float, seed: int, strain: float = 0.0):
     return pos, np.array([L, L, L]), rng
 
 
+def cubic_diamond(k: int, a: float, sigma: float = 0.0, seed: int = 0):
+    """k x k x k conventional cubic-diamond cells (8 atoms each: the fcc sites
+    and the same shifted by (1/4, 1/4, 1/4) a), loop order x slowest, Gaussian
+    jitter sigma (A), wrapped into the box. Returns (pos, cell lengths)."""
+    fcc = np.array([[0, 0, 0], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]], dtype=np.float64)
+    basis = np.concatenate([fcc, fcc + 0.25], axis=0)
+    pos = []
+    for i in range(k):
+        for j in range(k):
+            for l in range(k):
+                pos.append((basis + np.array([i, j, l], dtype=np.float64)) * a)
+    pos = np.concatenate(pos, axis=0)
+    L = k * a
+    if sigma > 0:
+        pos = pos + np.random.default_rng(seed).normal(0.0, sigma, pos.shape)
+    return np.mod(pos, L), np.array([L, L, L])
+
+
 @dataclass
 class Workload:
     name: str
@@ -128,7 +146,8 @@ class Workload:
 
 
 def workload(name: str) -> Workload:
-    """The five C60 workloads (names 'c60_240' ... 'c60_15360')."""
+    """The five C60 workloads (names 'c60_240' ... 'c60_15360') and the
+    4 x 4 x 4 cubic-diamond cell 'diamond_512'."""
     if name == "c60_240":           # one compressed conventional cell
         pos, L, _ = fcc_c60(1, 12.5, 0.02, 1001)
         return Workload(name, pos, L, r_cut=6.0, r=30)
@@ -146,10 +165,13 @@ def workload(name: str) -> Workload:
     if name == "c60_15360":         # 4x4x4 cells, full scale
         pos, L, _ = fcc_c60(4, 11.6, 0.10, 1005)
         return Workload(name, pos, L, r_cut=8.0, r=50)
+    if name == "diamond_512":       # 4x4x4 cubic-diamond cells (pressure / EOS)
+        pos, L = cubic_diamond(4, 3.567, 0.02, 1006)
+        return Workload(name, pos, L, r_cut=6.0, r=30)
     raise KeyError(name)
 
 
-WORKLOADS = ("c60_240", "c60_1920", "c60_6480_strained", "c60_1920_hot", "c60_15360")
+WORKLOADS = ("c60_240", "c60_1920", "c60_6480_strained", "c60_1920_hot", "c60_15360", "diamond_512")
 
 
 def maxwell_velocities(n: int, T: float, seed: int, mass: float = MASS_C) -> np.ndarray:

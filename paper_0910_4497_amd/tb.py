@@ -23,7 +23,7 @@ ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4:
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
               "max_cluster_pos", "memory_bytes", "reorth_second_pass", "reorth_steps", "basis_bytes")
 EXPORTS = ("tb_create", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
-           "tb_energy_forces", "tb_get_stats", "tb_set_launch", "tb_autotune", "tb_profile_enable", "tb_profile_read",
+           "tb_energy_forces", "tb_get_stats", "tb_virial", "tb_set_launch", "tb_autotune", "tb_profile_enable", "tb_profile_read",
            "tb_last_error")
 PHASES = ("lists_local", "lanczos", "eig", "mu", "rho", "forces")
 RHO_ROWS_MAX = 25          # rho row atoms per target: itself + at most 24 neighbours
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tb_rho_layout.argtypes = [P, ctypes.POINTER(I64), P, P]
     lib.tb_energy_forces.argtypes = [P, P, P]
     lib.tb_get_stats.argtypes = [P, ctypes.POINTER(I64), I]
+    lib.tb_virial.argtypes = [P, P]
     lib.tb_set_launch.argtypes = [P, I]
     lib.tb_autotune.argtypes = [P, I, P, I, ctypes.POINTER(I)]
     lib.tb_profile_enable.argtypes = [P, I]
@@ -184,6 +185,13 @@ class TBContext:
             forces = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=self.device)
         _check(self.lib.tb_energy_forces(self.h, _ptr(e_out), _ptr(forces)))
         return e_out, forces
+
+    def virial(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        """W [3][3] (eV) of the last energy_forces(); stress = W / V."""
+        if out is None:
+            out = torch.empty((3, 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.tb_virial(self.h, _ptr(out)))
+        return out
 
     def autotune(self, r: int, precision: str = "fp64", r_per_atom: torch.Tensor | None = None) -> dict:
         """Times the launch shapes of the Krylov kernel and the eigensolver on

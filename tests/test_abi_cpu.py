@@ -52,3 +52,4 @@ def test_last_error_callable_without_device():
     assert b"null" in lib.tb_last_error()
     assert lib.tb_set_launch(None, 1) == -1
     assert lib.tb_autotune(None, 10, None, 0, None) == -1
+    assert lib.tb_virial(None, None) == -1

@@ -11,7 +11,11 @@ invariants (no GPU).
     forces are minus the finite-difference gradient of E_band - TS + E_rep;
   * finite r and cutoff (periodic cell): trace identity E_band = sum Tr[H rho],
     electron count, zero net force, frozen-rho finite difference of the band
-    term, translation and permutation equivariance.
+    term, translation and permutation equivariance;
+  * virial: W = -sum R (x) F for an isolated system; in the exact limit every
+    component is the strain derivative of the exact free energy; the periodic
+    repulsive virial is the derivative under axis scaling; perfect diamond
+    gives an isotropic virial.
 """
 import numpy as np
 import pytest
@@ -191,3 +195,61 @@ def test_subset_mode_matches_full(cfg1_run):
                  force_atoms=S, processes=1)
     for k in S:
         assert np.abs(sub["forces_sampled"][k] - res["forces"][k]).max() < 1e-12
+
+
+# ------------------------------------------------------------------ virial
+def test_virial_isolated_identity():
+    """Isolated system, finite r: the pair virial equals -sum_k R_k (x) F_k
+    (the forces sum the same pair derivatives with d_ij = R_j - R_i)."""
+    rng = np.random.default_rng(31)
+    mol = inputs.c60_ideal() + rng.normal(0, 0.05, (60, 3))
+    res = tb.run(mol, BIG, ISO, P, 6.0, 12, KT, n_electrons=240.0, processes=4)
+    W = res["virial"]
+    ref = -mol.T @ res["forces"]
+    assert np.abs(W - ref).max() <= 1e-10 * np.abs(W).max()
+
+
+def test_virial_exact_limit_is_strain_derivative(isolated_exact_limit):
+    """Exact limit: every component of the virial equals the central finite
+    difference of the exact (fully diagonalised) free energy under the
+    homogeneous deformation R -> (I + h e_a e_b^T) R: dE/d eps_ab = W[b][a]."""
+    mol, kr, ex = isolated_exact_limit
+    W = kr["virial"]
+    h = 1e-5
+    scale = np.abs(W).max()
+    for a in range(3):
+        for b in range(3):
+            e2 = []
+            for sgn in (1.0, -1.0):
+                D = np.eye(3)
+                D[a, b] += sgn * h
+                e2.append(exact.solve(mol @ D.T, BIG, ISO, P, KT, n_electrons=240.0)["e_total"])
+            fd = (e2[0] - e2[1]) / (2 * h)
+            assert abs(fd - W[b, a]) <= 1e-7 * scale, (a, b, fd, W[b, a])
+
+
+def test_repulsion_virial_periodic_scaling():
+    """Periodic cell: the diagonal of the repulsive virial is the derivative of
+    E_rep when one axis of the cell and of every position is scaled by 1 + h."""
+    w = inputs.workload("c60_240")
+    W = tb.repulsion_virial(w.pos, w.cell, (1, 1, 1), P)
+    h = 1e-6
+    for a in range(3):
+        e2 = []
+        for sgn in (1.0, -1.0):
+            s = np.ones(3)
+            s[a] += sgn * h
+            e2.append(tb.repulsion(w.pos * s, w.cell * s, (1, 1, 1), P)[0])
+        fd = (e2[0] - e2[1]) / (2 * h)
+        assert abs(fd - W[a, a]) <= 1e-7 * np.abs(W).max(), (a, fd, W[a, a])
+
+
+def test_perfect_diamond_virial_is_isotropic():
+    """Perfect cubic diamond (4 x 4 x 4 cells): by cubic symmetry the virial is
+    a multiple of the identity, band and repulsive parts separately."""
+    pos, L = inputs.cubic_diamond(4, 3.55)
+    res = tb.run(pos, L, (1, 1, 1), P, 6.0, 30, KT, n_electrons=4.0 * len(pos), processes=8)
+    for W in (res["virial"], res["virial_band"]):
+        d = np.diag(W)
+        assert np.abs(W - np.diag(d)).max() <= 1e-9 * np.abs(d).max()
+        assert np.ptp(d) <= 1e-9 * np.abs(d).max()
