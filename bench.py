@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -127,9 +129,11 @@ def run_md(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, torch, inpu
     phases = ctx.profile_read()
     ctx.profile(False)
     ctx.set_launch(0)
+    W = ctx.virial().cpu().numpy()          # of the last timed step
     stats = ctx.stats()
+    V = float(np.prod(np.asarray(w.cell, dtype=np.float64)))
     return {"seconds": t1 - t0, "phases": phases, "f_first": f_first, "e_first": e_first,
-            "e_last": e, "stats": stats}
+            "e_last": e, "stats": stats, "pressure_GPa": -float(np.trace(W)) / (3.0 * V) * 160.21766208}
 
 
 def run_graph(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, stream, torch, rpa=None,
@@ -272,7 +276,8 @@ def main():
                        "phase_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in r["phases"].items()},
                        "reorth_second_passes": r["stats"]["reorth_second_pass"],
                        "reorth_steps_per_atom": round(r["stats"]["reorth_steps"] / N, 2),
-                       "lanczos_basis_bytes_per_launch": r["stats"]["basis_bytes"]}
+                       "lanczos_basis_bytes_per_launch": r["stats"]["basis_bytes"],
+                       "pressure_GPa_last_step": round(r["pressure_GPa"], 4)}
         if prec in shapes:
             extra[prec]["launch_shape"] = shapes[prec]
         if "graph" in r:
@@ -297,7 +302,9 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f32+f64", "bf16": "bf16+f32+f64"}.get(head_prec, "f64"),
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {N} C atoms, fcc C60 crystal, periodic",
+        "config": {"workload": f"{args.workload}: {N} C atoms, "
+                               + ("4x4x4 cubic diamond" if args.workload.startswith("diamond") else "fcc C60 crystal")
+                               + ", periodic",
                    "n_atoms": N, "r_cluster_A": w.r_cut, "krylov_block_steps": w.r, "kT_eV": w.kT,
                    "cluster_atoms_mean": float(np.mean(n_cluster)), "cluster_atoms_max": n_max,
                    "precision": head_prec, "dt_fs": args.dt,

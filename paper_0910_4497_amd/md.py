@@ -75,6 +75,16 @@ class TBForceField:
                                          precision=s.precision, r_per_atom=s.r_per_atom)
         return self.ctx.energy_forces()
 
+    def virial(self) -> torch.Tensor:
+        """W [3][3] (eV) of the last evaluation (tb_virial)."""
+        return self.ctx.virial()
+
+    def pressure(self) -> torch.Tensor:
+        """P = -tr(W) / (3 V) in eV/A^3 of the last evaluation (orthorhombic cell)."""
+        cell = np.asarray(self.s.cell, dtype=np.float64)
+        V = float(np.prod(np.diag(cell) if cell.ndim == 2 else cell))
+        return -torch.trace(self.ctx.virial()) / (3.0 * V)
+
     def close(self):
         self.ctx.close()
 
