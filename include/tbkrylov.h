@@ -166,6 +166,21 @@ int tb_energy_forces(tb_ctx *ctx, double *e_out, double *forces);
  * Errors: TB_EINVAL, TB_ESTATE (tb_energy_forces not called on this rho). */
 int tb_virial(tb_ctx *ctx, double *virial_out);
 
+/* Seeding of the Krylov spaces (Sec. 3). TB_SEEDS_BLOCK (the default): the
+ * four orbitals of the target atom form one seed block, K_r = span{Phi,
+ * H Phi, ..., H^{r-1} Phi}, block recursion with full 4x4 A_k and
+ * upper-triangular B_k. TB_SEEDS_ORBITAL: the paper's own seeding, one scalar
+ * Krylov space K_r(H, |i alpha>) per orbital alpha (Eq. 4 with the orbital as
+ * seed), the four chains run together with diagonal A_k, B_k (Eqs. 8-9),
+ * each re-orthogonalised against its own vectors only; the density-matrix
+ * column of orbital alpha comes from its own chain. The orbital form is not
+ * invariant under rotations of the atoms at finite r (the block form is), and
+ * needs r up to the grade of each orbital (~4x the block order) to reach the
+ * exact limit. Host-side setting; applies to later tb_krylov_rho calls.
+ * Errors: TB_EINVAL. */
+enum { TB_SEEDS_BLOCK = 0, TB_SEEDS_ORBITAL = 1 };
+int tb_set_seeds(tb_ctx *ctx, int seeds);
+
 /* Launch granularity of the per-atom phases of tb_krylov_rho (block Lanczos,
  * projected eigensolve, density-matrix assembly). Every target atom's local
  * solve is independent once the couplings are built (Sec. 2, the cutoff

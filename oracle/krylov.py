@@ -25,6 +25,16 @@ given; every quantity computed from them depends only on the subspace:
                          passes; the QR step is pivoted Householder, columns
                          with |R_cc| <= tol are dropped.
 
+The paper's own seeding (Sec. 3, Eqs. 6-9) is one orbital at a time: one
+scalar chain per orbital of the target atom, batched with diagonal A_k, B_k.
+For that form:
+
+  orbital_krylov_basis -- Arnoldi for K_r(H, e_c) with two classical
+                          Gram-Schmidt passes (the scalar case of the above);
+  orbital_lanczos      -- the scalar three-term recursion of Eqs. (6)-(7)
+                          with two full re-orthogonalisation passes, giving
+                          alpha_k, beta_k of the tridiagonal T directly.
+
 Deflation threshold: tol = tau * ||H||_F with tau = 1e-12.  A column that is
 dropped lies in the span already built, so the subspace is unchanged; if all
 columns of a block drop, the space is invariant and the recursion stops.
@@ -147,3 +157,59 @@ def block_lanczos(H, r, tau=TAU_DEFLATE, reorth=True):
         T[offs[k + 1]:offs[k + 2], offs[k]:offs[k + 1]] = B
         T[offs[k]:offs[k + 1], offs[k + 1]:offs[k + 2]] = B.T
     return np.hstack(blocks), T
+
+
+def orbital_krylov_basis(H, r, c, tau=TAU_DEFLATE, reorth=True):
+    """Orthonormal basis (columns) of K_r(H, e_c), e_c the c-th unit vector;
+    stops when the new vector's norm after orthogonalisation is <= tol (the
+    space is invariant)."""
+    dim = H.shape[0]
+    tol = deflation_tol(H, tau)
+    Q = np.zeros((dim, r))
+    Q[c, 0] = 1.0
+    nq = 1
+    npass = 2 if reorth else 1
+    for _k in range(1, r):
+        w = H @ Q[:, nq - 1]
+        for _ in range(npass):
+            w = w - Q[:, :nq] @ (Q[:, :nq].T @ w)
+        nrm = np.linalg.norm(w)
+        if nrm <= tol:
+            break
+        Q[:, nq] = w / nrm
+        nq += 1
+    return Q[:, :nq]
+
+
+def orbital_lanczos(H, r, c, tau=TAU_DEFLATE, reorth=True):
+    """Scalar three-term recursion (Eqs. 6-7) seeded with e_c:
+    l_k = H v_k - alpha_k v_k - beta_{k-1} v_{k-1}, v_{k+1} = l_k / beta_k,
+    alpha_k = v_k.H v_k, beta_k = |l_k|, with two full re-orthogonalisation
+    passes of l_k. Returns (V, alpha, beta): the Lanczos vectors, the diagonal
+    and the off-diagonal of T."""
+    dim = H.shape[0]
+    tol = deflation_tol(H, tau)
+    v = np.zeros(dim)
+    v[c] = 1.0
+    V = [v]
+    alpha, beta = [], []
+    v_prev, b_prev = np.zeros(dim), 0.0
+    for k in range(r):
+        w = H @ v
+        a = float(v @ w)
+        alpha.append(a)
+        if k == r - 1:
+            break
+        w = w - a * v - b_prev * v_prev
+        if reorth:
+            Vm = np.array(V).T
+            for _ in range(2):
+                w = w - Vm @ (Vm.T @ w)
+        b = float(np.linalg.norm(w))
+        if b <= tol:
+            break
+        beta.append(b)
+        v_prev, b_prev, v = v, b, w / b
+        V.append(v)
+    return np.array(V).T, np.array(alpha), np.array(beta)
+

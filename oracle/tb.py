@@ -77,16 +77,57 @@ def chemical_potential(lams, ws, n_electrons, kT, n_iter=N_BISECT):
 
 
 # --------------------------------------------------------- per-atom solve
+def orbital_solve(H, r, route="arnoldi", reorth=True):
+    """The paper's per-orbital seeding (Sec. 3, Eqs. 6-9): one scalar Krylov
+    space K_r(H, e_c) per orbital c of the target atom, T_c = Q_c^T H Q_c,
+    T_c = Y_c diag(lambda_c) Y_c^T. Packed so that the column-block formulas
+    of the block form apply: lam and the columns of Q Y are the four chains'
+    concatenated, and Y1[c', m] is the seed component Y_c[0, m] of chain c's
+    Ritz pair m in row c' = c, zero in the other rows (the density-matrix
+    column of orbital c uses its own chain only)."""
+    lams, QYs, Y1s = [], [], []
+    for c in range(4):
+        if route == "arnoldi":
+            Q = krylov.orbital_krylov_basis(H, r, c, reorth=reorth)
+            T = Q.T @ H @ Q
+            T = 0.5 * (T + T.T)
+        else:
+            Q, a, b = krylov.orbital_lanczos(H, r, c, reorth=reorth)
+            T = np.diag(a) + np.diag(b[:len(a) - 1], 1) + np.diag(b[:len(a) - 1], -1)
+        lam, Y = np.linalg.eigh(T)
+        lams.append(lam)
+        QYs.append(Q @ Y)
+        y1 = np.zeros((4, len(lam)))
+        y1[c] = Y[0]
+        Y1s.append(y1)
+    return np.concatenate(lams), np.concatenate(QYs, axis=1), np.concatenate(Y1s, axis=1)
+
+
 def atom_solve(i, pos, cell, periodic, p, r_cut, r, full_column=False,
-               route="arnoldi", reorth=True):
+               route="arnoldi", reorth=True, seeds="block"):
     """Krylov solve for target atom i.
 
     Returns dict with lam [d], w [d], J (global ids: i then hop(i) sorted),
     P = (Q Y) restricted to the rows of J, shape (4|J|, d), Y1 = Y[0:4, :],
     and with full_column also the cluster ids and Q Y on all cluster rows.
+    seeds="orbital": the paper's one scalar chain per orbital (orbital_solve).
     """
     idx, x = geometry.cluster(i, pos, cell, periodic, r_cut)
     H = krylov.cluster_hamiltonian(x, p)
+    if seeds == "orbital":
+        lam, QY, Y1 = orbital_solve(H, r, route, reorth)
+        w = np.sum(Y1 ** 2, axis=0)
+        rloc = np.linalg.norm(x, axis=1)
+        j_local = np.nonzero((rloc < p["rm"]) & (np.arange(len(idx)) > 0))[0]
+        j_local = j_local[np.argsort(idx[j_local])]
+        J_local = np.concatenate([[0], j_local])
+        rows = (4 * J_local[:, None] + np.arange(4)[None, :]).ravel()
+        out = {"i": i, "lam": lam, "w": w, "J": idx[J_local], "P": QY[rows, :],
+               "Y1": Y1, "n_cluster": len(idx), "dim": len(lam)}
+        if full_column:
+            out["cluster"] = idx
+            out["QY"] = QY
+        return out
     if route == "arnoldi":
         Q, _w = krylov.block_krylov_basis(H, r, reorth=reorth)
         T = Q.T @ H @ Q
@@ -214,7 +255,7 @@ def _worker(i):
     g = _G
     return atom_solve(i, g["pos"], g["cell"], g["periodic"], g["p"], g["r_cut"],
                       int(g["r_of"](i)), full_column=g["full_column"],
-                      route=g["route"], reorth=g["reorth"])
+                      route=g["route"], reorth=g["reorth"], seeds=g["seeds"])
 
 
 def _limit_blas():
@@ -226,11 +267,11 @@ def _limit_blas():
 
 
 def solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, r_per_atom=None,
-                full_column=False, route="arnoldi", reorth=True, processes=None):
+                full_column=False, route="arnoldi", reorth=True, processes=None, seeds="block"):
     """atom_solve over a list of atoms, in worker processes (one BLAS thread each)."""
     r_of = (lambda i: r_per_atom[i]) if r_per_atom is not None else (lambda i: r)
     _G.update(pos=pos, cell=cell, periodic=periodic, p=p, r_cut=r_cut, r_of=r_of,
-              full_column=full_column, route=route, reorth=reorth)
+              full_column=full_column, route=route, reorth=reorth, seeds=seeds)
     atoms = list(atoms)
     if processes is None:
         processes = len(os.sched_getaffinity(0))
@@ -245,19 +286,21 @@ def solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, r_per_atom=None,
 # --------------------------------------------------------------- driver
 def run(pos, cell, periodic, p, r_cut, r, kT, n_electrons=None, mu=None,
         r_per_atom=None, atoms=None, force_atoms=None, full_column=False,
-        route="arnoldi", reorth=True, processes=None):
+        route="arnoldi", reorth=True, processes=None, seeds="block"):
     """The whole path for one geometry.
 
     atoms=None solves every atom; mu must then be None (bisection on
     n_electrons) or given.  With a subset of atoms, mu must be given, and
     forces are returned for force_atoms (each needs itself and hop() solved).
+    seeds: "block" (four-orbital seed block) or "orbital" (one scalar chain
+    per orbital, Eqs. 6-9).
     """
     pos = np.asarray(pos, dtype=np.float64)
     N = pos.shape[0]
     all_atoms = atoms is None
     atoms = list(range(N)) if all_atoms else list(atoms)
     sols = solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, r_per_atom,
-                       full_column, route, reorth, processes)
+                       full_column, route, reorth, processes, seeds)
     by_atom = {s["i"]: s for s in sols}
     if mu is None:
         if not all_atoms:

@@ -326,6 +326,7 @@ static LanczosArgs lanczos_args(const tb_ctx* c, int n, int r, const int* r_per_
   // rounding term uses the BF16 epsilon, so the passes run at every step
   la.eps_unit = precision == TB_BF16 ? 0.0078125 : (fp32 ? (double)FLT_EPSILON : DBL_EPSILON);
   la.om_lds = la.ab_lds = la.vprev_lds = 0;
+  la.scalar = c->seeds == TB_SEEDS_ORBITAL ? 1 : 0;
   return la;
 }
 
@@ -575,6 +576,13 @@ extern "C" int tb_get_stats(tb_ctx* c, int64_t* stats_host, int n_stats) {
   if (s[ST_FLAGS] & (FL_HOP_OVERFLOW | FL_CLUSTER_OVERFLOW | FL_COUPLING_OVERFLOW))
     return fail(TB_ECAPACITY, "device list overflow (flags 0x%llx)", (unsigned long long)s[ST_FLAGS]);
   if (s[ST_FLAGS]) return fail(TB_EDEVICE, "device error flags 0x%llx", (unsigned long long)s[ST_FLAGS]);
+  return TB_OK;
+}
+
+extern "C" int tb_set_seeds(tb_ctx* c, int seeds) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (seeds != TB_SEEDS_BLOCK && seeds != TB_SEEDS_ORBITAL) return fail(TB_EINVAL, "unknown seeds %d", seeds);
+  c->seeds = seeds;
   return TB_OK;
 }
 

@@ -177,6 +177,7 @@ struct LanczosArgs {
   int om_lds;                  // estimates kept in LDS
   int ab_lds;                  // FP32 copies of A_j, B_j kept in LDS (needs om_lds)
   int vprev_lds;               // V_{k-1} kept in a second LDS block buffer
+  int scalar;                  // orbital seeds: four independent scalar chains (diagonal A_k, B_k)
   double eta, eps_unit;        // re-orthogonalisation threshold, unit roundoff of VT
   int64_t* stats;
 };
@@ -265,6 +266,7 @@ struct tb_ctx {
   int lz_per_cu_max;     // workspace is sized for this many per compute unit
   int eig_per_cu, eig_per_cu_max;   // persistent k_eig workgroups per compute unit
   int atoms_per_launch;  // 0: one launch per phase; k: per-atom phases in launches of k atoms
+  int seeds;             // TB_SEEDS_BLOCK or TB_SEEDS_ORBITAL
   size_t bytes;
 
   // state

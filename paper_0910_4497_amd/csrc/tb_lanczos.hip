@@ -354,7 +354,8 @@ k_lanczos(LanczosArgs g) {
         lds_barrier();
         if (tid < 16) {
           const int c = tid >> 2, d = tid & 3;
-          const double av = 0.5 * (X[c * 4 + d] + X[d * 4 + c]);
+          // orbital seeds: independent scalar chains, A_k diagonal
+          const double av = (g.scalar && c != d) ? 0.0 : 0.5 * (X[c * 4 + d] + X[d * 4 + c]);
           A[tid] = av;
           tab[(size_t)k * 32 + tid] = av;
           if (g.ab_lds) s_ab[k * 32 + tid] = (float)av;
@@ -413,7 +414,7 @@ k_lanczos(LanczosArgs g) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) actk[c] = s_flag[c] != 0;
 #pragma unroll
-          for (int q = 0; q < 16; ++q) Gf[q] = G[map[q]];
+          for (int q = 0; q < 16; ++q) Gf[q] = (g.scalar && q % 5 != 0) ? 0.0 : G[map[q]];
           const bool ok = chol4r(Gf, actk, Ur, tol * tol, ratio);
           inv_upper4r(Ur, actk, Xr);
           double tn = s_misc[208];
@@ -476,7 +477,9 @@ k_lanczos(LanczosArgs g) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) o += __shfl(m, (lane & ~3) | c, 64) * (float)Xe[c * 4 + b];
           Okp[j * 16 + a * 4 + b] = o;
-          lmax = fmax(lmax, (double)fabsf(o));
+          // orbital seeds: only a chain's own entries estimate a loss of
+          // orthogonality (different chains are not orthogonal)
+          if (!g.scalar || a == b) lmax = fmax(lmax, (double)fabsf(o));
         }
         lmax = wave_max(lmax);
         if (lane == 0) s_red[wave] = lmax;
@@ -560,8 +563,10 @@ k_lanczos(LanczosArgs g) {
           int which;
           const double sum = wave_sum16(acc, lane, which);
           if ((lane & 3) == 0) {
-            if (parts == 1) s_C[j * 16 + which] = sum;
-            else s_Cp[it * 16 + which] = sum;
+            // orbital seeds: a chain is orthogonalised against its own vectors only
+            const double cv = (g.scalar && (which >> 2) != (which & 3)) ? 0.0 : sum;
+            if (parts == 1) s_C[j * 16 + which] = cv;
+            else s_Cp[it * 16 + which] = cv;
           }
           if (want_norm) {
 #pragma unroll
@@ -650,7 +655,31 @@ k_lanczos(LanczosArgs g) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) act[c] = s_flag[c] != 0;
       const int map[16] = {0, 1, 2, 3, 1, 4, 5, 6, 2, 5, 7, 8, 3, 6, 8, 9};
-      {
+      if (g.scalar) {
+        // orbital seeds: B_k = diag(|w_c|); a column whose norm is <= tol
+        // ends its chain (its space is invariant)
+        const int dg[4] = {0, 4, 7, 9};
+        bool keep[4];
+        double nrm[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          keep[c] = act[c] && G[dg[c]] > tol * tol;
+          nrm[c] = keep[c] ? sqrt(G[dg[c]]) : 0.0;
+        }
+        lds_barrier();                              // every thread has read G
+        if (tid == 0) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q) { X[q] = 0.0; B[q] = 0.0; }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (keep[c]) { B[c * 5] = nrm[c]; X[c * 5] = 1.0 / nrm[c]; }
+            if (act[c] && !keep[c]) ++ndefl;
+            s_flag[c] = keep[c] ? 1 : 0;
+          }
+          s_flag[5] = 0;
+        }
+        lds_barrier();
+      } else {
         double Gf[16], Ur[16], Xr[16], ratio;
 #pragma unroll
         for (int q = 0; q < 16; ++q) Gf[q] = G[map[q]];

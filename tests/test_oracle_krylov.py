@@ -164,3 +164,67 @@ def test_invariant_space_equals_cluster_solution():
         exact = (U * tb.fermi(ev, mu, 0.1)) @ U[:4, :].T
         got = tb.rho_column_full(sol, mu, 0.1).reshape(-1, 4)
         assert np.abs(exact - got).max() < 1e-12
+
+
+# ---------------------------------------------------- orbital seeds (Eqs. 6-9)
+def test_orbital_chain_closed_form():
+    """Uniform s-only chain, seed = the s orbital of the centre site: the
+    scalar recursion of Eqs. (6)-(7) gives alpha_k = E_s = 0, beta_1 = sqrt(2)|t|
+    and beta_k = |t| after; a p seed is an eigenvector (its chain stops at once)."""
+    p = s_only_params(t=1.0)
+    M = 10
+    H, _, _ = chain_H(2 * M + 1, p)
+    V, a, b = krylov.orbital_lanczos(H, M, 0)
+    assert np.allclose(a, 0.0, atol=1e-13)
+    assert abs(b[0] - np.sqrt(2.0)) < 1e-13 and np.allclose(b[1:], 1.0, atol=1e-13)
+    assert np.abs(V.T @ V - np.eye(V.shape[1])).max() < 1e-13
+    for c in (1, 2, 3):
+        Vp, ap, bp = krylov.orbital_lanczos(H, M, c)
+        assert len(bp) == 0 and abs(ap[0] - 10.0) < 1e-13
+
+
+def test_orbital_routes_agree(cfg1_cluster):
+    """Per orbital, the Ritz values of the Arnoldi basis of K_r(H, e_c) equal
+    those of the three-term recursion (two independent constructions)."""
+    H, w = cfg1_cluster
+    for c in range(4):
+        Q = krylov.orbital_krylov_basis(H, w.r, c)
+        lam1 = np.linalg.eigvalsh(Q.T @ H @ Q)
+        V, a, b = krylov.orbital_lanczos(H, w.r, c)
+        T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+        lam2 = np.linalg.eigvalsh(T)
+        assert np.abs(lam1 - lam2).max() < 1e-10
+
+
+def test_orbital_space_is_inside_block_space(cfg1_cluster):
+    """K_r(H, e_c) is a subspace of the block space K_r(H, Phi)."""
+    H, w = cfg1_cluster
+    Qb, _ = krylov.block_krylov_basis(H, w.r)
+    for c in range(4):
+        Q = krylov.orbital_krylov_basis(H, w.r, c)
+        assert np.abs(Q - Qb @ (Qb.T @ Q)).max() < 1e-9
+
+
+def test_orbital_exact_limit_and_rotation():
+    """Isolated C60 with every sphere the whole molecule: with r past every
+    orbital's grade the orbital form equals full diagonalisation; at a finite
+    r its energy changes under a rigid rotation of the molecule, while the
+    block form's does not (its result depends on span(Phi) only)."""
+    from oracle import exact
+    rng = np.random.default_rng(21)
+    mol = inputs.c60_ideal() + rng.normal(0, 0.04, (60, 3))
+    big = np.array([200.0, 200.0, 200.0])
+    kr = tb.run(mol, big, (0, 0, 0), P, 8.0, 250, 0.1, n_electrons=240.0, processes=8, seeds="orbital")
+    ex = exact.solve(mol, big, (0, 0, 0), P, 0.1, n_electrons=240.0)
+    assert abs(kr["mu"] - ex["mu"]) < 1e-10
+    assert abs(kr["e_total"] - ex["e_total"]) < 1e-9 * abs(ex["e_total"])
+    assert np.abs(kr["forces"] - ex["forces"]).max() < 1e-9
+    Rm = inputs.random_rotation(np.random.default_rng(5))
+    c0 = mol.mean(axis=0)
+    rot = (mol - c0) @ Rm.T + c0
+    e = {}
+    for seeds in ("block", "orbital"):
+        e[seeds] = [tb.run(x, big, (0, 0, 0), P, 6.0, 10, 0.1, n_electrons=240.0, processes=8,
+                           seeds=seeds)["e_total"] for x in (mol, rot)]
+    assert abs(e["block"][0] - e["block"][1]) < 1e-9 * abs(e["block"][0])
+    assert abs(e["orbital"][0] - e["orbital"][1]) > 1e-6
