@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="MD steps timed on the plain FP64 path with one launch per atom for each "
                          "per-atom phase (0: skip)")
+    ap.add_argument("--seeds", choices=("block", "orbital"), default="block",
+                    help="block: four-orbital seed block; orbital: one scalar chain per orbital")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing the candidates first")
     ap.add_argument("--no-graph", action="store_true",
@@ -195,6 +197,7 @@ def main():
         r_atoms = np.asarray(w.r_per_atom)
         rpa = torch.tensor(r_atoms.astype(np.int32), device=dev)
     ctx = TBContext(N, n_max + 24, int(r_atoms.max()))
+    ctx.set_seeds(args.seeds)
     if args.calib_copy_mb:
         src = torch.ones(args.calib_copy_mb << 17, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -307,7 +310,7 @@ def main():
                                + ", periodic",
                    "n_atoms": N, "r_cluster_A": w.r_cut, "krylov_block_steps": w.r, "kT_eV": w.kT,
                    "cluster_atoms_mean": float(np.mean(n_cluster)), "cluster_atoms_max": n_max,
-                   "precision": head_prec, "dt_fs": args.dt,
+                   "precision": head_prec, "dt_fs": args.dt, "seeds": args.seeds,
                    "steps_from": "one fixed start state" if fixed else "a velocity-Verlet trajectory"},
         "roofline": roof,
         "cpu_baseline": cpu,

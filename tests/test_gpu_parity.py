@@ -199,3 +199,40 @@ def test_parity_large_sampled_fixed_mu(torch_cuda, name, n_cluster):
     err = rel_inf(G, F)
     print(f"  {name}: sampled force rel err {err:.3e}")
     assert err <= 1e-8
+
+
+def test_parity_c60_240_orbital_seeds(torch_cuda):
+    """The paper's per-orbital seeding (tb_set_seeds TB_SEEDS_ORBITAL) against
+    the oracle's orbital mode: FP64 to the parity bar, FP32 within 1e-3 eV/A."""
+    w = inputs.workload("c60_240")
+    ora = otb.run(w.pos, w.cell, (1, 1, 1), P, w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                  processes=NPROC, seeds="orbital")
+    ctx = make_ctx(w.n_atoms, 128, w.r)
+    ctx.set_seeds("orbital")
+    res = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons)
+    assert abs(res["mu"] - ora["mu"]) < 1e-9
+    check_against_oracle(res, ora, range(w.n_atoms))
+    r32 = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                  precision="fp32")
+    fe = float(np.abs(r32["forces"] - ora["forces"]).max())
+    print(f"  orbital seeds: fp32 max force err {fe:.3e} eV/A; reorth steps/atom "
+          f"{res['stats']['reorth_steps'] / w.n_atoms:.1f} (fp64)")
+    assert fe <= 1e-3
+
+
+def test_orbital_seeds_exact_limit_small_cluster(torch_cuda):
+    """An isolated jittered 8-atom diamond cell, every sphere the whole cluster
+    (32 orbitals), r = 40 past every orbital's grade: the orbital form equals
+    full diagonalisation, as does the block form at r = 10."""
+    pos, _ = inputs.cubic_diamond(1, 3.567, 0.05, 77)
+    pos = pos - pos.mean(axis=0) + 100.0
+    ex = exact.solve(pos, BIG, (0, 0, 0), P, 0.1, n_electrons=32.0)
+    for seeds, r in (("orbital", 40), ("block", 10)):
+        ctx = make_ctx(8, 8, r)
+        ctx.set_seeds(seeds)
+        res = gpu_run(ctx, pos, BIG, (0, 0, 0), 8.0, r, 0.1, n_electrons=32.0)
+        ctx.close()
+        print(f"  {seeds}: mu err {abs(res['mu'] - ex['mu']):.2e}, force err {np.abs(res['forces'] - ex['forces']).max():.2e}")
+        assert abs(res["mu"] - ex["mu"]) < 1e-9
+        assert rel_inf(res["forces"], ex["forces"]) < 1e-8
+        assert abs(res["e"][3] - ex["e_total"]) < 1e-10 * abs(ex["e_total"])
