@@ -137,6 +137,66 @@ def velocity_verlet(ff: TBForceField, pos: torch.Tensor, vel: torch.Tensor, dt: 
     return pos, vel, rec
 
 
+EV_A3_GPA = 160.21766208      # 1 eV/A^3 in GPa
+
+
+def npt_berendsen(evaluate, pos: torch.Tensor, vel: torch.Tensor, cell: torch.Tensor, dt: float,
+                  steps: int, T0: float, P0_GPa: float, tau_T: float, tau_P: float,
+                  compressibility: float, mass: float = inputs.MASS_C, periodic=(True, True, True)):
+    """NPT molecular dynamics: velocity Verlet with a Berendsen thermostat and
+    an isotropic Berendsen barostat (the compression runs of Sec. 4 need a
+    pressure control; the paper does not say which, so a generic weak-coupling
+    scheme is used).
+
+    evaluate(pos, cell) -> (E_tot, forces [N][3], virial [3][3]) at the given
+    positions and orthorhombic cell lengths (tensors on pos.device).
+    Per step: half kick, drift, wrap, evaluate, half kick; then
+      T = 2 K / (3N - 3) k_B,  velocities *= sqrt(1 + dt/tau_T (T0/T - 1)),
+      P = (2 K / 3 - tr(W) / 3) / V,  scale = (1 - compressibility dt/tau_P (P0 - P))^(1/3),
+      positions and cell *= scale
+    (units: A, fs, eV, K; compressibility in 1/GPa, P in GPa). The forces are
+    kept through the cell scaling (weak coupling). Returns (pos, vel, cell,
+    record [steps][4] of E_tot, T, P in GPa, V)."""
+    N = pos.shape[0]
+    acc_unit = inputs.ACC_UNIT / mass
+    ke_unit = 0.5 * mass / inputs.ACC_UNIT
+    per = torch.tensor([bool(x) for x in periodic], device=pos.device)
+    pos, vel, cell = pos.clone(), vel.clone(), cell.clone()
+    e, f, W = evaluate(pos, cell)
+    acc = f * acc_unit
+    rec = torch.empty((steps, 4), dtype=torch.float64, device=pos.device)
+    for k in range(steps):
+        vel = vel + 0.5 * dt * acc
+        pos = pos + dt * vel
+        pos = torch.where(per, torch.remainder(pos, cell), pos)
+        e, f, W = evaluate(pos, cell)
+        acc = f * acc_unit
+        vel = vel + 0.5 * dt * acc
+        ke = ke_unit * (vel * vel).sum()
+        T = 2.0 * ke / ((3 * N - 3) * inputs.K_B)
+        vel = vel * torch.sqrt(1.0 + dt / tau_T * (T0 / T - 1.0))
+        V = torch.prod(cell)
+        P = (2.0 * ke / 3.0 - torch.trace(W) / 3.0) / V * EV_A3_GPA
+        scale = (1.0 - compressibility * dt / tau_P * (P0_GPa - P)) ** (1.0 / 3.0)
+        pos = pos * scale
+        cell = cell * scale
+        rec[k, 0] = e
+        rec[k, 1] = T
+        rec[k, 2] = P
+        rec[k, 3] = V
+    return pos, vel, cell, rec
+
+
+def library_evaluator(ff: TBForceField):
+    """evaluate(pos, cell) for npt_berendsen through the library (the cell
+    lengths are read to the host for the list build)."""
+    def evaluate(pos, cell):
+        ff.s.cell = tuple(float(x) for x in cell.tolist())
+        e, f = ff(pos)
+        return e[3], f, ff.ctx.virial()
+    return evaluate
+
+
 class GraphedVerlet:
     """Velocity-Verlet MD with one whole step (position update, lists, Krylov
     solve, eigensolve, chemical potential, density matrix, forces, velocity
