@@ -69,17 +69,22 @@ __device__ __forceinline__ void givens(double x, double y, double& c, double& s,
   c = x * inv; s = y * inv; r = q * inv;
 }
 
-// Number of eigenvalues of the tridiagonal (D, E^2) below sigma: the count of
-// negative pivots of the LDL^T factorisation of S - sigma I (Sylvester's law
-// of inertia), pivots of magnitude below pivmin replaced by -pivmin. The
-// quotient E^2 / q uses the hardware reciprocal refined by one Newton step
-// (relative error near the unit roundoff, which perturbs each pivot by a few
-// ulps; bisection only needs the counts of a nearby matrix). E2s holds E^2
-// shifted by one (E2s[k] = E[k-1]^2, E2s[0] = 0) and d is a multiple of 4, so
-// four steps take two 16-byte loads of each array.
+// Number of eigenvalues of the tridiagonal (D, E^2) below sigma: the number
+// of sign changes in the sequence of leading principal minors of S - sigma I
+// (Sturm), p_k = (D_k - sigma) p_{k-1} - E_{k-1}^2 p_{k-2}, p_{-1} = 1,
+// p_{-2} = 0 -- equivalently the count of negative pivots of its LDL^T. The
+// recurrence needs no division (the pivot form spends most of its issue slots
+// on the FP64 reciprocal); p is brought back near 1 by a power of two every
+// four steps, scaled by the larger of the last two (four steps change |p| by
+// far less than the exponent range), and an exact zero becomes -2^-100 times
+// its predecessor: a sign change, like the pivot form's -pivmin, and the next
+// minor, ~ -E^2 p_{k-2}, keeps its size. E2s holds E^2 shifted by one (E2s[k] = E[k-1]^2,
+// E2s[0] = 0) and d is a multiple of 4, so four steps take two 16-byte loads
+// of each array.
 __device__ __forceinline__ int sturm_count(const double* D, const double* E2s, int d, double sigma,
                                            double pivmin) {
-  double q = 1.0;
+  (void)pivmin;
+  double p1 = 1.0, p2 = 0.0;
   int cnt = 0;
   for (int k = 0; k < d; k += 4) {
     const double2 d01 = *(const double2*)(D + k), d23 = *(const double2*)(D + k + 2);
@@ -87,12 +92,15 @@ __device__ __forceinline__ int sturm_count(const double* D, const double* E2s, i
     const double dv[4] = {d01.x, d01.y, d23.x, d23.y}, ev[4] = {e01.x, e01.y, e23.x, e23.y};
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      double rq = __builtin_amdgcn_rcp(q);
-      rq = fma(rq, fma(-q, rq, 1.0), rq);
-      q = (dv[u] - sigma) - ev[u] * rq;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
+      double p = fma(dv[u] - sigma, p1, -(ev[u] * p2));
+      if (p == 0.0) p = -0x1p-100 * p1;          // a sign change, like a pivot of -0
+      cnt += (int)(((unsigned)__double2hiint(p) ^ (unsigned)__double2hiint(p1)) >> 31);
+      p2 = p1;
+      p1 = p;
     }
+    const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(p1), fabs(p2)));
+    p1 = __builtin_amdgcn_ldexp(p1, -e);
+    p2 = __builtin_amdgcn_ldexp(p2, -e);
   }
   return cnt;
 }
