@@ -194,7 +194,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(counter, 16);
   ALLOC(xrep, 2 * N);
   ALLOC(eparts, 8);
-  ALLOC(wpart, ((N + 255) / 256) * 9);
+  ALLOC(wpart, ((N + 63) / 64) * 9);          // blocks of k_forces (64 atoms each)
   ALLOC(virial, 9);
   ALLOC(stats, ST_NSTATS);
 #undef ALLOC

@@ -9,7 +9,7 @@
 // D = V_pps - V_ppp, u_a = X_{s,a} - X_{a,s}. The pair adds +g to the energy
 // gradient on R_j and -g on R_i, so for atom k
 //   F_k = sum_{j in hop(k)} (g_kj - g_jk) + repulsive part,
-// gathered per atom (no atomics, fixed order). Repulsion
+// gathered per atom by a quad of lanes (no atomics, fixed order). Repulsion
 // E_rep = sum_i F(x_i), x_i = sum_j phi(r_ij), gives
 //   F_k += sum_j (F'(x_k) + F'(x_j)) phi'(r_kj) d_kj / r_kj.
 // Virial (pressure of the diamond cell, Sec. 5): with the same pair terms,
@@ -74,18 +74,23 @@ __global__ void __launch_bounds__(F_NT) k_rep_x(ForceArgs g) {
   g.xrep[2 * i + 1] = F;
 }
 
+// Four lanes per atom: lane q of the quad takes hop pairs q, q + 4, ...;
+// the quad then sums in a fixed order (shuffles), so the result does not
+// depend on timing.
+constexpr int F_APB = F_NT / 4;     // atoms per block
+
 __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
   __shared__ double s_w[F_NT / 64][9];
-  const int k = blockIdx.x * F_NT + threadIdx.x;
-  double W[9];
+  const int q4 = threadIdx.x & 3;
+  const int k = blockIdx.x * F_APB + (threadIdx.x >> 2);
+  double W[9], F[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < 9; ++q) W[q] = 0.0;
   if (k < g.n_atoms) {
-    double F[3] = {0.0, 0.0, 0.0};
     const int nh = g.hop_n[k];
     const int64_t pk = g.row_ptr[k];
     const double dFk = g.xrep[2 * k];
-    for (int t = 0; t < nh; ++t) {
+    for (int t = q4; t < nh; t += 4) {
       const size_t q = (size_t)k * ZMAX + t;
       const int j = g.hop_j[q];
       const double* dv = g.hop_d + 4 * q;
@@ -109,11 +114,16 @@ __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) W[a * 3 + b] += dv[a] * (gkj[b] + rep_k * dv[b]);
     }
-    if (g.forces) {
-      g.forces[3 * k] = F[0];
-      g.forces[3 * k + 1] = F[1];
-      g.forces[3 * k + 2] = F[2];
-    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    F[c] += __shfl_xor(F[c], 1, 64);
+    F[c] += __shfl_xor(F[c], 2, 64);
+  }
+  if (k < g.n_atoms && q4 == 0 && g.forces) {
+    g.forces[3 * k] = F[0];
+    g.forces[3 * k + 1] = F[1];
+    g.forces[3 * k + 2] = F[2];
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) W[q] = wave_sum(W[q]);
@@ -134,7 +144,7 @@ __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
 __global__ void __launch_bounds__(F_NT) k_energy(ForceArgs g) {
   __shared__ double red[F_NT / 64];
   if (threadIdx.x < 9) {                    // virial: blocks in a fixed order
-    const int nb = (g.n_atoms + F_NT - 1) / F_NT;
+    const int nb = (g.n_atoms + F_APB - 1) / F_APB;
     double t = 0.0;
     for (int b = 0; b < nb; ++b) t += g.wpart[(size_t)b * 9 + threadIdx.x];
     g.virial[threadIdx.x] = t;
@@ -159,7 +169,7 @@ __global__ void __launch_bounds__(F_NT) k_energy(ForceArgs g) {
 void launch_forces(const ForceArgs& a, hipStream_t st) {
   const int nb = (a.n_atoms + F_NT - 1) / F_NT;
   hipLaunchKernelGGL(k_rep_x, dim3(nb), dim3(F_NT), 0, st, a);
-  hipLaunchKernelGGL(k_forces, dim3(nb), dim3(F_NT), 0, st, a);
+  hipLaunchKernelGGL(k_forces, dim3((a.n_atoms + F_APB - 1) / F_APB), dim3(F_NT), 0, st, a);
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(F_NT), 0, st, a);
 }
 

@@ -310,7 +310,7 @@ struct tb_ctx {
   unsigned int* counter; // last-block counters
   double* xrep;          // [N]: sum_j phi, then F'(x)
   double* eparts;        // [4] band, entropy, rep, count
-  double* wpart;         // [ceil(N/256)][9] per-block virial sums
+  double* wpart;         // [ceil(N/64)][9] per-block virial sums
   double* virial;        // [9] virial of the last tb_energy_forces
   int have_virial;       // tb_energy_forces ran on the current rho
   int64_t* stats;        // [ST_NSTATS]
