@@ -166,6 +166,10 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(pair64, N * ZMAX * 4);
   ALLOC(pair32, N * ZMAX * 4);
   ALLOC(pair16, N * ZMAX * 4);
+  ALLOC(cell_of, N);
+  ALLOC(cell_atoms, N);
+  ALLOC(cell_cnt, (int64_t)NCELL_AXIS_MAX * NCELL_AXIS_MAX * NCELL_AXIS_MAX);
+  ALLOC(cell_start, (int64_t)NCELL_AXIS_MAX * NCELL_AXIS_MAX * NCELL_AXIS_MAX + 1);
   ALLOC(clu_n, N);
   ALLOC(clu_j, N * NC);
   ALLOC(loc_off, N * (NC + 1));

@@ -62,6 +62,12 @@ struct Box {
   int per[3];
 };
 
+constexpr int NCELL_AXIS_MAX = 64;   // cells per axis of the neighbour search
+struct CellGrid {
+  int n[3];        // cells per axis (1 on a non-periodic axis)
+  double len[3];   // cell edge (>= the cluster radius on a periodic axis with n > 1)
+};
+
 // --------------------------------------------------------------- helpers
 __device__ __forceinline__ double mic(double d, double L, int per) {
   return per ? d - L * rint(d / L) : d;
@@ -285,6 +291,8 @@ struct tb_ctx {
   double* pair64; float* pair32;                           // [N][ZMAX][4]: hx hy hz s
   uint16_t* pair16;                                        // [N][ZMAX][4]: the same in BF16
   int* clu_n; int* clu_j;                                  // [N][NC]
+  int* cell_of; int* cell_atoms;                           // [N]: cell of each atom, atoms by cell
+  int* cell_cnt; int* cell_start;                          // [CELLS], [CELLS + 1]
   int* loc_off; uint16_t* loc_ent;                         // [N][NC+1], [N][EMAX]
   double* hnorm;                                           // [N]
   int* jloc;                                               // [N][JMAX]

@@ -6,6 +6,14 @@
 //                the sphere C_i = {i} + {j : |d_ij| < r_cluster}, both sorted
 //                by j. Brute force over j keeps the lists deterministic; at
 //                the sizes here (N <= ~2e4) it is a small part of a step.
+//   k_cell_*     cell lists: on each periodic axis the box is cut into
+//                cells no shorter than the cluster radius (at most 64), a
+//                non-periodic axis is one cell; atoms are binned by counting
+//                (count, scan, scatter).
+//   k_lists      one workgroup per atom: the candidates of the 27 (fewer
+//                when an axis has fewer than 3 cells) neighbouring cells,
+//                hop list and cutoff sphere by minimum image, each put in
+//                index order by rank (the sphere after its target).
 //   k_pairs      per ordered pair: direction cosines h = d/|d| and the hopping
 //                scale s(|d|) (FP64, FP32 and BF16 copies), and the reverse slot.
 //   k_local      one workgroup per sphere: local couplings (a -> b, slot) with
@@ -26,67 +34,145 @@ __device__ __forceinline__ void stat_flag(int64_t* stats, int64_t bits) {
   atomicOr((unsigned long long*)&stats[ST_FLAGS], (unsigned long long)bits);
 }
 
+__global__ void k_cell_zero(int* __restrict__ cnt, int m) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) cnt[q] = 0;
+}
+
+__device__ __forceinline__ int cell_coord(double x, const Box& box, const CellGrid& cg, int a) {
+  if (cg.n[a] == 1) return 0;
+  double w = x - box.L[a] * floor(x / box.L[a]);          // into [0, L)
+  if (!(w >= 0.0)) w = 0.0;                               // non-finite: flagged by k_lists
+  int c = (int)(w / cg.len[a]);
+  return c < 0 ? 0 : (c >= cg.n[a] ? cg.n[a] - 1 : c);
+}
+
+__global__ void k_cell_count(int n, const double* __restrict__ pos, Box box, CellGrid cg,
+                             int* __restrict__ cell_of, int* __restrict__ cell_cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c0 = cell_coord(pos[3 * i], box, cg, 0), c1 = cell_coord(pos[3 * i + 1], box, cg, 1),
+            c2 = cell_coord(pos[3 * i + 2], box, cg, 2);
+  const int id = (c0 * cg.n[1] + c1) * cg.n[2] + c2;
+  cell_of[i] = id;
+  atomicAdd(&cell_cnt[id], 1);
+}
+
+// single workgroup: exclusive scan of the counts into cell_start[0..m], and
+// the counts reset to serve as scatter cursors
+__global__ void __launch_bounds__(LIST_NT) k_cell_scan(int m, int* __restrict__ cell_cnt,
+                                                       int* __restrict__ cell_start) {
+  __shared__ int s_part[LIST_NT];
+  __shared__ int s_base;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_base = 0;
+  __syncthreads();
+  for (int base = 0; base < m; base += LIST_NT) {
+    const int q = base + tid;
+    const int v = q < m ? cell_cnt[q] : 0;
+    s_part[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < LIST_NT; off <<= 1) {
+      const int add = tid >= off ? s_part[tid - off] : 0;
+      __syncthreads();
+      s_part[tid] += add;
+      __syncthreads();
+    }
+    if (q < m) {
+      cell_start[q] = s_base + s_part[tid] - v;
+      cell_cnt[q] = s_base + s_part[tid] - v;
+    }
+    __syncthreads();
+    if (tid == LIST_NT - 1) s_base += s_part[tid];
+    __syncthreads();
+  }
+  if (tid == 0) cell_start[m] = s_base;
+}
+
+__global__ void k_cell_fill(int n, const int* __restrict__ cell_of, int* __restrict__ cursor,
+                            int* __restrict__ cell_atoms) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cell_atoms[atomicAdd(&cursor[cell_of[i]], 1)] = i;
+}
+
+// Dynamic LDS: s_cj [nc_max] sphere members (unsorted, target excluded).
 __global__ void __launch_bounds__(LIST_NT)
-k_lists(int n, const double* __restrict__ pos, Box box, double r_list, double r_cluster,
-        int nc_max, int* __restrict__ hop_n, int* __restrict__ hop_j, double* __restrict__ hop_d,
-        int* __restrict__ clu_n, int* __restrict__ clu_j, int64_t* stats) {
+k_lists(int n, const double* __restrict__ pos, Box box, CellGrid cg, const int* __restrict__ cell_of,
+        const int* __restrict__ cell_start, const int* __restrict__ cell_atoms, double r_list,
+        double r_cluster, int nc_max, int* __restrict__ hop_n, int* __restrict__ hop_j,
+        double* __restrict__ hop_d, int* __restrict__ clu_n, int* __restrict__ clu_j, int64_t* stats) {
+  extern __shared__ int s_cj[];
+  __shared__ int s_hj[ZMAX];
+  __shared__ double s_hd[ZMAX][4];
+  __shared__ int s_nh, s_nc;
   const int i = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ int s_cnt[2][LIST_NT / 64];
-  __shared__ int s_base[2];
-  if (tid == 0) { s_base[0] = 0; s_base[1] = 1; }   // sphere slot 0 is the target
+  const int tid = threadIdx.x;
+  if (tid == 0) { s_nh = 0; s_nc = 0; }
   const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-  if (tid == 0) clu_j[(int64_t)i * nc_max] = i;
   const double rl2 = r_list * r_list, rc2 = r_cluster * r_cluster;
   bool nonfinite = !(isfinite(xi) && isfinite(yi) && isfinite(zi));
+  // the cells to scan on each axis: the atom's and its two neighbours, or
+  // every cell when the axis has fewer than three
+  const int ci = cell_of[i];
+  const int cc[3] = {ci / (cg.n[1] * cg.n[2]), (ci / cg.n[2]) % cg.n[1], ci % cg.n[2]};
+  int lo[3], cnt[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (cg.n[a] >= 3) { lo[a] = cc[a] - 1; cnt[a] = 3; }
+    else { lo[a] = 0; cnt[a] = cg.n[a]; }
+  }
   __syncthreads();
-  for (int base = 0; base < n; base += LIST_NT) {
-    const int j = base + tid;
-    bool in_hop = false, in_clu = false;
-    double dx = 0, dy = 0, dz = 0, r2 = 0;
-    if (j < n && j != i) {
-      dx = mic(pos[3 * j] - xi, box.L[0], box.per[0]);
-      dy = mic(pos[3 * j + 1] - yi, box.L[1], box.per[1]);
-      dz = mic(pos[3 * j + 2] - zi, box.L[2], box.per[2]);
-      r2 = dx * dx + dy * dy + dz * dz;
-      in_hop = r2 < rl2;
-      in_clu = r2 < rc2;
-      if (!isfinite(r2)) nonfinite = true;
-    }
-    const uint64_t bh = __ballot(in_hop), bc = __ballot(in_clu);
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int ph = __popcll(bh & below), pc = __popcll(bc & below);
-    if (lane == 0) { s_cnt[0][wave] = __popcll(bh); s_cnt[1][wave] = __popcll(bc); }
-    __syncthreads();
-    int oh = s_base[0], oc = s_base[1];
-    for (int w = 0; w < wave; ++w) { oh += s_cnt[0][w]; oc += s_cnt[1][w]; }
-    if (in_hop) {
-      const int slot = oh + ph;
-      if (slot < ZMAX) {
-        const int64_t q = (int64_t)i * ZMAX + slot;
-        hop_j[q] = j;
-        hop_d[4 * q] = dx; hop_d[4 * q + 1] = dy; hop_d[4 * q + 2] = dz; hop_d[4 * q + 3] = sqrt(r2);
+  for (int u0 = 0; u0 < cnt[0]; ++u0)
+    for (int u1 = 0; u1 < cnt[1]; ++u1)
+      for (int u2 = 0; u2 < cnt[2]; ++u2) {
+        const int a0 = (lo[0] + u0 + cg.n[0]) % cg.n[0], a1 = (lo[1] + u1 + cg.n[1]) % cg.n[1],
+                  a2 = (lo[2] + u2 + cg.n[2]) % cg.n[2];
+        const int cell = (a0 * cg.n[1] + a1) * cg.n[2] + a2;
+        const int b0 = cell_start[cell], b1 = cell_start[cell + 1];
+        for (int q = b0 + tid; q < b1; q += LIST_NT) {
+          const int j = cell_atoms[q];
+          if (j == i) continue;
+          const double dx = mic(pos[3 * j] - xi, box.L[0], box.per[0]);
+          const double dy = mic(pos[3 * j + 1] - yi, box.L[1], box.per[1]);
+          const double dz = mic(pos[3 * j + 2] - zi, box.L[2], box.per[2]);
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (!isfinite(r2)) nonfinite = true;
+          if (r2 < rl2) {
+            const int slot = atomicAdd(&s_nh, 1);
+            if (slot < ZMAX) { s_hj[slot] = j; s_hd[slot][0] = dx; s_hd[slot][1] = dy; s_hd[slot][2] = dz; s_hd[slot][3] = sqrt(r2); }
+          }
+          if (r2 < rc2) {
+            const int slot = atomicAdd(&s_nc, 1);
+            if (slot < nc_max - 1) s_cj[slot] = j;
+          }
+        }
       }
-    }
-    if (in_clu) {
-      const int slot = oc + pc;
-      if (slot < nc_max) clu_j[(int64_t)i * nc_max + slot] = j;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int th = 0, tc = 0;
-      for (int w = 0; w < LIST_NT / 64; ++w) { th += s_cnt[0][w]; tc += s_cnt[1][w]; }
-      s_base[0] += th; s_base[1] += tc;
-    }
-    __syncthreads();
+  __syncthreads();
+  const int nh = s_nh, ncl = s_nc + 1;          // the sphere counts its target
+  const int mh = nh < ZMAX ? nh : ZMAX, mc = ncl - 1 < nc_max - 1 ? ncl - 1 : nc_max - 1;
+  // index order by rank (the members are distinct)
+  if (tid < mh) {
+    const int j = s_hj[tid];
+    int rank = 0;
+    for (int e = 0; e < mh; ++e) rank += s_hj[e] < j;
+    const int64_t q = (int64_t)i * ZMAX + rank;
+    hop_j[q] = j;
+    hop_d[4 * q] = s_hd[tid][0]; hop_d[4 * q + 1] = s_hd[tid][1];
+    hop_d[4 * q + 2] = s_hd[tid][2]; hop_d[4 * q + 3] = s_hd[tid][3];
+  }
+  for (int t = tid; t < mc; t += LIST_NT) {
+    const int j = s_cj[t];
+    int rank = 0;
+    for (int e = 0; e < mc; ++e) rank += s_cj[e] < j;
+    clu_j[(int64_t)i * nc_max + 1 + rank] = j;
   }
   if (nonfinite) stat_flag(stats, FL_NONFINITE);
   if (tid == 0) {
-    const int nh = s_base[0], ncl = s_base[1];
+    clu_j[(int64_t)i * nc_max] = i;
     if (nh > ZMAX) stat_flag(stats, FL_HOP_OVERFLOW);
     if (ncl > nc_max) stat_flag(stats, FL_CLUSTER_OVERFLOW);
-    hop_n[i] = nh < ZMAX ? nh : ZMAX;
-    clu_n[i] = ncl < nc_max ? ncl : nc_max;
+    hop_n[i] = mh;
+    clu_n[i] = mc + 1;
     stat_max(stats, ST_MAX_HOP, nh);
     stat_max(stats, ST_MAX_CLUSTER, ncl);
   }
@@ -253,8 +339,24 @@ __global__ void k_rowptr(int n, const int* __restrict__ hop_n, const int* __rest
 
 void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st) {
   const int n = (int)c->n_atoms;
-  hipLaunchKernelGGL(k_lists, dim3(n), dim3(LIST_NT), 0, st, n, pos, c->box, r_list, c->r_cluster, c->nc_max,
-                     c->hop_n, c->hop_j, c->hop_d, c->clu_n, c->clu_j, c->stats);
+  // cells no shorter than the cluster radius on periodic axes (so a sphere
+  // lies in the 3 x 3 x 3 cells around its target); one cell otherwise
+  CellGrid cg;
+  for (int a = 0; a < 3; ++a) {
+    int m = c->box.per[a] ? (int)floor(c->box.L[a] / c->r_cluster) : 1;
+    m = m < 1 ? 1 : (m > NCELL_AXIS_MAX ? NCELL_AXIS_MAX : m);
+    cg.n[a] = m;
+    cg.len[a] = c->box.L[a] / m;
+  }
+  const int ncell = cg.n[0] * cg.n[1] * cg.n[2];
+  const int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_cell_zero, dim3((ncell + 255) / 256), dim3(256), 0, st, c->cell_cnt, ncell);
+  hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(256), 0, st, n, pos, c->box, cg, c->cell_of, c->cell_cnt);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(LIST_NT), 0, st, ncell, c->cell_cnt, c->cell_start);
+  hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(256), 0, st, n, c->cell_of, c->cell_cnt, c->cell_atoms);
+  hipLaunchKernelGGL(k_lists, dim3(n), dim3(LIST_NT), (size_t)c->nc_max * sizeof(int), st, n, pos, c->box, cg,
+                     c->cell_of, c->cell_start, c->cell_atoms, r_list, c->r_cluster, c->nc_max, c->hop_n,
+                     c->hop_j, c->hop_d, c->clu_n, c->clu_j, c->stats);
   const int64_t np = (int64_t)n * ZMAX;
   hipLaunchKernelGGL(k_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, n, c->model, c->hop_n,
                      c->hop_j, c->hop_d, c->pair64, c->pair32, c->pair16, c->hop_rev);
