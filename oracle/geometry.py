@@ -50,3 +50,33 @@ def cluster(i, pos, cell, periodic, r_cut):
     idx = np.concatenate([[i], sel]).astype(np.int64)
     x = np.concatenate([np.zeros((1, 3)), d[sel]], axis=0)
     return idx, x
+
+
+def group_of(i, m, n_atoms):
+    """The group of atom i in the paper's grouped form (Sec. 3, Eqs. 6-9):
+    consecutive index blocks {g m, ..., g m + m - 1} (the last one ragged)."""
+    g0 = (i // m) * m
+    return np.arange(g0, min(n_atoms, g0 + m))
+
+
+def group_cluster(i, m, pos, cell, periodic, r_cut):
+    """Union sphere C_G of the group G of atom i, shared by the group's chains
+    (Sec. 3: the m atoms of a group run their recursions on one Hamiltonian):
+    {i} followed by {j != i : min_{k in G} |d_kj| < R_cut} in increasing j,
+    with positions x_j = d_ij in the frame of i.  Those are the right images
+    only when |(d_ik)_a| + R_cut < L_a / 2 for every member k and periodic
+    axis a; otherwise ValueError."""
+    N = pos.shape[0]
+    members = group_of(i, m, N)
+    d_i = displacements_from(i, pos, cell, periodic)
+    for ax in range(3):
+        if periodic[ax] and np.any(np.abs(d_i[members, ax]) + r_cut >= 0.5 * cell[ax]):
+            raise ValueError("group spread plus cutoff reaches half the cell: ambiguous images")
+    inside = np.zeros(N, dtype=bool)
+    for k in members:
+        inside |= np.linalg.norm(displacements_from(k, pos, cell, periodic), axis=1) < r_cut
+    sel = np.nonzero(inside)[0]
+    sel = sel[sel != i]
+    idx = np.concatenate([[i], sel]).astype(np.int64)
+    x = np.concatenate([np.zeros((1, 3)), d_i[sel]], axis=0)
+    return idx, x

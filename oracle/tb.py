@@ -104,15 +104,20 @@ def orbital_solve(H, r, route="arnoldi", reorth=True):
 
 
 def atom_solve(i, pos, cell, periodic, p, r_cut, r, full_column=False,
-               route="arnoldi", reorth=True, seeds="block"):
+               route="arnoldi", reorth=True, seeds="block", group=1):
     """Krylov solve for target atom i.
 
     Returns dict with lam [d], w [d], J (global ids: i then hop(i) sorted),
     P = (Q Y) restricted to the rows of J, shape (4|J|, d), Y1 = Y[0:4, :],
     and with full_column also the cluster ids and Q Y on all cluster rows.
     seeds="orbital": the paper's one scalar chain per orbital (orbital_solve).
+    group=m > 1: the grouped form of Sec. 3 -- the recursion runs on the union
+    sphere of the m-atom group of i (geometry.group_cluster) instead of i's own.
     """
-    idx, x = geometry.cluster(i, pos, cell, periodic, r_cut)
+    if group > 1:
+        idx, x = geometry.group_cluster(i, group, pos, cell, periodic, r_cut)
+    else:
+        idx, x = geometry.cluster(i, pos, cell, periodic, r_cut)
     H = krylov.cluster_hamiltonian(x, p)
     if seeds == "orbital":
         lam, QY, Y1 = orbital_solve(H, r, route, reorth)
@@ -255,7 +260,7 @@ def _worker(i):
     g = _G
     return atom_solve(i, g["pos"], g["cell"], g["periodic"], g["p"], g["r_cut"],
                       int(g["r_of"](i)), full_column=g["full_column"],
-                      route=g["route"], reorth=g["reorth"], seeds=g["seeds"])
+                      route=g["route"], reorth=g["reorth"], seeds=g["seeds"], group=g["group"])
 
 
 def _limit_blas():
@@ -267,11 +272,12 @@ def _limit_blas():
 
 
 def solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, r_per_atom=None,
-                full_column=False, route="arnoldi", reorth=True, processes=None, seeds="block"):
+                full_column=False, route="arnoldi", reorth=True, processes=None, seeds="block",
+                group=1):
     """atom_solve over a list of atoms, in worker processes (one BLAS thread each)."""
     r_of = (lambda i: r_per_atom[i]) if r_per_atom is not None else (lambda i: r)
     _G.update(pos=pos, cell=cell, periodic=periodic, p=p, r_cut=r_cut, r_of=r_of,
-              full_column=full_column, route=route, reorth=reorth, seeds=seeds)
+              full_column=full_column, route=route, reorth=reorth, seeds=seeds, group=group)
     atoms = list(atoms)
     if processes is None:
         processes = len(os.sched_getaffinity(0))
@@ -286,21 +292,22 @@ def solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, r_per_atom=None,
 # --------------------------------------------------------------- driver
 def run(pos, cell, periodic, p, r_cut, r, kT, n_electrons=None, mu=None,
         r_per_atom=None, atoms=None, force_atoms=None, full_column=False,
-        route="arnoldi", reorth=True, processes=None, seeds="block"):
+        route="arnoldi", reorth=True, processes=None, seeds="block", group=1):
     """The whole path for one geometry.
 
     atoms=None solves every atom; mu must then be None (bisection on
     n_electrons) or given.  With a subset of atoms, mu must be given, and
     forces are returned for force_atoms (each needs itself and hop() solved).
     seeds: "block" (four-orbital seed block) or "orbital" (one scalar chain
-    per orbital, Eqs. 6-9).
+    per orbital, Eqs. 6-9).  group: atoms per group of the grouped form
+    (Sec. 3; union spheres, geometry.group_cluster), 1 = each atom's own sphere.
     """
     pos = np.asarray(pos, dtype=np.float64)
     N = pos.shape[0]
     all_atoms = atoms is None
     atoms = list(range(N)) if all_atoms else list(atoms)
     sols = solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, r_per_atom,
-                       full_column, route, reorth, processes, seeds)
+                       full_column, route, reorth, processes, seeds, group)
     by_atom = {s["i"]: s for s in sols}
     if mu is None:
         if not all_atoms:

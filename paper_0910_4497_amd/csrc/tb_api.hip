@@ -75,7 +75,8 @@ extern "C" int tb_destroy(tb_ctx* c) {
   void* ptrs[] = {c->hop_n, c->hop_j, c->hop_rev, c->hop_d, c->pair64, c->pair32, c->clu_n, c->clu_j,
                   c->loc_off, c->loc_ent, c->hnorm, c->jloc, c->row_ptr, c->col_j, c->vbuf, c->tab,
                   c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->rot_cs, c->rot_p,
-                  c->rot_n, c->seg, c->seg_n, c->evec, c->tri, c->eig_scratch, c->omega, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats};
+                  c->rot_n, c->seg, c->seg_n, c->evec, c->tri, c->eig_scratch, c->omega, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats,
+                  c->pair16, c->cell_of, c->cell_atoms, c->cell_cnt, c->cell_start, c->wpart, c->virial};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (c->ev_pool) {
