@@ -72,6 +72,9 @@ def parse():
                          "per-atom phase (0: skip)")
     ap.add_argument("--seeds", choices=("block", "orbital"), default="block",
                     help="block: four-orbital seed block; orbital: one scalar chain per orbital")
+    ap.add_argument("--groups", type=int, default=1,
+                    help="grouped form: groups of this many atoms (put in compact index blocks) "
+                         "share their union sphere; 1: each atom's own sphere")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing the candidates first")
     ap.add_argument("--no-graph", action="store_true",
@@ -181,11 +184,14 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     torch.cuda.set_stream(stream)
     N = w.n_atoms
+    if args.groups > 1:                    # compact groups of consecutive indices
+        w.pos = np.ascontiguousarray(w.pos[inputs.group_order(w.pos, w.cell, (1, 1, 1), args.groups)])
     pos0 = torch.tensor(w.pos, dtype=torch.float64, device=dev)
     vel0 = torch.tensor(inputs.maxwell_velocities(N, args.temperature, seed=7), dtype=torch.float64,
                         device=dev)
     # size the sphere capacity from the geometry (plus a margin for the MD motion)
     probe = TBContext(N, 560, 1)
+    probe.set_groups(args.groups)
     sizes = probe.build_local_H(pos0, w.cell, (1, 1, 1), params, w.r_cut, want_sizes=True)
     n_max = int(sizes.max().item())
     n_cluster = sizes.cpu().numpy()
@@ -198,6 +204,7 @@ def main():
         rpa = torch.tensor(r_atoms.astype(np.int32), device=dev)
     ctx = TBContext(N, n_max + 24, int(r_atoms.max()))
     ctx.set_seeds(args.seeds)
+    ctx.set_groups(args.groups)
     if args.calib_copy_mb:
         src = torch.ones(args.calib_copy_mb << 17, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -263,7 +270,7 @@ def main():
         procs = min(16, len(os.sched_getaffinity(0)))
         sample = args.cpu_sample or min(N, 2048)
         t = timing.time_atom_solves(w.pos, w.cell, (1, 1, 1), params, w.r_cut, w.r, sample,
-                                    seed=11, processes=procs)
+                                    seed=11, processes=procs, seeds=args.seeds, group=args.groups)
         cpu = {"value": round(t["steps_per_s"], 5), "unit": "MD steps/s", "cores": t["cores"],
                "kind": "oracle",
                "sample": f"{t['n_sample']} seeded atom-solves of {args.workload} "
@@ -310,7 +317,7 @@ def main():
                                + ", periodic",
                    "n_atoms": N, "r_cluster_A": w.r_cut, "krylov_block_steps": w.r, "kT_eV": w.kT,
                    "cluster_atoms_mean": float(np.mean(n_cluster)), "cluster_atoms_max": n_max,
-                   "precision": head_prec, "dt_fs": args.dt, "seeds": args.seeds,
+                   "precision": head_prec, "dt_fs": args.dt, "seeds": args.seeds, "groups": args.groups,
                    "steps_from": "one fixed start state" if fixed else "a velocity-Verlet trajectory"},
         "roofline": roof,
         "cpu_baseline": cpu,

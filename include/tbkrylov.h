@@ -181,6 +181,26 @@ int tb_virial(tb_ctx *ctx, double *virial_out);
 enum { TB_SEEDS_BLOCK = 0, TB_SEEDS_ORBITAL = 1 };
 int tb_set_seeds(tb_ctx *ctx, int seeds);
 
+/* Grouped form (Sec. 3): the atoms are taken in groups of m consecutive
+ * indices {g m, ..., g m + m - 1} (the last group ragged), and the m atoms of
+ * a group run their recursions on one Hamiltonian, that of the union of the
+ * group's cutoff spheres: for every member i the sphere becomes
+ *     C_G(i) = {i} + {j != i : min over members k of |d_kj| < r_cluster},
+ * sorted by j, with positions relative to i (minimum image). With
+ * TB_SEEDS_ORBITAL this is the paper's form, 4m scalar chains with diagonal
+ * A_k, B_k per group; with TB_SEEDS_BLOCK each member's seed block runs on
+ * the union sphere. m = 1 (the default) is each atom's own sphere. Callers
+ * order the atoms so that a group's members are close (atoms of one molecule
+ * consecutive, or a spatial sort); n_cluster_max must hold the union spheres.
+ * Every member must satisfy |(d_ik)_a| + r_cluster < L_a / 2 on each periodic
+ * axis a (unique images); otherwise the next tb_get_stats returns
+ * TB_ECUTOFF. Host-side setting: the next tb_build_local_H builds the
+ * unions (one workgroup per group, sort and unique in LDS), and until then
+ * the context counts as not built.
+ * Errors: TB_EINVAL (m outside [1, 8]), TB_ECAPACITY (m * n_cluster_max
+ * > 8192). */
+int tb_set_groups(tb_ctx *ctx, int m);
+
 /* Launch granularity of the per-atom phases of tb_krylov_rho (block Lanczos,
  * projected eigensolve, density-matrix assembly). Every target atom's local
  * solve is independent once the couplings are built (Sec. 2, the cutoff

@@ -18,14 +18,14 @@ from . import tb
 
 
 def time_atom_solves(pos, cell, periodic, p, r_cut, r, n_sample, seed=0,
-                     processes=None):
+                     processes=None, seeds="block", group=1):
     N = pos.shape[0]
     rng = np.random.default_rng(seed)
     atoms = sorted(rng.choice(N, size=min(n_sample, N), replace=False).tolist())
     if processes is None:
         processes = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    tb.solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, processes=processes)
+    tb.solve_atoms(atoms, pos, cell, periodic, p, r_cut, r, processes=processes, seeds=seeds, group=group)
     dt = time.perf_counter() - t0
     per_atom = dt / len(atoms)
     return {"n_sample": len(atoms), "seconds": dt, "cores": processes,

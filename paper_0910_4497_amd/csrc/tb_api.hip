@@ -578,6 +578,9 @@ extern "C" int tb_get_stats(tb_ctx* c, int64_t* stats_host, int n_stats) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   s[ST_MEMORY] = (int64_t)c->bytes;
   for (int q = 0; q < n_stats && q < ST_NSTATS; ++q) stats_host[q] = s[q];
+  if (s[ST_FLAGS] & FL_GROUP_IMAGE)
+    return fail(TB_ECUTOFF, "a group's spread plus r_cluster reaches half a box length (flags 0x%llx)",
+                (unsigned long long)s[ST_FLAGS]);
   if (s[ST_FLAGS] & (FL_HOP_OVERFLOW | FL_CLUSTER_OVERFLOW | FL_COUPLING_OVERFLOW))
     return fail(TB_ECAPACITY, "device list overflow (flags 0x%llx)", (unsigned long long)s[ST_FLAGS]);
   if (s[ST_FLAGS]) return fail(TB_EDEVICE, "device error flags 0x%llx", (unsigned long long)s[ST_FLAGS]);
@@ -588,6 +591,16 @@ extern "C" int tb_set_seeds(tb_ctx* c, int seeds) {
   if (!c) return fail(TB_EINVAL, "ctx is null");
   if (seeds != TB_SEEDS_BLOCK && seeds != TB_SEEDS_ORBITAL) return fail(TB_EINVAL, "unknown seeds %d", seeds);
   c->seeds = seeds;
+  return TB_OK;
+}
+
+extern "C" int tb_set_groups(tb_ctx* c, int m) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (m < 1 || m > GROUP_MAX) return fail(TB_EINVAL, "group size %d outside [1, %d]", m, GROUP_MAX);
+  if ((int64_t)m * c->nc_max > UNION_LDS_MAX)
+    return fail(TB_ECAPACITY, "group size %d x sphere capacity %d exceeds %d", m, c->nc_max, UNION_LDS_MAX);
+  c->group_m = m;
+  c->stage = 0;                               // the spheres must be rebuilt
   return TB_OK;
 }
 

@@ -47,7 +47,8 @@ enum StatSlot {
 };
 enum FlagBits {
   FL_HOP_OVERFLOW = 1, FL_CLUSTER_OVERFLOW = 2, FL_COUPLING_OVERFLOW = 4,
-  FL_NONFINITE = 8, FL_EIG_NOCONV = 16, FL_ROTLOG_OVERFLOW = 32, FL_SEG_OVERFLOW = 64
+  FL_NONFINITE = 8, FL_EIG_NOCONV = 16, FL_ROTLOG_OVERFLOW = 32, FL_SEG_OVERFLOW = 64,
+  FL_GROUP_IMAGE = 128
 };
 
 // Model parameters as the kernels see them (plain struct, passed by value).
@@ -63,6 +64,8 @@ struct Box {
 };
 
 constexpr int NCELL_AXIS_MAX = 64;   // cells per axis of the neighbour search
+constexpr int GROUP_MAX = 8;          // atoms per group of the grouped form
+constexpr int UNION_LDS_MAX = 8192;   // group members' sphere entries a union is built from (32 KiB)
 struct CellGrid {
   int n[3];        // cells per axis (1 on a non-periodic axis)
   double len[3];   // cell edge (>= the cluster radius on a periodic axis with n > 1)
@@ -273,6 +276,7 @@ struct tb_ctx {
   int eig_per_cu, eig_per_cu_max;   // persistent k_eig workgroups per compute unit
   int atoms_per_launch;  // 0: one launch per phase; k: per-atom phases in launches of k atoms
   int seeds;             // TB_SEEDS_BLOCK or TB_SEEDS_ORBITAL
+  int group_m;           // atoms per group of the grouped form (union spheres); 0 or 1: own spheres
   size_t bytes;
 
   // state

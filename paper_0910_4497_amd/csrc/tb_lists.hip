@@ -1,11 +1,6 @@
 // Neighbour lists, cutoff spheres, Slater-Koster pair data and the local
 // coupling structure of every sphere (Sec. 2: locality; Eq. 1: Hamiltonian).
 //
-//   k_lists      one workgroup per atom i scans all j in order and compacts
-//                (order-preserving) the hop list {j : |d_ij| < r_list} and
-//                the sphere C_i = {i} + {j : |d_ij| < r_cluster}, both sorted
-//                by j. Brute force over j keeps the lists deterministic; at
-//                the sizes here (N <= ~2e4) it is a small part of a step.
 //   k_cell_*     cell lists: on each periodic axis the box is cut into
 //                cells no shorter than the cluster radius (at most 64), a
 //                non-periodic axis is one cell; atoms are binned by counting
@@ -14,6 +9,10 @@
 //                when an axis has fewer than 3 cells) neighbouring cells,
 //                hop list and cutoff sphere by minimum image, each put in
 //                index order by rank (the sphere after its target).
+//   k_union      grouped form (Sec. 3: the m atoms of a group share one
+//                Hamiltonian): one workgroup per group of consecutive atoms;
+//                the union of the members' spheres (sort + unique in LDS)
+//                replaces each member's sphere, the member first.
 //   k_pairs      per ordered pair: direction cosines h = d/|d| and the hopping
 //                scale s(|d|) (FP64, FP32 and BF16 copies), and the reverse slot.
 //   k_local      one workgroup per sphere: local couplings (a -> b, slot) with
@@ -175,6 +174,98 @@ k_lists(int n, const double* __restrict__ pos, Box box, CellGrid cg, const int* 
     clu_n[i] = mc + 1;
     stat_max(stats, ST_MAX_HOP, nh);
     stat_max(stats, ST_MAX_CLUSTER, ncl);
+  }
+}
+
+// Dynamic LDS: s_v [pcap] (a power of two >= m * nc_max). Every read of the
+// members' spheres ends before the first barrier, and the groups own disjoint
+// rows, so the spheres are rewritten in place.
+__global__ void __launch_bounds__(LIST_NT)
+k_union(int n, int m, const double* __restrict__ pos, Box box, double r_cluster, int nc_max,
+        int* __restrict__ clu_n, int* __restrict__ clu_j, int64_t* stats) {
+  extern __shared__ int s_v[];
+  __shared__ int s_off[GROUP_MAX + 1];
+  __shared__ int s_pos[GROUP_MAX];          // rank of each member in the union
+  __shared__ int s_part[LIST_NT];
+  const int tid = threadIdx.x;
+  const int g0 = blockIdx.x * m;
+  const int mm = n - g0 < m ? n - g0 : m;
+  if (tid == 0) {
+    int o = 0;
+    for (int k = 0; k < mm; ++k) { s_off[k] = o; o += clu_n[g0 + k]; }
+    s_off[mm] = o;
+  }
+  __syncthreads();
+  const int tot = s_off[mm];
+  int P = 1;
+  while (P < tot) P <<= 1;
+  for (int k = 0; k < mm; ++k) {
+    const int nk = s_off[k + 1] - s_off[k];
+    for (int t = tid; t < nk; t += LIST_NT) s_v[s_off[k] + t] = clu_j[(int64_t)(g0 + k) * nc_max + t];
+  }
+  for (int t = tot + tid; t < P; t += LIST_NT) s_v[t] = INT_MAX;
+  // images: the union is taken in the frame of each member, which is
+  // unambiguous while |(d_ik)_a| + r_cluster < L_a / 2 for all members i, k
+  for (int q = tid; q < mm * mm; q += LIST_NT) {
+    const int i = g0 + q / mm, k = g0 + q % mm;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (box.per[a] && !(fabs(mic(pos[3 * k + a] - pos[3 * i + a], box.L[a], 1)) + r_cluster < 0.5 * box.L[a]))
+        stat_flag(stats, FL_GROUP_IMAGE);
+  }
+  __syncthreads();
+  // bitonic sort, ascending
+  for (int size = 2; size <= P; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < P / 2; t += LIST_NT) {
+        const int lo = 2 * stride * (t / stride) + t % stride, hi = lo + stride;
+        const int a = s_v[lo], b = s_v[hi];
+        if ((a > b) == ((lo & size) == 0)) { s_v[lo] = b; s_v[hi] = a; }
+      }
+      __syncthreads();
+    }
+  // unique values: first of each run; chunked exclusive scan of their count
+  const int C = (tot + LIST_NT - 1) / LIST_NT;
+  const int t0 = tid * C, t1 = t0 + C < tot ? t0 + C : tot;
+  int cnt = 0;
+  for (int t = t0; t < t1; ++t) cnt += (t == 0 || s_v[t] != s_v[t - 1]);
+  s_part[tid] = cnt;
+  __syncthreads();
+  for (int off = 1; off < LIST_NT; off <<= 1) {
+    const int add = tid >= off ? s_part[tid - off] : 0;
+    __syncthreads();
+    s_part[tid] += add;
+    __syncthreads();
+  }
+  const int u = s_part[LIST_NT - 1];
+  int p = s_part[tid] - cnt;
+  for (int t = t0; t < t1; ++t) {
+    if (!(t == 0 || s_v[t] != s_v[t - 1])) continue;
+    const int v = s_v[t] - g0;
+    if (v >= 0 && v < mm) s_pos[v] = p;
+    ++p;
+  }
+  __syncthreads();
+  // member i: slot 0 = i, then the union without i, in index order
+  p = s_part[tid] - cnt;
+  for (int t = t0; t < t1; ++t) {
+    if (!(t == 0 || s_v[t] != s_v[t - 1])) continue;
+    const int v = s_v[t];
+    for (int k = 0; k < mm; ++k) {
+      const int pi = s_pos[k];
+      if (p == pi) continue;
+      const int slot = p < pi ? p + 1 : p;
+      if (slot < nc_max) clu_j[(int64_t)(g0 + k) * nc_max + slot] = v;
+    }
+    ++p;
+  }
+  if (tid < mm) {
+    clu_j[(int64_t)(g0 + tid) * nc_max] = g0 + tid;
+    clu_n[g0 + tid] = u < nc_max ? u : nc_max;
+  }
+  if (tid == 0) {
+    if (u > nc_max) stat_flag(stats, FL_CLUSTER_OVERFLOW);
+    stat_max(stats, ST_MAX_CLUSTER, u);
   }
 }
 
@@ -357,6 +448,12 @@ void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st) {
   hipLaunchKernelGGL(k_lists, dim3(n), dim3(LIST_NT), (size_t)c->nc_max * sizeof(int), st, n, pos, c->box, cg,
                      c->cell_of, c->cell_start, c->cell_atoms, r_list, c->r_cluster, c->nc_max, c->hop_n,
                      c->hop_j, c->hop_d, c->clu_n, c->clu_j, c->stats);
+  if (c->group_m > 1) {
+    int pcap = 1;
+    while (pcap < c->group_m * c->nc_max) pcap <<= 1;
+    hipLaunchKernelGGL(k_union, dim3((n + c->group_m - 1) / c->group_m), dim3(LIST_NT), (size_t)pcap * sizeof(int),
+                       st, n, c->group_m, pos, c->box, c->r_cluster, c->nc_max, c->clu_n, c->clu_j, c->stats);
+  }
   const int64_t np = (int64_t)n * ZMAX;
   hipLaunchKernelGGL(k_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, n, c->model, c->hop_n,
                      c->hop_j, c->hop_d, c->pair64, c->pair32, c->pair16, c->hop_rev);

@@ -197,3 +197,31 @@ def chain_positions(n_sites: int, spacing: float, axis: int = 2) -> np.ndarray:
     pos = np.zeros((n_sites, 3))
     pos[:, axis] = (np.arange(n_sites) - n_sites // 2) * spacing
     return pos
+
+
+def group_order(pos: np.ndarray, cell, periodic, m: int) -> np.ndarray:
+    """Permutation that puts the atoms in compact groups of m consecutive
+    indices (for the grouped form, whose groups are index blocks): recursive
+    median bisection along the widest axis of the wrapped coordinates, the
+    parts kept at multiples of m atoms; each leaf (m atoms, one ragged) is a
+    group, its members in increasing index. pos[perm] is the reordered input;
+    m = 1 keeps the order."""
+    if m <= 1:
+        return np.arange(np.asarray(pos).shape[0])
+    x = np.array(pos, dtype=np.float64)
+    cell = np.asarray(cell, dtype=np.float64)
+    for a in range(3):
+        if periodic[a]:
+            x[:, a] -= cell[a] * np.floor(x[:, a] / cell[a])
+    out, stack = [], [np.arange(x.shape[0])]
+    while stack:
+        idx = stack.pop()
+        if len(idx) <= m:
+            out.append(np.sort(idx))
+            continue
+        a = int(np.argmax(x[idx].max(axis=0) - x[idx].min(axis=0)))
+        k = ((len(idx) // m + 1) // 2) * m
+        o = idx[np.argsort(x[idx, a], kind="stable")]
+        stack.append(o[k:])
+        stack.append(o[:k])
+    return np.concatenate(out)

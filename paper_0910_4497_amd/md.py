@@ -36,6 +36,8 @@ class TBSettings:
     mu: float | None = None
     precision: str = "fp64"
     r_per_atom: torch.Tensor | None = None
+    seeds: str = "block"                  # or "orbital": one scalar chain per orbital
+    groups: int = 1                       # grouped form: atoms per union sphere (index blocks)
 
 
 class TBForceField:
@@ -45,11 +47,14 @@ class TBForceField:
         self.s = settings
         r_max = settings.r if settings.r_per_atom is None else max(settings.r, int(settings.r_per_atom.max()))
         self.ctx = TBContext(n_atoms, n_cluster_max, r_max, device=device)
+        self.ctx.set_seeds(settings.seeds)
+        self.ctx.set_groups(settings.groups)
         self.mu = None
 
     @classmethod
     def from_context(cls, ctx: TBContext, settings: TBSettings) -> "TBForceField":
-        """Wraps an existing context (its stream, capacities and buffers)."""
+        """Wraps an existing context (its stream, capacities, buffers, and its own seeds
+        and groups settings; those fields of `settings` are not applied)."""
         ff = cls.__new__(cls)
         ff.s, ff.ctx, ff.mu = settings, ctx, None
         return ff
@@ -60,6 +65,7 @@ class TBForceField:
         s = settings
         cap = PROBE_CLUSTER_CAP
         probe = TBContext(pos.shape[0], cap, 1, device=pos.device.index or 0)
+        probe.set_groups(s.groups)
         sizes = probe.build_local_H(pos, s.cell, s.periodic, s.params, s.r_cluster, want_sizes=True)
         n_max = int(sizes.max().item())
         probe.close()

@@ -23,7 +23,7 @@ ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4:
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
               "max_cluster_pos", "memory_bytes", "reorth_second_pass", "reorth_steps", "basis_bytes")
 EXPORTS = ("tb_create", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
-           "tb_energy_forces", "tb_get_stats", "tb_virial", "tb_set_seeds", "tb_set_launch", "tb_autotune", "tb_profile_enable", "tb_profile_read",
+           "tb_energy_forces", "tb_get_stats", "tb_virial", "tb_set_seeds", "tb_set_groups", "tb_set_launch", "tb_autotune", "tb_profile_enable", "tb_profile_read",
            "tb_last_error")
 PHASES = ("lists_local", "lanczos", "eig", "mu", "rho", "forces")
 RHO_ROWS_MAX = 25          # rho row atoms per target: itself + at most 24 neighbours
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tb_get_stats.argtypes = [P, ctypes.POINTER(I64), I]
     lib.tb_virial.argtypes = [P, P]
     lib.tb_set_seeds.argtypes = [P, I]
+    lib.tb_set_groups.argtypes = [P, I]
     lib.tb_set_launch.argtypes = [P, I]
     lib.tb_autotune.argtypes = [P, I, P, I, ctypes.POINTER(I)]
     lib.tb_profile_enable.argtypes = [P, I]
@@ -206,6 +207,12 @@ class TBContext:
     def set_seeds(self, seeds: str):
         """'block' (four-orbital seed block) or 'orbital' (one scalar chain per orbital)."""
         _check(self.lib.tb_set_seeds(self.h, {"block": 0, "orbital": 1}[seeds]))
+
+    def set_groups(self, m: int):
+        """Grouped form: groups of m consecutive atoms share their union sphere
+        (1: each atom's own sphere). The spheres are rebuilt by the next
+        build_local_H."""
+        _check(self.lib.tb_set_groups(self.h, int(m)))
 
     def set_launch(self, atoms_per_launch: int):
         """0: one launch per per-atom phase; k: launches over groups of k atoms."""

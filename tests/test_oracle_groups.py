@@ -126,3 +126,25 @@ def test_group_cluster_brute_force_images():
     bad[1, 0] = 3.0
     with pytest.raises(ValueError):
         geometry.group_cluster(0, 4, bad, np.array([11.0, 50.0, 50.0]), per, 3.0)
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 7])
+def test_group_order_permutation_and_compactness(m):
+    """inputs.group_order is a permutation whose index blocks of m are compact:
+    on the 1920-atom crystal every group of 2 or 4 satisfies the image
+    condition of the union spheres at R_cut = 7 A (spread + R_cut < L/2)."""
+    w = inputs.workload("c60_1920")
+    L = np.asarray(w.cell)
+    perm = inputs.group_order(w.pos, L, (1, 1, 1), m)
+    assert sorted(perm.tolist()) == list(range(w.n_atoms))
+    pos = w.pos[perm]
+    worst = 0.0
+    for g0 in range(0, w.n_atoms, m):
+        G = np.arange(g0, min(w.n_atoms, g0 + m))
+        for i in G:
+            d = geometry.min_image(pos[G] - pos[i], L, (1, 1, 1))
+            worst = max(worst, float(np.abs(d).max()))
+    if m in (2, 4):
+        assert worst + w.r_cut < 0.5 * L.min(), worst
+    if m == 1:
+        assert list(perm) == list(range(w.n_atoms))
