@@ -343,6 +343,7 @@ static EigArgs eig_args(const tb_ctx* c, int n) {
   ea.seg = c->seg; ea.seg_n = c->seg_n; ea.seg_max = c->seg_max;
   ea.counter = c->work_counter + 1; ea.scratch = c->eig_scratch; ea.evec = c->evec; ea.tri = c->tri;
   ea.stats = c->stats;
+  ea.scalar = c->seeds == TB_SEEDS_ORBITAL ? 1 : 0;
   return ea;
 }
 

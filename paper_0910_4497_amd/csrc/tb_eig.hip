@@ -569,6 +569,169 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
   }
 }
 
+// Orbital seeds: T is the direct sum of four scalar chains, chain c on the
+// rows 4k + c (k < K) of the block layout (A_k, B_k diagonal). Each chain is
+// its own symmetric tridiagonal (D = alpha^c, E = beta^c) and is solved on
+// its own, with no band reduction (Z = I, an empty rotation log): bisection
+// on the chain's Sturm sequence, clusters only among the chain's own
+// eigenvalues, eigenvectors by twisted factorisation or inverse iteration on
+// the chain, written to the rows 4k + c of U (the other rows zero).
+// Eigenpair t = c K + j is the j-th of chain c, and Y[0:4, t] = U[0:4, t] is
+// nonzero in row c only. The chains are stored chain-major at a stride Kp =
+// K rounded up to 4 (the Sturm count reads four rows at a time), padded with
+// D = 1e30, E = 0: rows that add no sign change below any eigenvalue.
+__global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
+  extern __shared__ double esm[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = blockDim.x, nw = nt / 64;
+  const int dmax = 4 * g.r_max;
+  const int DP = 4 * ((g.r_max + 3) & ~3);
+  double* Dg = esm;                        // [4][Kp] chain-major, padded
+  double* Eg = Dg + DP;
+  double* E2 = Eg + DP;
+  double* E2s = E2 + DP;                   // E2s[k] = E[k-1]^2 within the chain
+  double* lam_s = E2s + DP;                // [dmax] eigenvalues, ascending within each chain
+  double* red = lam_s + dmax;              // [EIG_NT/64][4]
+  int* pos_s = (int*)(red + 4 * (EIG_NT / 64));   // [dmax] position inside a cluster
+  __shared__ int s_atom, s_maxpos;
+  __shared__ double s_lo, s_hi, s_e2max;
+  double* scr = g.scratch + (size_t)blockIdx.x * dmax * 4 * nt + tid;
+  const size_t ld = 4 * (size_t)dmax;      // chain row k -> row 4k + c of U
+
+  for (;;) {
+    if (tid == 0) s_atom = atomicAdd(g.counter, 1);
+    __syncthreads();
+    const int atom = g.atom0 + s_atom;
+    if (atom >= g.n_atoms) break;
+    const int K = g.kused[atom];
+    const int d = 4 * K;
+    const int Kp = (K + 3) & ~3;
+    const double* tab = g.tab + (size_t)atom * g.r_max * 32;
+    double glo = 1e300, ghi = -1e300, e2m = 0.0;
+    for (int q = tid; q < 4 * Kp; q += nt) {
+      const int c = q / Kp, k = q % Kp;
+      double Dk = 1e30, Ek = 0.0, Em = 0.0;
+      if (k < K) {
+        Dk = tab[(size_t)k * 32 + 5 * c];
+        Ek = (k + 1 < K) ? tab[(size_t)k * 32 + 16 + 5 * c] : 0.0;
+        Em = (k > 0) ? tab[(size_t)(k - 1) * 32 + 16 + 5 * c] : 0.0;
+        const double rad = fabs(Ek) + fabs(Em);
+        glo = fmin(glo, Dk - rad); ghi = fmax(ghi, Dk + rad); e2m = fmax(e2m, Ek * Ek);
+      }
+      Dg[q] = Dk; Eg[q] = Ek; E2[q] = Ek * Ek; E2s[q] = Em * Em;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      glo = fmin(glo, __shfl_xor(glo, off, 64));
+      ghi = fmax(ghi, __shfl_xor(ghi, off, 64));
+      e2m = fmax(e2m, __shfl_xor(e2m, off, 64));
+    }
+    if (lane == 0) { red[wave * 4] = glo; red[wave * 4 + 1] = ghi; red[wave * 4 + 2] = e2m; }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 1e300, b = -1e300, e = 0.0;
+      for (int w = 0; w < nw; ++w) { a = fmin(a, red[w * 4]); b = fmax(b, red[w * 4 + 1]); e = fmax(e, red[w * 4 + 2]); }
+      const double pad = 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + 1e-300;
+      s_lo = a - pad; s_hi = b + pad; s_e2max = e;
+    }
+    __syncthreads();
+    const double lo0 = s_lo, hi0 = s_hi;
+    const double anorm = fmax(fabs(lo0), fabs(hi0));
+    const double pivmin = DBL_MIN * fmax(1.0, s_e2max);
+    for (int t = tid; t < d; t += nt) {
+      const int c = t / K, j = t - c * K;
+      const double* Dc = Dg + c * Kp;
+      const double* E2c = E2s + c * Kp;
+      double l = lo0, h = hi0;
+      for (int it = 0; it < 128; ++it) {
+        const double m = 0.5 * (l + h);
+        if (sturm_count(Dc, E2c, Kp, m, pivmin) <= j) l = m; else h = m;
+        if (h - l <= 4.0 * DBL_EPSILON * fmax(fabs(l), fabs(h)) + pivmin) break;
+      }
+      lam_s[t] = 0.5 * (l + h);
+    }
+    __syncthreads();
+    const double ctol = fmax(1e-6 * anorm, 1e-5);
+    const double small = DBL_EPSILON * anorm + 1e-300;
+    int mp = 0;
+    for (int t = tid; t < d; t += nt) {
+      const int c0 = (t / K) * K;
+      int p = 0;
+      while (t - p - 1 >= c0 && lam_s[t - p] - lam_s[t - p - 1] < ctol) ++p;
+      pos_s[t] = p;
+      mp = p > mp ? p : mp;
+    }
+    for (int off = 32; off > 0; off >>= 1) { const int o = __shfl_xor(mp, off, 64); mp = o > mp ? o : mp; }
+    if (tid == 0) s_maxpos = 0;
+    __syncthreads();
+    if (lane == 0) atomicMax(&s_maxpos, mp);
+    __syncthreads();
+    const int maxpos = s_maxpos;
+    double* Ua = g.evec + (size_t)atom * dmax * dmax;       // U[k][t], row stride dmax
+    for (int q = tid; q < d * d; q += nt) {                  // rows of the other chains
+      const int row = q / d, t = q - row * d;
+      if ((row & 3) != t / K) Ua[(size_t)row * dmax + t] = 0.0;
+    }
+    for (int round = 0; round <= maxpos; ++round) {
+      for (int t = tid; t < d; t += nt) {
+        if (pos_s[t] != round) continue;
+        const int c = t / K, cend = (c + 1) * K;
+        const double* Dc = Dg + c * Kp;
+        const double* Ec = Eg + c * Kp;
+        const double* E2c = E2 + c * Kp;
+        double* xc = Ua + (size_t)c * dmax + t;
+        if (round == 0 && (t + 1 >= cend || pos_s[t + 1] == 0)) {
+          twisted_vec(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
+          continue;
+        }
+        double nrm = inv_solve(Dc, Ec, K, lam_s[t], small, t, nullptr, xc, ld, scr, nt);
+        double sc = 1.0 / sqrt(nrm);
+        for (int k = 0; k < K; ++k) xc[(size_t)k * ld] *= sc;
+        nrm = inv_solve(Dc, Ec, K, lam_s[t], small, t, xc, xc, ld, scr, nt);
+        sc = 1.0 / sqrt(nrm);
+        for (int k = 0; k < K; ++k) xc[(size_t)k * ld] *= sc;
+        if (round > 0) {
+          for (int rep = 0; rep < 2; ++rep) {
+            for (int j = t - round; j < t; ++j) {
+              const double* uj = Ua + (size_t)c * dmax + j;
+              double dot = 0.0;
+              for (int k = 0; k < K; ++k) dot += uj[(size_t)k * ld] * xc[(size_t)k * ld];
+              for (int k = 0; k < K; ++k) xc[(size_t)k * ld] -= dot * uj[(size_t)k * ld];
+            }
+            nrm = 0.0;
+            for (int k = 0; k < K; ++k) nrm += xc[(size_t)k * ld] * xc[(size_t)k * ld];
+            sc = 1.0 / sqrt(nrm);
+            for (int k = 0; k < K; ++k) xc[(size_t)k * ld] *= sc;
+            if (rep == 0) {
+              nrm = inv_solve(Dc, Ec, K, lam_s[t], small, t, xc, xc, ld, scr, nt);
+              sc = 1.0 / sqrt(nrm);
+              for (int k = 0; k < K; ++k) xc[(size_t)k * ld] *= sc;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    double* lam = g.lam + (size_t)atom * dmax;
+    double* wgt = g.wgt + (size_t)atom * dmax;
+    double* y1 = g.y1 + (size_t)atom * 4 * dmax;
+    for (int t = tid; t < dmax; t += nt) {
+      const int c = t < d ? t / K : -1;
+      const double a = t < d ? Ua[(size_t)c * dmax + t] : 0.0;    // chain row 0 = block row c
+      lam[t] = t < d ? lam_s[t] : 0.0;
+      wgt[t] = a * a;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) y1[(size_t)cc * dmax + t] = (cc == c) ? a : 0.0;
+    }
+    if (tid == 0) {
+      g.rot_n[atom] = 0;
+      g.seg_n[2 * atom] = 0;
+      g.seg_n[2 * atom + 1] = 0;
+      atomicMax((unsigned long long*)&g.stats[ST_MAX_CLUSTER_POS], (unsigned long long)maxpos);
+    }
+    __syncthreads();
+  }
+}
+
 // One wave per atom.
 __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   extern __shared__ double rsm[];
@@ -704,7 +867,11 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
 
 size_t eig_lds_bytes(int r_max) {
   const size_t dmax = 4 * (size_t)r_max;
-  return (4 * dmax + 5 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) + (dmax + EIG_NT) * sizeof(int) + 64;
+  const size_t band = (4 * dmax + 5 * dmax) * sizeof(double) + 4 * (EIG_NT / 64) * sizeof(double) +
+                      (dmax + EIG_NT) * sizeof(int) + 64;
+  const size_t dp = 4 * (size_t)((r_max + 3) & ~3);          // k_eig_chains
+  const size_t chains = (4 * dp + dmax + 4 * (EIG_NT / 64)) * sizeof(double) + dmax * sizeof(int) + 64;
+  return band > chains ? band : chains;
 }
 size_t band_lds_bytes(int r_max) { return 2 * band_atom_doubles(r_max) * sizeof(double) + 64; }
 size_t rho_lds_bytes(int r_max) {
@@ -720,6 +887,9 @@ hipError_t eig_set_lds(int r_max) {
   hipError_t e = hipFuncSetAttribute((const void*)k_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)eig_lds_bytes(r_max));
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_eig_chains, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)eig_lds_bytes(r_max));
+  if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_band, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)band_lds_bytes(r_max));
   if (e != hipSuccess) return e;
@@ -728,6 +898,10 @@ hipError_t eig_set_lds(int r_max) {
 }
 
 void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
+  if (a.scalar) {
+    hipLaunchKernelGGL(k_eig_chains, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
+    return;
+  }
   hipLaunchKernelGGL(k_band, dim3((a.n_atoms - a.atom0 + 1) / 2), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
   hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
 }

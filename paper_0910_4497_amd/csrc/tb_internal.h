@@ -207,6 +207,7 @@ struct EigArgs {
   double* evec;                        // [N][4 r_max][4 r_max]: eigenvectors of the tridiagonal, [k][t]
   double* tri;                         // [N][2][4 r_max]: diagonal and off-diagonal of the tridiagonal
   int64_t* stats;
+  int scalar;                          // orbital seeds: T is four independent chains (k_eig_chains)
 };
 struct RhoArgs {
   int atom0, n_atoms, r_max;           // target atoms [atom0, n_atoms) of this launch
