@@ -30,10 +30,11 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_lanczos_c60_1920_traffic.md")
 
 
-def measured_traffic(workload, precision):
+def measured_traffic(workload, precision, kernel, workgroups):
     """HBM bytes per k_lanczos launch from the committed FETCH_SIZE/WRITE_SIZE
-    record, if it was taken on this workload and precision with the current
-    kernel source (else None)."""
+    record, if it was taken on this workload and precision, with the current
+    kernel source, for the same kernel instance and workgroup count (the
+    fetched bytes depend on how many spheres share each L2), else None."""
     import hashlib
     try:
         rec = None
@@ -42,6 +43,8 @@ def measured_traffic(workload, precision):
                 if line.startswith("traffic-record:"):
                     rec = json.loads(line.split(":", 1)[1])
         if rec is None or rec["workload"] != workload or rec["precision"] != precision:
+            return None
+        if rec["kernel"] != kernel or int(rec["workgroups"]) != int(workgroups):
             return None
         with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()[:16]
@@ -259,8 +262,18 @@ def main():
     # blocks of 4n x 4 values per re-orthogonalisation pass at step k
     bytes_launch = float(head["stats"]["basis_bytes"])
     achieved = bytes_launch / (lz_avg_ms * 1e-3) / 1e9
+    # the kernel instance and workgroup count of the timed launches (known
+    # when the tuner chose them); the traffic record applies to that shape only
+    traffic = None
+    shape = shapes.get(head_prec)
+    if shape:
+        lz_kernel = "k_lanczos<{}, {}, {}, {}>".format("double" if head_prec == "fp64" else "float",
+                                                      shape["lanczos_threads"], shape["lanczos_waves_per_simd"],
+                                                      "true" if head_prec == "bf16" else "false")
+        n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+        traffic = measured_traffic(args.workload, head_prec, lz_kernel, min(n_cu * shape["lanczos_wg_per_cu"], N))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(args.workload, head_prec),
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": "k_lanczos", "avg_ms": round(lz_avg_ms, 4),
             "algorithmic_bytes_per_launch": bytes_launch}
 

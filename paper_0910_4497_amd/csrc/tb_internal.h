@@ -35,7 +35,7 @@ constexpr int RMAX_LIMIT = 256;
 constexpr int PROF_MAX = 4096;
 constexpr int N_PHASES = 6;
 constexpr size_t LDS_CU = 160 * 1024;   // LDS per compute unit (gfx950)
-constexpr size_t LDS_RESERVE = 1024;    // per workgroup: static LDS and allocation granularity
+constexpr size_t LDS_RESERVE = 512;     // per workgroup: static LDS (a few bytes) and allocation rounding
 constexpr int LZ_PER_CU_MAX = 4;   // Krylov workgroups per compute unit the tuner may pick
 constexpr int EIG_PER_CU_MAX = 8;  // k_eig workgroups per compute unit the tuner may pick
 
