@@ -180,7 +180,7 @@ def main():
     from paper_0910_4497_amd.tb import TBContext
 
     w = inputs.workload(args.workload)
-    params = inputs.load_params()
+    params = inputs.load_params(w.params)
     dev = torch.device("cuda", 0)
     # every launch goes to one non-default stream (default priority), so an MD
     # step can be captured into a graph
@@ -193,7 +193,7 @@ def main():
     vel0 = torch.tensor(inputs.maxwell_velocities(N, args.temperature, seed=7), dtype=torch.float64,
                         device=dev)
     # size the sphere capacity from the geometry (plus a margin for the MD motion)
-    probe = TBContext(N, 560, 1)
+    probe = TBContext(N, 560, 1, hop_max=w.hop_max)
     probe.set_groups(args.groups)
     sizes = probe.build_local_H(pos0, w.cell, (1, 1, 1), params, w.r_cut, want_sizes=True)
     n_max = int(sizes.max().item())
@@ -205,7 +205,7 @@ def main():
     if w.r_per_atom is not None:
         r_atoms = np.asarray(w.r_per_atom)
         rpa = torch.tensor(r_atoms.astype(np.int32), device=dev)
-    ctx = TBContext(N, n_max + 24, int(r_atoms.max()))
+    ctx = TBContext(N, n_max + 24, int(r_atoms.max()), hop_max=w.hop_max)
     ctx.set_seeds(args.seeds)
     ctx.set_groups(args.groups)
     if args.calib_copy_mb:
@@ -327,7 +327,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {N} C atoms, "
                                + ("4x4x4 cubic diamond" if args.workload.startswith("diamond") else "fcc C60 crystal")
+                               + (", hopping to 7 A (long-range variant of the Xu form)"
+                                  if w.params == inputs.PARAMS_LONG else "")
                                + ", periodic",
+                   "params": os.path.basename(w.params), "hop_capacity": w.hop_max,
                    "n_atoms": N, "r_cluster_A": w.r_cut, "krylov_block_steps": w.r, "kT_eV": w.kT,
                    "cluster_atoms_mean": float(np.mean(n_cluster)), "cluster_atoms_max": n_max,
                    "precision": head_prec, "dt_fs": args.dt, "seeds": args.seeds, "groups": args.groups,

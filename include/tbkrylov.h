@@ -84,10 +84,21 @@ typedef struct tb_ctx tb_ctx;
 /* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`
  * (a hipStream_t, or NULL for the default stream). Capacities: at most
  * n_atoms_max atoms, n_cluster_max atoms per cutoff sphere, r_max Krylov
- * block steps; hop lists hold at most 24 neighbours within max(rm, dm).
+ * block steps; hop lists hold at most 24 neighbours within max(rm, dm)
+ * (tb_create_ex sets another capacity).
  * Allocates all work memory (size reported by tb_get_stats). */
 int tb_create(tb_ctx **ctx, int hip_device, void *hip_stream,
               int64_t n_atoms_max, int n_cluster_max, int r_max);
+
+/* tb_create with a hop-list capacity of hop_max neighbours within max(rm, dm)
+ * per atom (1 <= hop_max <= 256): hopping ranges longer than the 2.6 A of
+ * Xu's set, such as the 7 A interlayer range of the paper's second
+ * parameter set (Sec. 4), need ~200. The density-matrix blocks of a target
+ * are its hop list plus itself, so rho_out needs room for
+ * n_atoms * (hop_max + 1) blocks. tb_create is tb_create_ex with 24.
+ * Errors: as tb_create, and TB_EINVAL for hop_max outside [1, 256]. */
+int tb_create_ex(tb_ctx **ctx, int hip_device, void *hip_stream,
+                 int64_t n_atoms_max, int n_cluster_max, int r_max, int hop_max);
 
 int tb_destroy(tb_ctx *ctx);
 

@@ -91,8 +91,14 @@ extern "C" int tb_destroy(tb_ctx* c) {
 
 extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t n_atoms_max,
                          int n_cluster_max, int r_max) {
+  return tb_create_ex(out, hip_device, hip_stream, n_atoms_max, n_cluster_max, r_max, ZMAX_DEFAULT);
+}
+
+extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int64_t n_atoms_max,
+                            int n_cluster_max, int r_max, int hop_max) {
   if (!out) return fail(TB_EINVAL, "ctx pointer is null");
   *out = nullptr;
+  if (hop_max < 1 || hop_max > ZMAX_CAP) return fail(TB_EINVAL, "hop_max must be in [1, %d]", ZMAX_CAP);
   if (n_atoms_max < 1 || n_atoms_max > (1 << 24)) return fail(TB_EINVAL, "n_atoms_max out of range");
   if (n_cluster_max < 1 || n_cluster_max > NCLUSTER_LIMIT)
     return fail(TB_EINVAL, "n_cluster_max must be in [1, %d]", NCLUSTER_LIMIT);
@@ -108,7 +114,8 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   c->na_max = n_atoms_max;
   c->nc_max = n_cluster_max;
   c->r_max = r_max;
-  c->emax = (int64_t)n_cluster_max * ZMAX;
+  c->zmax = hop_max;
+  c->emax = (int64_t)n_cluster_max * hop_max;
   const int64_t dmax = 4 * (int64_t)r_max;
   // band -> tridiagonal takes fewer than (1/8 + 1/6 + 1/4) d^2 + 3 d rotations
   c->rot_max = (3 * dmax * dmax) / 4 + 16 * dmax;
@@ -156,17 +163,17 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   const int64_t n_wg_eig_max = (int64_t)c->n_cu * c->eig_per_cu_max < n_atoms_max
                                    ? (int64_t)c->n_cu * c->eig_per_cu_max : n_atoms_max;
 
-  const int64_t N = n_atoms_max, NC = n_cluster_max;
+  const int64_t N = n_atoms_max, NC = n_cluster_max, Z = hop_max;
   hipError_t a = hipSuccess;
 #define ALLOC(ptr, cnt) \
   if (a == hipSuccess) a = alloc(c, &c->ptr, (size_t)(cnt));
   ALLOC(hop_n, N);
-  ALLOC(hop_j, N * ZMAX);
-  ALLOC(hop_rev, N * ZMAX);
-  ALLOC(hop_d, N * ZMAX * 4);
-  ALLOC(pair64, N * ZMAX * 4);
-  ALLOC(pair32, N * ZMAX * 4);
-  ALLOC(pair16, N * ZMAX * 4);
+  ALLOC(hop_j, N * Z);
+  ALLOC(hop_rev, N * Z);
+  ALLOC(hop_d, N * Z * 4);
+  ALLOC(pair64, N * Z * 4);
+  ALLOC(pair32, N * Z * 4);
+  ALLOC(pair16, N * Z * 4);
   ALLOC(cell_of, N);
   ALLOC(cell_atoms, N);
   ALLOC(cell_cnt, (int64_t)NCELL_AXIS_MAX * NCELL_AXIS_MAX * NCELL_AXIS_MAX);
@@ -176,9 +183,9 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   ALLOC(loc_off, N * (NC + 1));
   ALLOC(loc_ent, N * c->emax);
   ALLOC(hnorm, N);
-  ALLOC(jloc, N * JMAX);
+  ALLOC(jloc, N * (Z + 1));
   ALLOC(row_ptr, N + 1);
-  ALLOC(col_j, N * JMAX);
+  ALLOC(col_j, N * (Z + 1));
   ALLOC(tab, N * r_max * 32);
   ALLOC(kused, N);
   ALLOC(work_counter, 16);
@@ -211,7 +218,7 @@ extern "C" int tb_create(tb_ctx** out, int hip_device, void* hip_stream, int64_t
   }
   if (a == hipSuccess) {
     double* v = nullptr;
-    a = alloc(c, &v, (size_t)N * 4 * JMAX * dmax);
+    a = alloc(c, &v, (size_t)N * 4 * (Z + 1) * dmax);
     c->vj = v;
   }
   if (a != hipSuccess) {
@@ -314,6 +321,7 @@ static LanczosArgs lanczos_args(const tb_ctx* c, int n, int r, const int* r_per_
   LanczosArgs la;
   la.atom0 = 0; la.n_atoms = n; la.r_default = r; la.r_per_atom = r_per_atom;
   la.clu_n = c->clu_n; la.clu_j = c->clu_j; la.loc_off = c->loc_off; la.loc_ent = c->loc_ent;
+  la.zmax = c->zmax;
   la.hnorm = c->hnorm; la.jloc = c->jloc; la.hop_n = c->hop_n;
   la.pair = precision == TB_BF16 ? (const void*)c->pair16
           : (fp32 ? (const void*)c->pair32 : (const void*)c->pair64);
@@ -412,7 +420,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   // K7: density-matrix blocks
   RhoArgs ra;
   ra.n_atoms = n; ra.r_max = c->r_max; ra.kused = c->kused; ra.hop_n = c->hop_n; ra.clu_j = c->clu_j;
-  ra.nc_max = c->nc_max; ra.lam = c->lam; ra.y1 = c->y1; ra.rot_cs = c->rot_cs; ra.rot_p = c->rot_p;
+  ra.nc_max = c->nc_max; ra.zmax = c->zmax; ra.lam = c->lam; ra.y1 = c->y1; ra.rot_cs = c->rot_cs; ra.rot_p = c->rot_p;
   ra.rot_n = c->rot_n; ra.rot_max = c->rot_max;
   ra.seg = c->seg; ra.seg_n = c->seg_n; ra.seg_max = c->seg_max; ra.evec = c->evec; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
   ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out; ra.stats = c->stats;
@@ -548,7 +556,7 @@ extern "C" int tb_energy_forces(tb_ctx* c, double* e_out, double* forces) {
   if (!e_out) return fail(TB_EINVAL, "e_out is null");
   HIP_TRY(hipSetDevice(c->device));
   ForceArgs fa;
-  fa.n_atoms = (int)c->n_atoms; fa.M = c->model;
+  fa.n_atoms = (int)c->n_atoms; fa.zmax = c->zmax; fa.M = c->model;
   fa.hop_n = c->hop_n; fa.hop_j = c->hop_j; fa.hop_rev = c->hop_rev; fa.hop_d = c->hop_d;
   fa.row_ptr = c->row_ptr; fa.rho = c->rho_last; fa.xrep = c->xrep; fa.forces = forces;
   fa.eparts = c->eparts; fa.kT = c->kT; fa.e_out = e_out;

@@ -848,7 +848,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     double acc[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    const size_t row0 = (size_t)atom * (4 * JMAX) + q0;
+    const size_t row0 = (size_t)atom * (4 * (g.zmax + 1)) + q0;
     for (int m = lane; m < d; m += RHO_NT) {
       const double x0 = x[XS * m], x1 = x[XS * m + 1], x2 = x[XS * m + 2], x3 = x[XS * m + 3];
 #pragma unroll

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(F_NT) k_rep_x(ForceArgs g) {
   const int nh = g.hop_n[i];
   for (int t = 0; t < nh; ++t) {
     double phi, dphi;
-    pair_term(g.M, g.hop_d[((size_t)i * ZMAX + t) * 4 + 3], phi, dphi);
+    pair_term(g.M, g.hop_d[((size_t)i * g.zmax + t) * 4 + 3], phi, dphi);
     x += phi;
   }
   const double* c = g.M.frep;
@@ -91,14 +91,14 @@ __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
     const int64_t pk = g.row_ptr[k];
     const double dFk = g.xrep[2 * k];
     for (int t = q4; t < nh; t += 4) {
-      const size_t q = (size_t)k * ZMAX + t;
+      const size_t q = (size_t)k * g.zmax + t;
       const int j = g.hop_j[q];
       const double* dv = g.hop_d + 4 * q;
       double gkj[3], gjk[3];
       pair_grad(g.M, dv, g.rho + (size_t)(pk + 1 + t) * 16, gkj);
       const int rt = g.hop_rev[q];
       if (rt >= 0) {
-        const size_t qj = (size_t)j * ZMAX + rt;
+        const size_t qj = (size_t)j * g.zmax + rt;
         pair_grad(g.M, g.hop_d + 4 * qj, g.rho + (size_t)(g.row_ptr[j] + 1 + rt) * 16, gjk);
       } else {
         gjk[0] = gjk[1] = gjk[2] = 0.0;     // only after a list overflow (flagged)

@@ -27,8 +27,8 @@ __device__ __forceinline__ float bf16_round(float x) {
   return __uint_as_float(u & 0xffff0000u);
 }
 
-constexpr int ZMAX = 24;           // neighbours within max(rm, dm) per atom
-constexpr int JMAX = ZMAX + 1;     // rho row atoms per target: itself + hop list
+constexpr int ZMAX_DEFAULT = 24;   // hop-list capacity of tb_create: neighbours within max(rm, dm)
+constexpr int ZMAX_CAP = 256;      // largest hop-list capacity (tb_create_ex); rho rows = capacity + 1
 constexpr int LOCAL_BITS = 11;     // local atom index bits in a packed coupling
 constexpr int NCLUSTER_LIMIT = (1 << LOCAL_BITS) - 1;
 constexpr int RMAX_LIMIT = 256;
@@ -172,15 +172,16 @@ __device__ __forceinline__ double wave_max(double v) {
 struct LanczosArgs {
   int atom0, n_atoms, r_default;       // target atoms [atom0, n_atoms) of this launch
   const int* r_per_atom;
-  const int* clu_n; const int* clu_j; const int* loc_off; const uint16_t* loc_ent;
+  const int* clu_n; const int* clu_j; const int* loc_off; const uint32_t* loc_ent;
+  int zmax;                    // hop-list capacity (rho rows per target: zmax + 1)
   const double* hnorm; const int* jloc; const int* hop_n;
-  const void* pair;            // [N][ZMAX][4] double or float: hx hy hz s
+  const void* pair;            // [N][zmax][4] double or float: hx hy hz s
   int nc_max; int64_t emax; int r_max;
   double eps_s, eps_p, v_sss, v_sps, v_pps, v_ppp;
   void* vbuf;                  // [WG][r_max][4*nc_max][4]
   double* tab;                 // [N][r_max][2][16]: A_k, B_k
   int* kused;
-  void* vj;                    // [N][4*JMAX][4*r_max]
+  void* vj;                    // [N][4*(zmax+1)][4*r_max]
   int* counter;
   double* omega;               // [WG][3][r_max][16] float orthogonality estimates (when not in LDS)
   int om_lds;                  // estimates kept in LDS
@@ -212,6 +213,7 @@ struct EigArgs {
 struct RhoArgs {
   int atom0, n_atoms, r_max;           // target atoms [atom0, n_atoms) of this launch
   const int* kused; const int* hop_n; const int* clu_j; int nc_max;
+  int zmax;                            // hop-list capacity (rho rows per target: zmax + 1)
   const double* lam; const double* y1;
   const double* rot_cs; const uint16_t* rot_p; const int* rot_n; int64_t rot_max;
   const int* seg; const int* seg_n; int seg_max;
@@ -240,7 +242,7 @@ int mu_blocks(int64_t n_pairs);
 void launch_mu(const MuArgs& a, double mu_fixed, bool fixed, int n_iter, hipStream_t st);
 
 struct ForceArgs {
-  int n_atoms;
+  int n_atoms, zmax;
   Model M;
   const int* hop_n; const int* hop_j; const int* hop_rev; const double* hop_d;
   const int64_t* row_ptr;
@@ -292,23 +294,24 @@ struct tb_ctx {
   const double* rho_last; // rho_out of the last tb_krylov_rho
 
   // lists (K1-K3)
-  int* hop_n; int* hop_j; int* hop_rev; double* hop_d;     // [N][ZMAX][4]: dx dy dz r
-  double* pair64; float* pair32;                           // [N][ZMAX][4]: hx hy hz s
-  uint16_t* pair16;                                        // [N][ZMAX][4]: the same in BF16
+  int zmax;                                                // hop-list capacity
+  int* hop_n; int* hop_j; int* hop_rev; double* hop_d;     // [N][zmax][4]: dx dy dz r
+  double* pair64; float* pair32;                           // [N][zmax][4]: hx hy hz s
+  uint16_t* pair16;                                        // [N][zmax][4]: the same in BF16
   int* clu_n; int* clu_j;                                  // [N][NC]
   int* cell_of; int* cell_atoms;                           // [N]: cell of each atom, atoms by cell
   int* cell_cnt; int* cell_start;                          // [CELLS], [CELLS + 1]
-  int* loc_off; uint16_t* loc_ent;                         // [N][NC+1], [N][EMAX]
+  int* loc_off; uint32_t* loc_ent;                         // [N][NC+1], [N][EMAX]: b | slot << LOCAL_BITS
   double* hnorm;                                           // [N]
-  int* jloc;                                               // [N][JMAX]
+  int* jloc;                                               // [N][zmax + 1]
   int64_t* row_ptr;                                        // [N+1]
-  int* col_j;                                              // [N*JMAX] (pairs, compact)
+  int* col_j;                                              // [N*(zmax + 1)] (pairs, compact)
   // Krylov (K4)
   void* vbuf;            // [WG][RMAX][4*NC][4] f64 or f32
   double* omega;         // [WG][3][RMAX][16] orthogonality estimates
   double* tab;           // [N][RMAX][2][16]
   int* kused;            // [N]
-  void* vj;              // [N][4*JMAX][4*RMAX] f64 or f32
+  void* vj;              // [N][4*(zmax + 1)][4*RMAX] f64 or f32
   int* work_counter;     // persistent-kernel atom queue
   // eigen (K5/K7)
   double* lam; double* wgt; double* y1;                    // [N][D], [N][D], [N][4][D]

@@ -142,7 +142,7 @@ k_lanczos(LanczosArgs g) {
   double* s_misc = s_red + LZ_NW * 16;                      // 224 doubles
   int* s_off = (int*)(s_misc + 224);                        // [ncap+1]
   int* s_gid = s_off + ncap + 1;                            // [ncap]
-  signed char* s_js = (signed char*)(s_gid + ncap);         // [ncap]
+  int16_t* s_js = (int16_t*)(s_gid + ncap);                 // [ncap] rho row index of a local atom, or -1
   float* s_om = (float*)(((uintptr_t)(s_js + ncap) + 15) & ~(uintptr_t)15);   // [3][r_max][16] if om_lds
   float* s_ab = s_om + (g.om_lds ? (size_t)3 * g.r_max * 16 : 0);                 // [r_max][32] if ab_lds
   // second block buffer (vprev_lds): V_k and V_{k+1} alternate, so the
@@ -173,12 +173,16 @@ k_lanczos(LanczosArgs g) {
     r_i = r_i < 1 ? 1 : (r_i > g.r_max ? g.r_max : r_i);       // device data: clamp to capacity
     const double tol = 1e-12 * g.hnorm[atom];
     const int* off_g = g.loc_off + (int64_t)atom * (ncap + 1);
-    const uint16_t* ent = g.loc_ent + (int64_t)atom * g.emax;
+    const uint32_t* ent = g.loc_ent + (int64_t)atom * g.emax;
+    const int jmax = g.zmax + 1;
     for (int a = tid; a <= n; a += LZ_NT) s_off[a] = off_g[a];
     for (int a = tid; a < n; a += LZ_NT) { s_gid[a] = g.clu_j[(int64_t)atom * ncap + a]; s_js[a] = -1; }
     __syncthreads();
     const int nh = g.hop_n[s_gid[0]];
-    if (tid <= nh) { const int la = g.jloc[(int64_t)atom * JMAX + tid]; if (la >= 0) s_js[la] = (signed char)tid; }
+    for (int t = tid; t <= nh; t += LZ_NT) {
+      const int la = g.jloc[(int64_t)atom * jmax + t];
+      if (la >= 0) s_js[la] = (int16_t)t;
+    }
     // seed block V_0 = Phi (target orbitals = rows 0..3)
     for (int row = tid; row < R; row += LZ_NT) {
       double v[4];
@@ -191,10 +195,10 @@ k_lanczos(LanczosArgs g) {
     if (tid < 4) s_flag[tid] = 1;
     if (tid == 0) s_misc[208] = 0.0;             // running bound of ||T||
     __syncthreads();
-    VT* vjrow = (VT*)g.vj + (size_t)atom * (4 * JMAX) * (4 * g.r_max);
+    VT* vjrow = (VT*)g.vj + (size_t)atom * (4 * jmax) * (4 * g.r_max);
     const int vjld = 4 * g.r_max;
     // J rows of V_0
-    for (int row = tid; row < 4 * JMAX; row += LZ_NT) {
+    for (int row = tid; row < 4 * jmax; row += LZ_NT) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) vjrow[(size_t)row * vjld + c] = (VT)((row == c) ? 1.0 : 0.0);
     }
@@ -246,7 +250,7 @@ k_lanczos(LanczosArgs g) {
           for (int e = s_off[a] + c; e < e1; e += 4) {
             const unsigned int pe = ent[e];
             const int slot = pe >> LOCAL_BITS, b = pe & NCLUSTER_LIMIT;
-            const V4 hp4 = *(const V4*)(pairs + ((size_t)gid * ZMAX + slot) * 4);
+            const V4 hp4 = *(const V4*)(pairs + ((size_t)gid * g.zmax + slot) * 4);
             const VT hx = hp4.x, hy = hp4.y, hz = hp4.z, sv = hp4.w;
             const V4 vs4 = *(const V4*)(s_V + 16 * b), vx4 = *(const V4*)(s_V + 16 * b + 4),
                      vy4 = *(const V4*)(s_V + 16 * b + 8), vz4 = *(const V4*)(s_V + 16 * b + 12);
@@ -300,11 +304,11 @@ k_lanczos(LanczosArgs g) {
               const int slot = pe[u] >> LOCAL_BITS;
               if constexpr (BF) {
                 // four BF16 values (x, y, z, s) -> FP32, exactly
-                const uint2 raw = *(const uint2*)((const uint16_t*)g.pair + ((size_t)gid * ZMAX + slot) * 4);
+                const uint2 raw = *(const uint2*)((const uint16_t*)g.pair + ((size_t)gid * g.zmax + slot) * 4);
                 hp4[u].x = __uint_as_float(raw.x << 16); hp4[u].y = __uint_as_float(raw.x & 0xffff0000u);
                 hp4[u].z = __uint_as_float(raw.y << 16); hp4[u].w = __uint_as_float(raw.y & 0xffff0000u);
               } else {
-                hp4[u] = *(const V4*)(pairs + ((size_t)gid * ZMAX + slot) * 4);
+                hp4[u] = *(const V4*)(pairs + ((size_t)gid * g.zmax + slot) * 4);
               }
             }
 #pragma unroll
@@ -829,7 +833,7 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, 
   size_t b = 2 * Rcap * 4 * vt + 16;
   const int cslots = r_max > 2 * nw ? r_max : 2 * nw;
   b += (size_t)cslots * 16 * 8 + nw * 16 * 8 + 224 * 8;
-  b += (size_t)(nc_max + 1) * 4 + (size_t)nc_max * 4 + (size_t)nc_max + 16;
+  b += (size_t)(nc_max + 1) * 4 + (size_t)nc_max * 4 + (size_t)nc_max * 2 + 16;
   if (om_lds) b += (size_t)3 * r_max * 16 * 4;
   if (ab_lds) b += (size_t)r_max * 32 * 4;
   if (vprev_lds) b += Rcap * 4 * vt + 16;

@@ -98,11 +98,11 @@ __global__ void k_cell_fill(int n, const int* __restrict__ cell_of, int* __restr
 __global__ void __launch_bounds__(LIST_NT)
 k_lists(int n, const double* __restrict__ pos, Box box, CellGrid cg, const int* __restrict__ cell_of,
         const int* __restrict__ cell_start, const int* __restrict__ cell_atoms, double r_list,
-        double r_cluster, int nc_max, int* __restrict__ hop_n, int* __restrict__ hop_j,
+        double r_cluster, int nc_max, int zmax, int* __restrict__ hop_n, int* __restrict__ hop_j,
         double* __restrict__ hop_d, int* __restrict__ clu_n, int* __restrict__ clu_j, int64_t* stats) {
   extern __shared__ int s_cj[];
-  __shared__ int s_hj[ZMAX];
-  __shared__ double s_hd[ZMAX][4];
+  __shared__ int s_hj[ZMAX_CAP];
+  __shared__ double s_hd[ZMAX_CAP][4];
   __shared__ int s_nh, s_nc;
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
@@ -138,7 +138,7 @@ k_lists(int n, const double* __restrict__ pos, Box box, CellGrid cg, const int* 
           if (!isfinite(r2)) nonfinite = true;
           if (r2 < rl2) {
             const int slot = atomicAdd(&s_nh, 1);
-            if (slot < ZMAX) { s_hj[slot] = j; s_hd[slot][0] = dx; s_hd[slot][1] = dy; s_hd[slot][2] = dz; s_hd[slot][3] = sqrt(r2); }
+            if (slot < zmax) { s_hj[slot] = j; s_hd[slot][0] = dx; s_hd[slot][1] = dy; s_hd[slot][2] = dz; s_hd[slot][3] = sqrt(r2); }
           }
           if (r2 < rc2) {
             const int slot = atomicAdd(&s_nc, 1);
@@ -148,13 +148,13 @@ k_lists(int n, const double* __restrict__ pos, Box box, CellGrid cg, const int* 
       }
   __syncthreads();
   const int nh = s_nh, ncl = s_nc + 1;          // the sphere counts its target
-  const int mh = nh < ZMAX ? nh : ZMAX, mc = ncl - 1 < nc_max - 1 ? ncl - 1 : nc_max - 1;
+  const int mh = nh < zmax ? nh : zmax, mc = ncl - 1 < nc_max - 1 ? ncl - 1 : nc_max - 1;
   // index order by rank (the members are distinct)
   if (tid < mh) {
     const int j = s_hj[tid];
     int rank = 0;
     for (int e = 0; e < mh; ++e) rank += s_hj[e] < j;
-    const int64_t q = (int64_t)i * ZMAX + rank;
+    const int64_t q = (int64_t)i * zmax + rank;
     hop_j[q] = j;
     hop_d[4 * q] = s_hd[tid][0]; hop_d[4 * q + 1] = s_hd[tid][1];
     hop_d[4 * q + 2] = s_hd[tid][2]; hop_d[4 * q + 3] = s_hd[tid][3];
@@ -168,7 +168,7 @@ k_lists(int n, const double* __restrict__ pos, Box box, CellGrid cg, const int* 
   if (nonfinite) stat_flag(stats, FL_NONFINITE);
   if (tid == 0) {
     clu_j[(int64_t)i * nc_max] = i;
-    if (nh > ZMAX) stat_flag(stats, FL_HOP_OVERFLOW);
+    if (nh > zmax) stat_flag(stats, FL_HOP_OVERFLOW);
     if (ncl > nc_max) stat_flag(stats, FL_CLUSTER_OVERFLOW);
     hop_n[i] = mh;
     clu_n[i] = mc + 1;
@@ -269,13 +269,13 @@ k_union(int n, int m, const double* __restrict__ pos, Box box, double r_cluster,
   }
 }
 
-__global__ void k_pairs(int n, Model M, const int* __restrict__ hop_n, const int* __restrict__ hop_j,
+__global__ void k_pairs(int n, int zmax, Model M, const int* __restrict__ hop_n, const int* __restrict__ hop_j,
                         const double* __restrict__ hop_d, double* __restrict__ pair64,
                         float* __restrict__ pair32, uint16_t* __restrict__ pair16,
                         int* __restrict__ hop_rev) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (int64_t)n * ZMAX) return;
-  const int i = (int)(q / ZMAX), slot = (int)(q % ZMAX);
+  if (q >= (int64_t)n * zmax) return;
+  const int i = (int)(q / zmax), slot = (int)(q % zmax);
   double hx = 0, hy = 0, hz = 0, s = 0;
   int rev = -1;
   if (slot < hop_n[i]) {
@@ -286,7 +286,7 @@ __global__ void k_pairs(int n, Model M, const int* __restrict__ hop_n, const int
     const int j = hop_j[q];
     const int nj = hop_n[j];
     for (int t = 0; t < nj; ++t)
-      if (hop_j[(int64_t)j * ZMAX + t] == i) { rev = t; break; }
+      if (hop_j[(int64_t)j * zmax + t] == i) { rev = t; break; }
   }
   pair64[4 * q] = hx; pair64[4 * q + 1] = hy; pair64[4 * q + 2] = hz; pair64[4 * q + 3] = s;
   pair32[4 * q] = (float)hx; pair32[4 * q + 1] = (float)hy; pair32[4 * q + 2] = (float)hz;
@@ -311,10 +311,10 @@ __device__ __forceinline__ int find_local(const int* c, int n, int g) {
 }
 
 __global__ void __launch_bounds__(LIST_NT)
-k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_max, int64_t emax,
+k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_max, int zmax, int64_t emax,
         const int* __restrict__ hop_n, const int* __restrict__ hop_j, const double* __restrict__ hop_d,
         const double* __restrict__ pair64, const int* __restrict__ clu_n, const int* __restrict__ clu_j,
-        int* __restrict__ loc_off, uint16_t* __restrict__ loc_ent, double* __restrict__ hnorm,
+        int* __restrict__ loc_off, uint32_t* __restrict__ loc_ent, double* __restrict__ hnorm,
         int* __restrict__ jloc, int64_t* stats) {
   extern __shared__ unsigned char smem[];
   const int i = blockIdx.x, tid = threadIdx.x;
@@ -343,7 +343,7 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
     int cnt = 0;
     fro += M.eps_s * M.eps_s + 3 * M.eps_p * M.eps_p;
     for (int t = 0; t < nh; ++t) {
-      const int64_t q = (int64_t)g * ZMAX + t;
+      const int64_t q = (int64_t)g * zmax + t;
       if (hop_d[4 * q + 3] >= M.rm) continue;
       const int b = find_local(s_c, n, hop_j[q]);
       if (b < 0) continue;
@@ -376,28 +376,28 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
     const int nh = hop_n[g];
     int64_t e = s_cnt[a];
     for (int t = 0; t < nh; ++t) {
-      const int64_t q = (int64_t)g * ZMAX + t;
+      const int64_t q = (int64_t)g * zmax + t;
       if (hop_d[4 * q + 3] >= M.rm) continue;
       const int b = find_local(s_c, n, hop_j[q]);
       if (b < 0) continue;
       const double ex = s_x[3 * b] - s_x[3 * a], ey = s_x[3 * b + 1] - s_x[3 * a + 1],
                    ez = s_x[3 * b + 2] - s_x[3 * a + 2];
       if (ex * ex + ey * ey + ez * ez >= rm2) continue;
-      if (e < emax) loc_ent[(int64_t)i * emax + e] = (uint16_t)(b | (t << LOCAL_BITS));
+      if (e < emax) loc_ent[(int64_t)i * emax + e] = (uint32_t)b | ((uint32_t)t << LOCAL_BITS);
       ++e;
     }
   }
   // rho row atoms: J[0] = target (local 0), then hop(i) in list order
   if (tid == 0) {
-    int* jl = jloc + (int64_t)i * JMAX;
+    int* jl = jloc + (int64_t)i * (zmax + 1);
     jl[0] = 0;
     const int nh = hop_n[i];
-    for (int t = 0; t < nh; ++t) jl[1 + t] = find_local(s_c, n, hop_j[(int64_t)i * ZMAX + t]);
-    for (int t = nh + 1; t < JMAX; ++t) jl[t] = -1;
+    for (int t = 0; t < nh; ++t) jl[1 + t] = find_local(s_c, n, hop_j[(int64_t)i * zmax + t]);
+    for (int t = nh + 1; t < zmax + 1; ++t) jl[t] = -1;
   }
 }
 
-__global__ void k_rowptr(int n, const int* __restrict__ hop_n, const int* __restrict__ hop_j,
+__global__ void k_rowptr(int n, int zmax, const int* __restrict__ hop_n, const int* __restrict__ hop_j,
                          int64_t* __restrict__ row_ptr, int* __restrict__ col_j) {
   // single workgroup: sequential chunks with a workgroup scan
   __shared__ int64_t s_part[LIST_NT];
@@ -420,7 +420,7 @@ __global__ void k_rowptr(int n, const int* __restrict__ hop_n, const int* __rest
     if (i < n) {
       row_ptr[i + 1] = start + v;
       col_j[start] = i;
-      for (int t = 0; t < hop_n[i]; ++t) col_j[start + 1 + t] = hop_j[(int64_t)i * ZMAX + t];
+      for (int t = 0; t < hop_n[i]; ++t) col_j[start + 1 + t] = hop_j[(int64_t)i * zmax + t];
     }
     __syncthreads();
     if (tid == LIST_NT - 1) s_base += s_part[tid];
@@ -446,7 +446,7 @@ void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st) {
   hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(LIST_NT), 0, st, ncell, c->cell_cnt, c->cell_start);
   hipLaunchKernelGGL(k_cell_fill, dim3(nb), dim3(256), 0, st, n, c->cell_of, c->cell_cnt, c->cell_atoms);
   hipLaunchKernelGGL(k_lists, dim3(n), dim3(LIST_NT), (size_t)c->nc_max * sizeof(int), st, n, pos, c->box, cg,
-                     c->cell_of, c->cell_start, c->cell_atoms, r_list, c->r_cluster, c->nc_max, c->hop_n,
+                     c->cell_of, c->cell_start, c->cell_atoms, r_list, c->r_cluster, c->nc_max, c->zmax, c->hop_n,
                      c->hop_j, c->hop_d, c->clu_n, c->clu_j, c->stats);
   if (c->group_m > 1) {
     int pcap = 1;
@@ -454,14 +454,14 @@ void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st) {
     hipLaunchKernelGGL(k_union, dim3((n + c->group_m - 1) / c->group_m), dim3(LIST_NT), (size_t)pcap * sizeof(int),
                        st, n, c->group_m, pos, c->box, c->r_cluster, c->nc_max, c->clu_n, c->clu_j, c->stats);
   }
-  const int64_t np = (int64_t)n * ZMAX;
-  hipLaunchKernelGGL(k_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, n, c->model, c->hop_n,
+  const int64_t np = (int64_t)n * c->zmax;
+  hipLaunchKernelGGL(k_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, n, c->zmax, c->model, c->hop_n,
                      c->hop_j, c->hop_d, c->pair64, c->pair32, c->pair16, c->hop_rev);
   const size_t lds_local = (size_t)c->nc_max * (4 + 4 + 24) + 64;
   hipLaunchKernelGGL(k_local, dim3(n), dim3(LIST_NT), lds_local, st, n, c->model, pos, c->box, c->nc_max,
-                     c->emax, c->hop_n, c->hop_j, c->hop_d, c->pair64, c->clu_n, c->clu_j, c->loc_off,
+                     c->zmax, c->emax, c->hop_n, c->hop_j, c->hop_d, c->pair64, c->clu_n, c->clu_j, c->loc_off,
                      c->loc_ent, c->hnorm, c->jloc, c->stats);
-  hipLaunchKernelGGL(k_rowptr, dim3(1), dim3(LIST_NT), 0, st, n, c->hop_n, c->hop_j, c->row_ptr, c->col_j);
+  hipLaunchKernelGGL(k_rowptr, dim3(1), dim3(LIST_NT), 0, st, n, c->zmax, c->hop_n, c->hop_j, c->row_ptr, c->col_j);
 }
 
 }  // namespace tbk

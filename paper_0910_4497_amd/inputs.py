@@ -31,6 +31,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 PARAMS_XU = os.path.join(_HERE, "params", "xu1992.json")
+PARAMS_LONG = os.path.join(_HERE, "params", "xu_longrange.json")   # hopping to 7 A
 
 # Unit system: eV, Angstrom, fs, amu.
 K_B = 8.617333262e-5            # eV / K
@@ -135,6 +136,8 @@ class Workload:
     kT: float = 0.1                 # eV
     r_per_atom: np.ndarray | None = None
     extra: dict = field(default_factory=dict)
+    params: str = PARAMS_XU         # parameter file
+    hop_max: int = 24               # hop-list capacity the workload needs
 
     @property
     def n_atoms(self) -> int:
@@ -146,8 +149,9 @@ class Workload:
 
 
 def workload(name: str) -> Workload:
-    """The five C60 workloads (names 'c60_240' ... 'c60_15360') and the
-    4 x 4 x 4 cubic-diamond cell 'diamond_512'."""
+    """The five C60 workloads (names 'c60_240' ... 'c60_15360'), the
+    4 x 4 x 4 cubic-diamond cell 'diamond_512', and 'c60_1920_long' (the
+    1920-atom crystal with the long-range hopping of PARAMS_LONG)."""
     if name == "c60_240":           # one compressed conventional cell
         pos, L, _ = fcc_c60(1, 12.5, 0.02, 1001)
         return Workload(name, pos, L, r_cut=6.0, r=30)
@@ -168,10 +172,14 @@ def workload(name: str) -> Workload:
     if name == "diamond_512":       # 4x4x4 cubic-diamond cells (pressure / EOS)
         pos, L = cubic_diamond(4, 3.567, 0.02, 1006)
         return Workload(name, pos, L, r_cut=6.0, r=30)
+    if name == "c60_1920_long":     # the 1920-atom crystal with hopping to 7 A (dense local H)
+        pos, L, _ = fcc_c60(2, 12.0, 0.05, 1002)
+        return Workload(name, pos, L, r_cut=8.0, r=40, params=PARAMS_LONG, hop_max=256)
     raise KeyError(name)
 
 
-WORKLOADS = ("c60_240", "c60_1920", "c60_6480_strained", "c60_1920_hot", "c60_15360", "diamond_512")
+WORKLOADS = ("c60_240", "c60_1920", "c60_6480_strained", "c60_1920_hot", "c60_15360", "diamond_512",
+             "c60_1920_long")
 
 
 def maxwell_velocities(n: int, T: float, seed: int, mass: float = MASS_C) -> np.ndarray:

@@ -38,6 +38,7 @@ class TBSettings:
     r_per_atom: torch.Tensor | None = None
     seeds: str = "block"                  # or "orbital": one scalar chain per orbital
     groups: int = 1                       # grouped form: atoms per union sphere (index blocks)
+    hop_max: int = 24                     # hop-list capacity (neighbours within max(rm, dm))
 
 
 class TBForceField:
@@ -46,7 +47,7 @@ class TBForceField:
     def __init__(self, n_atoms: int, n_cluster_max: int, settings: TBSettings, device: int = 0):
         self.s = settings
         r_max = settings.r if settings.r_per_atom is None else max(settings.r, int(settings.r_per_atom.max()))
-        self.ctx = TBContext(n_atoms, n_cluster_max, r_max, device=device)
+        self.ctx = TBContext(n_atoms, n_cluster_max, r_max, device=device, hop_max=settings.hop_max)
         self.ctx.set_seeds(settings.seeds)
         self.ctx.set_groups(settings.groups)
         self.mu = None
@@ -64,7 +65,7 @@ class TBForceField:
         """Sizes the sphere capacity from the geometry itself (plus a margin for motion)."""
         s = settings
         cap = PROBE_CLUSTER_CAP
-        probe = TBContext(pos.shape[0], cap, 1, device=pos.device.index or 0)
+        probe = TBContext(pos.shape[0], cap, 1, device=pos.device.index or 0, hop_max=s.hop_max)
         probe.set_groups(s.groups)
         sizes = probe.build_local_H(pos, s.cell, s.periodic, s.params, s.r_cluster, want_sizes=True)
         n_max = int(sizes.max().item())

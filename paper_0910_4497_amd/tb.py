@@ -22,11 +22,11 @@ ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4:
           -5: "TB_EUNSUPPORTED", -6: "TB_EHIP", -7: "TB_ESTATE", -8: "TB_EDEVICE"}
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
               "max_cluster_pos", "memory_bytes", "reorth_second_pass", "reorth_steps", "basis_bytes")
-EXPORTS = ("tb_create", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
+EXPORTS = ("tb_create", "tb_create_ex", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
            "tb_energy_forces", "tb_get_stats", "tb_virial", "tb_set_seeds", "tb_set_groups", "tb_set_launch", "tb_autotune", "tb_profile_enable", "tb_profile_read",
            "tb_last_error")
 PHASES = ("lists_local", "lanczos", "eig", "mu", "rho", "forces")
-RHO_ROWS_MAX = 25          # rho row atoms per target: itself + at most 24 neighbours
+HOP_MAX_DEFAULT = 24       # hop-list capacity of tb_create (rho row atoms per target: itself + hop list)
 
 
 class TBError(RuntimeError):
@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib = ctypes.CDLL(path)
     P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.tb_create.argtypes = [ctypes.POINTER(P), I, P, I64, I, I]
+    lib.tb_create_ex.argtypes = [ctypes.POINTER(P), I, P, I64, I, I, I]
     lib.tb_destroy.argtypes = [P]
     lib.tb_build_local_H.argtypes = [P, I64, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I),
                                      ctypes.POINTER(TBParams), ctypes.c_double, P]
@@ -107,14 +108,15 @@ class TBContext:
     """Owns one library context on one device and stream."""
 
     def __init__(self, n_atoms_max: int, n_cluster_max: int, r_max: int, device: int = 0,
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, hop_max: int = HOP_MAX_DEFAULT):
         self.lib = load_library()
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        _check(self.lib.tb_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream),
-                                  n_atoms_max, n_cluster_max, r_max))
+        _check(self.lib.tb_create_ex(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream),
+                                     n_atoms_max, n_cluster_max, r_max, hop_max))
         self.h = h
+        self.hop_max = hop_max
         self.n_atoms = 0
         self.nnz = None
         self.rho = None
@@ -163,10 +165,10 @@ class TBContext:
     def krylov_rho(self, r: int, kT: float, mu: float | None = None, n_electrons: float | None = None,
                    precision: str = "fp64", r_per_atom: torch.Tensor | None = None,
                    rho_out: torch.Tensor | None = None):
-        """rho_out defaults to a buffer of capacity n_atoms * RHO_ROWS_MAX blocks, so no
-        host synchronisation is needed; rho_layout() gives the used prefix."""
+        """rho_out defaults to a buffer of capacity n_atoms * (hop_max + 1) blocks, so
+        no host synchronisation is needed; rho_layout() gives the used prefix."""
         if rho_out is None:
-            cap = self.n_atoms * RHO_ROWS_MAX
+            cap = self.n_atoms * (self.hop_max + 1)
             if self.rho is None or self.rho.shape[0] < cap:
                 self.rho = torch.empty((cap, 4, 4), dtype=torch.float64, device=self.device)
             rho_out = self.rho
