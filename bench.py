@@ -267,9 +267,10 @@ def main():
     traffic = None
     shape = shapes.get(head_prec)
     if shape:
-        lz_kernel = "k_lanczos<{}, {}, {}, {}>".format("double" if head_prec == "fp64" else "float",
-                                                      shape["lanczos_threads"], shape["lanczos_waves_per_simd"],
-                                                      "true" if head_prec == "bf16" else "false")
+        lz_kernel = "k_lanczos<{}, {}, {}, {}, {}>".format("double" if head_prec == "fp64" else "float",
+                                                          shape["lanczos_threads"], shape["lanczos_waves_per_simd"],
+                                                          "true" if head_prec == "bf16" else "false",
+                                                          "true" if shape.get("lanczos_wide") else "false")
         n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
         traffic = measured_traffic(args.workload, head_prec, lz_kernel, min(n_cu * shape["lanczos_wg_per_cu"], N))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -235,14 +235,30 @@ int tb_set_launch(tb_ctx *ctx, int atoms_per_launch);
  * change launch geometry, registers and LDS residency, and with the thread
  * count the order of the workgroup reductions: later results agree with
  * those of the default shape to rounding (FP64: ~1e-15 relative). r, r_per_atom: as for
- * tb_krylov_rho. shape_out (host, nullable) [5]: Krylov threads per
+ * tb_krylov_rho. shape_out (host, nullable) [6]: Krylov threads per
  * workgroup, Krylov workgroups per compute unit, eigensolver workgroups per
  * compute unit, candidates timed, Krylov waves per SIMD of the register
- * budget (4: 128 VGPRs, 2: 256). Synchronises the stream (not for graph
+ * budget (4: 128 VGPRs, 2: 256), and for TB_FP32 the layout of the H.V
+ * work items (0: one column per lane; 1: four columns per lane over every
+ * fourth coupling, which loads each coupling once; both are timed).
+ * Synchronises the stream (not for graph
  * capture); tb_krylov_rho must run again before tb_energy_forces, and the
  * counters of tb_get_stats are those of before the call.
  * Errors: TB_EINVAL, TB_ESTATE, TB_ECAPACITY (r > r_max), TB_EHIP. */
 int tb_autotune(tb_ctx *ctx, int r, const int *r_per_atom, int precision, int *shape_out);
+
+/* Fixes the Krylov launch shape of later tb_krylov_rho calls at `precision`
+ * without timing (the shapes tb_autotune chooses among): threads per
+ * workgroup (256 or 512), waves per SIMD of the register budget (4: 128
+ * VGPRs, 2: 256), persistent workgroups per compute unit (they must stay
+ * co-resident: wg_per_cu * threads / 64 <= 4 * waves_per_simd, and the
+ * sphere capacity must fit their LDS) and, for TB_FP32, the H.V item layout
+ * (wide = 1: four columns per lane over every fourth coupling). Results of
+ * different shapes agree to rounding; one shape gives the same bits on every
+ * run. Host-side setting, no device work.
+ * Errors: TB_EINVAL (a value outside those sets), TB_ECAPACITY (the LDS
+ * of the workgroups does not fit a compute unit). */
+int tb_set_shape(tb_ctx *ctx, int precision, int threads, int waves_per_simd, int wg_per_cu, int wide);
 
 /* Diagnostics (host): counters since the last tb_build_local_H. stats_host
  * receives up to n_stats values: [0] device error flags, [1] max cluster

@@ -146,7 +146,7 @@ extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int6
   // (at most 2), for both precisions; tb_autotune may change it
   int per_cu = (int)(LDS_CU / (lds + LDS_RESERVE));
   per_cu = per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu);
-  for (int q = 0; q < 3; ++q) { c->lz_nt[q] = 512; c->lz_minw[q] = 4; c->lz_per_cu[q] = per_cu; }
+  for (int q = 0; q < 3; ++q) { c->lz_nt[q] = 512; c->lz_minw[q] = 4; c->lz_per_cu[q] = per_cu; c->lz_wide[q] = 0; }
   // workspace for the largest shape the tuner may pick: the smallest (FP32,
   // 256-thread) footprint, at most LZ_PER_CU_MAX per compute unit
   const size_t lds_min = lanczos_lds_bytes(n_cluster_max, r_max, true, 256, false, false, false);
@@ -394,7 +394,8 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
     const int a1 = n - a0 > chunk ? a0 + chunk : n;
     if (a0 > 0) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 1);
     la.atom0 = a0; la.n_atoms = a1;
-    launch_lanczos(la, precision, plan.nt, plan.minw, plan.n_wg < a1 - a0 ? plan.n_wg : a1 - a0, plan.lds, st);
+    launch_lanczos(la, precision, plan.nt, plan.minw, c->lz_wide[precision],
+                   plan.n_wg < a1 - a0 ? plan.n_wg : a1 - a0, plan.lds, st);
   }
   prof_end(c, pk);
   // K5: projected eigensolve
@@ -472,10 +473,13 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
   };
   LanczosArgs la = lanczos_args(c, n, r, r_per_atom, precision);
   int best_nt = c->lz_nt[precision], best_mw = c->lz_minw[precision], best_pc = c->lz_per_cu[precision];
+  int best_wide = c->lz_wide[precision];
   int tried = 0;
   float best = 3.0e38f;
   hipError_t err = hipSuccess;
   const int nts[2] = {256, 512}, mws[2] = {4, 2};
+  const int n_wide = precision == TB_FP32 ? 2 : 1;      // FP32: both H.V item layouts
+  for (int wd = 0; wd < n_wide && err == hipSuccess; ++wd)
   for (int m = 0; m < 2 && err == hipSuccess; ++m) {
     for (int q = 0; q < 2 && err == hipSuccess; ++q) {
       for (int pc = 1; pc <= c->lz_per_cu_max && err == hipSuccess; ++pc) {
@@ -487,10 +491,10 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
         float t = 3.0e38f;
         err = timed([&] {
           hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, c->work_counter, 16);
-          launch_lanczos(la, precision, p.nt, p.minw, p.n_wg < n ? p.n_wg : n, p.lds, st);
+          launch_lanczos(la, precision, p.nt, p.minw, wd, p.n_wg < n ? p.n_wg : n, p.lds, st);
         }, t);
         ++tried;
-        if (t < best) { best = t; best_nt = p.nt; best_mw = p.minw; best_pc = pc; }
+        if (t < best) { best = t; best_nt = p.nt; best_mw = p.minw; best_pc = pc; best_wide = wd; }
       }
     }
   }
@@ -499,6 +503,7 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
     c->lz_nt[precision] = best_nt;
     c->lz_minw[precision] = best_mw;
     c->lz_per_cu[precision] = best_pc;
+    c->lz_wide[precision] = best_wide;
     // k_eig consumes the recursion of the last Krylov run (identical for every shape)
     EigArgs ea = eig_args(c, n);
     const int cand[5] = {2, 3, 4, 6, 8};
@@ -529,6 +534,7 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
     shape_out[2] = c->eig_per_cu;
     shape_out[3] = tried;
     shape_out[4] = c->lz_minw[precision];
+    shape_out[5] = c->lz_wide[precision];
   }
   return TB_OK;
 }
@@ -610,6 +616,28 @@ extern "C" int tb_set_groups(tb_ctx* c, int m) {
     return fail(TB_ECAPACITY, "group size %d x sphere capacity %d exceeds %d", m, c->nc_max, UNION_LDS_MAX);
   c->group_m = m;
   c->stage = 0;                               // the spheres must be rebuilt
+  return TB_OK;
+}
+
+extern "C" int tb_set_shape(tb_ctx* c, int precision, int threads, int waves_per_simd, int wg_per_cu, int wide) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (precision != TB_FP64 && precision != TB_FP32 && precision != TB_BF16)
+    return fail(TB_EINVAL, "unknown precision %d", precision);
+  if (threads != 256 && threads != 512) return fail(TB_EINVAL, "threads=%d is not 256 or 512", threads);
+  if (waves_per_simd != 2 && waves_per_simd != 4)
+    return fail(TB_EINVAL, "waves_per_simd=%d is not 2 or 4", waves_per_simd);
+  if (wg_per_cu < 1 || wg_per_cu > c->lz_per_cu_max)
+    return fail(TB_EINVAL, "wg_per_cu=%d outside [1, %d]", wg_per_cu, c->lz_per_cu_max);
+  if (wide && precision != TB_FP32) return fail(TB_EINVAL, "the wide H.V layout is for TB_FP32 only");
+  if (wg_per_cu * threads / 64 > 4 * waves_per_simd)
+    return fail(TB_EINVAL, "%d workgroups of %d threads exceed %d waves per SIMD", wg_per_cu, threads,
+                waves_per_simd);
+  if (!lanczos_plan(c, precision != TB_FP64, threads, waves_per_simd, wg_per_cu).lds)
+    return fail(TB_ECAPACITY, "the sphere capacity does not fit %d workgroups per compute unit", wg_per_cu);
+  c->lz_nt[precision] = threads;
+  c->lz_minw[precision] = waves_per_simd;
+  c->lz_per_cu[precision] = wg_per_cu;
+  c->lz_wide[precision] = wide ? 1 : 0;
   return TB_OK;
 }
 

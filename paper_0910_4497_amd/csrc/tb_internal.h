@@ -194,7 +194,9 @@ struct LanczosArgs {
 size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, bool ab_lds, bool vprev_lds);
 // precision: TB_FP64 / TB_FP32 / TB_BF16; nt: 256 or 512 threads; minw: 2 or
 // 4 waves per SIMD (register budget)
-void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int n_wg, size_t lds, hipStream_t st);
+// wide: FP32 only, the four-columns-per-lane H.V items (see k_lanczos)
+void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int wide, int n_wg, size_t lds,
+                    hipStream_t st);
 hipError_t lanczos_set_lds(size_t lds);
 
 struct EigArgs {
@@ -274,7 +276,7 @@ struct tb_ctx {
   // launch shape of the Krylov kernel per precision ([0] FP64, [1] FP32, [2] BF16):
   // threads per workgroup, register budget (waves per SIMD) and persistent
   // workgroups per compute unit
-  int lz_nt[3], lz_minw[3], lz_per_cu[3];
+  int lz_nt[3], lz_minw[3], lz_per_cu[3], lz_wide[3];
   int lz_per_cu_max;     // workspace is sized for this many per compute unit
   int eig_per_cu, eig_per_cu_max;   // persistent k_eig workgroups per compute unit
   int atoms_per_launch;  // 0: one launch per phase; k: per-atom phases in launches of k atoms

@@ -123,11 +123,16 @@ __device__ __forceinline__ void inv_upper4r(const double (&U)[16], const bool (&
 // must allow (4: 128 VGPRs, some spilled; 2: 256 VGPRs, none spilled). BF
 // (with VT = float): the operands of H.V -- the coupling data, the on-site and
 // bond parameters, and V_k -- are rounded to BF16 and the products
-// accumulated in FP32; everything else is the FP32 recursion.
-template <typename VT, int LZ_NT, int MINW, bool BF = false>
+// accumulated in FP32; everything else is the FP32 recursion. WIDE (FP32,
+// not BF): the H.V items of the FP64 kernel (each lane all four columns of
+// every fourth coupling, then a reduce-scatter over the four lanes), which
+// loads each coupling's entry, pair data and V_k rows once instead of once
+// per column: the better choice when spheres have many couplings per atom.
+template <typename VT, int LZ_NT, int MINW, bool BF = false, bool WIDE = false>
 __global__ void __launch_bounds__(LZ_NT, MINW)
 k_lanczos(LanczosArgs g) {
   static_assert(!BF || sizeof(VT) == 4, "BF16 operands with the FP32 recursion only");
+  static_assert(!(BF && WIDE), "the wide H.V items take unrounded operands");
   constexpr int LZ_NW = LZ_NT / 64;
   extern __shared__ unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -229,7 +234,7 @@ k_lanczos(LanczosArgs g) {
         for (int item = tid; item < 4 * n; item += LZ_NT) {
           VT w0, w1, w2, w3;
           const int a = item >> 2, c = cq;
-          if constexpr (sizeof(VT) == 8) {
+          if constexpr (sizeof(VT) == 8 || WIDE) {
 
           VT w[16];                                   // [orbital][column]
           if (c == 0) {
@@ -840,31 +845,35 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, 
   return b + 64;
 }
 
-template <typename VT, bool BF = false>
+template <typename VT, bool BF = false, bool WIDE = false>
 static void launch_lz(const LanczosArgs& a, int nt, int minw, int n_wg, size_t lds, hipStream_t st) {
   if (minw == 2) {
-    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2, BF>), dim3(n_wg), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_lanczos<VT, 512, 2, BF>), dim3(n_wg), dim3(512), lds, st, a);
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2, BF, WIDE>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 2, BF, WIDE>), dim3(n_wg), dim3(512), lds, st, a);
   } else {
-    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4, BF>), dim3(n_wg), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_lanczos<VT, 512, 4, BF>), dim3(n_wg), dim3(512), lds, st, a);
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4, BF, WIDE>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 4, BF, WIDE>), dim3(n_wg), dim3(512), lds, st, a);
   }
 }
 
-void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int n_wg, size_t lds, hipStream_t st) {
+void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int wide, int n_wg, size_t lds,
+                    hipStream_t st) {
   if (precision == TB_BF16) launch_lz<float, true>(a, nt, minw, n_wg, lds, st);
+  else if (precision == TB_FP32 && wide) launch_lz<float, false, true>(a, nt, minw, n_wg, lds, st);
   else if (precision == TB_FP32) launch_lz<float>(a, nt, minw, n_wg, lds, st);
   else launch_lz<double>(a, nt, minw, n_wg, lds, st);
 }
 
 hipError_t lanczos_set_lds(size_t lds) {
-  const void* fn[12] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
+  const void* fn[16] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
                         (const void*)k_lanczos<float, 256, 4>, (const void*)k_lanczos<float, 512, 4>,
                         (const void*)k_lanczos<double, 256, 2>, (const void*)k_lanczos<double, 512, 2>,
                         (const void*)k_lanczos<float, 256, 2>, (const void*)k_lanczos<float, 512, 2>,
                         (const void*)k_lanczos<float, 256, 4, true>, (const void*)k_lanczos<float, 512, 4, true>,
-                        (const void*)k_lanczos<float, 256, 2, true>, (const void*)k_lanczos<float, 512, 2, true>};
-  for (int q = 0; q < 12; ++q) {
+                        (const void*)k_lanczos<float, 256, 2, true>, (const void*)k_lanczos<float, 512, 2, true>,
+                        (const void*)k_lanczos<float, 256, 4, false, true>, (const void*)k_lanczos<float, 512, 4, false, true>,
+                        (const void*)k_lanczos<float, 256, 2, false, true>, (const void*)k_lanczos<float, 512, 2, false, true>};
+  for (int q = 0; q < 16; ++q) {
     hipError_t e = hipFuncSetAttribute(fn[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }

@@ -23,7 +23,7 @@ ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4:
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
               "max_cluster_pos", "memory_bytes", "reorth_second_pass", "reorth_steps", "basis_bytes")
 EXPORTS = ("tb_create", "tb_create_ex", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
-           "tb_energy_forces", "tb_get_stats", "tb_virial", "tb_set_seeds", "tb_set_groups", "tb_set_launch", "tb_autotune", "tb_profile_enable", "tb_profile_read",
+           "tb_energy_forces", "tb_get_stats", "tb_virial", "tb_set_seeds", "tb_set_groups", "tb_set_launch", "tb_set_shape", "tb_autotune", "tb_profile_enable", "tb_profile_read",
            "tb_last_error")
 PHASES = ("lists_local", "lanczos", "eig", "mu", "rho", "forces")
 HOP_MAX_DEFAULT = 24       # hop-list capacity of tb_create (rho row atoms per target: itself + hop list)
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tb_set_seeds.argtypes = [P, I]
     lib.tb_set_groups.argtypes = [P, I]
     lib.tb_set_launch.argtypes = [P, I]
+    lib.tb_set_shape.argtypes = [P, I, I, I, I, I]
     lib.tb_autotune.argtypes = [P, I, P, I, ctypes.POINTER(I)]
     lib.tb_profile_enable.argtypes = [P, I]
     lib.tb_profile_read.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I]
@@ -201,10 +202,10 @@ class TBContext:
         """Times the launch shapes of the Krylov kernel and the eigensolver on
         the current spheres and keeps the fastest for this precision (later
         results agree with the default shape's to rounding)."""
-        out = (ctypes.c_int * 5)()
+        out = (ctypes.c_int * 6)()
         _check(self.lib.tb_autotune(self.h, int(r), _ptr(r_per_atom), PRECISIONS[precision], out))
         return {"lanczos_threads": out[0], "lanczos_wg_per_cu": out[1], "lanczos_waves_per_simd": out[4],
-                "eig_wg_per_cu": out[2], "candidates": out[3]}
+                "lanczos_wide": out[5], "eig_wg_per_cu": out[2], "candidates": out[3]}
 
     def set_seeds(self, seeds: str):
         """'block' (four-orbital seed block) or 'orbital' (one scalar chain per orbital)."""
@@ -215,6 +216,11 @@ class TBContext:
         (1: each atom's own sphere). The spheres are rebuilt by the next
         build_local_H."""
         _check(self.lib.tb_set_groups(self.h, int(m)))
+
+    def set_shape(self, precision: str, threads: int, waves_per_simd: int, wg_per_cu: int, wide: bool = False):
+        """Fixes the Krylov launch shape at this precision (see tb_set_shape)."""
+        _check(self.lib.tb_set_shape(self.h, PRECISIONS[precision], int(threads), int(waves_per_simd),
+                                     int(wg_per_cu), int(bool(wide))))
 
     def set_launch(self, atoms_per_launch: int):
         """0: one launch per per-atom phase; k: launches over groups of k atoms."""

@@ -55,3 +55,4 @@ def test_last_error_callable_without_device():
     assert lib.tb_virial(None, None) == -1
     assert lib.tb_set_seeds(None, 1) == -1
     assert lib.tb_set_groups(None, 4) == -1
+    assert lib.tb_set_shape(None, 1, 256, 4, 1, 1) == -1

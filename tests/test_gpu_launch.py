@@ -108,3 +108,30 @@ def test_destroy_returns_every_buffer(torch_cuda):
     torch_cuda.cuda.empty_cache()
     free1, _ = torch_cuda.cuda.mem_get_info()
     assert free0 - free1 < 4 << 20, (free0, free1)
+
+
+def test_fp32_hv_layouts_agree(torch_cuda):
+    """The two FP32 H.V item layouts (one column per lane; four columns per
+    lane over every fourth coupling), fixed with tb_set_shape at the same
+    launch shape, agree to FP32 rounding; invalid shapes are refused."""
+    from paper_0910_4497_amd.tb import TBContext, TBError
+    w = inputs.workload("c60_240")
+    ctx = TBContext(w.n_atoms, 130, 30)
+    runs = {}
+    for wide in (False, True):
+        ctx.set_shape("fp32", 256, 4, 2, wide=wide)
+        runs[wide] = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                             precision="fp32")
+    for bad in (dict(precision="fp64", threads=256, waves_per_simd=4, wg_per_cu=1, wide=True),
+                dict(precision="fp32", threads=128, waves_per_simd=4, wg_per_cu=1),
+                dict(precision="fp32", threads=512, waves_per_simd=2, wg_per_cu=3)):
+        with pytest.raises(TBError) as e:
+            ctx.set_shape(**bad)
+        assert e.value.name == "TB_EINVAL", bad
+    ctx.close()
+    a, b = runs[False], runs[True]
+    assert np.array_equal(a["row_ptr"], b["row_ptr"])
+    df = float(np.abs(a["forces"] - b["forces"]).max())
+    dr = float(np.abs(a["rho"] - b["rho"]).max())
+    print(f"  wide vs narrow FP32 H.V: force {df:.2e} eV/A, rho {dr:.2e}, mu {abs(a['mu'] - b['mu']):.2e}")
+    assert df <= 1e-4 and dr <= 1e-5 and abs(a["mu"] - b["mu"]) <= 1e-6
