@@ -56,3 +56,7 @@ def test_last_error_callable_without_device():
     assert lib.tb_set_seeds(None, 1) == -1
     assert lib.tb_set_groups(None, 4) == -1
     assert lib.tb_set_shape(None, 1, 256, 4, 1, 1) == -1
+    h = ctypes.c_void_p()
+    for bad_hop in (0, 257):     # checked before any device call
+        assert lib.tb_create_ex(ctypes.byref(h), 0, None, 10, 10, 10, bad_hop) == -1
+        assert b"hop_max" in lib.tb_last_error()
