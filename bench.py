@@ -172,7 +172,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-atom solves "
-              "shard by target atom, but this build measures a single GPU's share.", file=sys.stderr)
+              "shard by target atom, but this benchmark measures a single GPU's share.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
