@@ -733,6 +733,8 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
 }
 
 // One wave per atom.
+// VJ: element type of the rho row vectors V_J (float after the FP32 recursion).
+template <typename VJ>
 __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   extern __shared__ double rsm[];
   const int lane = threadIdx.x;
@@ -853,8 +855,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
       const double x0 = x[XS * m], x1 = x[XS * m + 1], x2 = x[XS * m + 2], x3 = x[XS * m + 3];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double vv = g.vj_fp32 ? (double)((const float*)g.vj)[(row0 + r) * vld + m]
-                                    : ((const double*)g.vj)[(row0 + r) * vld + m];
+        const double vv = (double)((const VJ*)g.vj)[(row0 + r) * vld + m];
         acc[r * 4] += vv * x0; acc[r * 4 + 1] += vv * x1; acc[r * 4 + 2] += vv * x2; acc[r * 4 + 3] += vv * x3;
       }
     }
@@ -893,7 +894,10 @@ hipError_t eig_set_lds(int r_max) {
   e = hipFuncSetAttribute((const void*)k_band, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)band_lds_bytes(r_max));
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_rho, hipFuncAttributeMaxDynamicSharedMemorySize,
+  e = hipFuncSetAttribute((const void*)k_rho<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)rho_lds_bytes(r_max));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_rho<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)rho_lds_bytes(r_max));
 }
 
@@ -906,7 +910,8 @@ void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
   hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
 }
 void launch_rho(const RhoArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_rho, dim3(a.n_atoms - a.atom0), dim3(RHO_NT), rho_lds_bytes(a.r_max), st, a);
+  if (a.vj_fp32) hipLaunchKernelGGL(k_rho<float>, dim3(a.n_atoms - a.atom0), dim3(RHO_NT), rho_lds_bytes(a.r_max), st, a);
+  else hipLaunchKernelGGL(k_rho<double>, dim3(a.n_atoms - a.atom0), dim3(RHO_NT), rho_lds_bytes(a.r_max), st, a);
 }
 
 }  // namespace tbk

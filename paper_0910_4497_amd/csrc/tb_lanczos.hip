@@ -299,11 +299,15 @@ k_lanczos(LanczosArgs g) {
           const int gid = s_gid[a];
           int e1 = s_off[a + 1];
           if (e1 > g.emax) e1 = (int)g.emax;
-          for (int e0 = s_off[a]; e0 < e1; e0 += 4) {
-            unsigned int pe[4];
-            V4 hp4[4];
+          // the entries of the next group of four couplings are loaded with
+          // the pair data of the current one (one dependent round trip per
+          // group instead of two)
+          unsigned int pe[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) pe[u] = (e0 + u < e1) ? ent[e0 + u] : 0u;
+          for (int u = 0; u < 4; ++u) pe[u] = (s_off[a] + u < e1) ? ent[s_off[a] + u] : 0u;
+          for (int e0 = s_off[a]; e0 < e1; e0 += 4) {
+            V4 hp4[4];
+            unsigned int pn[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const int slot = pe[u] >> LOCAL_BITS;
@@ -316,6 +320,8 @@ k_lanczos(LanczosArgs g) {
                 hp4[u] = *(const V4*)(pairs + ((size_t)gid * g.zmax + slot) * 4);
               }
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pn[u] = (e0 + 4 + u < e1) ? ent[e0 + 4 + u] : 0u;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               if (e0 + u >= e1) break;
@@ -331,6 +337,8 @@ k_lanczos(LanczosArgs g) {
               w2 += t * hy + sp * vy;
               w3 += t * hz + sp * vz;
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pe[u] = pn[u];
           }
           }
           VT* wa = s_W + 16 * a + c;
