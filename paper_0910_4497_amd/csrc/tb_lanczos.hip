@@ -251,11 +251,14 @@ k_lanczos(LanczosArgs g) {
           const int gid = s_gid[a];
           int e1 = s_off[a + 1];
           if (e1 > g.emax) e1 = (int)g.emax;
+          // this lane's next coupling entry loads with the current pair data
+          unsigned int pcur = (s_off[a] + c < e1) ? ent[s_off[a] + c] : 0u;
 #pragma unroll 2
           for (int e = s_off[a] + c; e < e1; e += 4) {
-            const unsigned int pe = ent[e];
+            const unsigned int pe = pcur;
             const int slot = pe >> LOCAL_BITS, b = pe & NCLUSTER_LIMIT;
             const V4 hp4 = *(const V4*)(pairs + ((size_t)gid * g.zmax + slot) * 4);
+            pcur = (e + 4 < e1) ? ent[e + 4] : 0u;
             const VT hx = hp4.x, hy = hp4.y, hz = hp4.z, sv = hp4.w;
             const V4 vs4 = *(const V4*)(s_V + 16 * b), vx4 = *(const V4*)(s_V + 16 * b + 4),
                      vy4 = *(const V4*)(s_V + 16 * b + 8), vz4 = *(const V4*)(s_V + 16 * b + 12);
