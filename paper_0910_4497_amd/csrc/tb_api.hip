@@ -76,7 +76,7 @@ extern "C" int tb_destroy(tb_ctx* c) {
                   c->loc_off, c->loc_ent, c->hnorm, c->jloc, c->row_ptr, c->col_j, c->vbuf, c->tab,
                   c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->rot_cs, c->rot_p,
                   c->rot_n, c->seg, c->seg_n, c->evec, c->tri, c->eig_scratch, c->omega, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats,
-                  c->pair16, c->cell_of, c->cell_atoms, c->cell_cnt, c->cell_start, c->wpart, c->virial};
+                  c->pair16, c->cell_of, c->cell_atoms, c->cell_cnt, c->cell_start, c->wpart, c->virial, c->vsc};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (c->ev_pool) {
@@ -199,6 +199,7 @@ extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int6
   ALLOC(seg, N * c->seg_max);
   ALLOC(seg_n, 2 * N);
   ALLOC(evec, N * dmax * dmax);
+  ALLOC(vsc, N * dmax);
   ALLOC(tri, N * 2 * dmax);
   ALLOC(eig_scratch, n_wg_eig_max * dmax * 4 * eig_threads(r_max));
   ALLOC(mu_state, 16);
@@ -349,7 +350,7 @@ static EigArgs eig_args(const tb_ctx* c, int n) {
   ea.lam = c->lam; ea.wgt = c->wgt; ea.y1 = c->y1;
   ea.rot_cs = c->rot_cs; ea.rot_p = c->rot_p; ea.rot_n = c->rot_n; ea.rot_max = c->rot_max;
   ea.seg = c->seg; ea.seg_n = c->seg_n; ea.seg_max = c->seg_max;
-  ea.counter = c->work_counter + 1; ea.scratch = c->eig_scratch; ea.evec = c->evec; ea.tri = c->tri;
+  ea.counter = c->work_counter + 1; ea.scratch = c->eig_scratch; ea.evec = c->evec; ea.vsc = c->vsc; ea.tri = c->tri;
   ea.stats = c->stats;
   ea.scalar = c->seeds == TB_SEEDS_ORBITAL ? 1 : 0;
   return ea;
@@ -423,7 +424,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   ra.n_atoms = n; ra.r_max = c->r_max; ra.kused = c->kused; ra.hop_n = c->hop_n; ra.clu_j = c->clu_j;
   ra.nc_max = c->nc_max; ra.zmax = c->zmax; ra.lam = c->lam; ra.y1 = c->y1; ra.rot_cs = c->rot_cs; ra.rot_p = c->rot_p;
   ra.rot_n = c->rot_n; ra.rot_max = c->rot_max;
-  ra.seg = c->seg; ra.seg_n = c->seg_n; ra.seg_max = c->seg_max; ra.evec = c->evec; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
+  ra.seg = c->seg; ra.seg_n = c->seg_n; ra.seg_max = c->seg_max; ra.evec = c->evec; ra.vsc = c->vsc; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
   ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out; ra.stats = c->stats;
   pk = prof_begin(c, 4);
   for (int a0 = 0; a0 < n; a0 += chunk) {

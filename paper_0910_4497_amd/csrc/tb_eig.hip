@@ -20,7 +20,8 @@
 //      with partial pivoting, deterministic pseudo-random start), then
 //      Gram-Schmidt against the earlier members, one more step and
 //      Gram-Schmidt again (Peters & Wilkinson; LAPACK's stein does the same).
-//      The eigenvector matrix U of S goes to HBM;
+//      The eigenvector matrix U of S goes to HBM, the columns of the twisted
+//      factorisations unnormalised, with their normalising factors apart;
 //   4. Y[0:4, :] = Z[0:4, :] U, weights w_m = ||Y[0:4, m]||^2, Ritz values.
 //
 // k_rho (after the chemical potential is known): x = U (f(Lambda) Y[0:4,:]^T),
@@ -173,8 +174,10 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
 // z_k = -E_k z_{k+1} / d+_k (k < r), z_k = -E_{k-1} z_{k-1} / d-_k (k > r).
 // Pivots of magnitude below `small` are replaced by +-small. Scratch: d+ at
 // scr[k * ns], d- at scr[(d + k) * ns], read back in chunks so that the loads
-// do not wait one by one. The normalised vector goes to xcol (stride ld).
-__device__ void twisted_vec(const double* D, const double* E, const double* E2, int d, double lam, double small,
+// do not wait one by one. The vector goes to xcol (stride ld) unnormalised;
+// the return value is the factor that normalises it (applied by the readers,
+// which saves a pass over the column).
+__device__ double twisted_vec(const double* D, const double* E, const double* E2, int d, double lam, double small,
                             double* xcol, size_t ld, double* scr, int ns) {
   constexpr int CH = 8;                        // scratch values prefetched per chunk
   double* sp = scr;                            // d+_k at sp[k * ns]
@@ -237,9 +240,7 @@ __device__ void twisted_vec(const double* D, const double* E, const double* E2, 
       nrm += z * z;
     }
   }
-  const double sc = 1.0 / sqrt(nrm);
-#pragma unroll 8
-  for (int k = 0; k < d; ++k) xcol[(size_t)k * ld] *= sc;
+  return 1.0 / sqrt(nrm);
 }
 
 // One time step of the chases that reduce the half-bandwidth from BC to BC-1,
@@ -503,15 +504,17 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     __syncthreads();
     const int maxpos = s_maxpos;
     double* Ua = g.evec + (size_t)atom * dmax * dmax;       // U[k][t], row stride dmax
+    double* vsc = g.vsc + (size_t)atom * dmax;              // normalising factor of column t
     for (int round = 0; round <= maxpos; ++round) {
       for (int t = tid; t < d; t += nt) {
         if (pos_s[t] != round) continue;
         double* xc = Ua + t;
         if (round == 0 && (t + 1 >= d || pos_s[t + 1] == 0)) {
-          // not in a cluster: twisted factorisation
-          twisted_vec(Dg, Eg, E2, d, lam_s[t], small, xc, dmax, scr, nt);
+          // not in a cluster: twisted factorisation (column scale kept apart)
+          vsc[t] = twisted_vec(Dg, Eg, E2, d, lam_s[t], small, xc, dmax, scr, nt);
           continue;
         }
+        vsc[t] = 1.0;                                // normalised below
         // cluster members: two steps of inverse iteration (the second one
         // squares the contamination left by a start vector with a small
         // target component), then Gram-Schmidt against the earlier members
@@ -556,6 +559,8 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
           const double x = xc[(size_t)k * dmax];
           a0 += R1[k] * x; a1 += R1[(size_t)d + k] * x; a2 += R1[(size_t)2 * d + k] * x; a3 += R1[(size_t)3 * d + k] * x;
         }
+        const double sc = vsc[t];
+        a0 *= sc; a1 *= sc; a2 *= sc; a3 *= sc;
         lam[t] = lam_s[t];
         wgt[t] = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
         y1[t] = a0; y1[dmax + t] = a1; y1[2 * dmax + t] = a2; y1[3 * dmax + t] = a3;
@@ -667,6 +672,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
     __syncthreads();
     const int maxpos = s_maxpos;
     double* Ua = g.evec + (size_t)atom * dmax * dmax;       // U[k][t], row stride dmax
+    double* vsc = g.vsc + (size_t)atom * dmax;              // normalising factor of column t
     for (int q = tid; q < d * d; q += nt) {                  // rows of the other chains
       const int row = q / d, t = q - row * d;
       if ((row & 3) != t / K) Ua[(size_t)row * dmax + t] = 0.0;
@@ -680,9 +686,10 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
         const double* E2c = E2 + c * Kp;
         double* xc = Ua + (size_t)c * dmax + t;
         if (round == 0 && (t + 1 >= cend || pos_s[t + 1] == 0)) {
-          twisted_vec(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
+          vsc[t] = twisted_vec(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
           continue;
         }
+        vsc[t] = 1.0;                                // normalised below
         double nrm = inv_solve(Dc, Ec, K, lam_s[t], small, t, nullptr, xc, ld, scr, nt);
         double sc = 1.0 / sqrt(nrm);
         for (int k = 0; k < K; ++k) xc[(size_t)k * ld] *= sc;
@@ -716,7 +723,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
     double* y1 = g.y1 + (size_t)atom * 4 * dmax;
     for (int t = tid; t < dmax; t += nt) {
       const int c = t < d ? t / K : -1;
-      const double a = t < d ? Ua[(size_t)c * dmax + t] : 0.0;    // chain row 0 = block row c
+      const double a = t < d ? Ua[(size_t)c * dmax + t] * vsc[t] : 0.0;   // chain row 0 = block row c
       lam[t] = t < d ? lam_s[t] : 0.0;
       wgt[t] = a * a;
 #pragma unroll
@@ -747,12 +754,13 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   {
     const double* lam = g.lam + (size_t)atom * dmax;
     const double* y1 = g.y1 + (size_t)atom * 4 * dmax;
+    const double* vsc = g.vsc + (size_t)atom * dmax;     // U is stored with unnormalised columns
     for (int q = lane; q < 4 * d; q += RHO_NT) {
       const int m = q >> 2, col = q & 3;
       const double z = (lam[m] - mu) / g.kT;
       const double e = exp(-fabs(z));
       const double f = (z > 0.0) ? 2.0 * e / (1.0 + e) : 2.0 / (1.0 + e);
-      v[q] = f * y1[(size_t)col * dmax + m];
+      v[q] = f * y1[(size_t)col * dmax + m] * vsc[m];
     }
   }
   __syncthreads();

@@ -208,6 +208,7 @@ struct EigArgs {
   int* counter;                        // persistent-kernel atom queue (zeroed before launch)
   double* scratch;                     // [WG][4 r_max][4][threads]: LU factors of inverse iteration
   double* evec;                        // [N][4 r_max][4 r_max]: eigenvectors of the tridiagonal, [k][t]
+  double* vsc;                         // [N][4 r_max]: factor that normalises column t of evec
   double* tri;                         // [N][2][4 r_max]: diagonal and off-diagonal of the tridiagonal
   int64_t* stats;
   int scalar;                          // orbital seeds: T is four independent chains (k_eig_chains)
@@ -219,7 +220,7 @@ struct RhoArgs {
   const double* lam; const double* y1;
   const double* rot_cs; const uint16_t* rot_p; const int* rot_n; int64_t rot_max;
   const int* seg; const int* seg_n; int seg_max;
-  const double* evec;
+  const double* evec; const double* vsc;
   const void* vj; int vj_fp32;
   const int64_t* row_ptr;
   const double* mu_state; double kT;
@@ -320,6 +321,7 @@ struct tb_ctx {
   double* rot_cs; uint16_t* rot_p; int* rot_n;             // [N][ROT][2], [N][ROT], [N]
   int* seg; int* seg_n; int seg_max;                       // [N][SEG], [N][2]
   double* evec;                                            // [N][D][D]
+  double* vsc;                                             // [N][D] normalising factors of the evec columns
   double* tri;                                             // [N][2][D]
   double* eig_scratch;                                     // [WG_EIG][D][4][EIG_NT]
   // mu / energies (K6/K8)
