@@ -3,26 +3,33 @@
 //
 // One persistent workgroup solves one sphere at a time and takes the next
 // atom from a queue. Per block step k (V_k: 4n x 4, n = sphere size):
-//   1. W = H V_k                block-sparse, SK blocks rebuilt from the pair
-//                               data (h, s), V_k and W in LDS
-//   2. A_k = V_k^T W            workgroup reduction (FP64)
-//   3. W -= V_k A_k + V_{k-1} B_{k-1}^T          (three-term recursion)
-//   4. C = V_{0..k}^T W         one sweep over the stored basis (HBM)
-//   5. W -= V_{0..k} C          second sweep, also Gram W^T W and the
-//                               column norms before/after (FP64 reductions);
-//                               steps 4-5 repeat once if a norm fell by more
-//                               than a factor sqrt(2) (twice-is-enough rule)
-//   6. W = V_{k+1} B_k          Cholesky QR twice, B_k upper triangular with
-//                               positive diagonal; columns whose residual norm
-//                               is below tol = 1e-12 ||H^(i)||_F are dropped
-//                               (deflation: zero columns, zero rows of B_k)
-//                               through a modified Gram-Schmidt fallback.
-// The basis V_0..V_k lives in a per-workgroup HBM buffer (the full
-// re-orthogonalisation reads it twice per step: the kernel's HBM roofline);
-// A_k, B_k go to the projected-matrix buffer, and the rows of V on the rho
-// row atoms J = {i} + hop(i) are kept for the density-matrix assembly.
+//   1. W = H V_k and A_k = V_k^T W: block-sparse H.V with the SK blocks
+//      rebuilt from the pair data (h, s), V_k and W in LDS; A_k by a
+//      workgroup reduction (FP64).
+//   2. W -= V_k A_k + V_{k-1} B_{k-1}^T (three-term recursion), with the Gram
+//      matrix W^T W.
+//   3. A running estimate of |V_j^T V_{k+1}| for every j <= k (block form of
+//      Simon's recurrence, kept in FP32). When it exceeds eta (1e-12 FP64,
+//      1e-4 FP32), C = V_{0..k}^T W and W -= V_{0..k} C: two sweeps over the
+//      stored basis (HBM), for this block and the next, repeated once if a
+//      column norm fell by more than a factor sqrt(2).
+//   4. W = V_{k+1} B_k by Cholesky QR (twice when the pivots are poorly
+//      separated), B_k upper triangular with positive diagonal; a modified
+//      Gram-Schmidt fallback drops columns whose residual norm is below
+//      tol = 1e-12 ||H^(i)||_F (deflation: zero columns, zero rows of B_k).
+//   5. V_{k+1} to LDS (the next step's V_k), to the basis buffer and to the
+//      rows on the rho row atoms J = {i} + hop(i).
+// With orbital seeds (LanczosArgs::scalar) the four columns are four scalar
+// chains: A_k and B_k diagonal, each chain re-orthogonalised against its
+// own vectors, and only a chain's own entries enter the estimate.
+// H.V work items: one column of one atom per lane (FP32), or all four
+// columns of every fourth coupling per lane with a reduce-scatter over the
+// four lanes (FP64, and the WIDE FP32 variant).
 // VT = double (FP64 mode) or float (FP32 mode: basis, W and H.V in FP32 with
-// FP32 accumulation; A_k, Gram, norms, Cholesky and B_k stay FP64).
+// FP32 accumulation; A_k, Gram, norms, Cholesky and B_k stay FP64). The
+// estimates, FP32 copies of A_j, B_j and a second LDS buffer for V_{k-1} stay
+// in LDS when the launch shape leaves room (LanczosArgs::om_lds, ab_lds,
+// vprev_lds), else in global memory.
 #include "tb_internal.h"
 
 namespace tbk {
