@@ -19,7 +19,8 @@
 //                the cluster-frame rule |x_b - x_a| < rm, x = position
 //                relative to the target; Frobenius norm of the local H; the
 //                local indices of the rho row atoms J = {i} + hop(i).
-//   k_rowptr     prefix sum of 1 + |hop(i)| (rho pair layout).
+//   k_rowptr     prefix sum of 1 + |hop(i)| (rho pair layout); k_colj fills
+//                the pair columns, one thread per entry.
 #include "tb_internal.h"
 
 namespace tbk {
@@ -336,25 +337,54 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
   const double rm2 = M.rm * M.rm;
   const double kfro = M.v_sss * M.v_sss + 2 * M.v_sps * M.v_sps + M.v_pps * M.v_pps + 2 * M.v_ppp * M.v_ppp;
   double fro = 0.0;
+  // the coupling rule: hop pair (g -> hop slot t) of local atom a couples a
+  // to local atom b when both lie in the sphere and |x_b - x_a| < rm
+  auto coupling = [&](int a, int g, int t, int& b) -> bool {
+    const int64_t q = (int64_t)g * zmax + t;
+    if (hop_d[4 * q + 3] >= M.rm) return false;
+    b = find_local(s_c, n, hop_j[q]);
+    if (b < 0) return false;
+    const double ex = s_x[3 * b] - s_x[3 * a], ey = s_x[3 * b + 1] - s_x[3 * a + 1],
+                 ez = s_x[3 * b + 2] - s_x[3 * a + 2];
+    return ex * ex + ey * ey + ez * ez < rm2;             // else it wraps behind the target
+  };
+  // long hop lists (zmax > 32): a wave per local atom, lanes over its hop
+  // slots; short ones: a thread per local atom
+  const bool by_wave = zmax > 32;
+  const int lane = tid & 63, wave = tid >> 6;
   // pass 1: count couplings per local atom
-  for (int a = tid; a < n; a += LIST_NT) {
-    const int g = s_c[a];
-    const int nh = hop_n[g];
-    int cnt = 0;
-    fro += M.eps_s * M.eps_s + 3 * M.eps_p * M.eps_p;
-    for (int t = 0; t < nh; ++t) {
-      const int64_t q = (int64_t)g * zmax + t;
-      if (hop_d[4 * q + 3] >= M.rm) continue;
-      const int b = find_local(s_c, n, hop_j[q]);
-      if (b < 0) continue;
-      const double ex = s_x[3 * b] - s_x[3 * a], ey = s_x[3 * b + 1] - s_x[3 * a + 1],
-                   ez = s_x[3 * b + 2] - s_x[3 * a + 2];
-      if (ex * ex + ey * ey + ez * ez >= rm2) continue;   // wraps behind the target
-      ++cnt;
-      const double s = pair64[4 * q + 3];
-      fro += kfro * s * s;
+  if (by_wave) {
+    for (int a = wave; a < n; a += LIST_NT / 64) {
+      const int g = s_c[a];
+      const int nh = hop_n[g];
+      int cnt = 0;
+      if (lane == 0) fro += M.eps_s * M.eps_s + 3 * M.eps_p * M.eps_p;
+      for (int t = lane; t < nh; t += 64) {
+        int b;
+        if (!coupling(a, g, t, b)) continue;
+        ++cnt;
+        const double sv = pair64[4 * ((int64_t)g * zmax + t) + 3];
+        fro += kfro * sv * sv;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+      if (lane == 0) s_cnt[a + 1] = cnt;
     }
-    s_cnt[a + 1] = cnt;
+  } else {
+    for (int a = tid; a < n; a += LIST_NT) {
+      const int g = s_c[a];
+      const int nh = hop_n[g];
+      int cnt = 0;
+      fro += M.eps_s * M.eps_s + 3 * M.eps_p * M.eps_p;
+      for (int t = 0; t < nh; ++t) {
+        int b;
+        if (!coupling(a, g, t, b)) continue;
+        ++cnt;
+        const double sv = pair64[4 * ((int64_t)g * zmax + t) + 3];
+        fro += kfro * sv * sv;
+      }
+      s_cnt[a + 1] = cnt;
+    }
   }
   if (tid == 0) s_cnt[0] = 0;
   fro = wave_sum(fro);
@@ -371,34 +401,44 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
   __syncthreads();
   for (int a = tid; a <= n; a += LIST_NT) loc_off[(int64_t)i * (nc_max + 1) + a] = s_cnt[a];
   // pass 2: write couplings (b | slot << LOCAL_BITS) in hop-list order
-  for (int a = tid; a < n; a += LIST_NT) {
-    const int g = s_c[a];
-    const int nh = hop_n[g];
-    int64_t e = s_cnt[a];
-    for (int t = 0; t < nh; ++t) {
-      const int64_t q = (int64_t)g * zmax + t;
-      if (hop_d[4 * q + 3] >= M.rm) continue;
-      const int b = find_local(s_c, n, hop_j[q]);
-      if (b < 0) continue;
-      const double ex = s_x[3 * b] - s_x[3 * a], ey = s_x[3 * b + 1] - s_x[3 * a + 1],
-                   ez = s_x[3 * b + 2] - s_x[3 * a + 2];
-      if (ex * ex + ey * ey + ez * ez >= rm2) continue;
-      if (e < emax) loc_ent[(int64_t)i * emax + e] = (uint32_t)b | ((uint32_t)t << LOCAL_BITS);
-      ++e;
+  if (by_wave) {
+    for (int a = wave; a < n; a += LIST_NT / 64) {
+      const int g = s_c[a];
+      const int nh = hop_n[g];
+      int64_t base = s_cnt[a];
+      for (int t0 = 0; t0 < nh; t0 += 64) {
+        const int t = t0 + lane;
+        int b = 0;
+        const bool ok = t < nh && coupling(a, g, t, b);
+        const uint64_t m = __ballot(ok);
+        const int64_t e = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (ok && e < emax) loc_ent[(int64_t)i * emax + e] = (uint32_t)b | ((uint32_t)t << LOCAL_BITS);
+        base += __popcll(m);
+      }
+    }
+  } else {
+    for (int a = tid; a < n; a += LIST_NT) {
+      const int g = s_c[a];
+      const int nh = hop_n[g];
+      int64_t e = s_cnt[a];
+      for (int t = 0; t < nh; ++t) {
+        int b;
+        if (!coupling(a, g, t, b)) continue;
+        if (e < emax) loc_ent[(int64_t)i * emax + e] = (uint32_t)b | ((uint32_t)t << LOCAL_BITS);
+        ++e;
+      }
     }
   }
   // rho row atoms: J[0] = target (local 0), then hop(i) in list order
-  if (tid == 0) {
+  {
     int* jl = jloc + (int64_t)i * (zmax + 1);
-    jl[0] = 0;
     const int nh = hop_n[i];
-    for (int t = 0; t < nh; ++t) jl[1 + t] = find_local(s_c, n, hop_j[(int64_t)i * zmax + t]);
-    for (int t = nh + 1; t < zmax + 1; ++t) jl[t] = -1;
+    for (int t = tid; t < zmax + 1; t += LIST_NT)
+      jl[t] = t == 0 ? 0 : (t <= nh ? find_local(s_c, n, hop_j[(int64_t)i * zmax + t - 1]) : -1);
   }
 }
 
-__global__ void k_rowptr(int n, int zmax, const int* __restrict__ hop_n, const int* __restrict__ hop_j,
-                         int64_t* __restrict__ row_ptr, int* __restrict__ col_j) {
+__global__ void k_rowptr(int n, const int* __restrict__ hop_n, int64_t* __restrict__ row_ptr) {
   // single workgroup: sequential chunks with a workgroup scan
   __shared__ int64_t s_part[LIST_NT];
   __shared__ int64_t s_base;
@@ -417,15 +457,22 @@ __global__ void k_rowptr(int n, int zmax, const int* __restrict__ hop_n, const i
       __syncthreads();
     }
     const int64_t start = s_base + s_part[tid] - v;
-    if (i < n) {
-      row_ptr[i + 1] = start + v;
-      col_j[start] = i;
-      for (int t = 0; t < hop_n[i]; ++t) col_j[start + 1 + t] = hop_j[(int64_t)i * zmax + t];
-    }
+    if (i < n) row_ptr[i + 1] = start + v;
     __syncthreads();
     if (tid == LIST_NT - 1) s_base += s_part[tid];
     __syncthreads();
   }
+}
+
+// rho pair layout: row i lists the target i, then its hop list (one thread
+// per entry, after the scan of k_rowptr)
+__global__ void k_colj(int n, int zmax, const int* __restrict__ hop_n, const int* __restrict__ hop_j,
+                       const int64_t* __restrict__ row_ptr, int* __restrict__ col_j) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)n * (zmax + 1)) return;
+  const int i = (int)(q / (zmax + 1)), t = (int)(q % (zmax + 1));
+  if (t > hop_n[i]) return;
+  col_j[row_ptr[i] + t] = t == 0 ? i : hop_j[(int64_t)i * zmax + t - 1];
 }
 
 void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st) {
@@ -461,7 +508,10 @@ void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st) {
   hipLaunchKernelGGL(k_local, dim3(n), dim3(LIST_NT), lds_local, st, n, c->model, pos, c->box, c->nc_max,
                      c->zmax, c->emax, c->hop_n, c->hop_j, c->hop_d, c->pair64, c->clu_n, c->clu_j, c->loc_off,
                      c->loc_ent, c->hnorm, c->jloc, c->stats);
-  hipLaunchKernelGGL(k_rowptr, dim3(1), dim3(LIST_NT), 0, st, n, c->zmax, c->hop_n, c->hop_j, c->row_ptr, c->col_j);
+  hipLaunchKernelGGL(k_rowptr, dim3(1), dim3(LIST_NT), 0, st, n, c->hop_n, c->row_ptr);
+  const int64_t nq = (int64_t)n * (c->zmax + 1);
+  hipLaunchKernelGGL(k_colj, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, n, c->zmax, c->hop_n, c->hop_j,
+                     c->row_ptr, c->col_j);
 }
 
 }  // namespace tbk
