@@ -17,7 +17,7 @@
 namespace tbk {
 
 constexpr int MU_NT = 256;
-constexpr int MU_NB = 512;         // blocks of the reduction kernels
+constexpr int MU_NB = 256;         // blocks of the reduction kernels (timed: 128, 256, 512)
 constexpr int MU_P = 31;           // points per multisection step
 
 enum { MS_LO = 0, MS_HI = 1, MS_MU = 2, MS_DONE = 3, MS_N = 4, MS_STEP = 5, MS_IT = 6 };
