@@ -41,7 +41,7 @@ namespace tbk {
 
 constexpr int EIG_NT = 256;
 constexpr int BAND_NT = 64;
-constexpr int RHO_NT = 64;
+constexpr int RHO_NT = 256;     // k_rho: four waves per atom
 constexpr int RHO_SEGW = 256;      // segment-table window of k_rho
 constexpr int RHO_ROTW = 512;      // rotation-log window of k_rho (>= rotations of any one segment)
 constexpr int XS = 5;              // row stride (doubles) of the 4-column vectors in k_rho's LDS
@@ -739,12 +739,13 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
   }
 }
 
-// One wave per atom.
+// Four waves per atom (the replay of the band rotations on one of them).
 // VJ: element type of the rho row vectors V_J (float after the FP32 recursion).
 template <typename VJ>
 __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   extern __shared__ double rsm[];
-  const int lane = threadIdx.x;
+  constexpr int NW = RHO_NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int atom = g.atom0 + blockIdx.x;
   const int dmax = 4 * g.r_max;
   double* v = rsm;                       // [dmax][4]: f(Lambda) Y[0:4,:]^T
@@ -755,7 +756,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     const double* lam = g.lam + (size_t)atom * dmax;
     const double* y1 = g.y1 + (size_t)atom * 4 * dmax;
     const double* vsc = g.vsc + (size_t)atom * dmax;     // U is stored with unnormalised columns
-    for (int q = lane; q < 4 * d; q += RHO_NT) {
+    for (int q = tid; q < 4 * d; q += RHO_NT) {
       const int m = q >> 2, col = q & 3;
       const double z = (lam[m] - mu) / g.kT;
       const double e = exp(-fabs(z));
@@ -764,14 +765,15 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     }
   }
   __syncthreads();
-  // x = U v (eigenvectors of the tridiagonal): four rows of U at a time,
-  // read along the row by the lanes (coalesced), 16 sums reduced over the wave
+  // x = U v (eigenvectors of the tridiagonal): four rows of U at a time per
+  // wave, read along the row by the lanes (coalesced), 16 sums reduced over
+  // the wave
   const double* Ua = g.evec + (size_t)atom * dmax * dmax;
-  for (int k0 = 0; k0 < d; k0 += 4) {
+  for (int k0 = 4 * wave; k0 < d; k0 += 4 * NW) {
     double acc[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    for (int m = lane; m < d; m += RHO_NT) {
+    for (int m = lane; m < d; m += 64) {
       const double v0 = v[4 * m], v1 = v[4 * m + 1], v2 = v[4 * m + 2], v3 = v[4 * m + 3];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -784,9 +786,11 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     if ((lane & 3) == 0) x[XS * (k0 + (which >> 2)) + (which & 3)] = sum;
   }
   __syncthreads();
-  // c = Z x: band steps in reverse; the rotations of one step commute. The
-  // segment table and the rotation log are staged through LDS in windows
-  // (coalesced loads), and the steps are ordered by wave-scope fences.
+  // c = Z x: band steps in reverse; the rotations of one step commute. One
+  // wave replays them: the segment table and the rotation log are staged
+  // through LDS in windows (coalesced loads), and the steps are ordered by
+  // wave-scope fences.
+  if (wave == 0) {
   const double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
   const uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
   const int* seg = g.seg + (size_t)atom * g.seg_max;
@@ -799,21 +803,21 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   while (k >= 0) {
     // segment starts seg[k0 .. k]
     const int k0 = k - RHO_SEGW + 1 > 0 ? k - RHO_SEGW + 1 : 0;
-    for (int q = k0 + lane; q <= k; q += RHO_NT) s_seg[q - k0] = seg[q];
+    for (int q = k0 + lane; q <= k; q += 64) s_seg[q - k0] = seg[q];
     const int en = (k + 1 < nb) ? seg[k + 1] : nrot;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // the window: segments kw .. k whose rotations fit in RHO_ROTW (at least one)
     int kw = k;
-    for (int base = k; base >= k0; base -= RHO_NT) {
+    for (int base = k; base >= k0; base -= 64) {
       const int q = base - lane;
       const bool fits = q >= k0 && en - s_seg[q - k0] <= RHO_ROTW;
       const uint64_t m = __ballot(fits);
       // lanes are ordered by decreasing q; the fitting ones form a prefix
       const int nfit = __popcll(m);
       if (nfit > 0) kw = base - nfit + 1;
-      if (nfit < RHO_NT) break;
+      if (nfit < 64) break;
     }
     const int w0 = s_seg[kw - k0];
     if (en - w0 > RHO_ROTW) {         // one segment with more rotations than the window: not
@@ -821,7 +825,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
         atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
       break;
     }
-    for (int e = w0 + lane; e < en; e += RHO_NT) {
+    for (int e = w0 + lane; e < en; e += 64) {
       const double2 cs = *(const double2*)(lcs + 2 * (size_t)e);
       s_cs[2 * (e - w0)] = cs.x;
       s_cs[2 * (e - w0) + 1] = cs.y;
@@ -833,7 +837,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     for (int kk = k; kk >= kw; --kk) {
       const int st = s_seg[kk - k0] - w0;
       const int se = (kk == k ? en : s_seg[kk + 1 - k0]) - w0;
-      for (int e = st + lane; e < se; e += RHO_NT) {
+      for (int e = st + lane; e < se; e += 64) {
         const double c = s_cs[2 * e], s = s_cs[2 * e + 1];
         const int p = s_p[e];
         double* xp = x + XS * p;
@@ -849,17 +853,20 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     }
     k = kw - 1;
   }
+  }
+  __syncthreads();
   // rho_{J,i}[4 js + a][col] = sum_m V_J[4 js + a][m] x[m][col]: four rows of
-  // V_J at a time, read along the row by the lanes, reduced over the wave
+  // V_J at a time per wave, read along the row by the lanes, reduced over the
+  // wave
   const int nJ = 1 + g.hop_n[atom];
   const int64_t p0 = g.row_ptr[atom];
   const int vld = 4 * g.r_max;
-  for (int q0 = 0; q0 < 4 * nJ; q0 += 4) {
+  for (int q0 = 4 * wave; q0 < 4 * nJ; q0 += 4 * NW) {
     double acc[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
     const size_t row0 = (size_t)atom * (4 * (g.zmax + 1)) + q0;
-    for (int m = lane; m < d; m += RHO_NT) {
+    for (int m = lane; m < d; m += 64) {
       const double x0 = x[XS * m], x1 = x[XS * m + 1], x2 = x[XS * m + 2], x3 = x[XS * m + 3];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
