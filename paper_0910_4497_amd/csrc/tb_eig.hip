@@ -44,14 +44,30 @@ constexpr int BAND_NT = 64;
 constexpr int RHO_NT = 256;     // k_rho: four waves per atom
 constexpr int RHO_SEGW = 256;      // segment-table window of k_rho
 constexpr int RHO_ROTW = 512;      // rotation-log window of k_rho (>= rotations of any one segment)
-constexpr int XS = 5;              // row stride (doubles) of the 4-column vectors in k_rho's LDS
 constexpr int BW = 4;              // half-bandwidth of T
 constexpr int LB = BW + 2;         // stored lower diagonals incl. the bulge
 
+// LDS layout of one atom in k_band. The lanes of a chase step work on planes
+// 7, 8 or 5 rows apart (stages bc = 4, 3, 2); a plain row stride of LB = 6
+// doubles put the 8-row spacing on a quarter of the LDS banks. Skewed row and
+// column offsets give every lane of a 16- or 32-lane group its own bank pair
+// at all three spacings.
+__host__ __device__ inline int lb_row(int j) {           // band row j = -1 .. d-1
+  const int r = j + 1;
+  return r * LB + ((3 * r) >> 2);
+}
+__host__ __device__ inline int r1_col(int m) { return m + ((3 * m) >> 4); }
+__host__ __device__ inline int r1_stride(int d) { return r1_col(d - 1) + 1; }
+
+// Row m of the 4-column vectors in k_rho's LDS: the replay's lanes touch rows
+// 7, 8 or 5 apart and the final product consecutive rows; this skew gives
+// each lane of a 16- or 32-lane group its own bank pair in all four cases.
+__host__ __device__ inline int xrow(int m) { return 4 * m + ((3 * m) >> 3); }
+
 // LDS doubles of one atom in k_band: band rows -1 .. dmax-1 and Z[0:4, :].
 __host__ __device__ inline size_t band_atom_doubles(int r_max) {
-  const size_t dmax = 4 * (size_t)r_max;
-  return (dmax + 1) * LB + 4 * dmax;
+  const int dmax = 4 * r_max;
+  return (size_t)(lb_row(dmax - 1) + LB) + 4 * (size_t)r1_stride(dmax);
 }
 
 __device__ __forceinline__ double t_entry(const double* tab, int row, int col) {
@@ -251,7 +267,7 @@ __device__ double twisted_vec(const double* D, const double* E, const double* E2
 // takes chase jtop - hl, then jtop - 32 - hl, ... until a batch has no active
 // chase.
 template <int BC>
-__device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau, int hl, uint64_t hm,
+__device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int rs, int tau, int hl, uint64_t hm,
                                           uint64_t below, double* lcs, uint16_t* lp, int64_t rot_max,
                                           int64_t& nrot) {
   constexpr int I = (2 * BC + 3) / BC;       // ceil((BC + 4) / BC): 2, 3, 3
@@ -272,17 +288,19 @@ __device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau
     double c = 1.0, s = 0.0;
     if (act) {
       const int q = p + 1, ml = p - BC;
+      const int op = lb_row(p), oq = lb_row(q), cp = r1_col(p), cq = r1_col(q);
       double lu[BC], lv[BC], ru[BC], rv[BC], r1u[4], r1v[4];
 #pragma unroll
       for (int u = 0; u < BC; ++u) {
-        lu[u] = Lb[(ml + u) * LB + (BC - u)];         // T[p][m], m = ml + u
-        lv[u] = Lb[(ml + u) * LB + (BC + 1 - u)];     // T[q][m]
-        ru[u] = Lb[p * LB + 2 + u];                   // T[p + 2 + u][p]
-        rv[u] = Lb[q * LB + 1 + u];                   // T[p + 2 + u][q]
+        const int om = lb_row(ml + u);
+        lu[u] = Lb[om + (BC - u)];                    // T[p][m], m = ml + u
+        lv[u] = Lb[om + (BC + 1 - u)];                // T[q][m]
+        ru[u] = Lb[op + 2 + u];                       // T[p + 2 + u][p]
+        rv[u] = Lb[oq + 1 + u];                       // T[p + 2 + u][q]
       }
-      const double da = Lb[p * LB], db = Lb[p * LB + 1], de = Lb[q * LB];
+      const double da = Lb[op], db = Lb[op + 1], de = Lb[oq];
 #pragma unroll
-      for (int row = 0; row < 4; ++row) { r1u[row] = R1[row * d + p]; r1v[row] = R1[row * d + q]; }
+      for (int row = 0; row < 4; ++row) { r1u[row] = R1[row * rs + cp]; r1v[row] = R1[row * rs + cq]; }
       const double x = u0 ? lu[1] : lu[0], y = u0 ? lv[1] : lv[0];
       act = (y != 0.0);
       if (act) {
@@ -290,20 +308,20 @@ __device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau
         givens(x, y, c, s, r);
 #pragma unroll
         for (int u = 0; u < BC; ++u) {
-          const int m = ml + u;
-          Lb[m * LB + (BC - u)] = (u == u0) ? r : c * lu[u] + s * lv[u];
-          Lb[m * LB + (BC + 1 - u)] = (u == u0) ? 0.0 : -s * lu[u] + c * lv[u];
-          Lb[p * LB + 2 + u] = c * ru[u] + s * rv[u];
-          Lb[q * LB + 1 + u] = -s * ru[u] + c * rv[u];
+          const int om = lb_row(ml + u);
+          Lb[om + (BC - u)] = (u == u0) ? r : c * lu[u] + s * lv[u];
+          Lb[om + (BC + 1 - u)] = (u == u0) ? 0.0 : -s * lu[u] + c * lv[u];
+          Lb[op + 2 + u] = c * ru[u] + s * rv[u];
+          Lb[oq + 1 + u] = -s * ru[u] + c * rv[u];
         }
         const double cc = c * c, ss = s * s, cs = c * s;
-        Lb[p * LB] = cc * da + 2.0 * cs * db + ss * de;
-        Lb[q * LB] = ss * da - 2.0 * cs * db + cc * de;
-        Lb[p * LB + 1] = cs * (de - da) + (cc - ss) * db;
+        Lb[op] = cc * da + 2.0 * cs * db + ss * de;
+        Lb[oq] = ss * da - 2.0 * cs * db + cc * de;
+        Lb[op + 1] = cs * (de - da) + (cc - ss) * db;
 #pragma unroll
         for (int row = 0; row < 4; ++row) {
-          R1[row * d + p] = c * r1u[row] + s * r1v[row];
-          R1[row * d + q] = -s * r1u[row] + c * r1v[row];
+          R1[row * rs + cp] = c * r1u[row] + s * r1v[row];
+          R1[row * rs + cq] = -s * r1u[row] + c * r1v[row];
         }
       }
     }
@@ -322,7 +340,7 @@ __device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int tau
 // steps no two planes are closer than 2), so they commute and the reverse
 // replay takes them as one segment.
 template <int BC>
-__device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int hl, uint64_t hm, uint64_t below,
+__device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int rs, int hl, uint64_t hm, uint64_t below,
                                            double* lcs, uint16_t* lp, int64_t rot_max, int64_t& nrot, int* seg,
                                            int seg_max, int& nseg) {
   constexpr int I = (2 * BC + 3) / BC;
@@ -334,7 +352,7 @@ __device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int hl
   int64_t group_start = nrot;
   for (int tau = 0; tau < t_end; ++tau) {
     if (tau % MS == 0) group_start = nrot;
-    band_step<BC>(Lb, R1, d, tau, hl, hm, below, lcs, lp, rot_max, nrot);
+    band_step<BC>(Lb, R1, d, rs, tau, hl, hm, below, lcs, lp, rot_max, nrot);
     if ((tau % MS == MS - 1 || tau == t_end - 1) && nrot > group_start) {   // one segment per group
       if (hl == 0 && nseg < seg_max) seg[nseg] = (int)group_start;
       ++nseg;
@@ -348,29 +366,30 @@ __device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int hl
 }
 
 // Band -> tridiagonal reduction: one half-wave (32 lanes) per atom, one lane
-// per chase; two atoms per wave share the instruction stream.
-__global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
+// per chase; pw = 2 atoms per wave share the instruction stream (pw = 1 when
+// two atoms' band storage does not fit in LDS: the upper half-wave idles).
+__global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g, int pw) {
   extern __shared__ double bsm[];
   const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
-  const int atom = g.atom0 + 2 * blockIdx.x + half;
-  const bool valid = atom < g.n_atoms;
+  const int atom = g.atom0 + pw * blockIdx.x + half;
+  const bool valid = half < pw && atom < g.n_atoms;
   const int dmax = 4 * g.r_max;
   const int d = valid ? 4 * g.kused[atom] : 0;
   const uint64_t hm = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
   const uint64_t below = ((1ull << lane) - 1ull) & hm;
-  double* base = bsm + (size_t)half * band_atom_doubles(g.r_max);
-  double* Lb = base + LB;                  // [-1 .. d-1][LB]: Lb[j][t] = T[j+t][j]; row -1 zero
-  double* R1 = Lb + (size_t)dmax * LB;     // [4][d] first rows of the transform
+  double* Lb = bsm + (size_t)half * band_atom_doubles(g.r_max);  // row j at lb_row(j): Lb[t] = T[j+t][j]; row -1 zero
+  double* R1 = Lb + lb_row(dmax - 1) + LB;                        // [4][rs]: first rows of the transform
+  const int rs = r1_stride(d > 0 ? d : 1);
   if (valid) {
     const double* tab = g.tab + (size_t)atom * g.r_max * 32;
     for (int q = hl; q < (d + 1) * LB; q += 32) {
       const int j = q / LB - 1, t = q % LB;
       const int row = j + t;
-      base[q] = (j >= 0 && t <= BW && row < d) ? t_entry(tab, row, j) : 0.0;
+      Lb[lb_row(j) + t] = (j >= 0 && t <= BW && row < d) ? t_entry(tab, row, j) : 0.0;
     }
     for (int q = hl; q < 4 * d; q += 32) {
       const int c = q / d, m = q % d;
-      R1[q] = (m == c) ? 1.0 : 0.0;
+      R1[c * rs + r1_col(m)] = (m == c) ? 1.0 : 0.0;
     }
   }
   __syncthreads();
@@ -380,9 +399,9 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
     int* seg = g.seg + (size_t)atom * g.seg_max;
     int64_t nrot = 0;
     int nseg = 0;
-    band_stage<4>(Lb, R1, d, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
-    band_stage<3>(Lb, R1, d, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
-    band_stage<2>(Lb, R1, d, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
+    band_stage<4>(Lb, R1, d, rs, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
+    band_stage<3>(Lb, R1, d, rs, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
+    band_stage<2>(Lb, R1, d, rs, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
     if (hl == 0) {
       g.rot_n[atom] = (int)(nrot < g.rot_max ? nrot : g.rot_max);
       g.seg_n[2 * atom] = nseg < g.seg_max ? nseg : g.seg_max;
@@ -397,12 +416,12 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
     double* tri = g.tri + (size_t)atom * 2 * dmax;
     double* r1 = g.y1 + (size_t)atom * 4 * dmax;
     for (int k = hl; k < d; k += 32) {
-      tri[k] = Lb[(size_t)k * LB];
-      tri[dmax + k] = (k + 1 < d) ? Lb[(size_t)k * LB + 1] : 0.0;
+      tri[k] = Lb[lb_row(k)];
+      tri[dmax + k] = (k + 1 < d) ? Lb[lb_row(k) + 1] : 0.0;
     }
     for (int q = hl; q < 4 * d; q += 32) {
       const int c = q / d, m = q % d;
-      r1[(size_t)c * dmax + m] = R1[q];
+      r1[(size_t)c * dmax + m] = R1[c * rs + r1_col(m)];
     }
   }
 }
@@ -749,7 +768,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   const int atom = g.atom0 + blockIdx.x;
   const int dmax = 4 * g.r_max;
   double* v = rsm;                       // [dmax][4]: f(Lambda) Y[0:4,:]^T
-  double* x = rsm + (size_t)dmax * 4;    // [dmax][XS]: rows padded against LDS bank conflicts
+  double* x = rsm + (size_t)dmax * 4;    // row m at xrow(m)
   const double mu = g.mu_state[2];
   const int d = 4 * g.kused[atom];
   {
@@ -783,7 +802,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     }
     int which;
     const double sum = wave_sum16(acc, lane, which);
-    if ((lane & 3) == 0) x[XS * (k0 + (which >> 2)) + (which & 3)] = sum;
+    if ((lane & 3) == 0) x[xrow(k0 + (which >> 2)) + (which & 3)] = sum;
   }
   __syncthreads();
   // c = Z x: band steps in reverse; the rotations of one step commute. One
@@ -796,7 +815,7 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   const int* seg = g.seg + (size_t)atom * g.seg_max;
   const int nrot = g.rot_n[atom];
   const int nb = g.seg_n[2 * atom];
-  int* s_seg = (int*)(x + (size_t)dmax * XS);                // [RHO_SEGW]
+  int* s_seg = (int*)(x + xrow(dmax - 1) + 4);                // [RHO_SEGW]
   double* s_cs = (double*)(s_seg + RHO_SEGW);                // [RHO_ROTW][2]
   uint16_t* s_p = (uint16_t*)(s_cs + 2 * RHO_ROTW);          // [RHO_ROTW]
   int k = nb - 1;
@@ -840,8 +859,8 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
       for (int e = st + lane; e < se; e += 64) {
         const double c = s_cs[2 * e], s = s_cs[2 * e + 1];
         const int p = s_p[e];
-        double* xp = x + XS * p;
-        double* xq = xp + XS;
+        double* xp = x + xrow(p);
+        double* xq = x + xrow(p + 1);
         const double a0 = xp[0], a1 = xp[1], a2 = xp[2], a3 = xp[3];
         const double b0 = xq[0], b1 = xq[1], b2 = xq[2], b3 = xq[3];
         xp[0] = c * a0 - s * b0; xp[1] = c * a1 - s * b1; xp[2] = c * a2 - s * b2; xp[3] = c * a3 - s * b3;
@@ -867,7 +886,8 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
     const size_t row0 = (size_t)atom * (4 * (g.zmax + 1)) + q0;
     for (int m = lane; m < d; m += 64) {
-      const double x0 = x[XS * m], x1 = x[XS * m + 1], x2 = x[XS * m + 2], x3 = x[XS * m + 3];
+      const double* xm = x + xrow(m);
+      const double x0 = xm[0], x1 = xm[1], x2 = xm[2], x3 = xm[3];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const double vv = (double)((const VJ*)g.vj)[(row0 + r) * vld + m];
@@ -889,9 +909,13 @@ size_t eig_lds_bytes(int r_max) {
   const size_t chains = (4 * dp + dmax + 4 * (EIG_NT / 64)) * sizeof(double) + dmax * sizeof(int) + 64;
   return band > chains ? band : chains;
 }
-size_t band_lds_bytes(int r_max) { return 2 * band_atom_doubles(r_max) * sizeof(double) + 64; }
+// atoms per k_band wave: two unless their band storage exceeds the LDS
+static int band_per_wave(int r_max) { return 2 * band_atom_doubles(r_max) * sizeof(double) + 64 <= LDS_CU ? 2 : 1; }
+size_t band_lds_bytes(int r_max) { return band_per_wave(r_max) * band_atom_doubles(r_max) * sizeof(double) + 64; }
 size_t rho_lds_bytes(int r_max) {
-  return (size_t)4 * r_max * (4 + XS) * sizeof(double) + RHO_SEGW * sizeof(int) + RHO_ROTW * (2 * sizeof(double) + 2) + 64;
+  const int dmax = 4 * r_max;
+  return ((size_t)dmax * 4 + xrow(dmax - 1) + 4) * sizeof(double) + RHO_SEGW * sizeof(int) +
+         RHO_ROTW * (2 * sizeof(double) + 2) + 64;
 }
 // Threads of a k_eig workgroup: one per eigenvalue of the largest T.
 int eig_threads(int r_max) {
@@ -921,7 +945,9 @@ void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
     hipLaunchKernelGGL(k_eig_chains, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
     return;
   }
-  hipLaunchKernelGGL(k_band, dim3((a.n_atoms - a.atom0 + 1) / 2), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
+  const int pw = band_per_wave(a.r_max);
+  hipLaunchKernelGGL(k_band, dim3((a.n_atoms - a.atom0 + pw - 1) / pw), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a,
+                     pw);
   hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
 }
 void launch_rho(const RhoArgs& a, hipStream_t st) {

@@ -135,3 +135,30 @@ def test_fp32_hv_layouts_agree(torch_cuda):
     dr = float(np.abs(a["rho"] - b["rho"]).max())
     print(f"  wide vs narrow FP32 H.V: force {df:.2e} eV/A, rho {dr:.2e}, mu {abs(a['mu'] - b['mu']):.2e}")
     assert df <= 1e-4 and dr <= 1e-5 and abs(a["mu"] - b["mu"]) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_band_one_atom_per_wave_agrees(torch_cuda, precision):
+    """The band reduction runs two atoms per wave while their band storage
+    fits in LDS together (r_max up to 222) and one atom per wave above that.
+    A context sized for r_max = 240 (one atom per wave) and one sized for
+    r_max = 30 (two per wave) give the same result on the same r = 30 run, to
+    rounding (the eigensolver's thread count also follows r_max)."""
+    from paper_0910_4497_amd.tb import TBContext
+    w = inputs.workload("c60_240")
+    runs = {}
+    for r_max in (30, 240):
+        ctx = TBContext(w.n_atoms, 130, r_max)
+        runs[r_max] = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, 30, w.kT, n_electrons=w.n_electrons,
+                              precision=precision)
+        ctx.close()
+    a, b = runs[30], runs[240]
+    assert a["stats"]["flags"] == 0 and b["stats"]["flags"] == 0
+    assert np.array_equal(a["col_j"], b["col_j"])
+    drho = float(np.abs(a["rho"] - b["rho"]).max())
+    df = float(np.abs(a["forces"] - b["forces"]).max())
+    print(f"  {precision}: |d rho| {drho:.2e}, |d F| {df:.2e} eV/A, d mu {abs(a['mu'] - b['mu']):.2e}")
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert abs(a["mu"] - b["mu"]) <= tol * max(1.0, abs(a["mu"]))
+    assert drho <= tol * float(np.abs(a["rho"]).max())
+    assert df <= (1e-10 if precision == "fp64" else 1e-5)
