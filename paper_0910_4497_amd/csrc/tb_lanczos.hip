@@ -34,6 +34,12 @@
 
 namespace tbk {
 
+// Value of lane C of each quad (4 consecutive lanes), by a DPP broadcast.
+template <int C>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), C * 0x55, 0xF, 0xF, false));
+}
+
 
 template <typename VT> struct Vec4;
 template <> struct Vec4<double> { typedef double4 T; };
@@ -141,13 +147,19 @@ k_lanczos(LanczosArgs g) {
   static_assert(!BF || sizeof(VT) == 4, "BF16 operands with the FP32 recursion only");
   static_assert(!(BF && WIDE), "the wide H.V items take unrounded operands");
   constexpr int LZ_NW = LZ_NT / 64;
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ncap = g.nc_max, Rcap = 4 * ncap;
-  // LDS layout
+  // LDS layout. Every region is addressed from smem by a byte offset (rounded
+  // up to 16 bytes where vector loads need it), so that the compiler keeps the
+  // LDS address space of each pointer and emits LDS loads, not flat ones: a
+  // flat load's use waits for every global load in flight as well.
+  auto at16 = [&](const void* p) {
+    return smem + (((size_t)((const unsigned char*)p - smem) + 15) & ~(size_t)15);
+  };
   VT* s_Va = (VT*)smem;                                     // [Rcap][4] current V_k
   VT* s_W = s_Va + (size_t)Rcap * 4;                        // [Rcap][4]
-  double* s_C = (double*)(((uintptr_t)(s_W + (size_t)Rcap * 4) + 15) & ~(uintptr_t)15);
+  double* s_C = (double*)at16(s_W + (size_t)Rcap * 4);
   // s_C: [max(r_max, LZ_NW)][16] projection coefficients / partials
   const int cslots = (g.r_max > 2 * LZ_NW ? g.r_max : 2 * LZ_NW);
   double* s_red = s_C + (size_t)cslots * 16;                // [LZ_NW][16]
@@ -155,11 +167,11 @@ k_lanczos(LanczosArgs g) {
   int* s_off = (int*)(s_misc + 224);                        // [ncap+1]
   int* s_gid = s_off + ncap + 1;                            // [ncap]
   int16_t* s_js = (int16_t*)(s_gid + ncap);                 // [ncap] rho row index of a local atom, or -1
-  float* s_om = (float*)(((uintptr_t)(s_js + ncap) + 15) & ~(uintptr_t)15);   // [3][r_max][16] if om_lds
+  float* s_om = (float*)at16(s_js + ncap);                  // [3][r_max][16] if om_lds
   float* s_ab = s_om + (g.om_lds ? (size_t)3 * g.r_max * 16 : 0);                 // [r_max][32] if ab_lds
   // second block buffer (vprev_lds): V_k and V_{k+1} alternate, so the
   // three-term update reads V_{k-1} from LDS instead of HBM
-  VT* s_Vb = g.vprev_lds ? (VT*)(((uintptr_t)(s_ab + (g.ab_lds ? (size_t)g.r_max * 32 : 0)) + 15) & ~(uintptr_t)15)
+  VT* s_Vb = g.vprev_lds ? (VT*)at16(s_ab + (g.ab_lds ? (size_t)g.r_max * 32 : 0))
                          : s_Va;
   __shared__ int s_atom;
 
@@ -459,55 +471,92 @@ k_lanczos(LanczosArgs g) {
         }
         lds_barrier();
         const double rnd = 2.0 * g.eps_unit * s_misc[208];
-        float* om = g.om_lds ? s_om : (float*)g.omega + (size_t)blockIdx.x * 3 * g.r_max * 16;
-        const float* Ok = om + (size_t)(k % 3) * g.r_max * 16;          // Omega_{j,k}, j < k
-        const float* Okm = om + (size_t)((k + 2) % 3) * g.r_max * 16;   // Omega_{j,k-1}, j < k-1
-        float* Okp = om + (size_t)((k + 1) % 3) * g.r_max * 16;         // Omega_{j,k+1}, j <= k
         // one entry (j, a, b) of Omega_{j,k+1} per thread, in FP32 (an
-        // estimate); the four lanes holding row (j, a) exchange M by shuffles
+        // estimate); the four lanes holding row (j, a) exchange M by shuffles.
+        // The ring of three Omega blocks is in LDS or in global memory; the
+        // loop is instantiated for each with pointers of that address space,
+        // so that its loads are LDS or global loads (counted in order) rather
+        // than flat ones, whose every use waits for all loads in flight.
         const float rndf = (float)rnd;
         double lmax = 0.0;
-        for (int t = tid; t < 16 * (k + 1); t += LZ_NT) {
-          const int j = t >> 4, a = (t >> 2) & 3, b = t & 3;
-          float m = rndf;
-          if (j < k) {
-            // row a of A_j, column a of B_j, row a of B_{j-1}
-            float aj[4], bj[4], bjm[4];
+        const size_t ring = (size_t)g.r_max * 16;
+        // LZ_NT is a multiple of 16, so a thread keeps its row a and column b
+        // over the loop: its column of A_k, row of B_{k-1} and column of
+        // B_k^-1 are read once
+        static_assert(LZ_NT % 16 == 0, "entries (j, a, b) keep a and b per thread");
+        const int at = (tid >> 2) & 3, bt = tid & 3;
+        float Acol[4], Bprow[4], Xcol[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          Acol[c] = (float)A[c * 4 + bt]; Bprow[c] = (float)Bp[bt * 4 + c]; Xcol[c] = (float)Xe[c * 4 + bt];
+        }
+        auto estimate = [&](auto om, auto tabp) {
+          const auto Ok = om + (size_t)(k % 3) * ring;           // Omega_{j,k}, j < k
+          const auto Okm = om + (size_t)((k + 2) % 3) * ring;    // Omega_{j,k-1}, j < k-1
+          const auto Okp = om + (size_t)((k + 1) % 3) * ring;    // Omega_{j,k+1}, j <= k
+          for (int t = tid; t < 16 * (k + 1); t += LZ_NT) {
+            const int j = t >> 4, a = at, b = bt;
+            // The 16 lanes of block j each load one element (a, b) of every
+            // matrix the entry needs, at an in-range block index (the
+            // neighbours clamped to [0, k - 1]; k = 0 has no entries j < k),
+            // and take the rows and columns they need from the other lanes:
+            // within a quad (row a) by DPP broadcasts, across the 16 lanes
+            // (column b) by shuffles. The edge cases j = 0, j + 1 = k and
+            // j = k - 1 are applied by selects.
+            const int jc = j < k ? j : (k > 0 ? k - 1 : 0);
+            const int jm = jc > 0 ? jc - 1 : 0, jp = jc + 1 < k ? jc + 1 : jc;
+            const int own = a * 4 + b;
+            const float w_jk = Ok[jc * 16 + own];      // Omega_{j,k}[a][b]
+            const float w_jp = Ok[jp * 16 + own];      // Omega_{j+1,k}[a][b]
+            const float w_jm = Ok[jm * 16 + own];      // Omega_{j-1,k}[a][b]
+            const float w_l = Okm[jc * 16 + own];      // Omega_{j,k-1}[a][b]
+            float ea, eb, ebm;                         // A_j[a][b], B_j[b][a], B_{j-1}[a][b]
             if (g.ab_lds) {
-              const float* ABj = s_ab + j * 32;
-#pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                aj[c] = ABj[a * 4 + c]; bj[c] = ABj[16 + c * 4 + a];
-                bjm[c] = (j > 0) ? ABj[-16 + a * 4 + c] : 0.0f;
-              }
+              ea = s_ab[jc * 32 + own]; eb = s_ab[jc * 32 + 16 + b * 4 + a]; ebm = s_ab[jm * 32 + 16 + own];
             } else {
-              const double* ABj = tab + (size_t)j * 32;
-#pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                aj[c] = (float)ABj[a * 4 + c]; bj[c] = (float)ABj[16 + c * 4 + a];
-                bjm[c] = (j > 0) ? (float)ABj[-16 + a * 4 + c] : 0.0f;
-              }
+              ea = (float)tabp[jc * 32 + own]; eb = (float)tabp[jc * 32 + 16 + b * 4 + a];
+              ebm = (float)tabp[jm * 32 + 16 + own];
             }
-            const float* Ojk = Ok + j * 16;
-            float acc = 0.0f;
+            const float aj[4] = {quad_bcast<0>(ea), quad_bcast<1>(ea), quad_bcast<2>(ea), quad_bcast<3>(ea)};
+            const float bj[4] = {quad_bcast<0>(eb), quad_bcast<1>(eb), quad_bcast<2>(eb), quad_bcast<3>(eb)};
+            const float bjm[4] = {quad_bcast<0>(ebm), quad_bcast<1>(ebm), quad_bcast<2>(ebm), quad_bcast<3>(ebm)};
+            const float orow[4] = {quad_bcast<0>(w_jk), quad_bcast<1>(w_jk), quad_bcast<2>(w_jk), quad_bcast<3>(w_jk)};
+            const float olast[4] = {quad_bcast<0>(w_l), quad_bcast<1>(w_l), quad_bcast<2>(w_l), quad_bcast<3>(w_l)};
+            float ocol[4], onext[4], oprev[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-              const float ojp = (j + 1 == k) ? (c == b ? 1.0f : 0.0f) : Ojk[16 + c * 4 + b];
-              const float ol = (j == k - 1) ? (a == c ? 1.0f : 0.0f) : Okm[j * 16 + a * 4 + c];
-              acc += aj[c] * Ojk[c * 4 + b] - Ojk[a * 4 + c] * (float)A[c * 4 + b]
-                   + bj[c] * ojp - ol * (float)Bp[b * 4 + c];
-              if (j > 0) acc += bjm[c] * Ojk[-16 + c * 4 + b];
+              const int src = (lane & ~15) | (c * 4 + b);
+              ocol[c] = __shfl(w_jk, src, 64);
+              onext[c] = __shfl(w_jp, src, 64);
+              oprev[c] = __shfl(w_jm, src, 64);
             }
-            m = acc + copysignf(rndf, acc);
-          }
-          float o = 0.0f;
+            float m = rndf;
+            if (j < k) {
+              float acc = 0.0f;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) o += __shfl(m, (lane & ~3) | c, 64) * (float)Xe[c * 4 + b];
-          Okp[j * 16 + a * 4 + b] = o;
-          // orbital seeds: only a chain's own entries estimate a loss of
-          // orthogonality (different chains are not orthogonal)
-          if (!g.scalar || a == b) lmax = fmax(lmax, (double)fabsf(o));
-        }
+              for (int c = 0; c < 4; ++c) {
+                const float ojp = (j + 1 == k) ? (c == b ? 1.0f : 0.0f) : onext[c];
+                const float ol = (j == k - 1) ? (a == c ? 1.0f : 0.0f) : olast[c];
+                acc += aj[c] * ocol[c] - orow[c] * Acol[c] + bj[c] * ojp - ol * Bprow[c];
+                acc += (j > 0) ? bjm[c] * oprev[c] : 0.0f;
+              }
+              m = acc + copysignf(rndf, acc);
+            }
+            float o = 0.0f;
+  #pragma unroll
+            for (int c = 0; c < 4; ++c) o += __shfl(m, (lane & ~3) | c, 64) * Xcol[c];
+            Okp[j * 16 + a * 4 + b] = o;
+            // orbital seeds: only a chain's own entries estimate a loss of
+            // orthogonality (different chains are not orthogonal)
+            if (!g.scalar || a == b) lmax = fmax(lmax, (double)fabsf(o));
+          }
+        };
+        typedef __attribute__((address_space(1))) float g_float;
+        typedef __attribute__((address_space(3))) float l_float;
+        typedef __attribute__((address_space(1))) const double g_cdouble;
+        const auto tab_g = (g_cdouble*)tab;
+        if (g.om_lds) estimate((l_float*)s_om, tab_g);
+        else estimate((g_float*)((float*)g.omega + (size_t)blockIdx.x * 3 * ring), tab_g);
         lmax = wave_max(lmax);
         if (lane == 0) s_red[wave] = lmax;
         lds_barrier();
@@ -520,6 +569,7 @@ k_lanczos(LanczosArgs g) {
           // the pass restores orthogonality to rounding level (each thread
           // overwrites the entries it stored: the step's barriers order LDS
           // only, and the buffer may be in global memory)
+          float* Okp = (g.om_lds ? s_om : (float*)g.omega + (size_t)blockIdx.x * 3 * ring) + (size_t)((k + 1) % 3) * ring;
           for (int t = tid; t < 16 * (k + 1); t += LZ_NT) Okp[t] = (float)g.eps_unit;
           ++nreorth;
         }
