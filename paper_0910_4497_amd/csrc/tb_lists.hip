@@ -317,13 +317,14 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
         const double* __restrict__ pair64, const int* __restrict__ clu_n, const int* __restrict__ clu_j,
         int* __restrict__ loc_off, uint32_t* __restrict__ loc_ent, double* __restrict__ hnorm,
         int* __restrict__ jloc, int64_t* stats) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int i = blockIdx.x, tid = threadIdx.x;
   const int n = clu_n[i];
   int* s_c = (int*)smem;                               // [nc_max]
   int* s_cnt = s_c + nc_max;                           // [nc_max + 1]
-  double* s_x = (double*)(s_cnt + nc_max + 2);         // [nc_max][3] (8-byte aligned below)
-  s_x = (double*)(((uintptr_t)s_x + 7) & ~(uintptr_t)7);
+  // [nc_max][3], 8-byte aligned; addressed from smem by a byte offset so that
+  // its accesses stay LDS accesses (not flat ones)
+  double* s_x = (double*)(smem + ((((size_t)(2 * nc_max + 2) * sizeof(int)) + 7) & ~(size_t)7));
   __shared__ double s_red[LIST_NT / 64];
   const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
   for (int a = tid; a < n; a += LIST_NT) {
