@@ -3,9 +3,15 @@
 //
 //   N(mu) = sum_i sum_m f(lambda_m^i) w_m^i,  f(e) = 2 / (1 + exp((e - mu)/kT)),
 // solved for N(mu) = N_e. N is increasing in mu; every launch of k_mu_iter
-// evaluates N at 31 points that split the bracket [lo, hi] into 32 equal
-// parts and keeps the part where N crosses N_e (multisection: 5 bits per
-// launch, 13 launches take a 300 eV bracket to rounding level). A fixed number
+// evaluates N at 31 points of the bracket [lo, hi] and keeps the tightest
+// bracket they give. The first launch splits it into 32 equal parts; later
+// launches place 24 points evenly (25 parts: 4.6 bits whatever happens) and 7
+// around the root of the straight line through (lo, N(lo)) and (hi, N(hi)),
+// at offsets 0, +-2^-20, +-2^-12 and +-2^-4 of the bracket width. Once the
+// bracket is narrow against kT, N is nearly linear on it and the new bracket
+// is the gap between two of those points (12 to 20 bits per launch): about 7
+// launches reach rounding level where plain multisection takes 12, and 13
+// launches cover 60 bits in any case. A fixed number
 // of launches is enqueued; once the bracket has collapsed to rounding level,
 // later launches return at once, so the sequence is capturable in a graph. Reductions are two-level and in a
 // fixed order (per-block partials summed by the last block to finish), so
@@ -19,8 +25,9 @@ namespace tbk {
 constexpr int MU_NT = 256;
 constexpr int MU_NB = 256;         // blocks of the reduction kernels (timed: 128, 256, 512)
 constexpr int MU_P = 31;           // points per multisection step
+constexpr int MU_U = 24;           // of which evenly spaced after the first step
 
-enum { MS_LO = 0, MS_HI = 1, MS_MU = 2, MS_DONE = 3, MS_N = 4, MS_STEP = 5, MS_IT = 6 };
+enum { MS_LO = 0, MS_HI = 1, MS_MU = 2, MS_DONE = 3, MS_N = 4, MS_STEP = 5, MS_IT = 6, MS_NLO = 7, MS_NHI = 8 };
 
 
 // Sum M values over the grid. Every block stores its M block sums (fixed
@@ -93,19 +100,37 @@ __global__ void __launch_bounds__(MU_NT) k_mu_bracket(MuArgs g, double mu_fixed,
     s[MS_DONE] = fixed ? 1.0 : 0.0;
     s[MS_STEP] = s[MS_HI] - s[MS_LO];
     s[MS_IT] = 0.0;
+    s[MS_NLO] = 0.0; s[MS_NHI] = 0.0;        // N at lo and hi: known after the first step
   }
 }
 
-// One multisection step: N(mu) at the MU_P interior points of [lo, hi] that
-// split it into MU_P + 1 equal parts; the bracket becomes the part where N
-// crosses N_e (MU_P + 1 = 32: five bits per launch). Sums are per block in a
-// fixed order, then per point over the blocks in a fixed order by the last
-// block, so the result is reproducible bit for bit.
+// One multisection step: N(mu) at MU_P points of [lo, hi] (mu_point); the
+// bracket becomes the tightest one among them: lo' the largest point with
+// N < N_e, hi' the smallest with N >= N_e (N at a point equal to N_e exactly
+// ends the search there). Sums are per block in a fixed order, then per point
+// over the blocks in a fixed order by the last block, so the result is
+// reproducible bit for bit.
+__device__ __forceinline__ double mu_point(const double* s, double ne, int p) {
+  const double lo = s[MS_LO], hi = s[MS_HI], w = hi - lo;
+  if (s[MS_IT] == 0.0) return lo + (p + 1) * (w / (MU_P + 1));
+  if (p < MU_U) return lo + (p + 1) * (w / (MU_U + 1));
+  const double nlo = s[MS_NLO], nhi = s[MS_NHI];
+  double ms = (nhi > nlo) ? lo + (ne - nlo) / (nhi - nlo) * w : 0.5 * (lo + hi);
+  const int q = p - MU_U;                        // 0: the line's root; 2i-1, 2i: -+ 2^(-20+8(i-1)) w
+  if (q > 0) {
+    const double off = w * __builtin_amdgcn_ldexp(1.0, -20 + 8 * ((q - 1) >> 1));
+    ms += (q & 1) ? -off : off;
+  }
+  return fmin(fmax(ms, lo), hi);
+}
+
 __global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g) {
   if (g.state[MS_DONE] != 0.0) return;
   const double lo = g.state[MS_LO], hi = g.state[MS_HI];
-  const double h = (hi - lo) / (MU_P + 1);
   const double cut = 40.0 * g.kT;                 // f = 0 or 2 to rounding beyond this
+  double xs[MU_P];
+#pragma unroll
+  for (int p = 0; p < MU_P; ++p) xs[p] = mu_point(g.state, g.n_e, p);
   double v[MU_P];
 #pragma unroll
   for (int p = 0; p < MU_P; ++p) v[p] = 0.0;
@@ -119,7 +144,7 @@ __global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g) {
     } else if (l <= hi + cut) {
 #pragma unroll
       for (int p = 0; p < MU_P; ++p) {
-        const double z = (l - (lo + (p + 1) * h)) / g.kT;
+        const double z = (l - xs[p]) / g.kT;
         const double e = exp(-fabs(z));
         const double f = (z > 0.0) ? 2.0 * e / (1.0 + e) : 2.0 / (1.0 + e);
         v[p] += f * w;
@@ -131,16 +156,19 @@ __global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g) {
   const int tid = threadIdx.x;
   if (tid == 0) {
     double* s = g.state;
-    int below = 0;                               // points with N < N_e (N is increasing in mu)
+    double nlo = lo, nhi = hi, Nlo = s[MS_NLO], Nhi = s[MS_NHI];
     int exact = -1;
     for (int p = 0; p < MU_P; ++p) {
-      if (Np[p] < g.n_e) below = p + 1;
-      if (Np[p] == g.n_e && exact < 0) exact = p;
+      if (Np[p] < g.n_e) {
+        if (xs[p] > nlo) { nlo = xs[p]; Nlo = Np[p]; }
+      } else {
+        if (xs[p] < nhi) { nhi = xs[p]; Nhi = Np[p]; }
+        if (Np[p] == g.n_e && exact < 0) exact = p;
+      }
     }
-    double nlo = below == 0 ? lo : lo + below * h;
-    double nhi = below == MU_P ? hi : lo + (below + 1) * h;
-    if (exact >= 0) nlo = nhi = lo + (exact + 1) * h;
-    s[MS_LO] = nlo; s[MS_HI] = nhi; s[MS_IT] += 1.0;
+    if (exact >= 0) nlo = nhi = xs[exact];
+    else if (nlo >= nhi) nlo = nhi = 0.5 * (nlo + nhi);   // N not monotone at rounding level
+    s[MS_LO] = nlo; s[MS_HI] = nhi; s[MS_NLO] = Nlo; s[MS_NHI] = Nhi; s[MS_IT] += 1.0;
     s[MS_MU] = 0.5 * (nlo + nhi);
     const double scale = fmax(1.0, fabs(s[MS_MU]));
     if (nhi - nlo <= 4.0 * DBL_EPSILON * scale) s[MS_DONE] = 1.0;
