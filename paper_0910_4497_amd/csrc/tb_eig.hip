@@ -42,7 +42,6 @@ namespace tbk {
 constexpr int EIG_NT = 256;
 constexpr int BAND_NT = 64;
 constexpr int RHO_NT = 256;     // k_rho: four waves per atom
-constexpr int RHO_MU = 3;       // column blocks of 64 loaded together in k_rho's products
 constexpr int RHO_SEGW = 256;      // segment-table window of k_rho
 constexpr int RHO_ROTW = 512;      // rotation-log window of k_rho (>= rotations of any one segment)
 constexpr int BW = 4;              // half-bandwidth of T
@@ -831,28 +830,13 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     double acc[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    // RHO_MU column blocks of 64 at a time, all their loads issued before the
-    // sums; a column past d reads column 0 (in range) with v = 0, adding
-    // exact zeros, so the sums are those of the plain loop in its order
-    for (int mb = 0; mb < d; mb += 64 * RHO_MU) {
-      double u[RHO_MU][4], vm[RHO_MU][4];
+    for (int m = lane; m < d; m += 64) {
+      const double v0 = v[4 * m], v1 = v[4 * m + 1], v2 = v[4 * m + 2], v3 = v[4 * m + 3];
 #pragma unroll
-      for (int h = 0; h < RHO_MU; ++h) {
-        const int m = mb + 64 * h + lane;
-        const bool in = m < d;
-        const int mm = in ? m : 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) u[h][r] = Ua[(size_t)(k0 + r) * dmax + mm];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) vm[h][c] = in ? v[4 * mm + c] : 0.0;
+      for (int r = 0; r < 4; ++r) {
+        const double u = Ua[(size_t)(k0 + r) * dmax + m];
+        acc[r * 4] += u * v0; acc[r * 4 + 1] += u * v1; acc[r * 4 + 2] += u * v2; acc[r * 4 + 3] += u * v3;
       }
-#pragma unroll
-      for (int h = 0; h < RHO_MU; ++h)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          acc[r * 4] += u[h][r] * vm[h][0]; acc[r * 4 + 1] += u[h][r] * vm[h][1];
-          acc[r * 4 + 2] += u[h][r] * vm[h][2]; acc[r * 4 + 3] += u[h][r] * vm[h][3];
-        }
     }
     int which;
     const double sum = wave_sum16(acc, lane, which);
@@ -939,26 +923,14 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
     const size_t row0 = (size_t)atom * (4 * (g.zmax + 1)) + q0;
-    for (int mb = 0; mb < d; mb += 64 * RHO_MU) {      // as for x = U v above
-      double vv[RHO_MU][4], xv[RHO_MU][4];
+    for (int m = lane; m < d; m += 64) {
+      const double* xm = x + xrow(m);
+      const double x0 = xm[0], x1 = xm[1], x2 = xm[2], x3 = xm[3];
 #pragma unroll
-      for (int h = 0; h < RHO_MU; ++h) {
-        const int m = mb + 64 * h + lane;
-        const bool in = m < d;
-        const int mm = in ? m : 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) vv[h][r] = (double)((const VJ*)g.vj)[(row0 + r) * vld + mm];
-        const double* xm = x + xrow(mm);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) xv[h][c] = in ? xm[c] : 0.0;
+      for (int r = 0; r < 4; ++r) {
+        const double vv = (double)((const VJ*)g.vj)[(row0 + r) * vld + m];
+        acc[r * 4] += vv * x0; acc[r * 4 + 1] += vv * x1; acc[r * 4 + 2] += vv * x2; acc[r * 4 + 3] += vv * x3;
       }
-#pragma unroll
-      for (int h = 0; h < RHO_MU; ++h)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          acc[r * 4] += vv[h][r] * xv[h][0]; acc[r * 4 + 1] += vv[h][r] * xv[h][1];
-          acc[r * 4 + 2] += vv[h][r] * xv[h][2]; acc[r * 4 + 3] += vv[h][r] * xv[h][3];
-        }
     }
     int which;
     const double sum = wave_sum16(acc, lane, which);
