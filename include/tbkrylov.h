@@ -250,7 +250,8 @@ int tb_autotune(tb_ctx *ctx, int r, const int *r_per_atom, int precision, int *s
 /* Fixes the Krylov launch shape of later tb_krylov_rho calls at `precision`
  * without timing (the shapes tb_autotune chooses among): threads per
  * workgroup (256 or 512), waves per SIMD of the register budget (4: 128
- * VGPRs, 2: 256), persistent workgroups per compute unit (they must stay
+ * VGPRs, 3: 168, with 256 threads only, 2: 256), persistent workgroups per
+ * compute unit (they must stay
  * co-resident: wg_per_cu * threads / 64 <= 4 * waves_per_simd, and the
  * sphere capacity must fit their LDS) and, for TB_FP32, the H.V item layout
  * (wide = 1: four columns per lane over every fourth coupling). Results of

@@ -478,11 +478,12 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
   int tried = 0;
   float best = 3.0e38f;
   hipError_t err = hipSuccess;
-  const int nts[2] = {256, 512}, mws[2] = {4, 2};
+  const int nts[2] = {256, 512}, mws[3] = {4, 3, 2};   // waves per SIMD (3: 256 threads only)
   const int n_wide = precision == TB_FP32 ? 2 : 1;      // FP32: both H.V item layouts
   for (int wd = 0; wd < n_wide && err == hipSuccess; ++wd)
-  for (int m = 0; m < 2 && err == hipSuccess; ++m) {
+  for (int m = 0; m < 3 && err == hipSuccess; ++m) {
     for (int q = 0; q < 2 && err == hipSuccess; ++q) {
+      if (mws[m] == 3 && nts[q] != 256) continue;
       for (int pc = 1; pc <= c->lz_per_cu_max && err == hipSuccess; ++pc) {
         // co-resident only: waves per SIMD within the register budget
         if (pc * nts[q] / 64 > 4 * mws[m]) continue;
@@ -625,8 +626,9 @@ extern "C" int tb_set_shape(tb_ctx* c, int precision, int threads, int waves_per
   if (precision != TB_FP64 && precision != TB_FP32 && precision != TB_BF16)
     return fail(TB_EINVAL, "unknown precision %d", precision);
   if (threads != 256 && threads != 512) return fail(TB_EINVAL, "threads=%d is not 256 or 512", threads);
-  if (waves_per_simd != 2 && waves_per_simd != 4)
-    return fail(TB_EINVAL, "waves_per_simd=%d is not 2 or 4", waves_per_simd);
+  if (waves_per_simd != 2 && waves_per_simd != 3 && waves_per_simd != 4)
+    return fail(TB_EINVAL, "waves_per_simd=%d is not 2, 3 or 4", waves_per_simd);
+  if (waves_per_simd == 3 && threads != 256) return fail(TB_EINVAL, "waves_per_simd=3 needs 256 threads");
   if (wg_per_cu < 1 || wg_per_cu > c->lz_per_cu_max)
     return fail(TB_EINVAL, "wg_per_cu=%d outside [1, %d]", wg_per_cu, c->lz_per_cu_max);
   if (wide && precision != TB_FP32) return fail(TB_EINVAL, "the wide H.V layout is for TB_FP32 only");

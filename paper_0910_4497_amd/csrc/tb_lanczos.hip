@@ -918,6 +918,8 @@ static void launch_lz(const LanczosArgs& a, int nt, int minw, int n_wg, size_t l
   if (minw == 2) {
     if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2, BF, WIDE>), dim3(n_wg), dim3(256), lds, st, a);
     else hipLaunchKernelGGL((k_lanczos<VT, 512, 2, BF, WIDE>), dim3(n_wg), dim3(512), lds, st, a);
+  } else if (minw == 3) {                       // 256 threads only
+    hipLaunchKernelGGL((k_lanczos<VT, 256, 3, BF, WIDE>), dim3(n_wg), dim3(256), lds, st, a);
   } else {
     if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4, BF, WIDE>), dim3(n_wg), dim3(256), lds, st, a);
     else hipLaunchKernelGGL((k_lanczos<VT, 512, 4, BF, WIDE>), dim3(n_wg), dim3(512), lds, st, a);
@@ -933,15 +935,17 @@ void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int w
 }
 
 hipError_t lanczos_set_lds(size_t lds) {
-  const void* fn[16] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
+  const void* fn[20] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
                         (const void*)k_lanczos<float, 256, 4>, (const void*)k_lanczos<float, 512, 4>,
                         (const void*)k_lanczos<double, 256, 2>, (const void*)k_lanczos<double, 512, 2>,
                         (const void*)k_lanczos<float, 256, 2>, (const void*)k_lanczos<float, 512, 2>,
                         (const void*)k_lanczos<float, 256, 4, true>, (const void*)k_lanczos<float, 512, 4, true>,
                         (const void*)k_lanczos<float, 256, 2, true>, (const void*)k_lanczos<float, 512, 2, true>,
                         (const void*)k_lanczos<float, 256, 4, false, true>, (const void*)k_lanczos<float, 512, 4, false, true>,
-                        (const void*)k_lanczos<float, 256, 2, false, true>, (const void*)k_lanczos<float, 512, 2, false, true>};
-  for (int q = 0; q < 16; ++q) {
+                        (const void*)k_lanczos<float, 256, 2, false, true>, (const void*)k_lanczos<float, 512, 2, false, true>,
+                        (const void*)k_lanczos<double, 256, 3>, (const void*)k_lanczos<float, 256, 3>,
+                        (const void*)k_lanczos<float, 256, 3, true>, (const void*)k_lanczos<float, 256, 3, false, true>};
+  for (int q = 0; q < 20; ++q) {
     hipError_t e = hipFuncSetAttribute(fn[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }

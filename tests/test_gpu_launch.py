@@ -162,3 +162,31 @@ def test_band_one_atom_per_wave_agrees(torch_cuda, precision):
     assert abs(a["mu"] - b["mu"]) <= tol * max(1.0, abs(a["mu"]))
     assert drho <= tol * float(np.abs(a["rho"]).max())
     assert df <= (1e-10 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_three_waves_per_simd_shape_agrees(torch_cuda, precision):
+    """The 168-VGPR build of the Krylov kernel (3 waves per SIMD, 256
+    threads) runs the same arithmetic as the 128-VGPR one (4 waves per SIMD):
+    at the same workgroups per CU the results agree to rounding. Three waves
+    with 512 threads is refused."""
+    from paper_0910_4497_amd.tb import TBContext, TBError
+    w = inputs.workload("c60_240")
+    ctx = TBContext(w.n_atoms, 130, 30)
+    runs = {}
+    for waves in (4, 3):
+        ctx.set_shape(precision, 256, waves, 2)
+        runs[waves] = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                              precision=precision)
+    with pytest.raises(TBError) as e:
+        ctx.set_shape(precision, 512, 3, 1)
+    assert e.value.name == "TB_EINVAL"
+    ctx.close()
+    a, b = runs[4], runs[3]
+    assert a["stats"]["flags"] == 0 and b["stats"]["flags"] == 0
+    df = float(np.abs(a["forces"] - b["forces"]).max())
+    dr = float(np.abs(a["rho"] - b["rho"]).max())
+    print(f"  {precision}: 3 vs 4 waves per SIMD: force {df:.2e} eV/A, rho {dr:.2e}, "
+          f"bitwise {np.array_equal(a['rho'], b['rho']) and np.array_equal(a['forces'], b['forces'])}")
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert dr <= tol * float(np.abs(a["rho"]).max()) and df <= (1e-10 if precision == "fp64" else 1e-4)
