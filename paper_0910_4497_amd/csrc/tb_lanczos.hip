@@ -133,7 +133,8 @@ __device__ __forceinline__ void inv_upper4r(const double (&U)[16], const bool (&
 }
 
 // LZ_NT threads per workgroup; MINW waves per SIMD the register allocation
-// must allow (4: 128 VGPRs, some spilled; 2: 256 VGPRs, none spilled). BF
+// must allow (4: 128 VGPRs, some spilled; 3: 168, with 256 threads, fewer
+// spilled; 2: 256 VGPRs, none spilled in FP32). BF
 // (with VT = float): the operands of H.V -- the coupling data, the on-site and
 // bond parameters, and V_k -- are rounded to BF16 and the products
 // accumulated in FP32; everything else is the FP32 recursion. WIDE (FP32,
