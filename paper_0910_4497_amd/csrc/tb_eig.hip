@@ -312,7 +312,12 @@ __device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int rs,
   const int last = d - BC - 1;
   int jtop = tau / I;
   if (jtop > last) jtop = last;
-  for (int jb = jtop; jb >= 0; jb -= 32) {
+  // chase j is at plane p = BC tau + BC - 1 - j (I BC - 1) and active while
+  // p + 1 <= d - 1: the active chases are j >= jmin, so batches below jmin
+  // (all inactive) are not visited
+  const int num = BC * tau + BC + 1 - d;
+  const int jmin = num > 0 ? (num + I * BC - 2) / (I * BC - 1) : 0;
+  for (int jb = jtop; jb >= jmin; jb -= 32) {
     const int j = jb - hl;
     bool act = false;
     int p = 0, u0 = 0;
