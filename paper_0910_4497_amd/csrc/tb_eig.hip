@@ -231,8 +231,13 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
 // do not wait one by one. The vector goes to xcol (stride ld) unnormalised;
 // the return value is the factor that normalises it (applied by the readers,
 // which saves a pass over the column).
+// ACC: also accumulates y[c] = sum_k R1[c d + k] z_k, the column's projection
+// on the first four rows of Z (R1 in LDS, row stride d), as z is produced,
+// so that the column need not be read back.
+template <bool ACC>
 __device__ double twisted_vec(const double* D, const double* E, const double* E2, int d, double lam, double small,
-                            double* xcol, size_t ld, double* scr, int ns) {
+                            double* xcol, size_t ld, double* scr, int ns, const double* R1 = nullptr,
+                            double* y = nullptr) {
   constexpr int CH = 8;                        // scratch values prefetched per chunk
   double* sp = scr;                            // d+_k at sp[k * ns]
   double* sm = scr + (size_t)d * ns;           // d-_k at sm[k * ns]
@@ -267,6 +272,8 @@ __device__ double twisted_vec(const double* D, const double* E, const double* E2
   }
   double z = 1.0, nrm = 1.0;
   xcol[(size_t)r * ld] = 1.0;
+  double y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
+  if constexpr (ACC) { y0 = R1[r]; y1 = R1[(size_t)d + r]; y2 = R1[(size_t)2 * d + r]; y3 = R1[(size_t)3 * d + r]; }
   for (int k0 = r - 1; k0 >= 0; k0 -= CH) {
     double pv[CH];
 #pragma unroll
@@ -278,6 +285,9 @@ __device__ double twisted_vec(const double* D, const double* E, const double* E2
       z = -E[k] * z * rcp_nr(pv[u]);
       xcol[(size_t)k * ld] = z;
       nrm += z * z;
+      if constexpr (ACC) {
+        y0 += R1[k] * z; y1 += R1[(size_t)d + k] * z; y2 += R1[(size_t)2 * d + k] * z; y3 += R1[(size_t)3 * d + k] * z;
+      }
     }
   }
   z = 1.0;
@@ -292,8 +302,12 @@ __device__ double twisted_vec(const double* D, const double* E, const double* E2
       z = -E[k - 1] * z * rcp_nr(mv[u]);
       xcol[(size_t)k * ld] = z;
       nrm += z * z;
+      if constexpr (ACC) {
+        y0 += R1[k] * z; y1 += R1[(size_t)d + k] * z; y2 += R1[(size_t)2 * d + k] * z; y3 += R1[(size_t)3 * d + k] * z;
+      }
     }
   }
+  if constexpr (ACC) { y[0] = y0; y[1] = y1; y[2] = y2; y[3] = y3; }
   return 1.0 / sqrt(nrm);
 }
 
@@ -572,8 +586,17 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
         if (pos_s[t] != round) continue;
         double* xc = Ua + t;
         if (round == 0 && (t + 1 >= d || pos_s[t + 1] == 0)) {
-          // not in a cluster: twisted factorisation (column scale kept apart)
-          vsc[t] = twisted_vec(Dg, Eg, E2, d, lam_s[t], small, xc, dmax, scr, nt);
+          // not in a cluster: twisted factorisation (column scale kept apart),
+          // which also forms Y[0:4, t] = Z[0:4, :] U[:, t]; the outputs of
+          // the column are written here and skipped in step 4
+          double ya[4];
+          const double sc = twisted_vec<true>(Dg, Eg, E2, d, lam_s[t], small, xc, dmax, scr, nt, R1, ya);
+          vsc[t] = sc;
+          double* y1o = g.y1 + (size_t)atom * 4 * dmax;
+          const double a0 = ya[0] * sc, a1 = ya[1] * sc, a2 = ya[2] * sc, a3 = ya[3] * sc;
+          g.lam[(size_t)atom * dmax + t] = lam_s[t];
+          g.wgt[(size_t)atom * dmax + t] = a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+          y1o[t] = a0; y1o[dmax + t] = a1; y1o[2 * dmax + t] = a2; y1o[3 * dmax + t] = a3;
           continue;
         }
         vsc[t] = 1.0;                                // normalised below
@@ -613,6 +636,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     double* wgt = g.wgt + (size_t)atom * dmax;
     double* y1 = g.y1 + (size_t)atom * 4 * dmax;
     for (int t = tid; t < dmax; t += nt) {
+      if (t < d && pos_s[t] == 0 && (t + 1 >= d || pos_s[t + 1] == 0)) continue;   // written in step 3
       if (t < d) {
         const double* xc = Ua + t;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -748,7 +772,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
         const double* E2c = E2 + c * Kp;
         double* xc = Ua + (size_t)c * dmax + t;
         if (round == 0 && (t + 1 >= cend || pos_s[t + 1] == 0)) {
-          vsc[t] = twisted_vec(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
+          vsc[t] = twisted_vec<false>(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
           continue;
         }
         vsc[t] = 1.0;                                // normalised below
