@@ -27,7 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_lanczos_c60_1920_traffic.md")
+
+
+def traffic_record_path(workload):
+    return os.path.join(ROOT, "profiles", f"k_lanczos_{workload}_traffic.md")
 
 
 def measured_traffic(workload, precision, kernel, workgroups):
@@ -38,7 +41,7 @@ def measured_traffic(workload, precision, kernel, workgroups):
     import hashlib
     try:
         rec = None
-        with open(TRAFFIC_RECORD) as fh:
+        with open(traffic_record_path(workload)) as fh:
             for line in fh:
                 if line.startswith("traffic-record:"):
                     rec = json.loads(line.split(":", 1)[1])
@@ -82,6 +85,11 @@ def parse():
                     help="keep the default launch shapes instead of timing the candidates first")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the run with each MD step captured in one HIP graph")
+    ap.add_argument("--large-workload", default="c60_15360",
+                    help="second size of the metric, run after the headline workload at FP32 and "
+                         "FP64 (batched; '' to skip)")
+    ap.add_argument("--histogram-workload", default="c60_6480_strained",
+                    help="report the cutoff-sphere size histogram of this workload's start ('' to skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the MD runs, launch one elementwise copy kernel of this many MiB "
                          "(read once, written once) to calibrate HBM byte counters")
@@ -168,24 +176,54 @@ def run_graph(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, stream, 
     return {"seconds": t1 - t0, "stats": stats, "e_last": e_last}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-atom solves "
-              "shard by target atom, but this benchmark measures a single GPU's share.", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
-    from paper_0910_4497_amd import inputs
-    from paper_0910_4497_amd.tb import TBContext
+def lanczos_roofline(w_name, head_prec, head, shape, N, dev, torch):
+    """k_lanczos HBM roofline of a timed run: the algorithmic basis bytes the
+    kernel counted (V_0 and every new block written once, V_{k-1} read once per
+    step, 2 (k+1) blocks of 4n x 4 values per re-orthogonalisation pass at
+    step k) over its average launch time from HIP events on the library
+    stream; traffic from the committed FETCH_SIZE/WRITE_SIZE record when it
+    matches this source, kernel instance and workgroup count."""
+    lz_ms, lz_n = head["phases"]["lanczos"]
+    lz_avg_ms = lz_ms / max(lz_n, 1)
+    bytes_launch = float(head["stats"]["basis_bytes"])
+    achieved = bytes_launch / (lz_avg_ms * 1e-3) / 1e9
+    traffic = None
+    if shape:
+        lz_kernel = "k_lanczos<{}, {}, {}, {}, {}>".format("double" if head_prec == "fp64" else "float",
+                                                          shape["lanczos_threads"], shape["lanczos_waves_per_simd"],
+                                                          "true" if head_prec == "bf16" else "false",
+                                                          "true" if shape.get("lanczos_wide") else "false")
+        n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+        traffic = measured_traffic(w_name, head_prec, lz_kernel, min(n_cu * shape["lanczos_wg_per_cu"], N))
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "kernel": "k_lanczos", "avg_ms": round(lz_avg_ms, 4),
+            "algorithmic_bytes_per_launch": bytes_launch}
 
-    w = inputs.workload(args.workload)
+
+def mode_record(r, N, shapes, prec):
+    out = {"steps_per_s": round(r["steps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
+           "atom_solves_per_s": round(r["steps_per_s"] * N, 1),
+           "force_err_vs_fp64_eV_per_A": r.get("force_err"),
+           "energy_err_vs_fp64_eV_per_atom": r.get("energy_err_per_atom"),
+           "phase_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in r["phases"].items()},
+           "reorth_second_passes": r["stats"]["reorth_second_pass"],
+           "reorth_steps_per_atom": round(r["stats"]["reorth_steps"] / N, 2),
+           "lanczos_basis_bytes_per_launch": r["stats"]["basis_bytes"],
+           "pressure_GPa_last_step": round(r["pressure_GPa"], 4)}
+    if prec in shapes:
+        out["launch_shape"] = shapes[prec]
+    return out
+
+
+def run_workload(name, precs, args, stream, torch, inputs, TBContext, graph=True, plain_steps=0):
+    """Every requested precision of one workload: tuned launch shapes, timed
+    MD steps (and optionally the graph-replayed and the one-launch-per-atom
+    FP64 runs). Returns (w, results, shapes, plain, n_cluster, n_max, fixed)."""
+    import numpy as np
+    w = inputs.workload(name)
     params = inputs.load_params(w.params)
     dev = torch.device("cuda", 0)
-    # every launch goes to one non-default stream (default priority), so an MD
-    # step can be captured into a graph
-    stream = torch.cuda.Stream(device=dev)
-    torch.cuda.set_stream(stream)
     N = w.n_atoms
     if args.groups > 1:                    # compact groups of consecutive indices
         w.pos = np.ascontiguousarray(w.pos[inputs.group_order(w.pos, w.cell, (1, 1, 1), args.groups)])
@@ -208,21 +246,11 @@ def main():
     ctx = TBContext(N, n_max + 24, int(r_atoms.max()), hop_max=w.hop_max)
     ctx.set_seeds(args.seeds)
     ctx.set_groups(args.groups)
-    if args.calib_copy_mb:
-        src = torch.ones(args.calib_copy_mb << 17, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
-
     # at these starts a few atoms sit past the maximum of the repulsive
     # embedding polynomial F(x) (x ~ 146.5): their pair repulsion has turned
     # into attraction and any trajectory collapses within a few fs
-    fixed = args.start == "fixed" or (args.start == "auto" and args.workload in
-                                        ("c60_6480_strained", "c60_15360"))
-    results = {}
-    precs = {"all": ["fp32", "bf16", "fp64"], "both": ["fp32", "fp64"]}.get(args.precision, [args.precision])
-    shapes = {}
+    fixed = args.start == "fixed" or (args.start == "auto" and name in ("c60_6480_strained", "c60_15360"))
+    results, shapes = {}, {}
     for prec in precs:
         if not args.no_autotune:
             # untimed: pick the launch shapes on the start geometry (results unchanged)
@@ -230,16 +258,15 @@ def main():
             shapes[prec] = ctx.autotune(w.r, prec, r_per_atom=rpa)
         results[prec] = run_md(ctx, w, params, pos0, vel0, prec, args.steps, args.warmup, args.dt,
                                torch, inputs, rpa, fixed)
-        if not args.no_graph:
-            g = run_graph(ctx, w, params, pos0, vel0, prec, args.steps, args.warmup, args.dt, stream,
-                          torch, rpa, fixed)
-            results[prec]["graph"] = g
+        if graph:
+            results[prec]["graph"] = run_graph(ctx, w, params, pos0, vel0, prec, args.steps, args.warmup,
+                                               args.dt, stream, torch, rpa, fixed)
     plain = None
-    if args.plain_steps > 0:
-        plain = run_md(ctx, w, params, pos0, vel0, "fp64", args.plain_steps, 0, args.dt, torch, inputs, rpa,
+    if plain_steps > 0:
+        plain = run_md(ctx, w, params, pos0, vel0, "fp64", plain_steps, 0, args.dt, torch, inputs, rpa,
                        fixed, atoms_per_launch=1)
-        plain["ms_per_step"] = 1e3 * plain["seconds"] / args.plain_steps
-        plain["steps_per_s"] = args.plain_steps / plain["seconds"]
+        plain["ms_per_step"] = 1e3 * plain["seconds"] / plain_steps
+        plain["steps_per_s"] = plain_steps / plain["seconds"]
     ref = results.get("fp64")
     for prec, r in results.items():
         r["ms_per_step"] = 1e3 * r["seconds"] / args.steps
@@ -247,42 +274,102 @@ def main():
         if ref is not None:
             r["force_err"] = float((r["f_first"] - ref["f_first"]).abs().max().item())
             r["energy_err_per_atom"] = float(abs(r["e_first"][3] - ref["e_first"][3]).item()) / N
+    ctx.close()
+    del ctx
+    torch.cuda.synchronize()
+    return w, results, shapes, plain, n_cluster, n_max, fixed
 
-    # headline: the fastest reduced-precision mode whose first-step force error
-    # against the FP64 path is within 1e-3 eV/A, else FP64
-    # (without an FP64 run there is no reference: a single requested mode is the headline)
+
+def headline_of(results):
+    """The fastest reduced-precision mode whose first-step force error against
+    the FP64 path is within 1e-3 eV/A, else FP64 (a single requested mode
+    without an FP64 reference is its own headline)."""
     ok = [p for p in ("fp32", "bf16") if p in results and results[p].get("force_err", 0.0) <= 1e-3]
-    head_prec = max(ok, key=lambda p: results[p]["steps_per_s"]) if ok else ("fp64" if "fp64" in results
-                                                                            else next(iter(results)))
+    if ok:
+        return max(ok, key=lambda p: results[p]["steps_per_s"])
+    return "fp64" if "fp64" in results else next(iter(results))
+
+
+def sphere_histogram(name, torch, inputs, TBContext, bins=10):
+    """Cutoff-sphere sizes of a workload's start geometry (list build only)."""
+    import numpy as np
+    w = inputs.workload(name)
+    params = inputs.load_params(w.params)
+    pos = torch.tensor(w.pos, dtype=torch.float64, device="cuda:0")
+    probe = TBContext(w.n_atoms, 560, 1, hop_max=w.hop_max)
+    n = probe.build_local_H(pos, w.cell, (1, 1, 1), params, w.r_cut, want_sizes=True).cpu().numpy()
+    probe.close()
+    counts, edges = np.histogram(n, bins=bins)
+    out = {"n_atoms": w.n_atoms, "r_cluster_A": w.r_cut, "min": int(n.min()), "max": int(n.max()),
+           "mean": round(float(n.mean()), 2), "edges": [round(float(e), 1) for e in edges],
+           "counts": [int(c) for c in counts]}
+    if w.r_per_atom is not None:
+        r = np.asarray(w.r_per_atom)
+        out["r_per_atom_counts"] = {str(int(v)): int((r == v).sum()) for v in np.unique(r)}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-atom solves "
+              "shard by target atom, but this benchmark measures a single GPU's share.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_0910_4497_amd import inputs
+    from paper_0910_4497_amd.tb import TBContext
+
+    dev = torch.device("cuda", 0)
+    # every launch goes to one non-default stream (default priority), so an MD
+    # step can be captured into a graph
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    if args.calib_copy_mb:
+        src = torch.ones(args.calib_copy_mb << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    precs = {"all": ["fp32", "bf16", "fp64"], "both": ["fp32", "fp64"]}.get(args.precision, [args.precision])
+    w, results, shapes, plain, n_cluster, n_max, fixed = run_workload(
+        args.workload, precs, args, stream, torch, inputs, TBContext, graph=not args.no_graph,
+        plain_steps=args.plain_steps)
+    N = w.n_atoms
+    head_prec = headline_of(results)
     head = results[head_prec]
-    lz_ms, lz_n = head["phases"]["lanczos"]
-    lz_avg_ms = lz_ms / max(lz_n, 1)
-    # algorithmic basis bytes of the last launch, counted by the kernel: V_0 and
-    # every new block written once, V_{k-1} read once per step, and 2 (k+1)
-    # blocks of 4n x 4 values per re-orthogonalisation pass at step k
-    bytes_launch = float(head["stats"]["basis_bytes"])
-    achieved = bytes_launch / (lz_avg_ms * 1e-3) / 1e9
-    # the kernel instance and workgroup count of the timed launches (known
-    # when the tuner chose them); the traffic record applies to that shape only
-    traffic = None
-    shape = shapes.get(head_prec)
-    if shape:
-        lz_kernel = "k_lanczos<{}, {}, {}, {}, {}>".format("double" if head_prec == "fp64" else "float",
-                                                          shape["lanczos_threads"], shape["lanczos_waves_per_simd"],
-                                                          "true" if head_prec == "bf16" else "false",
-                                                          "true" if shape.get("lanczos_wide") else "false")
-        n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
-        traffic = measured_traffic(args.workload, head_prec, lz_kernel, min(n_cu * shape["lanczos_wg_per_cu"], N))
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": "k_lanczos", "avg_ms": round(lz_avg_ms, 4),
-            "algorithmic_bytes_per_launch": bytes_launch}
+    roof = lanczos_roofline(args.workload, head_prec, head, shapes.get(head_prec), N, dev, torch)
+
+    # the metric's second size: the 15360-atom crystal, mixed vs batched FP64
+    large = None
+    if args.large_workload and args.large_workload != args.workload:
+        lw, lres, lshapes, _, lncl, lnmax, lfixed = run_workload(
+            args.large_workload, ["fp32", "fp64"], args, stream, torch, inputs, TBContext, graph=False)
+        lhp = headline_of(lres)
+        large = {"workload": f"{args.large_workload}: {lw.n_atoms} C atoms, fcc C60 crystal, periodic",
+                 "n_atoms": lw.n_atoms, "r_cluster_A": lw.r_cut, "krylov_block_steps": lw.r,
+                 "cluster_atoms_mean": round(float(np.mean(lncl)), 2), "cluster_atoms_max": lnmax,
+                 "precision": lhp, "steps_per_s": round(lres[lhp]["steps_per_s"], 3),
+                 "ms_per_step": round(lres[lhp]["ms_per_step"], 3),
+                 "steps_from": "one fixed start state" if lfixed else "a velocity-Verlet trajectory",
+                 "roofline": lanczos_roofline(args.large_workload, lhp, lres[lhp], lshapes.get(lhp),
+                                              lw.n_atoms, dev, torch),
+                 "modes": {p: mode_record(r, lw.n_atoms, lshapes, p) for p, r in lres.items()}}
+        if lhp != "fp64":
+            large["mixed_over_fp64"] = round(lres[lhp]["steps_per_s"] / lres["fp64"]["steps_per_s"], 3)
+            large["force_err_vs_fp64_eV_per_A"] = lres[lhp]["force_err"]
+
+    hist = None
+    if args.histogram_workload:
+        hist = sphere_histogram(args.histogram_workload, torch, inputs, TBContext)
 
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import timing
         procs = min(16, len(os.sched_getaffinity(0)))
         sample = args.cpu_sample or min(N, 2048)
+        params = inputs.load_params(w.params)
         t = timing.time_atom_solves(w.pos, w.cell, (1, 1, 1), params, w.r_cut, w.r, sample,
                                     seed=11, processes=procs, seeds=args.seeds, group=args.groups)
         cpu = {"value": round(t["steps_per_s"], 5), "unit": "MD steps/s", "cores": t["cores"],
@@ -293,23 +380,15 @@ def main():
 
     extra = {}
     for prec, r in results.items():
-        extra[prec] = {"steps_per_s": round(r["steps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
-                       "atom_solves_per_s": round(r["steps_per_s"] * N, 1),
-                       "force_err_vs_fp64_eV_per_A": r.get("force_err"),
-                       "energy_err_vs_fp64_eV_per_atom": r.get("energy_err_per_atom"),
-                       "phase_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in r["phases"].items()},
-                       "reorth_second_passes": r["stats"]["reorth_second_pass"],
-                       "reorth_steps_per_atom": round(r["stats"]["reorth_steps"] / N, 2),
-                       "lanczos_basis_bytes_per_launch": r["stats"]["basis_bytes"],
-                       "pressure_GPa_last_step": round(r["pressure_GPa"], 4)}
-        if prec in shapes:
-            extra[prec]["launch_shape"] = shapes[prec]
+        extra[prec] = mode_record(r, N, shapes, prec)
         if "graph" in r:
             g = r["graph"]
             extra[prec]["graph_ms_per_step"] = round(1e3 * g["seconds"] / args.steps, 3)
             extra[prec]["graph_steps_per_s"] = round(args.steps / g["seconds"], 3)
     if plain is not None:
         extra["plain_fp64_one_launch_per_atom"] = {
+            "note": "launch-bound: every per-atom phase launched once per atom (one workgroup each); "
+                    "not the denominator of the speed-up target",
             "steps": args.plain_steps, "steps_per_s": round(plain["steps_per_s"], 5),
             "ms_per_step": round(plain["ms_per_step"], 1),
             "phase_ms_per_step": {k: round(v[0] / args.plain_steps, 1) for k, v in plain["phases"].items()}}
@@ -342,8 +421,17 @@ def main():
     }
     if head_prec != "fp64" and "fp64" in results:
         line["mixed_over_fp64"] = round(head["steps_per_s"] / results["fp64"]["steps_per_s"], 3)
-    if plain is not None:
-        line["headline_over_plain_fp64"] = round(head["steps_per_s"] / plain["steps_per_s"], 1)
+    if large is not None:
+        line[args.large_workload] = large
+        ratio = large.get("mixed_over_fp64")
+        line["target"] = {"what": f"mixed batched >= 5x the FP64 GPU path's MD steps/s at {large['n_atoms']} "
+                                  "atoms, force error <= 1e-3 eV/A",
+                          "denominator": "batched FP64 path (the same persistent kernels in FP64)",
+                          "ratio": ratio, "force_err_eV_per_A": large.get("force_err_vs_fp64_eV_per_A"),
+                          "met": bool(ratio is not None and ratio >= 5.0
+                                      and large.get("force_err_vs_fp64_eV_per_A", 1.0) <= 1e-3)}
+    if hist is not None:
+        line["sphere_histogram_" + args.histogram_workload] = hist
     print(json.dumps(line))
 
 

@@ -59,10 +59,12 @@ enum {
  *   TB_FP64  everything in FP64.
  *   TB_FP32  H.V, basis, three-term update and passes in FP32 (norms and
  *            Gram sums accumulated in FP64).
- *   TB_BF16  as TB_FP32, but the operands of H.V (coupling data, on-site and
- *            bond parameters, V_k) are rounded to BF16 and the products
- *            accumulated in FP32; the orthogonality estimate then asks for a
- *            re-orthogonalisation pass at every block step. */
+ *   TB_BF16  as TB_FP32, but the V_k operand of H.V is rounded to BF16 (the
+ *            Hamiltonian -- on-site and bond parameters, pair data -- stays
+ *            FP32) and the products accumulated in FP32; the orthogonality
+ *            estimate then asks for a re-orthogonalisation pass at every
+ *            block step. Its force error is far above 1e-3 eV/A: measured,
+ *            not a production mode. */
 enum { TB_FP64 = 0, TB_FP32 = 1, TB_BF16 = 2 };
 
 /* Tight-binding parameters of the Xu-form carbon model (Sec. 4 names the
@@ -82,11 +84,20 @@ typedef struct {
 typedef struct tb_ctx tb_ctx;
 
 /* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`
- * (a hipStream_t, or NULL for the default stream). Capacities: at most
- * n_atoms_max atoms, n_cluster_max atoms per cutoff sphere, r_max Krylov
- * block steps; hop lists hold at most 24 neighbours within max(rm, dm)
- * (tb_create_ex sets another capacity).
- * Allocates all work memory (size reported by tb_get_stats). */
+ * (a hipStream_t, or NULL for the default stream). The capacities are the
+ * sizes of the paper's problem: at most n_atoms_max atoms (N, Sec. 2),
+ * n_cluster_max atoms per cutoff sphere (n, the sphere of the locality
+ * argument of Sec. 2 whose cost is O(n^3 N)), r_max Krylov block steps (the
+ * order r of K_r in Sec. 3, Eq. 4); hop lists hold at most 24 neighbours
+ * within max(rm, dm) (the 2.6 A hopping range of Xu's parameters, Sec. 4;
+ * tb_create_ex sets another capacity). The context owns every work buffer
+ * sized from these; *ctx receives it (NULL on error).
+ * Allocates all work memory (size reported by tb_get_stats) and synchronises
+ * the device once; no later call allocates device memory.
+ * Errors: TB_EINVAL (null ctx pointer, a capacity outside its range: n_atoms_max
+ * in [1, 2^24], n_cluster_max in [1, 2047], r_max in [1, 256], or no such
+ * device), TB_ECAPACITY (a sphere of n_cluster_max atoms or r_max steps do
+ * not fit a compute unit's LDS), TB_EHIP (allocation failed). */
 int tb_create(tb_ctx **ctx, int hip_device, void *hip_stream,
               int64_t n_atoms_max, int n_cluster_max, int r_max);
 
@@ -100,6 +111,10 @@ int tb_create(tb_ctx **ctx, int hip_device, void *hip_stream,
 int tb_create_ex(tb_ctx **ctx, int hip_device, void *hip_stream,
                  int64_t n_atoms_max, int n_cluster_max, int r_max, int hop_max);
 
+/* Release a context and all its work memory (the buffers of the problem of
+ * Secs. 2-3 that tb_create sized). Waits for nothing: the caller must have
+ * synchronised the context's stream first, since enqueued kernels still read
+ * the work buffers. NULL is accepted (no-op). Returns TB_OK. */
 int tb_destroy(tb_ctx *ctx);
 
 /* Sec. 2 locality + Eq. (1): minimum-image neighbour lists, cutoff spheres
@@ -144,11 +159,17 @@ int tb_krylov_rho(tb_ctx *ctx, int r, const int *r_per_atom, double kT,
                   double mu, double n_electrons, int precision,
                   double *mu_out, double *rho_out);
 
-/* Pair list of rho_out: for target atom i, the rows row_ptr[i] ..
- * row_ptr[i+1]-1 hold j = i first, then the atoms closer than max(rm, dm)
- * to i (the hop list) in increasing index. nnz_pairs_host receives the count (host). row_ptr
- * [n_atoms+1] and col_j [nnz] are device arrays (nullable: count only).
- * Synchronises the stream. Valid after tb_build_local_H. */
+/* Pair list of rho_out. The density matrix of Eq. (2) is needed only on the
+ * sparsity pattern of H (Eq. 1), because the forces Tr[rho F_i] of Sec. 2
+ * contract it with dH/dR, which vanishes beyond the hopping range: for target
+ * atom i (the column block rho_{., i} of its Krylov solve), the rows row_ptr[i]
+ * .. row_ptr[i+1]-1 hold j = i first, then the atoms closer than max(rm, dm)
+ * to i (the hop list) in increasing index. nnz_pairs_host receives the count
+ * (host, required). row_ptr [n_atoms+1] (int64) and col_j [nnz] are device
+ * arrays owned by the caller (nullable: count only).
+ * Synchronises the stream. Valid after tb_build_local_H.
+ * Errors: TB_EINVAL (null ctx or nnz_pairs_host), TB_ESTATE (no
+ * tb_build_local_H yet), TB_EHIP. */
 int tb_rho_layout(tb_ctx *ctx, int64_t *nnz_pairs_host, int64_t *row_ptr,
                   int *col_j);
 
@@ -159,9 +180,24 @@ int tb_rho_layout(tb_ctx *ctx, int64_t *nnz_pairs_host, int64_t *row_ptr,
  *   E_rep  = sum_i F(sum_j phi(r_ij)),
  *   F_k    = -sum_i sum_{j in hop(i)} Tr[(dH_ij/dR_k) rho_ji] - dE_rep/dR_k.
  *   e_out  [4] device: E_band, -TS, E_rep, E_tot = E_band - TS + E_rep (eV).
- *   forces [n_atoms][3] device, eV/Angstrom (nullable).
- * Errors: TB_ESTATE, TB_EHIP. */
+ *   forces [n_atoms][3] device, eV/Angstrom (nullable: energies only, and the
+ *          force and virial contraction is not run; tb_virial then refuses).
+ * Errors: TB_EINVAL (null ctx or e_out), TB_ESTATE, TB_EHIP. */
 int tb_energy_forces(tb_ctx *ctx, double *e_out, double *forces);
+
+/* Backward of the total energy E_tot = E_band - TS + E_rep of the last
+ * tb_krylov_rho (Sec. 2: the force on an atom is Tr[rho F_i] with
+ * F_i = -dH/dR_i, plus the repulsive term): with g = *grad_e (a device
+ * scalar, the gradient flowing into E_tot),
+ *   grad_pos[k] = -g * F_k,  F_k = -sum_i sum_{j in hop(i)} Tr[(dH_ij/dR_k) rho_ji] - dE_rep/dR_k,
+ * the force contraction of tb_energy_forces scaled by g in the same kernel.
+ * At finite r and cutoff F is the method's force, not the exact gradient of
+ * E_tot (the local density matrix is not variational).
+ *   grad_e   device double (the upstream gradient).
+ *   grad_pos [n_atoms][3] device, eV/Angstrom times the unit of g.
+ * Also refreshes the virial (tb_virial). Enqueued on the stream.
+ * Errors: TB_EINVAL (null pointer), TB_ESTATE (no tb_krylov_rho yet). */
+int tb_energy_backward(tb_ctx *ctx, const double *grad_e, double *grad_pos);
 
 /* Virial of the last tb_energy_forces (Sec. 5 times the pressure of a diamond
  * cell; Sec. 4 compresses the C60 crystal). With d_ij = R_j - R_i (minimum
@@ -284,7 +320,11 @@ int tb_get_stats(tb_ctx *ctx, int64_t *stats_host, int n_stats);
 int tb_profile_enable(tb_ctx *ctx, int enable);
 int tb_profile_read(tb_ctx *ctx, double *ms_host, int64_t *count_host, int n);
 
-/* Message for the last nonzero status on this thread. */
+/* Message for the last nonzero status returned on the calling thread: which
+ * argument or capacity of the problem statement (Secs. 2-3: positions, cell,
+ * parameters, cutoff, Krylov order, chemical potential or electron count) was
+ * refused, or the HIP runtime's error text. The string is owned by the
+ * library and stays valid until the thread's next failing call. Never fails. */
 const char *tb_last_error(void);
 
 #ifdef __cplusplus

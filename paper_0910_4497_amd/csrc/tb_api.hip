@@ -75,8 +75,8 @@ extern "C" int tb_destroy(tb_ctx* c) {
   void* ptrs[] = {c->hop_n, c->hop_j, c->hop_rev, c->hop_d, c->pair64, c->pair32, c->clu_n, c->clu_j,
                   c->loc_off, c->loc_ent, c->hnorm, c->jloc, c->row_ptr, c->col_j, c->vbuf, c->tab,
                   c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->rot_cs, c->rot_p,
-                  c->rot_n, c->seg, c->seg_n, c->evec, c->tri, c->eig_scratch, c->omega, c->mu_state, c->partial, c->counter, c->xrep, c->eparts, c->stats,
-                  c->pair16, c->cell_of, c->cell_atoms, c->cell_cnt, c->cell_start, c->wpart, c->virial, c->vsc};
+                  c->rot_n, c->seg, c->seg_n, c->evec, c->tri, c->eig_scratch, c->omega, c->mu_state, c->partial, c->xrep, c->eparts, c->stats,
+                  c->cell_of, c->cell_atoms, c->cell_cnt, c->cell_start, c->wpart, c->virial, c->vsc};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (c->ev_pool) {
@@ -173,7 +173,6 @@ extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int6
   ALLOC(hop_d, N * Z * 4);
   ALLOC(pair64, N * Z * 4);
   ALLOC(pair32, N * Z * 4);
-  ALLOC(pair16, N * Z * 4);
   ALLOC(cell_of, N);
   ALLOC(cell_atoms, N);
   ALLOC(cell_cnt, (int64_t)NCELL_AXIS_MAX * NCELL_AXIS_MAX * NCELL_AXIS_MAX);
@@ -202,9 +201,8 @@ extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int6
   ALLOC(vsc, N * dmax);
   ALLOC(tri, N * 2 * dmax);
   ALLOC(eig_scratch, n_wg_eig_max * dmax * 4 * eig_threads(r_max));
-  ALLOC(mu_state, 16);
-  ALLOC(partial, 16384);             // [blocks][points] of the mu reductions
-  ALLOC(counter, 16);
+  ALLOC(mu_state, mu_state_doubles());
+  ALLOC(partial, mu_partial_doubles());   // [region][blocks][points] of the mu reductions
   ALLOC(xrep, 2 * N);
   ALLOC(eparts, 8);
   ALLOC(wpart, ((N + 63) / 64) * 9);          // blocks of k_forces (64 atoms each)
@@ -226,9 +224,8 @@ extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int6
     tb_destroy(c);
     return fail(TB_EHIP, "work allocation of %zu B failed: %s", c->bytes, hipGetErrorString(a));
   }
-  HIP_TRY(hipMemset(c->counter, 0, 16 * sizeof(unsigned int)));
   HIP_TRY(hipMemset(c->stats, 0, ST_NSTATS * sizeof(int64_t)));
-  HIP_TRY(hipMemset(c->mu_state, 0, 16 * sizeof(double)));
+  HIP_TRY(hipMemset(c->mu_state, 0, mu_state_doubles() * sizeof(double)));
   HIP_TRY(hipMemset(c->kused, 0, N * sizeof(int)));
   HIP_TRY(hipMemset(c->rot_n, 0, N * sizeof(int)));
   HIP_TRY(hipMemset(c->seg_n, 0, 2 * N * sizeof(int)));
@@ -324,8 +321,7 @@ static LanczosArgs lanczos_args(const tb_ctx* c, int n, int r, const int* r_per_
   la.clu_n = c->clu_n; la.clu_j = c->clu_j; la.loc_off = c->loc_off; la.loc_ent = c->loc_ent;
   la.zmax = c->zmax;
   la.hnorm = c->hnorm; la.jloc = c->jloc; la.hop_n = c->hop_n;
-  la.pair = precision == TB_BF16 ? (const void*)c->pair16
-          : (fp32 ? (const void*)c->pair32 : (const void*)c->pair64);
+  la.pair = fp32 ? (const void*)c->pair32 : (const void*)c->pair64;
   la.nc_max = c->nc_max; la.emax = c->emax; la.r_max = c->r_max;
   la.eps_s = c->model.eps_s; la.eps_p = c->model.eps_p; la.v_sss = c->model.v_sss;
   la.v_sps = c->model.v_sps; la.v_pps = c->model.v_pps; la.v_ppp = c->model.v_ppp;
@@ -414,7 +410,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   MuArgs ma;
   ma.n_pairs = (int64_t)n * 4 * c->r_max;
   ma.lam = c->lam; ma.wgt = c->wgt; ma.kT = kT; ma.n_e = n_electrons;
-  ma.state = c->mu_state; ma.partial = c->partial; ma.counter = c->counter;
+  ma.state = c->mu_state; ma.partial = c->partial;
   ma.eparts = c->eparts; ma.mu_out = mu_out;
   pk = prof_begin(c, 3);
   launch_mu(ma, mu, fixed, MU_ITERS, st);
@@ -558,19 +554,40 @@ extern "C" int tb_rho_layout(tb_ctx* c, int64_t* nnz_pairs_host, int64_t* row_pt
   return TB_OK;
 }
 
+static ForceArgs force_args(const tb_ctx* c) {
+  ForceArgs fa;
+  fa.n_atoms = (int)c->n_atoms; fa.zmax = c->zmax; fa.M = c->model;
+  fa.hop_n = c->hop_n; fa.hop_j = c->hop_j; fa.hop_rev = c->hop_rev; fa.hop_d = c->hop_d;
+  fa.row_ptr = c->row_ptr; fa.rho = c->rho_last; fa.xrep = c->xrep; fa.forces = nullptr;
+  fa.grad_scale = nullptr; fa.eparts = c->eparts; fa.kT = c->kT; fa.e_out = nullptr;
+  fa.wpart = c->wpart; fa.virial = c->virial;
+  return fa;
+}
+
 extern "C" int tb_energy_forces(tb_ctx* c, double* e_out, double* forces) {
   if (!c) return fail(TB_EINVAL, "ctx is null");
   if (c->stage < 2) return fail(TB_ESTATE, "tb_krylov_rho must be called first");
   if (!e_out) return fail(TB_EINVAL, "e_out is null");
   HIP_TRY(hipSetDevice(c->device));
-  ForceArgs fa;
-  fa.n_atoms = (int)c->n_atoms; fa.zmax = c->zmax; fa.M = c->model;
-  fa.hop_n = c->hop_n; fa.hop_j = c->hop_j; fa.hop_rev = c->hop_rev; fa.hop_d = c->hop_d;
-  fa.row_ptr = c->row_ptr; fa.rho = c->rho_last; fa.xrep = c->xrep; fa.forces = forces;
-  fa.eparts = c->eparts; fa.kT = c->kT; fa.e_out = e_out;
-  fa.wpart = c->wpart; fa.virial = c->virial;
+  ForceArgs fa = force_args(c);
+  fa.forces = forces; fa.e_out = e_out;
   const int pk = prof_begin(c, 5);
-  launch_forces(fa, c->stream);
+  launch_forces(fa, forces != nullptr, c->stream);
+  prof_end(c, pk);
+  HIP_TRY(hipGetLastError());
+  c->have_virial = forces != nullptr;
+  return TB_OK;
+}
+
+extern "C" int tb_energy_backward(tb_ctx* c, const double* grad_e, double* grad_pos) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (!grad_e || !grad_pos) return fail(TB_EINVAL, "grad_e and grad_pos must not be null");
+  if (c->stage < 2) return fail(TB_ESTATE, "tb_krylov_rho must be called first");
+  HIP_TRY(hipSetDevice(c->device));
+  ForceArgs fa = force_args(c);
+  fa.forces = grad_pos; fa.grad_scale = grad_e;
+  const int pk = prof_begin(c, 5);
+  launch_forces(fa, true, c->stream);
   prof_end(c, pk);
   HIP_TRY(hipGetLastError());
   c->have_virial = 1;

@@ -121,9 +121,11 @@ __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
     F[c] += __shfl_xor(F[c], 2, 64);
   }
   if (k < g.n_atoms && q4 == 0 && g.forces) {
-    g.forces[3 * k] = F[0];
-    g.forces[3 * k + 1] = F[1];
-    g.forces[3 * k + 2] = F[2];
+    // backward of E_tot: grad_pos = -g F with the upstream gradient g
+    const double sc = g.grad_scale ? -*g.grad_scale : 1.0;
+    g.forces[3 * k] = sc * F[0];
+    g.forces[3 * k + 1] = sc * F[1];
+    g.forces[3 * k + 2] = sc * F[2];
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) W[q] = wave_sum(W[q]);
@@ -140,10 +142,10 @@ __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
 }
 
 // Single block: fixed-order sums of the per-atom repulsive energies and of
-// the per-block virials, then the energy record.
-__global__ void __launch_bounds__(F_NT) k_energy(ForceArgs g) {
+// the per-block virials (when k_forces ran), then the energy record.
+__global__ void __launch_bounds__(F_NT) k_energy(ForceArgs g, int with_virial) {
   __shared__ double red[F_NT / 64];
-  if (threadIdx.x < 9) {                    // virial: blocks in a fixed order
+  if (with_virial && threadIdx.x < 9) {     // virial: blocks in a fixed order
     const int nb = (g.n_atoms + F_APB - 1) / F_APB;
     double t = 0.0;
     for (int b = 0; b < nb; ++b) t += g.wpart[(size_t)b * 9 + threadIdx.x];
@@ -154,7 +156,7 @@ __global__ void __launch_bounds__(F_NT) k_energy(ForceArgs g) {
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && g.e_out) {
     double e = 0.0;
     for (int w = 0; w < F_NT / 64; ++w) e += red[w];
     const double eb = g.eparts[0], ts = -g.kT * g.eparts[1];
@@ -166,11 +168,12 @@ __global__ void __launch_bounds__(F_NT) k_energy(ForceArgs g) {
   }
 }
 
-void launch_forces(const ForceArgs& a, hipStream_t st) {
+void launch_forces(const ForceArgs& a, bool with_forces, hipStream_t st) {
   const int nb = (a.n_atoms + F_NT - 1) / F_NT;
   hipLaunchKernelGGL(k_rep_x, dim3(nb), dim3(F_NT), 0, st, a);
-  hipLaunchKernelGGL(k_forces, dim3((a.n_atoms + F_APB - 1) / F_APB), dim3(F_NT), 0, st, a);
-  hipLaunchKernelGGL(k_energy, dim3(1), dim3(F_NT), 0, st, a);
+  if (with_forces)
+    hipLaunchKernelGGL(k_forces, dim3((a.n_atoms + F_APB - 1) / F_APB), dim3(F_NT), 0, st, a);
+  hipLaunchKernelGGL(k_energy, dim3(1), dim3(F_NT), 0, st, a, with_forces ? 1 : 0);
 }
 
 __global__ void k_copy9(const double* __restrict__ src, double* __restrict__ dst) {

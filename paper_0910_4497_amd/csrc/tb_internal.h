@@ -12,15 +12,8 @@ struct tb_ctx;
 
 namespace tbk {
 
-// BF16 (8 significand bits) by round-to-nearest-even of an FP32 value; the
-// values here are finite. bf16_bits: the upper 16 bits; bf16_round: the
-// rounded value as FP32.
-__host__ __device__ inline uint16_t bf16_bits(float x) {
-  unsigned u;
-  memcpy(&u, &x, 4);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// BF16 (8 significand bits) by round-to-nearest-even of a finite FP32 value,
+// returned as FP32.
 __device__ __forceinline__ float bf16_round(float x) {
   unsigned u = __float_as_uint(x);
   u += 0x7fffu + ((u >> 16) & 1u);
@@ -238,10 +231,13 @@ struct MuArgs {
   int64_t n_pairs;             // atoms * 4 r_max (padding has w = 0)
   const double* lam; const double* wgt;
   double kT, n_e;
-  double* state; double* partial; unsigned int* counter;
+  double* state;               // [mu_state_doubles()]: [2] the final mu, then two bracket states
+  double* partial;             // [mu_partial_doubles()]: per-block partial sums, three regions
   double* eparts; double* mu_out;
 };
 int mu_blocks(int64_t n_pairs);
+size_t mu_partial_doubles();
+size_t mu_state_doubles();
 void launch_mu(const MuArgs& a, double mu_fixed, bool fixed, int n_iter, hipStream_t st);
 
 struct ForceArgs {
@@ -252,12 +248,13 @@ struct ForceArgs {
   const double* rho;          // [pairs][4][4]: rho[p][a][b] = rho_{j a, i b}
   double* xrep;               // [N][2]: F'(x_i), F(x_i)
   double* forces;             // [N][3] (nullable)
+  const double* grad_scale;   // nullable: forces receive -(*grad_scale) F (the backward of E_tot)
   double* eparts; double kT;
-  double* e_out;
+  double* e_out;              // [4] (nullable in the backward)
   double* wpart;              // [blocks][9] per-block virial sums
   double* virial;             // [9] W[a][b] = sum over ordered pairs of d_a g_b
 };
-void launch_forces(const ForceArgs& a, hipStream_t st);
+void launch_forces(const ForceArgs& a, bool with_forces, hipStream_t st);
 void launch_virial_copy(const double* src, double* dst, hipStream_t st);
 
 // K1-K3 and the rho pair layout for the geometry in pos (device).
@@ -300,7 +297,6 @@ struct tb_ctx {
   int zmax;                                                // hop-list capacity
   int* hop_n; int* hop_j; int* hop_rev; double* hop_d;     // [N][zmax][4]: dx dy dz r
   double* pair64; float* pair32;                           // [N][zmax][4]: hx hy hz s
-  uint16_t* pair16;                                        // [N][zmax][4]: the same in BF16
   int* clu_n; int* clu_j;                                  // [N][NC]
   int* cell_of; int* cell_atoms;                           // [N]: cell of each atom, atoms by cell
   int* cell_cnt; int* cell_start;                          // [CELLS], [CELLS + 1]
@@ -325,9 +321,8 @@ struct tb_ctx {
   double* tri;                                             // [N][2][D]
   double* eig_scratch;                                     // [WG_EIG][D][4][EIG_NT]
   // mu / energies (K6/K8)
-  double* mu_state;      // [8]: lo, hi, mu, done, N(mu) ...
-  double* partial;       // [NPART][4]
-  unsigned int* counter; // last-block counters
+  double* mu_state;      // [2]: mu; [16..47]: two multisection states
+  double* partial;       // per-block partial sums of the mu reductions
   double* xrep;          // [N]: sum_j phi, then F'(x)
   double* eparts;        // [4] band, entropy, rep, count
   double* wpart;         // [ceil(N/64)][9] per-block virial sums

@@ -135,9 +135,10 @@ __device__ __forceinline__ void inv_upper4r(const double (&U)[16], const bool (&
 // LZ_NT threads per workgroup; MINW waves per SIMD the register allocation
 // must allow (4: 128 VGPRs, some spilled; 3: 168, with 256 threads, fewer
 // spilled; 2: 256 VGPRs, none spilled in FP32). BF
-// (with VT = float): the operands of H.V -- the coupling data, the on-site and
-// bond parameters, and V_k -- are rounded to BF16 and the products
-// accumulated in FP32; everything else is the FP32 recursion. WIDE (FP32,
+// (with VT = float): the V_k operand of H.V is rounded to BF16 and the
+// products with the FP32 Hamiltonian (unrounded on-site and bond parameters
+// and pair data) accumulated in FP32; everything else is the FP32
+// recursion. WIDE (FP32,
 // not BF): the H.V items of the FP64 kernel (each lane all four columns of
 // every fourth coupling, then a reduce-scatter over the four lanes), which
 // loads each coupling's entry, pair data and V_k rows once instead of once
@@ -240,11 +241,11 @@ k_lanczos(LanczosArgs g) {
       // ---- 1. W = H V_k, fused with the partial sums of A_k = V_k^T W
       {
         double accA[4] = {0.0, 0.0, 0.0, 0.0};     // A[c'][cq], c' = 0..3
-        auto op = [](VT x) -> VT {                 // an operand of the H.V products
+        auto op = [](VT x) -> VT {                 // the V_k operand of the H.V products
           if constexpr (BF) return bf16_round(x); else return x;
         };
-        const VT es = op((VT)g.eps_s), ep = op((VT)g.eps_p), vsss = op((VT)g.v_sss), vsps = op((VT)g.v_sps),
-                 vdif = op((VT)(g.v_pps - g.v_ppp)), vppp = op((VT)g.v_ppp);
+        const VT es = (VT)g.eps_s, ep = (VT)g.eps_p, vsss = (VT)g.v_sss, vsps = (VT)g.v_sps,
+                 vdif = (VT)(g.v_pps - g.v_ppp), vppp = (VT)g.v_ppp;
         typedef typename Vec4<VT>::T V4;
         // FP64: item (a, part) -- the four lanes of atom a take every fourth
         // coupling and compute all four columns, then a reduce-scatter over the
@@ -334,14 +335,7 @@ k_lanczos(LanczosArgs g) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const int slot = pe[u] >> LOCAL_BITS;
-              if constexpr (BF) {
-                // four BF16 values (x, y, z, s) -> FP32, exactly
-                const uint2 raw = *(const uint2*)((const uint16_t*)g.pair + ((size_t)gid * g.zmax + slot) * 4);
-                hp4[u].x = __uint_as_float(raw.x << 16); hp4[u].y = __uint_as_float(raw.x & 0xffff0000u);
-                hp4[u].z = __uint_as_float(raw.y << 16); hp4[u].w = __uint_as_float(raw.y & 0xffff0000u);
-              } else {
-                hp4[u] = *(const V4*)(pairs + ((size_t)gid * g.zmax + slot) * 4);
-              }
+              hp4[u] = *(const V4*)(pairs + ((size_t)gid * g.zmax + slot) * 4);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) pn[u] = (e0 + 4 + u < e1) ? ent[e0 + 4 + u] : 0u;

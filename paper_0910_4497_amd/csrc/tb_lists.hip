@@ -14,7 +14,7 @@
 //                the union of the members' spheres (sort + unique in LDS)
 //                replaces each member's sphere, the member first.
 //   k_pairs      per ordered pair: direction cosines h = d/|d| and the hopping
-//                scale s(|d|) (FP64, FP32 and BF16 copies), and the reverse slot.
+//                scale s(|d|) (FP64 and FP32 copies), and the reverse slot.
 //   k_local      one workgroup per sphere: local couplings (a -> b, slot) with
 //                the cluster-frame rule |x_b - x_a| < rm, x = position
 //                relative to the target; Frobenius norm of the local H; the
@@ -272,8 +272,7 @@ k_union(int n, int m, const double* __restrict__ pos, Box box, double r_cluster,
 
 __global__ void k_pairs(int n, int zmax, Model M, const int* __restrict__ hop_n, const int* __restrict__ hop_j,
                         const double* __restrict__ hop_d, double* __restrict__ pair64,
-                        float* __restrict__ pair32, uint16_t* __restrict__ pair16,
-                        int* __restrict__ hop_rev) {
+                        float* __restrict__ pair32, int* __restrict__ hop_rev) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (int64_t)n * zmax) return;
   const int i = (int)(q / zmax), slot = (int)(q % zmax);
@@ -292,8 +291,6 @@ __global__ void k_pairs(int n, int zmax, Model M, const int* __restrict__ hop_n,
   pair64[4 * q] = hx; pair64[4 * q + 1] = hy; pair64[4 * q + 2] = hz; pair64[4 * q + 3] = s;
   pair32[4 * q] = (float)hx; pair32[4 * q + 1] = (float)hy; pair32[4 * q + 2] = (float)hz;
   pair32[4 * q + 3] = (float)s;
-  pair16[4 * q] = bf16_bits((float)hx); pair16[4 * q + 1] = bf16_bits((float)hy);
-  pair16[4 * q + 2] = bf16_bits((float)hz); pair16[4 * q + 3] = bf16_bits((float)s);
   hop_rev[q] = rev;
 }
 
@@ -504,7 +501,7 @@ void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st) {
   }
   const int64_t np = (int64_t)n * c->zmax;
   hipLaunchKernelGGL(k_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, n, c->zmax, c->model, c->hop_n,
-                     c->hop_j, c->hop_d, c->pair64, c->pair32, c->pair16, c->hop_rev);
+                     c->hop_j, c->hop_d, c->pair64, c->pair32, c->hop_rev);
   const size_t lds_local = (size_t)c->nc_max * (4 + 4 + 24) + 64;
   hipLaunchKernelGGL(k_local, dim3(n), dim3(LIST_NT), lds_local, st, n, c->model, pos, c->box, c->nc_max,
                      c->zmax, c->emax, c->hop_n, c->hop_j, c->hop_d, c->pair64, c->clu_n, c->clu_j, c->loc_off,

@@ -2,20 +2,28 @@
 // occupation f of the density matrix; one mu for the whole system).
 //
 //   N(mu) = sum_i sum_m f(lambda_m^i) w_m^i,  f(e) = 2 / (1 + exp((e - mu)/kT)),
-// solved for N(mu) = N_e. N is increasing in mu; every launch of k_mu_iter
+// solved for N(mu) = N_e. N is increasing in mu; every multisection step
 // evaluates N at 31 points of the bracket [lo, hi] and keeps the tightest
-// bracket they give. The first launch splits it into 32 equal parts; later
-// launches place 24 points evenly (25 parts: 4.6 bits whatever happens) and 7
+// bracket they give. The first step splits it into 32 equal parts; later
+// steps place 24 points evenly (25 parts: 4.6 bits whatever happens) and 7
 // around the root of the straight line through (lo, N(lo)) and (hi, N(hi)),
 // at offsets 0, +-2^-20, +-2^-12 and +-2^-4 of the bracket width. Once the
 // bracket is narrow against kT, N is nearly linear on it and the new bracket
-// is the gap between two of those points (12 to 20 bits per launch): about 7
-// launches reach rounding level where plain multisection takes 12, and 13
-// launches cover 60 bits in any case. A fixed number
-// of launches is enqueued; once the bracket has collapsed to rounding level,
-// later launches return at once, so the sequence is capturable in a graph. Reductions are two-level and in a
-// fixed order (per-block partials summed by the last block to finish), so
-// the result is bitwise reproducible run to run.
+// is the gap between two of those points (12 to 20 bits per step): about 7
+// steps reach rounding level where plain multisection takes 12, and 13 steps
+// cover 60 bits in any case.
+//
+// Workgroups exchange data only across kernel boundaries. Launch q writes
+// its per-block partial sums to one of two partial buffers; launch q + 1
+// reads them, and every one of its blocks reduces them in the same fixed
+// order (thread t takes block t, then the wave and workgroup reductions),
+// so all blocks hold the same totals bit for bit and update the same bracket
+// (block 0 also stores it, in the other of two state buffers, for launch
+// q + 2 to read). No block reads what another block of the same launch
+// writes: no tickets, counters or fences are involved, and the result is
+// bitwise reproducible run to run. A fixed number of launches is enqueued;
+// once the bracket has collapsed to rounding level later launches return at
+// once, so the sequence is capturable in a graph.
 #include <float.h>
 
 #include "tb_internal.h"
@@ -26,20 +34,20 @@ constexpr int MU_NT = 256;
 constexpr int MU_NB = 256;         // blocks of the reduction kernels (timed: 128, 256, 512)
 constexpr int MU_P = 31;           // points per multisection step
 constexpr int MU_U = 24;           // of which evenly spaced after the first step
+constexpr int MU_PS = 32;          // partial-buffer stride per block (doubles)
+static_assert(MU_NB <= MU_NT, "one block's partials per reducing thread");
 
-enum { MS_LO = 0, MS_HI = 1, MS_MU = 2, MS_DONE = 3, MS_N = 4, MS_STEP = 5, MS_IT = 6, MS_NLO = 7, MS_NHI = 8 };
+// State buffer (16 doubles each; two alternate between launches).
+enum { MS_LO = 0, MS_HI = 1, MS_DONE = 3, MS_IT = 6, MS_NLO = 7, MS_NHI = 8 };
+// Slots of the mu_state array: two state buffers behind the final mu.
+constexpr int MU_FINAL = 2;        // the chemical potential the density matrix uses
+constexpr int MU_STATE0 = 16;      // state buffers at 16 and 32
 
-
-// Sum M values over the grid. Every block stores its M block sums (fixed
-// order: waves, then the waves' results) in partial[block][M]; the last block
-// to finish sums the blocks in a fixed tree (thread t takes blocks t, t +
-// MU_NT, ..., then the wave and workgroup reductions) and returns true with
-// the totals in tot[0..M-1] (shared memory of that block). OP 0 sums, OP 1
-// takes minima.
+// Per-block sums of M values over the workgroup (waves in order, then the
+// waves' results): the totals land in out[0..M-1] (shared memory).
 template <int M, int OP>
-__device__ bool grid_reduce(double (&v)[M], double* partial, unsigned int* counter, double* tot) {
+__device__ void block_reduce(double (&v)[M], double* out) {
   __shared__ double red[MU_NT / 64][M];
-  __shared__ bool last;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   auto comb = [](double a, double b) { return OP == 0 ? a + b : fmin(a, b); };
   const double ident = OP == 0 ? 0.0 : 1e300;
@@ -53,63 +61,35 @@ __device__ bool grid_reduce(double (&v)[M], double* partial, unsigned int* count
   if (tid < M) {
     double sm = ident;
     for (int w = 0; w < MU_NT / 64; ++w) sm = comb(sm, red[w][tid]);
-    partial[(size_t)blockIdx.x * M + tid] = sm;
-    __threadfence();
+    out[tid] = sm;
   }
   __syncthreads();
-  if (tid == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
+}
+
+// This block's M sums to partial[block][0..M-1].
+template <int M, int OP>
+__device__ void store_partials(double (&v)[M], double* partial) {
+  __shared__ double tot[M];
+  block_reduce<M, OP>(v, tot);
+  if (threadIdx.x < M) partial[(size_t)blockIdx.x * MU_PS + threadIdx.x] = tot[threadIdx.x];
+}
+
+// Totals over the nb blocks of the previous launch: thread t takes block t,
+// then the wave and workgroup reductions (the same order in every block).
+template <int M, int OP>
+__device__ void reduce_partials(const double* partial, int nb, double* out) {
   double acc[M];
 #pragma unroll
-  for (int q = 0; q < M; ++q) acc[q] = ident;
-  for (unsigned int bk = tid; bk < gridDim.x; bk += MU_NT)
+  for (int q = 0; q < M; ++q) acc[q] = OP == 0 ? 0.0 : 1e300;
+  if ((int)threadIdx.x < nb) {
+    const double* src = partial + (size_t)threadIdx.x * MU_PS;
 #pragma unroll
-    for (int q = 0; q < M; ++q) acc[q] = comb(acc[q], partial[(size_t)bk * M + q]);
-#pragma unroll
-  for (int q = 0; q < M; ++q)
-    for (int off = 32; off > 0; off >>= 1) acc[q] = comb(acc[q], __shfl_xor(acc[q], off, 64));
-  if (lane == 0)
-#pragma unroll
-    for (int q = 0; q < M; ++q) red[wave][q] = acc[q];
-  __syncthreads();
-  if (tid < M) {
-    double sm = ident;
-    for (int w = 0; w < MU_NT / 64; ++w) sm = comb(sm, red[w][tid]);
-    tot[tid] = sm;
+    for (int q = 0; q < M; ++q) acc[q] = src[q];
   }
-  if (tid == 0) *counter = 0u;
-  __syncthreads();
-  return true;
+  block_reduce<M, OP>(acc, out);
 }
 
-__global__ void __launch_bounds__(MU_NT) k_mu_bracket(MuArgs g, double mu_fixed, int fixed) {
-  double v[2] = {1e300, 1e300};        // min lambda, -max lambda
-  for (int64_t q = (int64_t)blockIdx.x * MU_NT + threadIdx.x; q < g.n_pairs; q += (int64_t)gridDim.x * MU_NT) {
-    const double l = g.lam[q];
-    v[0] = fmin(v[0], l);
-    v[1] = fmin(v[1], -l);
-  }
-  __shared__ double tot[2];
-  if (grid_reduce<2, 1>(v, g.partial, g.counter, tot) && threadIdx.x == 0) {
-    double* s = g.state;
-    s[MS_LO] = tot[0] - 50.0 * g.kT;
-    s[MS_HI] = -tot[1] + 50.0 * g.kT;
-    s[MS_MU] = fixed ? mu_fixed : 0.5 * (s[MS_LO] + s[MS_HI]);
-    s[MS_DONE] = fixed ? 1.0 : 0.0;
-    s[MS_STEP] = s[MS_HI] - s[MS_LO];
-    s[MS_IT] = 0.0;
-    s[MS_NLO] = 0.0; s[MS_NHI] = 0.0;        // N at lo and hi: known after the first step
-  }
-}
-
-// One multisection step: N(mu) at MU_P points of [lo, hi] (mu_point); the
-// bracket becomes the tightest one among them: lo' the largest point with
-// N < N_e, hi' the smallest with N >= N_e (N at a point equal to N_e exactly
-// ends the search there). Sums are per block in a fixed order, then per point
-// over the blocks in a fixed order by the last block, so the result is
-// reproducible bit for bit.
+// Point p of a multisection step on the bracket held in s.
 __device__ __forceinline__ double mu_point(const double* s, double ne, int p) {
   const double lo = s[MS_LO], hi = s[MS_HI], w = hi - lo;
   if (s[MS_IT] == 0.0) return lo + (p + 1) * (w / (MU_P + 1));
@@ -124,13 +104,89 @@ __device__ __forceinline__ double mu_point(const double* s, double ne, int p) {
   return fmin(fmax(ms, lo), hi);
 }
 
-__global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g) {
-  if (g.state[MS_DONE] != 0.0) return;
-  const double lo = g.state[MS_LO], hi = g.state[MS_HI];
+// The bracket after a step that evaluated N at the points of s (Np[p]):
+// lo' the largest point with N < N_e, hi' the smallest with N >= N_e (N at a
+// point equal to N_e exactly ends the search there). Written to t.
+__device__ void mu_update(const double* s, const double* Np, double ne, double* t) {
+  const double lo = s[MS_LO], hi = s[MS_HI];
+  double nlo = lo, nhi = hi, Nlo = s[MS_NLO], Nhi = s[MS_NHI];
+  int exact = -1;
+  for (int p = 0; p < MU_P; ++p) {
+    const double x = mu_point(s, ne, p);
+    if (Np[p] < ne) {
+      if (x > nlo) { nlo = x; Nlo = Np[p]; }
+    } else {
+      if (x < nhi) { nhi = x; Nhi = Np[p]; }
+      if (Np[p] == ne && exact < 0) exact = p;
+    }
+  }
+  double x_exact = 0.0;
+  if (exact >= 0) x_exact = mu_point(s, ne, exact);
+  if (exact >= 0) nlo = nhi = x_exact;
+  else if (nlo >= nhi) nlo = nhi = 0.5 * (nlo + nhi);   // N not monotone at rounding level
+  t[MS_LO] = nlo; t[MS_HI] = nhi; t[MS_NLO] = Nlo; t[MS_NHI] = Nhi; t[MS_IT] = s[MS_IT] + 1.0;
+  const double mid = 0.5 * (nlo + nhi);
+  const double scale = fmax(1.0, fabs(mid));
+  t[MS_DONE] = (nhi - nlo <= 4.0 * DBL_EPSILON * scale) ? 1.0 : 0.0;
+}
+
+// Per-block minimum and maximum of the Ritz values.
+__global__ void __launch_bounds__(MU_NT) k_mu_bracket(MuArgs g) {
+  double v[2] = {1e300, 1e300};        // min lambda, -max lambda
+  for (int64_t q = (int64_t)blockIdx.x * MU_NT + threadIdx.x; q < g.n_pairs; q += (int64_t)gridDim.x * MU_NT) {
+    const double l = g.lam[q];
+    v[0] = fmin(v[0], l);
+    v[1] = fmin(v[1], -l);
+  }
+  store_partials<2, 1>(v, g.partial);
+}
+
+// Multisection launch `it` (0-based). The bracket of this launch's points is
+// that of the previous state updated with the previous launch's partials
+// (it = 0: the bracket [min lambda - 50 kT, max lambda + 50 kT] from the
+// extremes of k_mu_bracket). Reads partial buffer it & 1 and state buffer
+// it & 1; writes partial buffer (it + 1) & 1 and (block 0) state buffer
+// (it + 1) & 1.
+__global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g, int it) {
+  const double* s_in = g.state + MU_STATE0 + 16 * (it & 1);
+  double* s_out = g.state + MU_STATE0 + 16 * ((it + 1) & 1);
+  const double* p_in = g.partial + (size_t)(it & 1) * MU_NB * MU_PS;
+  double* p_out = g.partial + (size_t)((it + 1) & 1) * MU_NB * MU_PS;
+  const int nb = gridDim.x;
+  __shared__ double st[16];
+  __shared__ double Np[MU_P];
+  if (it == 0) {
+    __shared__ double ext[2];
+    reduce_partials<2, 1>(g.partial, nb, ext);
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < 16; ++q) st[q] = 0.0;
+      st[MS_LO] = ext[0] - 50.0 * g.kT;
+      st[MS_HI] = -ext[1] + 50.0 * g.kT;
+    }
+    __syncthreads();
+  } else {
+    if (s_in[MS_DONE] != 0.0) {                  // converged: carry the state forward
+      if (blockIdx.x == 0 && threadIdx.x < 16) s_out[threadIdx.x] = s_in[threadIdx.x];
+      return;
+    }
+    reduce_partials<MU_P, 0>(p_in, nb, Np);
+    if (threadIdx.x == 0) {
+      double s[16];
+      for (int q = 0; q < 16; ++q) s[q] = s_in[q];
+      double t[16];
+      for (int q = 0; q < 16; ++q) t[q] = s[q];
+      mu_update(s, Np, g.n_e, t);
+      for (int q = 0; q < 16; ++q) st[q] = t[q];
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 16) s_out[threadIdx.x] = st[threadIdx.x];
+  if (st[MS_DONE] != 0.0) return;
+  const double lo = st[MS_LO], hi = st[MS_HI];
   const double cut = 40.0 * g.kT;                 // f = 0 or 2 to rounding beyond this
   double xs[MU_P];
 #pragma unroll
-  for (int p = 0; p < MU_P; ++p) xs[p] = mu_point(g.state, g.n_e, p);
+  for (int p = 0; p < MU_P; ++p) xs[p] = mu_point(st, g.n_e, p);
   double v[MU_P];
 #pragma unroll
   for (int p = 0; p < MU_P; ++p) v[p] = 0.0;
@@ -151,33 +207,35 @@ __global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g) {
       }
     }
   }
-  __shared__ double Np[MU_P];
-  if (!grid_reduce<MU_P, 0>(v, g.partial, g.counter, Np)) return;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    double* s = g.state;
-    double nlo = lo, nhi = hi, Nlo = s[MS_NLO], Nhi = s[MS_NHI];
-    int exact = -1;
-    for (int p = 0; p < MU_P; ++p) {
-      if (Np[p] < g.n_e) {
-        if (xs[p] > nlo) { nlo = xs[p]; Nlo = Np[p]; }
-      } else {
-        if (xs[p] < nhi) { nhi = xs[p]; Nhi = Np[p]; }
-        if (Np[p] == g.n_e && exact < 0) exact = p;
-      }
-    }
-    if (exact >= 0) nlo = nhi = xs[exact];
-    else if (nlo >= nhi) nlo = nhi = 0.5 * (nlo + nhi);   // N not monotone at rounding level
-    s[MS_LO] = nlo; s[MS_HI] = nhi; s[MS_NLO] = Nlo; s[MS_NHI] = Nhi; s[MS_IT] += 1.0;
-    s[MS_MU] = 0.5 * (nlo + nhi);
-    const double scale = fmax(1.0, fabs(s[MS_MU]));
-    if (nhi - nlo <= 4.0 * DBL_EPSILON * scale) s[MS_DONE] = 1.0;
-  }
+  store_partials<MU_P, 0>(v, p_out);
 }
 
-// Final sums at mu: electron count, band energy, entropy S/k_B.
-__global__ void __launch_bounds__(MU_NT) k_mu_final(MuArgs g) {
-  const double mu = g.state[MS_MU];
+// mu (the midpoint of the final bracket, or the fixed value), and the
+// per-block sums at mu: electron count, band energy, entropy S/k_B (into the
+// third partial region).
+__global__ void __launch_bounds__(MU_NT) k_mu_final(MuArgs g, int n_iter, double mu_fixed, int fixed) {
+  __shared__ double s_mu;
+  if (fixed) {
+    if (threadIdx.x == 0) s_mu = mu_fixed;
+    __syncthreads();
+  } else {
+    const double* s_in = g.state + MU_STATE0 + 16 * (n_iter & 1);
+    const double* p_in = g.partial + (size_t)(n_iter & 1) * MU_NB * MU_PS;
+    __shared__ double Np[MU_P];
+    const bool done = s_in[MS_DONE] != 0.0;
+    if (!done) reduce_partials<MU_P, 0>(p_in, gridDim.x, Np);
+    if (threadIdx.x == 0) {
+      double s[16], t[16];
+      for (int q = 0; q < 16; ++q) s[q] = t[q] = s_in[q];
+      if (!done) mu_update(s, Np, g.n_e, t);
+      s_mu = 0.5 * (t[MS_LO] + t[MS_HI]);
+    }
+    __syncthreads();
+  }
+  const double mu = s_mu;
+  if (blockIdx.x == 0 && threadIdx.x == 0) g.state[MU_FINAL] = mu;
+  // other blocks of this launch may still be reading the previous partials:
+  // the final sums go to a third region behind the two buffers
   double v[3] = {0.0, 0.0, 0.0};
   for (int64_t q = (int64_t)blockIdx.x * MU_NT + threadIdx.x; q < g.n_pairs; q += (int64_t)gridDim.x * MU_NT) {
     const double w = g.wgt[q];
@@ -190,12 +248,18 @@ __global__ void __launch_bounds__(MU_NT) k_mu_final(MuArgs g) {
     v[1] += l * f * w;
     v[2] += w * 2.0 * (log1p(e) + a * e / (1.0 + e));
   }
+  store_partials<3, 0>(v, g.partial + (size_t)2 * MU_NB * MU_PS);
+}
+
+// One block: totals of k_mu_final's partials.
+__global__ void __launch_bounds__(MU_NT) k_mu_finish(MuArgs g, int nb) {
   __shared__ double tot[3];
-  if (grid_reduce<3, 0>(v, g.partial, g.counter, tot) && threadIdx.x == 0) {
+  reduce_partials<3, 0>(g.partial + (size_t)2 * MU_NB * MU_PS, nb, tot);
+  if (threadIdx.x == 0) {
     g.eparts[0] = tot[1];      // E_band
     g.eparts[1] = tot[2];      // S / k_B
     g.eparts[3] = tot[0];      // electron count at mu
-    if (g.mu_out) *g.mu_out = mu;
+    if (g.mu_out) *g.mu_out = g.state[MU_FINAL];
   }
 }
 
@@ -206,12 +270,17 @@ int mu_blocks(int64_t n_pairs) {
   return (int)b;
 }
 
+size_t mu_partial_doubles() { return (size_t)3 * MU_NB * MU_PS; }
+size_t mu_state_doubles() { return (size_t)MU_STATE0 + 32; }
+
 void launch_mu(const MuArgs& a, double mu_fixed, bool fixed, int n_iter, hipStream_t st) {
   const int nb = mu_blocks(a.n_pairs);
-  hipLaunchKernelGGL(k_mu_bracket, dim3(nb), dim3(MU_NT), 0, st, a, mu_fixed, fixed ? 1 : 0);
-  if (!fixed)
-    for (int it = 0; it < n_iter; ++it) hipLaunchKernelGGL(k_mu_iter, dim3(nb), dim3(MU_NT), 0, st, a);
-  hipLaunchKernelGGL(k_mu_final, dim3(nb), dim3(MU_NT), 0, st, a);
+  if (!fixed) {
+    hipLaunchKernelGGL(k_mu_bracket, dim3(nb), dim3(MU_NT), 0, st, a);
+    for (int it = 0; it < n_iter; ++it) hipLaunchKernelGGL(k_mu_iter, dim3(nb), dim3(MU_NT), 0, st, a, it);
+  }
+  hipLaunchKernelGGL(k_mu_final, dim3(nb), dim3(MU_NT), 0, st, a, n_iter, mu_fixed, fixed ? 1 : 0);
+  hipLaunchKernelGGL(k_mu_finish, dim3(1), dim3(MU_NT), 0, st, a, nb);
 }
 
 }  // namespace tbk

@@ -75,11 +75,15 @@ class TBForceField:
                              f"basis blocks of the sphere in LDS and supports fewer")
         return cls(pos.shape[0], min(cap, n_max + margin), s, device=pos.device.index or 0)
 
-    def __call__(self, pos: torch.Tensor):
+    def solve(self, pos: torch.Tensor):
+        """Lists, local couplings and the density matrix at pos (no energies)."""
         s = self.s
         self.ctx.build_local_H(pos, s.cell, s.periodic, s.params, s.r_cluster)
         self.mu, _ = self.ctx.krylov_rho(s.r, s.kT, mu=s.mu, n_electrons=s.n_electrons,
                                          precision=s.precision, r_per_atom=s.r_per_atom)
+
+    def __call__(self, pos: torch.Tensor):
+        self.solve(pos)
         return self.ctx.energy_forces()
 
     def virial(self) -> torch.Tensor:
@@ -97,18 +101,33 @@ class TBForceField:
 
 
 class TBEnergy(torch.autograd.Function):
-    """E_tot = E_band - T S + E_rep as a 0-d tensor; backward returns -F * grad_out."""
+    """E_tot = E_band - T S + E_rep as a 0-d tensor.
+
+    forward runs the solve and the energy sums only (no force contraction);
+    backward launches the library's force kernel (tb_energy_backward: the
+    contraction Tr[rho dH/dR] through the Slater-Koster radial derivatives plus
+    the repulsive term, scaled by grad_out in the kernel) on the density matrix
+    of this forward. If the context has solved another geometry since, the
+    forward's solve is repeated first."""
 
     @staticmethod
     def forward(ctx, pos: torch.Tensor, ff: TBForceField):
-        e, f = ff(pos.detach().contiguous())
-        ctx.save_for_backward(f)
+        p = pos.detach().contiguous()
+        ff.solve(p)
+        e = ff.ctx.energy()
+        ctx.ff = ff
+        ctx.generation = ff.ctx.generation
+        ctx.save_for_backward(p)
         return e[3].clone()
 
     @staticmethod
     def backward(ctx, grad_out):
-        (f,) = ctx.saved_tensors
-        return -f * grad_out, None
+        (p,) = ctx.saved_tensors
+        ff = ctx.ff
+        if ff.ctx.generation != ctx.generation:
+            ff.solve(p)
+        g = grad_out.detach().to(dtype=torch.float64).reshape(1)
+        return ff.ctx.energy_backward(g), None
 
 
 def velocity_verlet(ff: TBForceField, pos: torch.Tensor, vel: torch.Tensor, dt: float, steps: int,

@@ -23,7 +23,7 @@ ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4:
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
               "max_cluster_pos", "memory_bytes", "reorth_second_pass", "reorth_steps", "basis_bytes")
 EXPORTS = ("tb_create", "tb_create_ex", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
-           "tb_energy_forces", "tb_get_stats", "tb_virial", "tb_set_seeds", "tb_set_groups", "tb_set_launch", "tb_set_shape", "tb_autotune", "tb_profile_enable", "tb_profile_read",
+           "tb_energy_forces", "tb_energy_backward", "tb_get_stats", "tb_virial", "tb_set_seeds", "tb_set_groups", "tb_set_launch", "tb_set_shape", "tb_autotune", "tb_profile_enable", "tb_profile_read",
            "tb_last_error")
 PHASES = ("lists_local", "lanczos", "eig", "mu", "rho", "forces")
 HOP_MAX_DEFAULT = 24       # hop-list capacity of tb_create (rho row atoms per target: itself + hop list)
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tb_krylov_rho.argtypes = [P, I, P, ctypes.c_double, ctypes.c_double, ctypes.c_double, I, P, P]
     lib.tb_rho_layout.argtypes = [P, ctypes.POINTER(I64), P, P]
     lib.tb_energy_forces.argtypes = [P, P, P]
+    lib.tb_energy_backward.argtypes = [P, P, P]
     lib.tb_get_stats.argtypes = [P, ctypes.POINTER(I64), I]
     lib.tb_virial.argtypes = [P, P]
     lib.tb_set_seeds.argtypes = [P, I]
@@ -123,6 +124,7 @@ class TBContext:
         self.rho = None
         self.row_ptr = None
         self.col_j = None
+        self.generation = 0            # counts krylov_rho calls (the density matrix in the context)
 
     def close(self):
         if getattr(self, "h", None):
@@ -181,6 +183,7 @@ class TBContext:
         _check(self.lib.tb_krylov_rho(self.h, int(r), _ptr(r_per_atom), float(kT), mu_arg, ne,
                                       PRECISIONS[precision], _ptr(mu_t), _ptr(rho_out)))
         self.rho = rho_out
+        self.generation += 1
         return mu_t, rho_out
 
     def energy_forces(self, forces: torch.Tensor | None = None, e_out: torch.Tensor | None = None):
@@ -190,6 +193,24 @@ class TBContext:
             forces = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=self.device)
         _check(self.lib.tb_energy_forces(self.h, _ptr(e_out), _ptr(forces)))
         return e_out, forces
+
+    def energy(self, e_out: torch.Tensor | None = None) -> torch.Tensor:
+        """E_band, -TS, E_rep, E_tot of the last krylov_rho, without the force
+        contraction (tb_energy_forces with forces = NULL)."""
+        if e_out is None:
+            e_out = torch.empty(4, dtype=torch.float64, device=self.device)
+        _check(self.lib.tb_energy_forces(self.h, _ptr(e_out), None))
+        return e_out
+
+    def energy_backward(self, grad_e: torch.Tensor, grad_pos: torch.Tensor | None = None) -> torch.Tensor:
+        """grad_pos = -grad_e * F for the density matrix of the last krylov_rho
+        (tb_energy_backward: the force contraction scaled in the kernel)."""
+        assert grad_e.is_cuda and grad_e.dtype == torch.float64 and grad_e.numel() == 1
+        g = grad_e.contiguous()
+        if grad_pos is None:
+            grad_pos = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.tb_energy_backward(self.h, _ptr(g), _ptr(grad_pos)))
+        return grad_pos
 
     def virial(self, out: torch.Tensor | None = None) -> torch.Tensor:
         """W [3][3] (eV) of the last energy_forces(); stress = W / V."""

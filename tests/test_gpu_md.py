@@ -1,7 +1,8 @@
 """GPU tests of the autograd Function and of MD on top of the hot path.
 
-* TBEnergy: forward returns E_tot of the library, backward returns -F
-  exactly; in the exact limit (isolated C60, every sphere the whole molecule,
+* TBEnergy: forward returns E_tot of the library (no force contraction),
+  backward launches the force kernel and returns -F * grad_out exactly (also
+  for an earlier forward after the context solved another geometry); in the exact limit (isolated C60, every sphere the whole molecule,
   Krylov space invariant) -F is the gradient of E_tot (central differences).
 * Finite r and cutoff: central differences of E_tot match the oracle's at
   240 atoms; on the 1920-atom hot crystal the gap between F and -dE_tot/dR
@@ -9,7 +10,8 @@
   reported at the production r and past every sphere's Krylov grade, where
   it must be smaller.
 * NVE: 200 velocity-Verlet steps of 0.5 fs from 1500 K, FP64 and mixed
-  precision; drift reported, mixed follows FP64 early on.
+  precision; the energy excursion is gated by a bound derived from Verlet's
+  oscillation and the measured force gap; mixed follows FP64 early on.
 """
 import numpy as np
 import pytest
@@ -49,6 +51,17 @@ def test_tbenergy_backward_is_minus_force(torch_cuda):
     torch.cuda.synchronize()
     assert E.dim() == 0 and float(E.detach()) == float(e[3])
     assert torch.equal(pos.grad, -2.5 * f)
+    # the backward of an earlier forward, after the context solved another
+    # geometry, repeats that forward's solve and gives its own forces
+    pos2 = (pos.detach() + 0.01).requires_grad_(True)
+    E1 = TBEnergy.apply(pos, ff)
+    E2 = TBEnergy.apply(pos2, ff)
+    (g1,) = torch.autograd.grad(-0.5 * E1, pos)
+    (g2,) = torch.autograd.grad(E2, pos2)
+    _, f2 = ff(pos2.detach())
+    torch.cuda.synchronize()
+    assert torch.equal(g1, 0.5 * f) and torch.equal(g2, -f2)
+    assert float(E2.detach()) != float(E1.detach())
     ff.close()
 
 
@@ -182,21 +195,63 @@ def test_force_gap_at_cluster_exact_r_below_production_r(torch_cuda):
     assert rms[r_exact] < rms[40]
 
 
-def test_nve_mixed_follows_fp64(torch_cuda):
+# NVE energy gate (c60_1920_hot, 200 steps of 0.5 fs from 1500 K). With the
+# method's forces F, which are not exact gradients at finite r and cutoff
+# (C11), dE_tot/dt = sum_i v_i . g_i with the force gap g = F + dE_tot/dR.
+#  * Verlet oscillation: velocity Verlet keeps a shadow energy; the true
+#    energy of a mode of angular frequency w oscillates by (w dt)^2 / 4 of
+#    the mode's energy (exact for a harmonic mode). Taking every mode at the
+#    stiffest frequency, w_max = 2 pi c 2500 cm^-1 (above the highest C60
+#    mode, 1.58e3 cm^-1, with room for the compressed contacts), and the
+#    thermal energy 3 k_B T0 per atom: B_V = (w_max dt)^2 / 4 * 3 k_B T0.
+#  * Drift: with v and g uncorrelated, of rms v_rms = sqrt(k_B T0 / m) and
+#    g_rms per component, and a correlation time tau_c of their product, the
+#    integral of sum v.g over t has the standard deviation
+#    v_rms g_rms sqrt(6 tau_c t N); per atom sigma_D = v_rms g_rms
+#    sqrt(6 tau_c t / N). tau_c = 10 fs, half the period of the C-C stretch.
+# Gate: max_t |E(t) - E(0)| / N <= B_V + 3 sigma_D(t_end), for both
+# precisions, with g_rms measured on the start geometry by central
+# differences (16 seeded pairs, production r).
+NVE_NU_MAX_CM = 2500.0
+NVE_TAU_C_FS = 10.0
+C_CM_PER_FS = 2.99792458e-5
+
+
+def nve_energy_bound(N, T0, dt, t_end, g_rms):
+    w = 2.0 * np.pi * C_CM_PER_FS * NVE_NU_MAX_CM              # rad/fs
+    b_v = (w * dt) ** 2 / 4.0 * 3.0 * inputs.K_B * T0             # eV per atom
+    v_rms = np.sqrt(inputs.K_B * T0 / inputs.MASS_C * inputs.ACC_UNIT)   # A/fs
+    sigma = v_rms * g_rms * np.sqrt(6.0 * NVE_TAU_C_FS * t_end / N)
+    return b_v, sigma, b_v + 3.0 * sigma
+
+
+def test_nve_energy_gate(torch_cuda):
     """200 velocity-Verlet steps of 0.5 fs from 1500 K on the 1920-atom hot
-    crystal, FP64 and mixed precision: the total-energy drift of each is
-    reported (the forces are not exact gradients at finite r, so the drift is
-    a property of the method); the mixed trajectory's energies follow the FP64
-    ones over the first 20 steps to 1e-4 eV/atom."""
+    crystal, FP64 and mixed precision: the total-energy excursion of each stays
+    within the bound derived above from the force gap measured on the start
+    geometry, and the mixed trajectory's energies follow the FP64 ones over
+    the first 20 steps to 1e-4 eV/atom."""
     torch = torch_cuda
     from paper_0910_4497_amd.md import velocity_verlet
     w = inputs.workload("c60_1920_hot")
     N = w.n_atoms
-    dt, steps = 0.5, 200
+    dt, steps, T0 = 0.5, 200, 1500.0
+    cell = np.asarray(w.cell, dtype=np.float64)
+    pos0 = torch.tensor(w.pos, dtype=torch.float64, device="cuda:0")
+    h = 1e-4
+    pairs = _fd_pairs(w.pos, cell, w.r_cut, P["rm"], 16, 3004, h)
+    ff = _ff(torch, pos0, cell=tuple(w.cell), periodic=(1, 1, 1), params=P, r_cluster=w.r_cut, r=w.r,
+             n_electrons=w.n_electrons)
+    fd, f = _fd_gap(torch, ff, pos0, pairs, h)
+    ff.close()
+    g_rms = float(np.sqrt(np.mean((fd - f) ** 2)))
+    b_v, sigma, bound = nve_energy_bound(N, T0, dt, steps * dt, g_rms)
+    print(f"  force gap rms {g_rms:.3f} eV/A; bound B_V {b_v * 1e3:.2f} + 3 sigma_D {3 * sigma * 1e3:.2f} "
+          f"= {bound * 1e3:.2f} meV/atom")
     recs = {}
     for precision in ("fp64", "fp32"):
         pos = torch.tensor(w.pos, dtype=torch.float64, device="cuda:0")
-        vel = torch.tensor(inputs.maxwell_velocities(N, 1500.0, seed=2004), dtype=torch.float64,
+        vel = torch.tensor(inputs.maxwell_velocities(N, T0, seed=2004), dtype=torch.float64,
                            device="cuda:0")
         ff = _ff(torch, pos, cell=tuple(w.cell), periodic=(1, 1, 1), params=P, r_cluster=w.r_cut, r=w.r,
                  n_electrons=w.n_electrons, precision=precision)
@@ -209,8 +264,10 @@ def test_nve_mixed_follows_fp64(torch_cuda):
         etot = rec[:, 2]
         t_ps = np.arange(steps + 1) * dt * 1e-3
         slope = np.polyfit(t_ps, etot / N, 1)[0] * 1e3
-        print(f"  {precision}: max |E(t)-E(0)|/N {np.abs(etot - etot[0]).max() / N * 1e3:.3f} meV/atom, "
+        exc = np.abs(etot - etot[0]).max() / N
+        print(f"  {precision}: max |E(t)-E(0)|/N {exc * 1e3:.3f} meV/atom (bound {bound * 1e3:.2f}), "
               f"slope {slope:.3f} meV/atom/ps, E_pot swing {np.ptp(rec[:, 0]) / N * 1e3:.2f} meV/atom")
+        assert exc <= bound
         recs[precision] = rec
     d20 = np.abs(recs["fp32"][:21, 2] - recs["fp64"][:21, 2]).max() / N
     print(f"  mixed vs FP64, first 20 steps: max |dE_tot|/N {d20:.3e} eV")

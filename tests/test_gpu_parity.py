@@ -3,7 +3,8 @@
 Bar (FP64 mode): normwise relative error <= 1e-8 for rho blocks and forces,
 <= 1e-10 relative for the energies; mu to 1e-9 eV. FP32 mode: force error
 <= 1e-3 eV/A (max-abs over all components), errors reported. BF16-operand
-mode: errors reported, bounded by the BF16 perturbation (bf16_check).
+mode: errors reported, bounded by the BF16 perturbation (bf16_check); the
+1e-3 eV/A bar is checked as an expected failure.
 """
 import os
 
@@ -143,13 +144,28 @@ def bf16_check(res, ora, n_atoms, label, w):
 
 
 def test_parity_c60_240_bf16(torch_cuda, c60_240_oracle):
-    """BF16 operands in H.V (FP32 accumulation, a pass at every step)."""
+    """BF16 V_k operand in H.V (FP32 Hamiltonian, FP32 accumulation, a pass at
+    every step): errors within the BF16 perturbation bounds."""
     w, ora = c60_240_oracle
     ctx = make_ctx(w.n_atoms, 128, w.r)
     res = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
                   precision="bf16")
     bf16_check(res, ora, w.n_atoms, "c60_240", w)
     assert res["stats"]["reorth_steps"] == w.n_atoms * (w.r - 1)
+
+
+@pytest.mark.xfail(strict=False, reason="no BF16-operand form meets 1e-3 eV/A: rounding V_k to 8 "
+                                        "significand bits moves the forces by ~1e-1 eV/A (c60_240)")
+def test_bf16_operand_force_bar_c60_240(torch_cuda, c60_240_oracle):
+    """The mixed-precision force bar (max-abs <= 1e-3 eV/A) applied to the
+    BF16-operand form: expected to fail, recorded so that the claim is checked."""
+    w, ora = c60_240_oracle
+    ctx = make_ctx(w.n_atoms, 128, w.r)
+    res = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                  precision="bf16")
+    fe = float(np.abs(res["forces"] - ora["forces"]).max())
+    print(f"  bf16 max force err {fe:.3e} eV/A")
+    assert fe <= 1e-3
 
 
 def test_parity_c60_1920_full(torch_cuda):
@@ -171,7 +187,7 @@ def test_parity_c60_1920_full(torch_cuda):
     bf16_check(rbf, ora, w.n_atoms, "c60_1920", w)
 
 
-def sampled_parity(name, mu_fixed, n_sample, seed, n_cluster, precision="fp64"):
+def sampled_parity(name, mu_fixed, n_sample, seed, n_cluster, precisions=("fp64",)):
     w = inputs.workload(name)
     rng = np.random.default_rng(seed)
     S = sorted(rng.choice(w.n_atoms, n_sample, replace=False).tolist())
@@ -180,25 +196,36 @@ def sampled_parity(name, mu_fixed, n_sample, seed, n_cluster, precision="fp64"):
                   force_atoms=S, r_per_atom=w.r_per_atom, processes=NPROC)
     r_max = int(np.max(w.r_per_atom)) if w.r_per_atom is not None else w.r
     ctx = make_ctx(w.n_atoms, n_cluster, r_max)
-    res = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, mu=mu_fixed,
-                  precision=precision, r_per_atom=w.r_per_atom)
+    res = {prec: gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, mu=mu_fixed,
+                         precision=prec, r_per_atom=w.r_per_atom) for prec in precisions}
+    ctx.close()
     return w, S, need, ora, res
 
 
 @pytest.mark.parametrize("name,n_cluster", [("c60_15360", 400), ("c60_6480_strained", 280)])
 def test_parity_large_sampled_fixed_mu(torch_cuda, name, n_cluster):
     """Full-size launch, outputs sampled on seeded atoms the oracle solves one
-    by one (chemical potential fixed at 3.5 eV on both sides)."""
-    w, S, need, ora, res = sampled_parity(name, 3.5, 12, 99, n_cluster)
-    assert res["stats"]["max_cluster"] <= n_cluster
-    worst, scale = compare_rho(res, ora["rho"], ora["sols"], need)
+    by one (chemical potential fixed at 3.5 eV on both sides). FP64: the parity
+    bar; mixed precision (FP32 recursion): max-abs force error <= 1e-3 eV/A on
+    the sampled atoms, the bar of the 15360-atom target."""
+    w, S, need, ora, res = sampled_parity(name, 3.5, 12, 99, n_cluster, precisions=("fp64", "fp32"))
+    r64, r32 = res["fp64"], res["fp32"]
+    assert r64["stats"]["max_cluster"] <= n_cluster
+    worst, scale = compare_rho(r64, ora["rho"], ora["sols"], need)
     print(f"  {name}: rho max abs err {worst:.3e} (scale {scale:.3e}) over {len(need)} seeds")
     assert worst <= 1e-8 * scale
     F = np.array([ora["forces_sampled"][k] for k in S])
-    G = res["forces"][S]
+    G = r64["forces"][S]
     err = rel_inf(G, F)
     print(f"  {name}: sampled force rel err {err:.3e}")
     assert err <= 1e-8
+    w32, _ = compare_rho(r32, ora["rho"], ora["sols"], need)
+    fe = float(np.abs(r32["forces"][S] - F).max())
+    fe_all = float(np.abs(r32["forces"] - r64["forces"]).max())
+    print(f"  {name} fp32: rho max abs err {w32:.3e}, sampled max force err {fe:.3e} eV/A "
+          f"(|F| max {np.abs(F).max():.2f}); all {w.n_atoms} atoms against the FP64 path: {fe_all:.3e} eV/A")
+    assert r32["stats"]["flags"] == 0
+    assert fe <= 1e-3 and fe_all <= 1e-3
 
 
 def test_parity_c60_240_orbital_seeds(torch_cuda):
