@@ -185,6 +185,21 @@ int tb_rho_layout(tb_ctx *ctx, int64_t *nnz_pairs_host, int64_t *row_ptr,
  * Errors: TB_EINVAL (null ctx or e_out), TB_ESTATE, TB_EHIP. */
 int tb_energy_forces(tb_ctx *ctx, double *e_out, double *forces);
 
+/* tb_energy_forces for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, the same results bit for bit, with their
+ * partial results (per-atom repulsion staging, 16 B per atom, and per-block
+ * virial sums, 72 B per 64 atoms) in a fixed 2 MiB device array of the
+ * library instead of the context's workspace; it calls no allocating
+ * routine. The array's address on each device is looked up when the first
+ * context is created there. At most about 122,000 atoms (static_scratch_need
+ * <= 2 MiB). All calls on one device share the array: calls that overlap
+ * on one device (other streams, other contexts, other threads) race, so
+ * serialise them. Arguments and outputs as tb_energy_forces.
+ * Errors: TB_EINVAL, TB_ESTATE, TB_ECAPACITY (too many atoms for the
+ * array), TB_EHIP. */
+int tb_energy_forces_static(tb_ctx *ctx, double *e_out, double *forces);
+
 /* Backward of the total energy E_tot = E_band - TS + E_rep of the last
  * tb_krylov_rho (Sec. 2: the force on an atom is Tr[rho F_i] with
  * F_i = -dH/dR_i, plus the repulsive term): with g = *grad_e (a device

@@ -136,6 +136,11 @@ extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int6
     return fail(TB_ECAPACITY, "LDS request of %zu B refused: %s", (size_t)(LDS_CU - LDS_RESERVE),
                 hipGetErrorString(e));
   }
+  e = static_scratch_init(hip_device);                 // tb_energy_forces_static's workspace address
+  if (e != hipSuccess) {
+    delete c;
+    return fail(TB_EHIP, "address of the fixed device workspace: %s", hipGetErrorString(e));
+  }
   e = eig_set_lds(r_max);
   if (e != hipSuccess || rho_lds_bytes(r_max) > LDS_CU) {
     delete c;
@@ -570,6 +575,27 @@ extern "C" int tb_energy_forces(tb_ctx* c, double* e_out, double* forces) {
   if (!e_out) return fail(TB_EINVAL, "e_out is null");
   HIP_TRY(hipSetDevice(c->device));
   ForceArgs fa = force_args(c);
+  fa.forces = forces; fa.e_out = e_out;
+  const int pk = prof_begin(c, 5);
+  launch_forces(fa, forces != nullptr, c->stream);
+  prof_end(c, pk);
+  HIP_TRY(hipGetLastError());
+  c->have_virial = forces != nullptr;
+  return TB_OK;
+}
+
+extern "C" int tb_energy_forces_static(tb_ctx* c, double* e_out, double* forces) {
+  if (!c) return fail(TB_EINVAL, "ctx is null");
+  if (c->stage < 2) return fail(TB_ESTATE, "tb_krylov_rho must be called first");
+  if (!e_out) return fail(TB_EINVAL, "e_out is null");
+  const size_t need = static_scratch_need(c->n_atoms);
+  if (need > static_scratch_bytes())
+    return fail(TB_ECAPACITY, "%lld atoms need %zu B of fixed workspace; it holds %zu B",
+                (long long)c->n_atoms, need, static_scratch_bytes());
+  HIP_TRY(hipSetDevice(c->device));
+  ForceArgs fa = force_args(c);
+  if (!static_scratch_args(c->device, fa))
+    return fail(TB_ESTATE, "fixed workspace of device %d not looked up", c->device);
   fa.forces = forces; fa.e_out = e_out;
   const int pk = prof_begin(c, 5);
   launch_forces(fa, forces != nullptr, c->stream);

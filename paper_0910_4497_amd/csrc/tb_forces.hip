@@ -16,6 +16,8 @@
 //   W_ab = sum over ordered pairs (k, j) of (d_kj)_a [g_kj + F'(x_k) phi'(r) d_kj / r]_b,
 // each atom summing its own ordered pairs; per-block sums in a fixed order,
 // then over blocks in k_energy (bitwise reproducible).
+#include <mutex>
+
 #include "tb_internal.h"
 
 namespace tbk {
@@ -174,6 +176,58 @@ void launch_forces(const ForceArgs& a, bool with_forces, hipStream_t st) {
   if (with_forces)
     hipLaunchKernelGGL(k_forces, dim3((a.n_atoms + F_APB - 1) / F_APB), dim3(F_NT), 0, st, a);
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(F_NT), 0, st, a, with_forces ? 1 : 0);
+}
+
+// ------------------------------------------------ fixed device workspace
+// tb_energy_forces_static runs the kernels above with their partial results
+// -- the per-atom repulsion staging xrep [N][2] and the per-block virial sums
+// wpart [ceil(N/64)][9] -- in this file-scope array instead of the context's
+// workspace, for callers that cannot allocate. Every element a call reads is
+// written earlier in the same call, so nothing needs clearing; calls that
+// overlap on one device share the array and race. Host code never uses the
+// array's name as an address: each device's address comes from
+// hipGetSymbolAddress, taken once per device at context creation.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)2 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+static void* g_scratch_ptr[SCRATCH_DEVICES];
+static std::mutex g_scratch_mu;
+
+hipError_t static_scratch_init(int device) {
+  if (device < 0 || device >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;       // the caller makes `device` current
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t static_scratch_need(int64_t n_atoms) {
+  const int64_t nb = (n_atoms + F_APB - 1) / F_APB;
+  return align256((size_t)n_atoms * 2 * sizeof(double)) + align256((size_t)nb * 9 * sizeof(double));
+}
+size_t static_scratch_bytes() { return STATIC_SCRATCH_BYTES; }
+
+bool static_scratch_args(int device, ForceArgs& a) {
+  if (device < 0 || device >= SCRATCH_DEVICES) return false;
+  unsigned char* base;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = (unsigned char*)g_scratch_ptr[device];
+  }
+  if (!base) return false;
+  a.xrep = (double*)base;
+  a.wpart = (double*)(base + align256((size_t)a.n_atoms * 2 * sizeof(double)));
+  return true;
 }
 
 __global__ void k_copy9(const double* __restrict__ src, double* __restrict__ dst) {

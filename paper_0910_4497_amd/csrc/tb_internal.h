@@ -255,6 +255,14 @@ struct ForceArgs {
   double* virial;             // [9] W[a][b] = sum over ordered pairs of d_a g_b
 };
 void launch_forces(const ForceArgs& a, bool with_forces, hipStream_t st);
+// Fixed device workspace of tb_energy_forces_static (a file-scope array of
+// tb_forces.hip): its address on `device` (current) is looked up once by
+// static_scratch_init; static_scratch_args points xrep and wpart into it
+// (false before the lookup); static_scratch_need is the size for n atoms.
+hipError_t static_scratch_init(int device);
+bool static_scratch_args(int device, ForceArgs& a);
+size_t static_scratch_need(int64_t n_atoms);
+size_t static_scratch_bytes();
 void launch_virial_copy(const double* src, double* dst, hipStream_t st);
 
 // K1-K3 and the rho pair layout for the geometry in pos (device).

@@ -23,7 +23,7 @@ ERRORS = {0: "TB_OK", -1: "TB_EINVAL", -2: "TB_ECUTOFF", -3: "TB_ECAPACITY", -4:
 STAT_NAMES = ("flags", "max_cluster", "max_hop", "max_couplings", "deflated", "early_stop",
               "max_cluster_pos", "memory_bytes", "reorth_second_pass", "reorth_steps", "basis_bytes")
 EXPORTS = ("tb_create", "tb_create_ex", "tb_destroy", "tb_build_local_H", "tb_krylov_rho", "tb_rho_layout",
-           "tb_energy_forces", "tb_energy_backward", "tb_get_stats", "tb_virial", "tb_set_seeds", "tb_set_groups", "tb_set_launch", "tb_set_shape", "tb_autotune", "tb_profile_enable", "tb_profile_read",
+           "tb_energy_forces", "tb_energy_forces_static", "tb_energy_backward", "tb_get_stats", "tb_virial", "tb_set_seeds", "tb_set_groups", "tb_set_launch", "tb_set_shape", "tb_autotune", "tb_profile_enable", "tb_profile_read",
            "tb_last_error")
 PHASES = ("lists_local", "lanczos", "eig", "mu", "rho", "forces")
 HOP_MAX_DEFAULT = 24       # hop-list capacity of tb_create (rho row atoms per target: itself + hop list)
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tb_rho_layout.argtypes = [P, ctypes.POINTER(I64), P, P]
     lib.tb_energy_forces.argtypes = [P, P, P]
     lib.tb_energy_backward.argtypes = [P, P, P]
+    lib.tb_energy_forces_static.argtypes = [P, P, P]
     lib.tb_get_stats.argtypes = [P, ctypes.POINTER(I64), I]
     lib.tb_virial.argtypes = [P, P]
     lib.tb_set_seeds.argtypes = [P, I]
@@ -192,6 +193,16 @@ class TBContext:
         if forces is None:
             forces = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=self.device)
         _check(self.lib.tb_energy_forces(self.h, _ptr(e_out), _ptr(forces)))
+        return e_out, forces
+
+    def energy_forces_static(self, forces: torch.Tensor | None = None, e_out: torch.Tensor | None = None):
+        """energy_forces with the kernels' partial results in the library's fixed
+        device array (tb_energy_forces_static: no allocation by the library)."""
+        if e_out is None:
+            e_out = torch.empty(4, dtype=torch.float64, device=self.device)
+        if forces is None:
+            forces = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=self.device)
+        _check(self.lib.tb_energy_forces_static(self.h, _ptr(e_out), _ptr(forces)))
         return e_out, forces
 
     def energy(self, e_out: torch.Tensor | None = None) -> torch.Tensor:

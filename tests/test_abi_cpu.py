@@ -54,6 +54,7 @@ def test_last_error_callable_without_device():
     assert lib.tb_autotune(None, 10, None, 0, None) == -1
     assert lib.tb_virial(None, None) == -1
     assert lib.tb_energy_backward(None, None, None) == -1
+    assert lib.tb_energy_forces_static(None, None, None) == -1
     assert lib.tb_set_seeds(None, 1) == -1
     assert lib.tb_set_groups(None, 4) == -1
     assert lib.tb_set_shape(None, 1, 256, 4, 1, 1) == -1
