@@ -12,10 +12,13 @@
 //      one rotation per active chase in parallel. Every rotation is applied to
 //      the first four rows of Z and logged (c, s, plane) with one segment per
 //      time step. D, E of S and Z[0:4, :] go to HBM.
-//   2. k_eig: eigenvalues of S by bisection on Sturm counts, one thread per
-//      eigenvalue index (all in parallel);
+//   2. k_eig: eigenvalues of S, one thread per eigenvalue index (all in
+//      parallel): a multisection round on a grid of Sturm counts, bisection
+//      until the eigenvalue is alone in its bracket, then Laguerre's
+//      iteration toward it inside the bracket (about four steps);
 //   3. eigenvectors of S: for an eigenvalue with no neighbour closer than
-//      max(1e-6 ||S||, 1e-5 eV), a twisted factorisation of S - lambda I;
+//      max(1e-6 ||S||, 1e-5 eV), a twisted factorisation of S - lambda I
+//      (its pivots recomputed from sparse checkpoints instead of stored);
 //      inside such a cluster, two steps of inverse iteration (tridiagonal LU
 //      with partial pivoting, deterministic pseudo-random start), then
 //      Gram-Schmidt against the earlier members, one more step and
@@ -160,6 +163,94 @@ __device__ __forceinline__ int sturm_count_fast(const double* D, const double* E
   return zero ? sturm_count(D, E2s, d, sigma, pivmin) : c;
 }
 
+// Sturm count at sigma (as sturm_count_nz) together with the ratios
+// g1 = p'/p and g2 = p''/p of the characteristic polynomial p(x) = det(S - x I)
+// at x = sigma: the minors recurrence differentiated once and twice,
+//   p'_k  = (D_k - x) p'_{k-1}  - p_{k-1}      - E_{k-1}^2 p'_{k-2},
+//   p''_k = (D_k - x) p''_{k-1} - 2 p'_{k-1}   - E_{k-1}^2 p''_{k-2},
+// rescaled together with p (the ratios are unchanged). zero: some minor came
+// out exactly zero (the count is then repeated with the guard).
+__device__ __forceinline__ int sturm_lag(const double* D, const double* E2s, int d, double sigma, double& g1,
+                                         double& g2, bool& zero) {
+  double p1 = 1.0, p2 = 0.0, q1 = 0.0, q2 = 0.0, s1 = 0.0, s2 = 0.0;
+  int cnt = 0;
+  bool z = false;
+  for (int k = 0; k < d; k += 4) {
+    const double2 d01 = *(const double2*)(D + k), d23 = *(const double2*)(D + k + 2);
+    const double2 e01 = *(const double2*)(E2s + k), e23 = *(const double2*)(E2s + k + 2);
+    const double dv[4] = {d01.x, d01.y, d23.x, d23.y}, ev[4] = {e01.x, e01.y, e23.x, e23.y};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double a = dv[u] - sigma;
+      const double p = fma(a, p1, -(ev[u] * p2));
+      const double q = fma(a, q1, -fma(ev[u], q2, p1));
+      const double r = fma(a, s1, -fma(ev[u], s2, 2.0 * q1));
+      z |= (p == 0.0);
+      cnt += (int)(((unsigned)__double2hiint(p) ^ (unsigned)__double2hiint(p1)) >> 31);
+      p2 = p1; p1 = p;
+      q2 = q1; q1 = q;
+      s2 = s1; s1 = r;
+    }
+    const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(p1), fabs(p2)));
+    p1 = __builtin_amdgcn_ldexp(p1, -e); p2 = __builtin_amdgcn_ldexp(p2, -e);
+    q1 = __builtin_amdgcn_ldexp(q1, -e); q2 = __builtin_amdgcn_ldexp(q2, -e);
+    s1 = __builtin_amdgcn_ldexp(s1, -e); s2 = __builtin_amdgcn_ldexp(s2, -e);
+  }
+  zero = z;
+  g1 = q1 / p1;
+  g2 = s1 / p1;
+  return cnt;
+}
+
+// Eigenvalue t of the tridiagonal S of n rows (D and the shifted squares E2s
+// as for sturm_count) from a bracket [l, h] whose Sturm counts are
+// cl <= t < ch. Bisection narrows the bracket until it holds
+// eigenvalue t alone (cl == t, ch == t + 1); then Laguerre's iteration for the
+// real-rooted polynomial p of degree n: with G = p'/p and H = G^2 - p''/p the
+// two iterates x - n / (G +- sqrt((n - 1)(n H - G^2))) lie on either side of x,
+// each between x and the nearest root on its side, and converge cubically to
+// it. The Sturm count at x says on which side eigenvalue t lies (the bracket
+// holds no other), so the step goes that way; every count also narrows the
+// bracket, and a step that would leave it (rounding) becomes the midpoint.
+// Stops when a step is below 1e-12 anorm (the next error is then at rounding
+// level) or the bracket is below 4 eps max(|l|, |h|) + pivmin.
+__device__ double eig_laguerre(const double* D, const double* E2s, int n, int t, double l, double h, int cl,
+                               int ch, double anorm, double pivmin) {
+  const double nd = (double)n;
+  auto narrow = [&](double x, int c) {
+    if (c <= t) { l = x; cl = c; } else { h = x; ch = c; }
+  };
+  auto done = [&]() { return h - l <= 4.0 * DBL_EPSILON * fmax(fabs(l), fabs(h)) + pivmin; };
+  int it = 0;
+  while (!(cl == t && ch == t + 1) && !done() && it < 128) {
+    const double m = 0.5 * (l + h);
+    narrow(m, sturm_count_fast(D, E2s, n, m, pivmin));
+    ++it;
+  }
+  double x = 0.5 * (l + h);
+  while (!done() && it < 128) {
+    ++it;
+    double g1, g2;
+    bool zero;
+    int c = sturm_lag(D, E2s, n, x, g1, g2, zero);
+    if (zero) c = sturm_count(D, E2s, n, x, pivmin);
+    narrow(x, c);
+    if (!(isfinite(g1) && isfinite(g2))) {        // x is an eigenvalue to rounding
+      if (c == t + 1 || c == t) return x;
+      x = 0.5 * (l + h);
+      continue;
+    }
+    const double hh = g1 * g1 - g2;
+    const double disc = sqrt(fmax((nd - 1.0) * (nd * hh - g1 * g1), 0.0));
+    const double den = (c > t) ? g1 + disc : g1 - disc;     // c > t: eigenvalue t lies left of x
+    const double step = nd / den;
+    const double xn = x - step;
+    if (fabs(step) <= 1e-12 * anorm) return fmin(fmax(xn, l), h);
+    x = (xn > l && xn < h) ? xn : 0.5 * (l + h);
+  }
+  return 0.5 * (l + h);
+}
+
 // 1 / q from the hardware reciprocal refined by one Newton step (relative
 // error near the unit roundoff).
 __device__ __forceinline__ double rcp_nr(double q) {
@@ -226,85 +317,108 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
 // pivots d-_k of U D U^T, the twist index r where
 // |gamma_r| = |d+_r + d-_r - (D_r - lam)| is smallest, then z_r = 1 and
 // z_k = -E_k z_{k+1} / d+_k (k < r), z_k = -E_{k-1} z_{k-1} / d-_k (k > r).
-// Pivots of magnitude below `small` are replaced by +-small. Scratch: d+ at
-// scr[k * ns], d- at scr[(d + k) * ns], read back in chunks so that the loads
-// do not wait one by one. The vector goes to xcol (stride ld) unnormalised;
-// the return value is the factor that normalises it (applied by the readers,
-// which saves a pass over the column).
-// ACC: also accumulates y[c] = sum_k R1[c d + k] z_k, the column's projection
-// on the first four rows of Z (R1 in LDS, row stride d), as z is produced,
-// so that the column need not be read back.
+// Pivots of magnitude below `small` are replaced by +-small. The vector goes
+// to xcol (stride ld) unnormalised; the return value is the factor that
+// normalises it (applied by the readers). ACC: also accumulates
+// y[c] = sum_k R1[c d + k] z_k, the column's projection on the first four rows
+// of Z (R1 in LDS, row stride d), as z is produced.
+// The pivots are not stored: every CK-th forward pivot
+// d+_k and backward pivot d-_k (k a multiple of CK) goes to the thread's
+// checkpoint scratch (ck[j * ns], 2 ceil(d / CK) values), and each pass that
+// needs a run of pivots in the other order recomputes the run from its
+// checkpoint into registers with the same operations (explicit FMAs), so the
+// values agree bit for bit with the first computation. Passes: forward pivots;
+// backward pivots with the forward ones of each run recomputed, giving the
+// twist index; z_k for k < r (forward pivots recomputed per run, consumed in
+// reverse); z_k for k > r (backward pivots recomputed per run from the next
+// run's checkpoint, consumed in order).
 template <bool ACC>
-__device__ double twisted_vec(const double* D, const double* E, const double* E2, int d, double lam, double small,
-                            double* xcol, size_t ld, double* scr, int ns, const double* R1 = nullptr,
-                            double* y = nullptr) {
-  constexpr int CH = 8;                        // scratch values prefetched per chunk
-  double* sp = scr;                            // d+_k at sp[k * ns]
-  double* sm = scr + (size_t)d * ns;           // d-_k at sm[k * ns]
-  double q = D[0] - lam;
-  if (fabs(q) < small) q = q < 0.0 ? -small : small;
-  sp[0] = q;
+__device__ double twisted_ck(const double* D, const double* E, const double* E2, int d, double lam, double small,
+                             double* xcol, size_t ld, double* ck, int ns, const double* R1 = nullptr,
+                             double* y = nullptr) {
+  constexpr int CK = 8;
+  const int nck = (d + CK - 1) / CK;
+  double* ckf = ck;                              // d+ at rows c CK
+  double* ckb = ck + (size_t)nck * ns;           // d- at rows c CK
+  auto guard = [&](double v) { return fabs(v) < small ? (v < 0.0 ? -small : small) : v; };
+  auto fwd = [&](double q, int k) { return guard(fma(-E2[k - 1], rcp_nr(q), D[k] - lam)); };   // d+_k
+  auto bwd = [&](double m, int k) { return guard(fma(-E2[k], rcp_nr(m), D[k] - lam)); };       // d-_k
+  double q = guard(D[0] - lam);
+  ckf[0] = q;
   for (int k = 1; k < d; ++k) {
-    q = (D[k] - lam) - E2[k - 1] * rcp_nr(q);
-    if (fabs(q) < small) q = q < 0.0 ? -small : small;
-    sp[(size_t)k * ns] = q;
+    q = fwd(q, k);
+    if ((k & (CK - 1)) == 0) ckf[(size_t)(k / CK) * ns] = q;
   }
-  double m = D[d - 1] - lam;
-  if (fabs(m) < small) m = m < 0.0 ? -small : small;
-  sm[(size_t)(d - 1) * ns] = m;
   int r = d - 1;
-  double best = fabs(q);                       // gamma_{d-1} = d+_{d-1}
-  for (int k0 = d - 2; k0 >= 0; k0 -= CH) {
-    double pv[CH];
+  double best = 3.0e300, m = 0.0;
+  for (int c = nck - 1; c >= 0; --c) {
+    const int k0 = c * CK;
+    double pv[CK];
+    pv[0] = ckf[(size_t)c * ns];
 #pragma unroll
-    for (int u = 0; u < CH; ++u) pv[u] = (k0 - u >= 0) ? sp[(size_t)(k0 - u) * ns] : 0.0;
+    for (int u = 1; u < CK; ++u) pv[u] = (k0 + u < d) ? fwd(pv[u - 1], k0 + u) : 0.0;
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int k = k0 - u;
-      if (k < 0) break;
-      const double a = D[k] - lam;
-      m = a - E2[k] * rcp_nr(m);
-      if (fabs(m) < small) m = m < 0.0 ? -small : small;
-      sm[(size_t)k * ns] = m;
-      const double gam = fabs(pv[u] + m - a);
+    for (int u = CK - 1; u >= 0; --u) {
+      const int k = k0 + u;
+      if (k >= d) continue;
+      double gam;
+      if (k == d - 1) {
+        m = guard(D[k] - lam);
+        gam = fabs(pv[u]);                       // gamma_{d-1} = d+_{d-1}
+      } else {
+        m = bwd(m, k);
+        gam = fabs(pv[u] + m - (D[k] - lam));
+      }
       if (gam < best) { best = gam; r = k; }
     }
+    ckb[(size_t)c * ns] = m;                     // d-_{k0}
   }
   double z = 1.0, nrm = 1.0;
   xcol[(size_t)r * ld] = 1.0;
   double y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
   if constexpr (ACC) { y0 = R1[r]; y1 = R1[(size_t)d + r]; y2 = R1[(size_t)2 * d + r]; y3 = R1[(size_t)3 * d + r]; }
-  for (int k0 = r - 1; k0 >= 0; k0 -= CH) {
-    double pv[CH];
+  auto acc = [&](int k, double zk) {
+    xcol[(size_t)k * ld] = zk;
+    nrm += zk * zk;
+    if constexpr (ACC) {
+      y0 += R1[k] * zk; y1 += R1[(size_t)d + k] * zk; y2 += R1[(size_t)2 * d + k] * zk; y3 += R1[(size_t)3 * d + k] * zk;
+    }
+  };
+  // k < r: z_k = -E_k z_{k+1} / d+_k
+  for (int c = (r - 1) / CK; r > 0 && c >= 0; --c) {
+    const int k0 = c * CK;
+    double pv[CK];
+    pv[0] = ckf[(size_t)c * ns];
 #pragma unroll
-    for (int u = 0; u < CH; ++u) pv[u] = (k0 - u >= 0) ? sp[(size_t)(k0 - u) * ns] : 1.0;
+    for (int u = 1; u < CK; ++u) pv[u] = (k0 + u < d) ? fwd(pv[u - 1], k0 + u) : 1.0;
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int k = k0 - u;
-      if (k < 0) break;
+    for (int u = CK - 1; u >= 0; --u) {
+      const int k = k0 + u;
+      if (k >= r) continue;
       z = -E[k] * z * rcp_nr(pv[u]);
-      xcol[(size_t)k * ld] = z;
-      nrm += z * z;
-      if constexpr (ACC) {
-        y0 += R1[k] * z; y1 += R1[(size_t)d + k] * z; y2 += R1[(size_t)2 * d + k] * z; y3 += R1[(size_t)3 * d + k] * z;
-      }
+      acc(k, z);
     }
   }
+  // k > r: z_k = -E_{k-1} z_{k-1} / d-_k
   z = 1.0;
-  for (int k0 = r + 1; k0 < d; k0 += CH) {
-    double mv[CH];
+  for (int c = (r + 1) / CK; c < nck; ++c) {
+    const int k0 = c * CK;
+    double mv[CK];
+    // d- over the run, downward from the next run's checkpoint (or from row d - 1)
+    double mm = (c + 1 < nck) ? ckb[(size_t)(c + 1) * ns] : 0.0;
 #pragma unroll
-    for (int u = 0; u < CH; ++u) mv[u] = (k0 + u < d) ? sm[(size_t)(k0 + u) * ns] : 1.0;
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
+    for (int u = CK - 1; u >= 0; --u) {
       const int k = k0 + u;
-      if (k >= d) break;
+      if (k >= d) { mv[u] = 1.0; continue; }
+      mm = (k == d - 1) ? guard(D[k] - lam) : bwd(mm, k);
+      mv[u] = mm;
+    }
+#pragma unroll
+    for (int u = 0; u < CK; ++u) {
+      const int k = k0 + u;
+      if (k <= r || k >= d) continue;
       z = -E[k - 1] * z * rcp_nr(mv[u]);
-      xcol[(size_t)k * ld] = z;
-      nrm += z * z;
-      if constexpr (ACC) {
-        y0 += R1[k] * z; y1 += R1[(size_t)d + k] * z; y2 += R1[(size_t)2 * d + k] * z; y3 += R1[(size_t)3 * d + k] * z;
-      }
+      acc(k, z);
     }
   }
   if constexpr (ACC) { y[0] = y0; y[1] = y1; y[2] = y2; y[3] = y3; }
@@ -514,7 +628,8 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
       R1[q] = r1[(size_t)c * dmax + m];
     }
 
-    // ---- 2. tridiagonal S, Gershgorin interval, eigenvalues by bisection
+    // ---- 2. tridiagonal S, Gershgorin interval, eigenvalues (multisection
+    // round, then bisection and Laguerre's iteration per eigenvalue)
     double glo = 1e300, ghi = -1e300, e2m = 0.0;
     for (int k = tid; k < d; k += nt) {
       const double Dk = tri[k];
@@ -554,13 +669,8 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
         const int im = (il + ih) >> 1;
         if (cnt_s[im] <= t) il = im; else ih = im;
       }
-      double l = il < 0 ? lo0 : lo0 + (il + 1) * hg, h = ih >= nt ? hi0 : lo0 + (ih + 1) * hg;
-      for (int it = 0; it < 128; ++it) {
-        const double m = 0.5 * (l + h);
-        if (sturm_count_fast(Dg, E2s, d, m, pivmin) <= t) l = m; else h = m;
-        if (h - l <= 4.0 * DBL_EPSILON * fmax(fabs(l), fabs(h)) + pivmin) break;
-      }
-      lam_s[t] = 0.5 * (l + h);
+      const double l = il < 0 ? lo0 : lo0 + (il + 1) * hg, h = ih >= nt ? hi0 : lo0 + (ih + 1) * hg;
+      lam_s[t] = eig_laguerre(Dg, E2s, d, t, l, h, il < 0 ? 0 : cnt_s[il], ih >= nt ? d : cnt_s[ih], anorm, pivmin);
     }
     __syncthreads();
     // ---- 3. clusters and inverse iteration
@@ -590,7 +700,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
           // which also forms Y[0:4, t] = Z[0:4, :] U[:, t]; the outputs of
           // the column are written here and skipped in step 4
           double ya[4];
-          const double sc = twisted_vec<true>(Dg, Eg, E2, d, lam_s[t], small, xc, dmax, scr, nt, R1, ya);
+          const double sc = twisted_ck<true>(Dg, Eg, E2, d, lam_s[t], small, xc, dmax, scr, nt, R1, ya);
           vsc[t] = sc;
           double* y1o = g.y1 + (size_t)atom * 4 * dmax;
           const double a0 = ya[0] * sc, a1 = ya[1] * sc, a2 = ya[2] * sc, a3 = ya[3] * sc;
@@ -663,7 +773,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
 // Orbital seeds: T is the direct sum of four scalar chains, chain c on the
 // rows 4k + c (k < K) of the block layout (A_k, B_k diagonal). Each chain is
 // its own symmetric tridiagonal (D = alpha^c, E = beta^c) and is solved on
-// its own, with no band reduction (Z = I, an empty rotation log): bisection
+// its own, with no band reduction (Z = I, an empty rotation log): Laguerre
 // on the chain's Sturm sequence, clusters only among the chain's own
 // eigenvalues, eigenvectors by twisted factorisation or inverse iteration on
 // the chain, written to the rows 4k + c of U (the other rows zero).
@@ -732,13 +842,8 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
       const int c = t / K, j = t - c * K;
       const double* Dc = Dg + c * Kp;
       const double* E2c = E2s + c * Kp;
-      double l = lo0, h = hi0;
-      for (int it = 0; it < 128; ++it) {
-        const double m = 0.5 * (l + h);
-        if (sturm_count_fast(Dc, E2c, Kp, m, pivmin) <= j) l = m; else h = m;
-        if (h - l <= 4.0 * DBL_EPSILON * fmax(fabs(l), fabs(h)) + pivmin) break;
-      }
-      lam_s[t] = 0.5 * (l + h);
+      // the padded rows (D = 1e30) are roots far above the chain's spectrum
+      lam_s[t] = eig_laguerre(Dc, E2c, Kp, j, lo0, hi0, 0, K, anorm, pivmin);
     }
     __syncthreads();
     const double ctol = fmax(1e-6 * anorm, 1e-5);
@@ -772,7 +877,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
         const double* E2c = E2 + c * Kp;
         double* xc = Ua + (size_t)c * dmax + t;
         if (round == 0 && (t + 1 >= cend || pos_s[t + 1] == 0)) {
-          vsc[t] = twisted_vec<false>(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
+          vsc[t] = twisted_ck<false>(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
           continue;
         }
         vsc[t] = 1.0;                                // normalised below

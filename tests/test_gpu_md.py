@@ -53,7 +53,8 @@ def test_tbenergy_backward_is_minus_force(torch_cuda):
     assert torch.equal(pos.grad, -2.5 * f)
     # the backward of an earlier forward, after the context solved another
     # geometry, repeats that forward's solve and gives its own forces
-    pos2 = (pos.detach() + 0.01).requires_grad_(True)
+    shift = torch.tensor(rng.normal(0, 0.01, (60, 3)), dtype=torch.float64, device="cuda:0")
+    pos2 = (pos.detach() + shift).requires_grad_(True)
     E1 = TBEnergy.apply(pos, ff)
     E2 = TBEnergy.apply(pos2, ff)
     (g1,) = torch.autograd.grad(-0.5 * E1, pos)
