@@ -74,8 +74,8 @@ extern "C" int tb_destroy(tb_ctx* c) {
   hipSetDevice(c->device);
   void* ptrs[] = {c->hop_n, c->hop_j, c->hop_rev, c->hop_d, c->pair64, c->pair32, c->clu_n, c->clu_j,
                   c->loc_off, c->loc_ent, c->hnorm, c->jloc, c->row_ptr, c->col_j, c->vbuf, c->tab,
-                  c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->rot_cs, c->rot_p,
-                  c->rot_n, c->seg, c->seg_n, c->evec, c->tri, c->eig_scratch, c->omega, c->mu_state, c->partial, c->xrep, c->eparts, c->stats,
+                  c->kused, c->vj, c->work_counter, c->lam, c->wgt, c->y1, c->ref_v, c->ref_p,
+                  c->ref_n, c->seg, c->seg_n, c->evec, c->tri, c->eig_scratch, c->omega, c->mu_state, c->partial, c->xrep, c->eparts, c->stats,
                   c->cell_of, c->cell_atoms, c->cell_cnt, c->cell_start, c->wpart, c->virial, c->vsc};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -117,9 +117,8 @@ extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int6
   c->zmax = hop_max;
   c->emax = (int64_t)n_cluster_max * hop_max;
   const int64_t dmax = 4 * (int64_t)r_max;
-  // band -> tridiagonal takes fewer than (1/8 + 1/6 + 1/4) d^2 + 3 d rotations
-  c->rot_max = (3 * dmax * dmax) / 4 + 16 * dmax;
-  if (c->rot_max > 65535 * 16) c->rot_max = 65535 * 16;
+  // band -> tridiagonal: reflectors of length 4, about d^2 / 8 of them
+  c->ref_max = band_reflectors((int)dmax);
 
   // persistent Krylov workgroups: as many as fit on the device at once
   const size_t lds = lanczos_lds_bytes(n_cluster_max, r_max, false, 512, false, false, false);
@@ -196,10 +195,10 @@ extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int6
   ALLOC(lam, N * dmax);
   ALLOC(wgt, N * dmax);
   ALLOC(y1, N * 4 * dmax);
-  ALLOC(rot_cs, N * c->rot_max * 2);
-  ALLOC(rot_p, N * c->rot_max);
-  ALLOC(rot_n, N);
-  c->seg_max = (int)(16 * dmax + 64);
+  ALLOC(ref_v, N * c->ref_max * 4);
+  ALLOC(ref_p, N * c->ref_max);
+  ALLOC(ref_n, N);
+  c->seg_max = band_segments((int)dmax);
   ALLOC(seg, N * c->seg_max);
   ALLOC(seg_n, 2 * N);
   ALLOC(evec, N * dmax * dmax);
@@ -232,7 +231,7 @@ extern "C" int tb_create_ex(tb_ctx** out, int hip_device, void* hip_stream, int6
   HIP_TRY(hipMemset(c->stats, 0, ST_NSTATS * sizeof(int64_t)));
   HIP_TRY(hipMemset(c->mu_state, 0, mu_state_doubles() * sizeof(double)));
   HIP_TRY(hipMemset(c->kused, 0, N * sizeof(int)));
-  HIP_TRY(hipMemset(c->rot_n, 0, N * sizeof(int)));
+  HIP_TRY(hipMemset(c->ref_n, 0, N * sizeof(int)));
   HIP_TRY(hipMemset(c->seg_n, 0, 2 * N * sizeof(int)));
   HIP_TRY(hipDeviceSynchronize());
   c->nnz_pairs = -1;
@@ -349,7 +348,7 @@ static EigArgs eig_args(const tb_ctx* c, int n) {
   EigArgs ea;
   ea.atom0 = 0; ea.n_atoms = n; ea.r_max = c->r_max; ea.tab = c->tab; ea.kused = c->kused;
   ea.lam = c->lam; ea.wgt = c->wgt; ea.y1 = c->y1;
-  ea.rot_cs = c->rot_cs; ea.rot_p = c->rot_p; ea.rot_n = c->rot_n; ea.rot_max = c->rot_max;
+  ea.ref_v = c->ref_v; ea.ref_p = c->ref_p; ea.ref_n = c->ref_n; ea.ref_max = c->ref_max;
   ea.seg = c->seg; ea.seg_n = c->seg_n; ea.seg_max = c->seg_max;
   ea.counter = c->work_counter + 1; ea.scratch = c->eig_scratch; ea.evec = c->evec; ea.vsc = c->vsc; ea.tri = c->tri;
   ea.stats = c->stats;
@@ -423,8 +422,8 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   // K7: density-matrix blocks
   RhoArgs ra;
   ra.n_atoms = n; ra.r_max = c->r_max; ra.kused = c->kused; ra.hop_n = c->hop_n; ra.clu_j = c->clu_j;
-  ra.nc_max = c->nc_max; ra.zmax = c->zmax; ra.lam = c->lam; ra.y1 = c->y1; ra.rot_cs = c->rot_cs; ra.rot_p = c->rot_p;
-  ra.rot_n = c->rot_n; ra.rot_max = c->rot_max;
+  ra.nc_max = c->nc_max; ra.zmax = c->zmax; ra.lam = c->lam; ra.y1 = c->y1; ra.ref_v = c->ref_v; ra.ref_p = c->ref_p;
+  ra.ref_n = c->ref_n; ra.ref_max = c->ref_max;
   ra.seg = c->seg; ra.seg_n = c->seg_n; ra.seg_max = c->seg_max; ra.evec = c->evec; ra.vsc = c->vsc; ra.vj = c->vj; ra.vj_fp32 = fp32 ? 1 : 0;
   ra.row_ptr = c->row_ptr; ra.mu_state = c->mu_state; ra.kT = kT; ra.rho = rho_out; ra.stats = c->stats;
   pk = prof_begin(c, 4);

@@ -1,17 +1,23 @@
 // Projected eigenproblem and density-matrix assembly (Sec. 3: the small
 // projected matrix is diagonalised; Sec. 2, Eq. 2: rho = sum |m> f <m|).
 //
-// k_band (one wave per atom) and k_eig (one persistent 256-thread workgroup
-// per atom at a time), FP64:
-//   1. k_band (two atoms per wave): T (block tridiagonal, 4x4 blocks A_k, upper-triangular B_k: a band of
-//      half-width 4) -> tridiagonal S = Z^T T Z by Givens rotations, one
-//      diagonal at a time (half-width bc -> bc-1 for bc = 4, 3, 2). The fill-in
-//      of each rotation is chased down the band; chase j starts at time j * I
-//      and advances one rotation per time step, and with I * bc - 1 >= bc + 3
-//      concurrent rotations touch disjoint entries, so each time step applies
-//      one rotation per active chase in parallel. Every rotation is applied to
-//      the first four rows of Z and logged (c, s, plane) with one segment per
-//      time step. D, E of S and Z[0:4, :] go to HBM.
+// k_band (one wave per atom) and k_eig (one persistent workgroup per atom at
+// a time), FP64:
+//   1. k_band: T (block tridiagonal, 4x4 blocks A_k, upper-triangular B_k: a
+//      band of half-width 4) -> tridiagonal S = Z^T T Z by Householder
+//      reflectors of length 4 with bulge chasing. Sweep j annihilates
+//      column j below its subdiagonal with a reflector on rows j+1..j+4;
+//      applied from both sides it fills a 4x4 bulge below the window, whose
+//      first column the sweep's next task annihilates with a reflector four
+//      rows further down, and so on to the end of the matrix (the fill stays
+//      within seven diagonals below the main one). Task (j, s) is the s-th of
+//      sweep j, its window at row p0 = j + 1 + 4 s; it runs at time step
+//      3 j + s, so the tasks of one step are 11 rows apart and touch
+//      disjoint entries: each step runs all its tasks at once, four lanes
+//      per task. Every reflector is applied to the first four rows of Z and
+//      logged (v, tau, p0); two consecutive time steps form one segment of
+//      commuting reflectors (disjoint row windows). D, E of S and Z[0:4, :]
+//      go to HBM.
 //   2. k_eig: eigenvalues of S, one thread per eigenvalue index (all in
 //      parallel): a multisection round on a grid of Sturm counts, bisection
 //      until the eigenvalue is alone in its bracket, then Laguerre's
@@ -28,14 +34,13 @@
 //   4. Y[0:4, :] = Z[0:4, :] U, weights w_m = ||Y[0:4, m]||^2, Ritz values.
 //
 // k_rho (after the chemical potential is known): x = U (f(Lambda) Y[0:4,:]^T),
-// then c = Z x by replaying the logged band rotations in reverse (steps in
-// reverse order, the rotations of one step in parallel), and
+// then c = Z x by replaying the logged reflectors in reverse (segments in
+// reverse order, the reflectors of one segment in parallel), and
 // rho_{J,i} = V_J c for the rho row atoms J.
 //
-// Rotation convention: a logged (c, s, p) acts on the column pair (p, p+1)
-// of a row vector set R as R_p <- c R_p + s R_{p+1}, R_{p+1} <- -s R_p + c R_{p+1}
-// (R <- R G^T); Z is the ordered product of all these, so Z x is the reverse
-// replay x_p <- c x_p - s x_{p+1}, x_{p+1} <- s x_p + c x_{p+1}.
+// Reflector convention: a logged (v1, v2, v3, tau, p0) is H = I - tau v v^T
+// with v = (1, v1, v2, v3) on rows p0 .. p0+3; T <- H T H in order of the
+// log, Z = H_1 H_2 ... H_n, so Z x applies H_n first.
 #include <float.h>
 
 #include "tb_internal.h"
@@ -43,35 +48,28 @@
 namespace tbk {
 
 constexpr int EIG_NT = 256;
-constexpr int BAND_NT = 64;
-constexpr int RHO_NT = 256;     // k_rho: four waves per atom
-constexpr int RHO_SEGW = 256;      // segment-table window of k_rho
-constexpr int RHO_ROTW = 512;      // rotation-log window of k_rho (>= rotations of any one segment)
+constexpr int BAND_NT = 64;        // k_band: one wave per atom
+constexpr int RHO_NT = 256;        // k_rho: four waves per atom
+constexpr int RHO_REFW = 512;      // reflector-log window of k_rho (>= reflectors of any one segment)
 constexpr int BW = 4;              // half-bandwidth of T
-constexpr int LB = BW + 2;         // stored lower diagonals incl. the bulge
+constexpr int SBR_NB = 8;          // stored lower diagonals of k_band (the fill reaches 7)
+constexpr int SBR_LAG = 3;         // time steps between the starts of consecutive sweeps
 
-// LDS layout of one atom in k_band. The lanes of a chase step work on planes
-// 7, 8 or 5 rows apart (stages bc = 4, 3, 2); a plain row stride of LB = 6
-// doubles put the 8-row spacing on a quarter of the LDS banks. Skewed row and
-// column offsets give every lane of a 16- or 32-lane group its own bank pair
-// at all three spacings.
-__host__ __device__ inline int lb_row(int j) {           // band row j = -1 .. d-1
-  const int r = j + 1;
-  return r * LB + ((3 * r) >> 2);
-}
-__host__ __device__ inline int r1_col(int m) { return m + ((3 * m) >> 4); }
-__host__ __device__ inline int r1_stride(int d) { return r1_col(d - 1) + 1; }
-
-// Row m of the 4-column vectors in k_rho's LDS: the replay's lanes touch rows
-// 7, 8 or 5 apart and the final product consecutive rows; this skew gives
-// each lane of a 16- or 32-lane group its own bank pair in all four cases.
+// Row m of the 4-column vectors in k_rho's LDS (skewed against bank conflicts).
 __host__ __device__ inline int xrow(int m) { return 4 * m + ((3 * m) >> 3); }
 
-// LDS doubles of one atom in k_band: band rows -1 .. dmax-1 and Z[0:4, :].
-__host__ __device__ inline size_t band_atom_doubles(int r_max) {
-  const int dmax = 4 * r_max;
-  return (size_t)(lb_row(dmax - 1) + LB) + 4 * (size_t)r1_stride(dmax);
+// Columns of k_band's band storage: the matrix's plus the rows and columns a
+// window at the end may reach (zero, and they stay zero).
+__host__ __device__ inline int band_cols(int dmax) { return dmax + 8; }
+
+// Reflectors of the reduction of a d x d T: sweep j (j = 0 .. d-3) has
+// floor((d - 3 - j) / 4) + 1 tasks; replay segments: two time steps each.
+int64_t band_reflectors(int d) {
+  int64_t n = 0;
+  for (int j = 0; j + 3 <= d; ++j) n += (d - 3 - j) / 4 + 1;
+  return n > 0 ? n : 1;
 }
+int band_segments(int d) { return d >= 3 ? (3 * (d - 3) + 1 + 1) / 2 + 1 : 1; }
 
 __device__ __forceinline__ double t_entry(const double* tab, int row, int col) {
   // lower triangle (row >= col) of the block tridiagonal T
@@ -79,14 +77,6 @@ __device__ __forceinline__ double t_entry(const double* tab, int row, int col) {
   if (kr == kc) return tab[(size_t)kc * 32 + ar * 4 + ac];
   if (kr == kc + 1) return (ar <= ac) ? tab[(size_t)kc * 32 + 16 + ar * 4 + ac] : 0.0;
   return 0.0;
-}
-
-// Givens pair from (x, y): r = hypot(x, y), c = x / r, s = y / r.
-__device__ __forceinline__ void givens(double x, double y, double& c, double& s, double& r) {
-  const double q = x * x + y * y;
-  if (q == 0.0) { c = 1.0; s = 0.0; r = 0.0; return; }
-  const double inv = rsqrt(q);
-  c = x * inv; s = y * inv; r = q * inv;
 }
 
 // Number of eigenvalues of the tridiagonal (D, E^2) below sigma: the number
@@ -425,175 +415,153 @@ __device__ double twisted_ck(const double* D, const double* E, const double* E2,
   return 1.0 / sqrt(nrm);
 }
 
-// One time step of the chases that reduce the half-bandwidth from BC to BC-1,
-// for the atom of one half-wave (32 lanes; hl = lane within the half, hm =
-// the half's lane mask). Lb points at row 0 of the band storage; row -1
-// exists and is zero, and the entries of rows p past the matrix end are zero,
-// so the rotation needs no bounds tests (rotating zeros gives zeros). Lane hl
-// takes chase jtop - hl, then jtop - 32 - hl, ... until a batch has no active
-// chase.
-template <int BC>
-__device__ __forceinline__ void band_step(double* Lb, double* R1, int d, int rs, int tau, int hl, uint64_t hm,
-                                          uint64_t below, double* lcs, uint16_t* lp, int64_t rot_max,
-                                          int64_t& nrot) {
-  constexpr int I = (2 * BC + 3) / BC;       // ceil((BC + 4) / BC): 2, 3, 3
-  const int last = d - BC - 1;
-  int jtop = tau / I;
-  if (jtop > last) jtop = last;
-  // chase j is at plane p = BC tau + BC - 1 - j (I BC - 1) and active while
-  // p + 1 <= d - 1: the active chases are j >= jmin, so batches below jmin
-  // (all inactive) are not visited
-  const int num = BC * tau + BC + 1 - d;
-  const int jmin = num > 0 ? (num + I * BC - 2) / (I * BC - 1) : 0;
-  for (int jb = jtop; jb >= jmin; jb -= 32) {
-    const int j = jb - hl;
-    bool act = false;
-    int p = 0, u0 = 0;
-    if (j >= 0) {
-      const int st = tau - j * I;
-      p = j + BC - 1 + st * BC;
-      act = (p + 1 <= d - 1);
-      u0 = (st == 0) ? 1 : 0;               // the annihilated entry is T[q][p - BC + u0]
-    }
-    const bool batch_done = (__ballot(act) & hm) == 0ull;
-    double c = 1.0, s = 0.0;
-    if (act) {
-      const int q = p + 1, ml = p - BC;
-      const int op = lb_row(p), oq = lb_row(q), cp = r1_col(p), cq = r1_col(q);
-      double lu[BC], lv[BC], ru[BC], rv[BC], r1u[4], r1v[4];
-#pragma unroll
-      for (int u = 0; u < BC; ++u) {
-        const int om = lb_row(ml + u);
-        lu[u] = Lb[om + (BC - u)];                    // T[p][m], m = ml + u
-        lv[u] = Lb[om + (BC + 1 - u)];                // T[q][m]
-        ru[u] = Lb[op + 2 + u];                       // T[p + 2 + u][p]
-        rv[u] = Lb[oq + 1 + u];                       // T[p + 2 + u][q]
-      }
-      const double da = Lb[op], db = Lb[op + 1], de = Lb[oq];
-#pragma unroll
-      for (int row = 0; row < 4; ++row) { r1u[row] = R1[row * rs + cp]; r1v[row] = R1[row * rs + cq]; }
-      const double x = u0 ? lu[1] : lu[0], y = u0 ? lv[1] : lv[0];
-      act = (y != 0.0);
-      if (act) {
-        double r;
-        givens(x, y, c, s, r);
-#pragma unroll
-        for (int u = 0; u < BC; ++u) {
-          const int om = lb_row(ml + u);
-          Lb[om + (BC - u)] = (u == u0) ? r : c * lu[u] + s * lv[u];
-          Lb[om + (BC + 1 - u)] = (u == u0) ? 0.0 : -s * lu[u] + c * lv[u];
-          Lb[op + 2 + u] = c * ru[u] + s * rv[u];
-          Lb[oq + 1 + u] = -s * ru[u] + c * rv[u];
-        }
-        const double cc = c * c, ss = s * s, cs = c * s;
-        Lb[op] = cc * da + 2.0 * cs * db + ss * de;
-        Lb[oq] = ss * da - 2.0 * cs * db + cc * de;
-        Lb[op + 1] = cs * (de - da) + (cc - ss) * db;
-#pragma unroll
-        for (int row = 0; row < 4; ++row) {
-          R1[row * rs + cp] = c * r1u[row] + s * r1v[row];
-          R1[row * rs + cq] = -s * r1u[row] + c * r1v[row];
-        }
-      }
-    }
-    // log in lane order (the rotations of one time step commute)
-    const uint64_t mask = __ballot(act) & hm;
-    const int64_t slot = nrot + __popcll(mask & below);
-    if (act && slot < rot_max) { lcs[2 * slot] = c; lcs[2 * slot + 1] = s; lp[slot] = (uint16_t)p; }
-    nrot += __popcll(mask);
-    if (batch_done) break;
+// Band -> tridiagonal reduction, one wave per atom. LDS: the lower band
+// L[c * 8 + t] = A[c + t][c] (t < SBR_NB) over band_cols(dmax) columns, then
+// the first four rows of Z (row stride band_cols). At time step t the
+// active sweeps are j in [jmin, jmax] with task s = t - 3 j and window p0 =
+// 4 t + 1 - 11 j <= d - 2; lanes 4 g .. 4 g + 3 take task jmax - g (then -16,
+// -32 ... while tasks remain). Each of the four lanes of a task forms the
+// reflector from the column it annihilates, then lane q transforms: the
+// column p0 - 3 + q left of the window (q < 3, tasks after the first of a
+// sweep), row q of the symmetric 4x4 window block (rank-2 form
+// A <- A - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau A v; the four p_q
+// summed over the quad by shuffles), row p0 + 4 + q below the window, and
+// row q of Z. Every lane loads everything it needs before any store, and the
+// LDS operations of a wave complete in issue order; wave-scope fences order
+// the time steps.
+__global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
+  extern __shared__ double bsm[];
+  const int lane = threadIdx.x;
+  const int atom = g.atom0 + blockIdx.x;
+  if (atom >= g.n_atoms) return;
+  const int dmax = 4 * g.r_max;
+  const int nc = band_cols(dmax);
+  double* L = bsm;                                   // [nc][SBR_NB]
+  double* Zr = bsm + (size_t)nc * SBR_NB;            // [4][nc]
+  const int d = 4 * g.kused[atom];
+  const double* tab = g.tab + (size_t)atom * g.r_max * 32;
+  for (int q = lane; q < nc * SBR_NB; q += BAND_NT) {
+    const int c = q / SBR_NB, t = q % SBR_NB;
+    L[q] = (t <= BW && c + t < d) ? t_entry(tab, c + t, c) : 0.0;
   }
-}
-
-// A stage of chases. The rotations of MS consecutive time steps act on
-// pairwise disjoint planes (chase j is at plane 3 + 4 tau - 7 j for BC = 4,
-// 2 + 3 tau - 8 j for BC = 3, 1 + 2 tau - 5 j for BC = 2: within MS = 2, 3, 2
-// steps no two planes are closer than 2), so they commute and the reverse
-// replay takes them as one segment.
-template <int BC>
-__device__ __forceinline__ void band_stage(double* Lb, double* R1, int d, int rs, int hl, uint64_t hm, uint64_t below,
-                                           double* lcs, uint16_t* lp, int64_t rot_max, int64_t& nrot, int* seg,
-                                           int seg_max, int& nseg) {
-  constexpr int I = (2 * BC + 3) / BC;
-  constexpr int MS = BC == 3 ? 3 : 2;
-  const int nchase = d - BC;
-  if (nchase <= 0) return;
-  const int last = nchase - 1;
-  const int t_end = last * I + (d - 1 - last - BC) / BC + 1;
-  int64_t group_start = nrot;
-  for (int tau = 0; tau < t_end; ++tau) {
-    if (tau % MS == 0) group_start = nrot;
-    band_step<BC>(Lb, R1, d, rs, tau, hl, hm, below, lcs, lp, rot_max, nrot);
-    if ((tau % MS == MS - 1 || tau == t_end - 1) && nrot > group_start) {   // one segment per group
-      if (hl == 0 && nseg < seg_max) seg[nseg] = (int)group_start;
-      ++nseg;
-    }
-    // the LDS operations of one wave complete in issue order: a wave-scope
-    // fence orders the time steps
+  for (int q = lane; q < 4 * nc; q += BAND_NT) Zr[q] = (q % nc == q / nc) ? 1.0 : 0.0;
+  auto wave_sync = [] {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  wave_sync();
+  double* lv = g.ref_v + (size_t)atom * g.ref_max * 4;
+  uint16_t* lp = g.ref_p + (size_t)atom * g.ref_max;
+  int* seg = g.seg + (size_t)atom * g.seg_max;
+  const int grp = lane >> 2, q = lane & 3, qb = lane & ~3;
+  int64_t nref = 0;
+  int nseg = 0;
+  const int T = d >= 3 ? SBR_LAG * (d - 3) + 1 : 0;
+  for (int t = 0; t < T; ++t) {
+    if ((t & 1) == 0) {                             // a segment: time steps t, t + 1
+      if (lane == 0 && nseg < g.seg_max) seg[nseg] = (int)nref;
+      ++nseg;
+    }
+    const int jmax = min(t / SBR_LAG, d - 3);
+    const int num = 4 * t + 3 - d;
+    const int jmin = num > 0 ? (num + 10) / 11 : 0;
+    const int ntask = jmax - jmin + 1;
+    for (int b0 = 0; b0 < ntask; b0 += 16) {
+      const int ti = b0 + grp;
+      if (ti < ntask) {
+        const int j = jmax - ti, s = t - SBR_LAG * j;
+        const int p0 = 4 * t + 1 - 11 * j;          // = j + 1 + 4 s
+        const int col = s == 0 ? j : p0 - 4;        // the column annihilated
+        const double* Lc = L + (size_t)col * SBR_NB + (p0 - col);
+        const double x0 = Lc[0], x1 = Lc[1], x2 = Lc[2], x3 = Lc[3];
+        // reflector H = I - tau v v^T, v = (1, v1, v2, v3), H x = (beta, 0, 0, 0)
+        const double sig = x1 * x1 + x2 * x2 + x3 * x3;
+        double v1 = 0.0, v2 = 0.0, v3 = 0.0, tau = 0.0, beta = x0;
+        if (sig != 0.0) {
+          const double mu = sqrt(fma(x0, x0, sig));
+          beta = x0 >= 0.0 ? -mu : mu;
+          const double iv0 = 1.0 / (x0 - beta);
+          v1 = x1 * iv0; v2 = x2 * iv0; v3 = x3 * iv0;
+          tau = (beta - x0) / beta;
+        }
+        const double vv[4] = {1.0, v1, v2, v3};
+        const double vq = vv[q];
+        // loads: left column, window row q, row below, Z row
+        const bool left = s > 0 && q < 3;
+        const int cl = p0 - 3 + q;
+        double ya[4], yd[4], yr[4], yz[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ya[i] = left ? L[(size_t)cl * SBR_NB + (p0 + i - cl)] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          yd[m] = m <= q ? L[(size_t)(p0 + m) * SBR_NB + (q - m)] : L[(size_t)(p0 + q) * SBR_NB + (m - q)];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) yr[m] = L[(size_t)(p0 + m) * SBR_NB + (4 + q - m)];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) yz[m] = Zr[(size_t)q * nc + p0 + m];
+        // left column and row below and Z row: y <- H y
+        const double da = ya[0] + v1 * ya[1] + v2 * ya[2] + v3 * ya[3];
+        const double dr = yr[0] + v1 * yr[1] + v2 * yr[2] + v3 * yr[3];
+        const double dz = yz[0] + v1 * yz[1] + v2 * yz[2] + v3 * yz[3];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          ya[i] -= tau * da * vv[i];
+          yr[i] -= tau * dr * vv[i];
+          yz[i] -= tau * dz * vv[i];
+        }
+        // window block: p_q = tau (A v)_q, K = (tau/2) sum p v, w = p - K v
+        const double pq = tau * (yd[0] + v1 * yd[1] + v2 * yd[2] + v3 * yd[3]);
+        double kq = pq * vq;
+        kq += __shfl_xor(kq, 1, 64);
+        kq += __shfl_xor(kq, 2, 64);
+        const double wq = pq - 0.5 * tau * kq * vq;
+        double wm[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) wm[m] = __shfl(wq, qb + m, 64);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) yd[m] -= vq * wm[m] + wq * vv[m];
+        // stores
+        L[(size_t)col * SBR_NB + (p0 + q - col)] = q == 0 ? beta : 0.0;
+        if (left) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) L[(size_t)cl * SBR_NB + (p0 + i - cl)] = ya[i];
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          if (m <= q) L[(size_t)(p0 + m) * SBR_NB + (q - m)] = yd[m];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) L[(size_t)(p0 + m) * SBR_NB + (4 + q - m)] = yr[m];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) Zr[(size_t)q * nc + p0 + m] = yz[m];
+        const int64_t slot = nref + ti;
+        if (q == 0 && slot < g.ref_max) {
+          *(double4*)(lv + 4 * slot) = make_double4(v1, v2, v3, tau);
+          lp[slot] = (uint16_t)p0;
+        }
+      }
+    }
+    nref += ntask > 0 ? ntask : 0;
+    wave_sync();
   }
-}
-
-// Band -> tridiagonal reduction: one half-wave (32 lanes) per atom, one lane
-// per chase; pw = 2 atoms per wave share the instruction stream (pw = 1 when
-// two atoms' band storage does not fit in LDS: the upper half-wave idles).
-__global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g, int pw) {
-  extern __shared__ double bsm[];
-  const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
-  const int atom = g.atom0 + pw * blockIdx.x + half;
-  const bool valid = half < pw && atom < g.n_atoms;
-  const int dmax = 4 * g.r_max;
-  const int d = valid ? 4 * g.kused[atom] : 0;
-  const uint64_t hm = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
-  const uint64_t below = ((1ull << lane) - 1ull) & hm;
-  double* Lb = bsm + (size_t)half * band_atom_doubles(g.r_max);  // row j at lb_row(j): Lb[t] = T[j+t][j]; row -1 zero
-  double* R1 = Lb + lb_row(dmax - 1) + LB;                        // [4][rs]: first rows of the transform
-  const int rs = r1_stride(d > 0 ? d : 1);
-  if (valid) {
-    const double* tab = g.tab + (size_t)atom * g.r_max * 32;
-    for (int q = hl; q < (d + 1) * LB; q += 32) {
-      const int j = q / LB - 1, t = q % LB;
-      const int row = j + t;
-      Lb[lb_row(j) + t] = (j >= 0 && t <= BW && row < d) ? t_entry(tab, row, j) : 0.0;
-    }
-    for (int q = hl; q < 4 * d; q += 32) {
-      const int c = q / d, m = q % d;
-      R1[c * rs + r1_col(m)] = (m == c) ? 1.0 : 0.0;
-    }
+  if (lane == 0) {
+    g.ref_n[atom] = (int)(nref < g.ref_max ? nref : g.ref_max);
+    const int ns = nseg < g.seg_max ? nseg : g.seg_max;
+    g.seg_n[2 * atom] = ns;
+    g.seg_n[2 * atom + 1] = ns;
+    if (nseg > g.seg_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_SEG_OVERFLOW);
+    if (nref > g.ref_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_REFLOG_OVERFLOW);
   }
-  __syncthreads();
-  if (valid) {
-    double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
-    uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
-    int* seg = g.seg + (size_t)atom * g.seg_max;
-    int64_t nrot = 0;
-    int nseg = 0;
-    band_stage<4>(Lb, R1, d, rs, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
-    band_stage<3>(Lb, R1, d, rs, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
-    band_stage<2>(Lb, R1, d, rs, hl, hm, below, lcs, lp, g.rot_max, nrot, seg, g.seg_max, nseg);
-    if (hl == 0) {
-      g.rot_n[atom] = (int)(nrot < g.rot_max ? nrot : g.rot_max);
-      g.seg_n[2 * atom] = nseg < g.seg_max ? nseg : g.seg_max;
-      g.seg_n[2 * atom + 1] = nseg < g.seg_max ? nseg : g.seg_max;
-      if (nseg > g.seg_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_SEG_OVERFLOW);
-      if (nrot > g.rot_max) atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
-    }
+  // tridiagonal S (D, E) and Z[0:4, :]
+  double* tri = g.tri + (size_t)atom * 2 * dmax;
+  double* r1 = g.y1 + (size_t)atom * 4 * dmax;
+  for (int k = lane; k < d; k += BAND_NT) {
+    tri[k] = L[(size_t)k * SBR_NB];
+    tri[dmax + k] = (k + 1 < d) ? L[(size_t)k * SBR_NB + 1] : 0.0;
   }
-  __syncthreads();
-  if (valid) {
-    // tridiagonal S (D, E) and Z[0:4, :]
-    double* tri = g.tri + (size_t)atom * 2 * dmax;
-    double* r1 = g.y1 + (size_t)atom * 4 * dmax;
-    for (int k = hl; k < d; k += 32) {
-      tri[k] = Lb[lb_row(k)];
-      tri[dmax + k] = (k + 1 < d) ? Lb[lb_row(k) + 1] : 0.0;
-    }
-    for (int q = hl; q < 4 * d; q += 32) {
-      const int c = q / d, m = q % d;
-      r1[(size_t)c * dmax + m] = R1[c * rs + r1_col(m)];
-    }
+  for (int qq = lane; qq < 4 * d; qq += BAND_NT) {
+    const int c = qq / d, m = qq % d;
+    r1[(size_t)c * dmax + m] = Zr[(size_t)c * nc + m];
   }
 }
 
@@ -921,7 +889,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
       for (int cc = 0; cc < 4; ++cc) y1[(size_t)cc * dmax + t] = (cc == c) ? a : 0.0;
     }
     if (tid == 0) {
-      g.rot_n[atom] = 0;
+      g.ref_n[atom] = 0;
       g.seg_n[2 * atom] = 0;
       g.seg_n[2 * atom + 1] = 0;
       atomicMax((unsigned long long*)&g.stats[ST_MAX_CLUSTER_POS], (unsigned long long)maxpos);
@@ -977,73 +945,79 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     if ((lane & 3) == 0) x[xrow(k0 + (which >> 2)) + (which & 3)] = sum;
   }
   __syncthreads();
-  // c = Z x: band steps in reverse; the rotations of one step commute. One
-  // wave replays them: the segment table and the rotation log are staged
-  // through LDS in windows (coalesced loads), and the steps are ordered by
-  // wave-scope fences.
+  // c = Z x: the reflector segments in reverse; the reflectors of one segment
+  // commute. One wave replays them: the segment table is staged in LDS, the
+  // reflector log in windows (coalesced loads), and the segments are ordered
+  // by wave-scope fences. Rows d .. d+3 of x are zero (windows at the end
+  // reach them; their reflector entries are zero).
   if (wave == 0) {
-  const double* lcs = g.rot_cs + (size_t)atom * g.rot_max * 2;
-  const uint16_t* lp = g.rot_p + (size_t)atom * g.rot_max;
-  const int* seg = g.seg + (size_t)atom * g.seg_max;
-  const int nrot = g.rot_n[atom];
-  const int nb = g.seg_n[2 * atom];
-  int* s_seg = (int*)(x + xrow(dmax - 1) + 4);                // [RHO_SEGW]
-  double* s_cs = (double*)(s_seg + RHO_SEGW);                // [RHO_ROTW][2]
-  uint16_t* s_p = (uint16_t*)(s_cs + 2 * RHO_ROTW);          // [RHO_ROTW]
-  int k = nb - 1;
-  while (k >= 0) {
-    // segment starts seg[k0 .. k]
-    const int k0 = k - RHO_SEGW + 1 > 0 ? k - RHO_SEGW + 1 : 0;
-    for (int q = k0 + lane; q <= k; q += 64) s_seg[q - k0] = seg[q];
-    const int en = (k + 1 < nb) ? seg[k + 1] : nrot;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // the window: segments kw .. k whose rotations fit in RHO_ROTW (at least one)
-    int kw = k;
-    for (int base = k; base >= k0; base -= 64) {
-      const int q = base - lane;
-      const bool fits = q >= k0 && en - s_seg[q - k0] <= RHO_ROTW;
-      const uint64_t m = __ballot(fits);
-      // lanes are ordered by decreasing q; the fitting ones form a prefix
-      const int nfit = __popcll(m);
-      if (nfit > 0) kw = base - nfit + 1;
-      if (nfit < 64) break;
-    }
-    const int w0 = s_seg[kw - k0];
-    if (en - w0 > RHO_ROTW) {         // one segment with more rotations than the window: not
-      if (lane == 0)                  // reached for d <= 1024 (at most 341 rotations per segment)
-        atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_ROTLOG_OVERFLOW);
-      break;
-    }
-    for (int e = w0 + lane; e < en; e += 64) {
-      const double2 cs = *(const double2*)(lcs + 2 * (size_t)e);
-      s_cs[2 * (e - w0)] = cs.x;
-      s_cs[2 * (e - w0) + 1] = cs.y;
-      s_p[e - w0] = lp[e];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int kk = k; kk >= kw; --kk) {
-      const int st = s_seg[kk - k0] - w0;
-      const int se = (kk == k ? en : s_seg[kk + 1 - k0]) - w0;
-      for (int e = st + lane; e < se; e += 64) {
-        const double c = s_cs[2 * e], s = s_cs[2 * e + 1];
-        const int p = s_p[e];
-        double* xp = x + xrow(p);
-        double* xq = x + xrow(p + 1);
-        const double a0 = xp[0], a1 = xp[1], a2 = xp[2], a3 = xp[3];
-        const double b0 = xq[0], b1 = xq[1], b2 = xq[2], b3 = xq[3];
-        xp[0] = c * a0 - s * b0; xp[1] = c * a1 - s * b1; xp[2] = c * a2 - s * b2; xp[3] = c * a3 - s * b3;
-        xq[0] = s * a0 + c * b0; xq[1] = s * a1 + c * b1; xq[2] = s * a2 + c * b2; xq[3] = s * a3 + c * b3;
-      }
+    const double* lv = g.ref_v + (size_t)atom * g.ref_max * 4;
+    const uint16_t* lp = g.ref_p + (size_t)atom * g.ref_max;
+    const int* seg = g.seg + (size_t)atom * g.seg_max;
+    const int nref = g.ref_n[atom];
+    const int nb = g.seg_n[2 * atom];
+    int* s_seg = (int*)(x + xrow(dmax + 3) + 4);                        // [seg_max]
+    double* s_v = (double*)(s_seg + ((g.seg_max + 3) & ~3));            // [RHO_REFW][4]
+    uint16_t* s_p = (uint16_t*)(s_v + 4 * RHO_REFW);                    // [RHO_REFW]
+    for (int q = lane; q < 16; q += 64) x[xrow(d + (q >> 2)) + (q & 3)] = 0.0;
+    for (int q = lane; q < nb; q += 64) s_seg[q] = seg[q];
+    auto wave_sync = [] {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    wave_sync();
+    int k = nb - 1;
+    while (k >= 0) {
+      const int en = (k + 1 < nb) ? s_seg[k + 1] : nref;
+      // the window: segments kw .. k whose reflectors fit in RHO_REFW (at least one)
+      int kw = k;
+      for (int base = k; base >= 0; base -= 64) {
+        const int qq = base - lane;
+        const bool fits = qq >= 0 && en - s_seg[qq] <= RHO_REFW;
+        const uint64_t msk = __ballot(fits);
+        // lanes are ordered by decreasing qq; the fitting ones form a prefix
+        const int nfit = __popcll(msk);
+        if (nfit > 0) kw = base - nfit + 1;
+        if (nfit < 64) break;
+      }
+      const int w0 = s_seg[kw];
+      if (en - w0 > RHO_REFW) {       // one segment with more reflectors than the window: not
+        if (lane == 0)                // reached for d <= 1024 (at most 2 (d / 11 + 1) per segment)
+          atomicOr((unsigned long long*)&g.stats[ST_FLAGS], (unsigned long long)FL_REFLOG_OVERFLOW);
+        break;
+      }
+      for (int e = w0 + lane; e < en; e += 64) {
+        *(double4*)(s_v + 4 * (size_t)(e - w0)) = *(const double4*)(lv + 4 * (size_t)e);
+        s_p[e - w0] = lp[e];
+      }
+      wave_sync();
+      for (int kk = k; kk >= kw; --kk) {
+        const int st = s_seg[kk] - w0;
+        const int se = (kk == k ? en : s_seg[kk + 1]) - w0;
+        for (int e = st + lane; e < se; e += 64) {
+          const double4 vt = *(const double4*)(s_v + 4 * (size_t)e);
+          const int p0 = s_p[e];
+          double* x0 = x + xrow(p0);
+          double* x1 = x + xrow(p0 + 1);
+          double* x2 = x + xrow(p0 + 2);
+          double* x3 = x + xrow(p0 + 3);
+          double a0[4], a1[4], a2[4], a3[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) { a0[c] = x0[c]; a1[c] = x1[c]; a2[c] = x2[c]; a3[c] = x3[c]; }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double f = vt.w * (a0[c] + vt.x * a1[c] + vt.y * a2[c] + vt.z * a3[c]);
+            x0[c] = a0[c] - f;
+            x1[c] = a1[c] - f * vt.x;
+            x2[c] = a2[c] - f * vt.y;
+            x3[c] = a3[c] - f * vt.z;
+          }
+        }
+        wave_sync();
+      }
+      k = kw - 1;
     }
-    k = kw - 1;
-  }
   }
   __syncthreads();
   // rho_{J,i}[4 js + a][col] = sum_m V_J[4 js + a][m] x[m][col]: four rows of
@@ -1081,13 +1055,15 @@ size_t eig_lds_bytes(int r_max) {
   const size_t chains = (4 * dp + dmax + 4 * (EIG_NT / 64)) * sizeof(double) + dmax * sizeof(int) + 64;
   return band > chains ? band : chains;
 }
-// atoms per k_band wave: two unless their band storage exceeds the LDS
-static int band_per_wave(int r_max) { return 2 * band_atom_doubles(r_max) * sizeof(double) + 64 <= LDS_CU ? 2 : 1; }
-size_t band_lds_bytes(int r_max) { return band_per_wave(r_max) * band_atom_doubles(r_max) * sizeof(double) + 64; }
+size_t band_lds_bytes(int r_max) {
+  const size_t nc = (size_t)band_cols(4 * r_max);
+  return (nc * SBR_NB + 4 * nc) * sizeof(double) + 64;
+}
 size_t rho_lds_bytes(int r_max) {
   const int dmax = 4 * r_max;
-  return ((size_t)dmax * 4 + xrow(dmax - 1) + 4) * sizeof(double) + RHO_SEGW * sizeof(int) +
-         RHO_ROTW * (2 * sizeof(double) + 2) + 64;
+  const size_t segs = ((size_t)band_segments(dmax) + 3) & ~(size_t)3;
+  return ((size_t)dmax * 4 + xrow(dmax + 3) + 4) * sizeof(double) + segs * sizeof(int) +
+         RHO_REFW * (4 * sizeof(double) + 2) + 64;
 }
 // Threads of a k_eig workgroup: one per eigenvalue of the largest T.
 int eig_threads(int r_max) {
@@ -1117,9 +1093,7 @@ void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
     hipLaunchKernelGGL(k_eig_chains, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
     return;
   }
-  const int pw = band_per_wave(a.r_max);
-  hipLaunchKernelGGL(k_band, dim3((a.n_atoms - a.atom0 + pw - 1) / pw), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a,
-                     pw);
+  hipLaunchKernelGGL(k_band, dim3(a.n_atoms - a.atom0), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
   hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
 }
 void launch_rho(const RhoArgs& a, hipStream_t st) {

@@ -40,7 +40,7 @@ enum StatSlot {
 };
 enum FlagBits {
   FL_HOP_OVERFLOW = 1, FL_CLUSTER_OVERFLOW = 2, FL_COUPLING_OVERFLOW = 4,
-  FL_NONFINITE = 8, FL_EIG_NOCONV = 16, FL_ROTLOG_OVERFLOW = 32, FL_SEG_OVERFLOW = 64,
+  FL_NONFINITE = 8, FL_EIG_NOCONV = 16, FL_REFLOG_OVERFLOW = 32, FL_SEG_OVERFLOW = 64,
   FL_GROUP_IMAGE = 128
 };
 
@@ -196,8 +196,8 @@ struct EigArgs {
   int atom0, n_atoms, r_max;           // target atoms [atom0, n_atoms) of this launch
   const double* tab; const int* kused;
   double* lam; double* wgt; double* y1;
-  double* rot_cs; uint16_t* rot_p; int* rot_n; int64_t rot_max;
-  int* seg; int* seg_n; int seg_max;   // [N][seg_max] segment starts; [N][2]: band steps, total
+  double* ref_v; uint16_t* ref_p; int* ref_n; int64_t ref_max;   // band reduction's reflector log
+  int* seg; int* seg_n; int seg_max;   // [N][seg_max] segment starts; [N][2]: segment counts
   int* counter;                        // persistent-kernel atom queue (zeroed before launch)
   double* scratch;                     // [WG][4 r_max][4][threads]: LU factors of inverse iteration
   double* evec;                        // [N][4 r_max][4 r_max]: eigenvectors of the tridiagonal, [k][t]
@@ -211,7 +211,7 @@ struct RhoArgs {
   const int* kused; const int* hop_n; const int* clu_j; int nc_max;
   int zmax;                            // hop-list capacity (rho rows per target: zmax + 1)
   const double* lam; const double* y1;
-  const double* rot_cs; const uint16_t* rot_p; const int* rot_n; int64_t rot_max;
+  const double* ref_v; const uint16_t* ref_p; const int* ref_n; int64_t ref_max;
   const int* seg; const int* seg_n; int seg_max;
   const double* evec; const double* vsc;
   const void* vj; int vj_fp32;
@@ -221,6 +221,8 @@ struct RhoArgs {
   int64_t* stats;
 };
 size_t eig_lds_bytes(int r_max);
+int64_t band_reflectors(int d);     // reflectors of the band reduction of a d x d T
+int band_segments(int d);           // replay segments of that reduction
 size_t rho_lds_bytes(int r_max);
 hipError_t eig_set_lds(int r_max);
 void launch_eig(const EigArgs& a, int n_wg, hipStream_t st);
@@ -277,7 +279,7 @@ struct tb_ctx {
   int64_t na_max;
   int nc_max, r_max;
   int64_t emax;          // couplings per sphere
-  int64_t rot_max;       // rotation-log entries per atom
+  int64_t ref_max;       // reflector-log entries per atom
   int n_cu;              // compute units of the device
   // launch shape of the Krylov kernel per precision ([0] FP64, [1] FP32, [2] BF16):
   // threads per workgroup, register budget (waves per SIMD) and persistent
@@ -322,7 +324,7 @@ struct tb_ctx {
   int* work_counter;     // persistent-kernel atom queue
   // eigen (K5/K7)
   double* lam; double* wgt; double* y1;                    // [N][D], [N][D], [N][4][D]
-  double* rot_cs; uint16_t* rot_p; int* rot_n;             // [N][ROT][2], [N][ROT], [N]
+  double* ref_v; uint16_t* ref_p; int* ref_n;             // [N][REF][4] (v1 v2 v3 tau), [N][REF] (row), [N]
   int* seg; int* seg_n; int seg_max;                       // [N][SEG], [N][2]
   double* evec;                                            // [N][D][D]
   double* vsc;                                             // [N][D] normalising factors of the evec columns

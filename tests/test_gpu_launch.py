@@ -138,12 +138,11 @@ def test_fp32_hv_layouts_agree(torch_cuda):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_band_one_atom_per_wave_agrees(torch_cuda, precision):
-    """The band reduction runs two atoms per wave while their band storage
-    fits in LDS together (r_max up to 222) and one atom per wave above that.
-    A context sized for r_max = 240 (one atom per wave) and one sized for
-    r_max = 30 (two per wave) give the same result on the same r = 30 run, to
-    rounding (the eigensolver's thread count also follows r_max)."""
+def test_large_r_max_capacity_agrees(torch_cuda, precision):
+    """The Krylov capacity r_max sizes the eigensolver's thread count, the band
+    storage of the reduction and the replay windows. A context sized for
+    r_max = 240 and one sized for r_max = 30 give the same result on the same
+    r = 30 run, to rounding."""
     from paper_0910_4497_amd.tb import TBContext
     w = inputs.workload("c60_240")
     runs = {}
