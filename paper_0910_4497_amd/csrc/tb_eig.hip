@@ -53,10 +53,16 @@ constexpr int RHO_NT = 256;        // k_rho: four waves per atom
 constexpr int RHO_REFW = 512;      // reflector-log window of k_rho (>= reflectors of any one segment)
 constexpr int BW = 4;              // half-bandwidth of T
 constexpr int SBR_NB = 8;          // stored lower diagonals of k_band (the fill reaches 7)
+constexpr int SBR_LS = 9;          // LDS doubles per band column: concurrent tasks are 11 columns
+                                   // apart, so a stride of 9 puts the 16 task groups of a wave on
+                                   // 16 different bank pairs (a stride of 8 put them on 2)
 constexpr int SBR_LAG = 3;         // time steps between the starts of consecutive sweeps
 
-// Row m of the 4-column vectors in k_rho's LDS (skewed against bank conflicts).
-__host__ __device__ inline int xrow(int m) { return 4 * m + ((3 * m) >> 3); }
+// Row m of the 4-column vectors in k_rho's LDS. The reflectors a replay step
+// applies at once start 11 rows apart; with this skew their 16 leading rows
+// in a wave fall on 16 different bank pairs (with a plain stride of 4
+// doubles, on 4).
+__host__ __device__ inline int xrow(int m) { return 4 * m + (m >> 3); }
 
 // Columns of k_band's band storage: the matrix's plus the rows and columns a
 // window at the end may reach (zero, and they stay zero).
@@ -416,8 +422,8 @@ __device__ double twisted_ck(const double* D, const double* E, const double* E2,
 }
 
 // Band -> tridiagonal reduction, one wave per atom. LDS: the lower band
-// L[c * 8 + t] = A[c + t][c] (t < SBR_NB) over band_cols(dmax) columns, then
-// the first four rows of Z (row stride band_cols). At time step t the
+// L[c * SBR_LS + t] = A[c + t][c] (t < SBR_NB) over band_cols(dmax) columns,
+// then the first four rows of Z (row stride zs, odd). At time step t the
 // active sweeps are j in [jmin, jmax] with task s = t - 3 j and window p0 =
 // 4 t + 1 - 11 j <= d - 2; lanes 4 g .. 4 g + 3 take task jmax - g (then -16,
 // -32 ... while tasks remain). Each of the four lanes of a task forms the
@@ -436,15 +442,16 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
   if (atom >= g.n_atoms) return;
   const int dmax = 4 * g.r_max;
   const int nc = band_cols(dmax);
-  double* L = bsm;                                   // [nc][SBR_NB]
-  double* Zr = bsm + (size_t)nc * SBR_NB;            // [4][nc]
+  const int zs = nc | 1;                             // Z row stride (odd: rows on different banks)
+  double* L = bsm;                                   // [nc][SBR_LS]
+  double* Zr = bsm + (size_t)nc * SBR_LS;            // [4][zs]
   const int d = 4 * g.kused[atom];
   const double* tab = g.tab + (size_t)atom * g.r_max * 32;
-  for (int q = lane; q < nc * SBR_NB; q += BAND_NT) {
-    const int c = q / SBR_NB, t = q % SBR_NB;
+  for (int q = lane; q < nc * SBR_LS; q += BAND_NT) {
+    const int c = q / SBR_LS, t = q % SBR_LS;
     L[q] = (t <= BW && c + t < d) ? t_entry(tab, c + t, c) : 0.0;
   }
-  for (int q = lane; q < 4 * nc; q += BAND_NT) Zr[q] = (q % nc == q / nc) ? 1.0 : 0.0;
+  for (int q = lane; q < 4 * zs; q += BAND_NT) Zr[q] = (q % zs == q / zs) ? 1.0 : 0.0;
   auto wave_sync = [] {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -473,7 +480,7 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
         const int j = jmax - ti, s = t - SBR_LAG * j;
         const int p0 = 4 * t + 1 - 11 * j;          // = j + 1 + 4 s
         const int col = s == 0 ? j : p0 - 4;        // the column annihilated
-        const double* Lc = L + (size_t)col * SBR_NB + (p0 - col);
+        const double* Lc = L + (size_t)col * SBR_LS + (p0 - col);
         const double x0 = Lc[0], x1 = Lc[1], x2 = Lc[2], x3 = Lc[3];
         // reflector H = I - tau v v^T, v = (1, v1, v2, v3), H x = (beta, 0, 0, 0)
         const double sig = x1 * x1 + x2 * x2 + x3 * x3;
@@ -492,14 +499,14 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
         const int cl = p0 - 3 + q;
         double ya[4], yd[4], yr[4], yz[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ya[i] = left ? L[(size_t)cl * SBR_NB + (p0 + i - cl)] : 0.0;
+        for (int i = 0; i < 4; ++i) ya[i] = left ? L[(size_t)cl * SBR_LS + (p0 + i - cl)] : 0.0;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-          yd[m] = m <= q ? L[(size_t)(p0 + m) * SBR_NB + (q - m)] : L[(size_t)(p0 + q) * SBR_NB + (m - q)];
+          yd[m] = m <= q ? L[(size_t)(p0 + m) * SBR_LS + (q - m)] : L[(size_t)(p0 + q) * SBR_LS + (m - q)];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) yr[m] = L[(size_t)(p0 + m) * SBR_NB + (4 + q - m)];
+        for (int m = 0; m < 4; ++m) yr[m] = L[(size_t)(p0 + m) * SBR_LS + (4 + q - m)];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) yz[m] = Zr[(size_t)q * nc + p0 + m];
+        for (int m = 0; m < 4; ++m) yz[m] = Zr[(size_t)q * zs + p0 + m];
         // left column and row below and Z row: y <- H y
         const double da = ya[0] + v1 * ya[1] + v2 * ya[2] + v3 * ya[3];
         const double dr = yr[0] + v1 * yr[1] + v2 * yr[2] + v3 * yr[3];
@@ -522,18 +529,18 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) yd[m] -= vq * wm[m] + wq * vv[m];
         // stores
-        L[(size_t)col * SBR_NB + (p0 + q - col)] = q == 0 ? beta : 0.0;
+        L[(size_t)col * SBR_LS + (p0 + q - col)] = q == 0 ? beta : 0.0;
         if (left) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) L[(size_t)cl * SBR_NB + (p0 + i - cl)] = ya[i];
+          for (int i = 0; i < 4; ++i) L[(size_t)cl * SBR_LS + (p0 + i - cl)] = ya[i];
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-          if (m <= q) L[(size_t)(p0 + m) * SBR_NB + (q - m)] = yd[m];
+          if (m <= q) L[(size_t)(p0 + m) * SBR_LS + (q - m)] = yd[m];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) L[(size_t)(p0 + m) * SBR_NB + (4 + q - m)] = yr[m];
+        for (int m = 0; m < 4; ++m) L[(size_t)(p0 + m) * SBR_LS + (4 + q - m)] = yr[m];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) Zr[(size_t)q * nc + p0 + m] = yz[m];
+        for (int m = 0; m < 4; ++m) Zr[(size_t)q * zs + p0 + m] = yz[m];
         const int64_t slot = nref + ti;
         if (q == 0 && slot < g.ref_max) {
           *(double4*)(lv + 4 * slot) = make_double4(v1, v2, v3, tau);
@@ -556,12 +563,12 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
   double* tri = g.tri + (size_t)atom * 2 * dmax;
   double* r1 = g.y1 + (size_t)atom * 4 * dmax;
   for (int k = lane; k < d; k += BAND_NT) {
-    tri[k] = L[(size_t)k * SBR_NB];
-    tri[dmax + k] = (k + 1 < d) ? L[(size_t)k * SBR_NB + 1] : 0.0;
+    tri[k] = L[(size_t)k * SBR_LS];
+    tri[dmax + k] = (k + 1 < d) ? L[(size_t)k * SBR_LS + 1] : 0.0;
   }
   for (int qq = lane; qq < 4 * d; qq += BAND_NT) {
     const int c = qq / d, m = qq % d;
-    r1[(size_t)c * dmax + m] = Zr[(size_t)c * nc + m];
+    r1[(size_t)c * dmax + m] = Zr[(size_t)c * zs + m];
   }
 }
 
@@ -1057,7 +1064,7 @@ size_t eig_lds_bytes(int r_max) {
 }
 size_t band_lds_bytes(int r_max) {
   const size_t nc = (size_t)band_cols(4 * r_max);
-  return (nc * SBR_NB + 4 * nc) * sizeof(double) + 64;
+  return (nc * SBR_LS + 4 * (nc | 1)) * sizeof(double) + 64;
 }
 size_t rho_lds_bytes(int r_max) {
   const int dmax = 4 * r_max;
