@@ -189,10 +189,12 @@ def lanczos_roofline(w_name, head_prec, head, shape, N, dev, torch):
     achieved = bytes_launch / (lz_avg_ms * 1e-3) / 1e9
     traffic = None
     if shape:
-        lz_kernel = "k_lanczos<{}, {}, {}, {}, {}>".format("double" if head_prec == "fp64" else "float",
-                                                          shape["lanczos_threads"], shape["lanczos_waves_per_simd"],
-                                                          "true" if head_prec == "bf16" else "false",
-                                                          "true" if shape.get("lanczos_wide") else "false")
+        layout = shape.get("lanczos_wide", 0)
+        lz_kernel = "k_lanczos<{}, {}, {}, {}, {}{}>".format("double" if head_prec == "fp64" else "float",
+                                                            shape["lanczos_threads"], shape["lanczos_waves_per_simd"],
+                                                            "true" if head_prec == "bf16" else "false",
+                                                            "true" if layout == 1 else "false",
+                                                            ", true" if layout == 2 else "")
         n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
         traffic = measured_traffic(w_name, head_prec, lz_kernel, min(n_cu * shape["lanczos_wg_per_cu"], N))
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -291,7 +291,9 @@ int tb_set_launch(tb_ctx *ctx, int atoms_per_launch);
  * compute unit, candidates timed, Krylov waves per SIMD of the register
  * budget (4: 128 VGPRs, 2: 256), and for TB_FP32 the layout of the H.V
  * work items (0: one column per lane; 1: four columns per lane over every
- * fourth coupling, which loads each coupling once; both are timed).
+ * fourth coupling, which loads each coupling once; 2: the 4x4 Slater-Koster
+ * blocks times the 4x4 blocks of V_k on the matrix cores, 16 target atoms per
+ * wave; all three are timed).
  * Synchronises the stream (not for graph
  * capture); tb_krylov_rho must run again before tb_energy_forces, and the
  * counters of tb_get_stats are those of before the call.
@@ -305,7 +307,9 @@ int tb_autotune(tb_ctx *ctx, int r, const int *r_per_atom, int precision, int *s
  * compute unit (they must stay
  * co-resident: wg_per_cu * threads / 64 <= 4 * waves_per_simd, and the
  * sphere capacity must fit their LDS) and, for TB_FP32, the H.V item layout
- * (wide = 1: four columns per lane over every fourth coupling). Results of
+ * (wide = 0: one column per lane; 1: four columns per lane over every fourth
+ * coupling; 2: the 4x4 blocks of 16 target atoms per wave on the matrix cores,
+ * v_mfma_f32_4x4x1_16b_f32, one coupling slot per four MFMAs). Results of
  * different shapes agree to rounding; one shape gives the same bits on every
  * run. Host-side setting, no device work.
  * Errors: TB_EINVAL (a value outside those sets), TB_ECAPACITY (the LDS

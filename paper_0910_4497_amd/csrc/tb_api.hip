@@ -479,7 +479,7 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
   float best = 3.0e38f;
   hipError_t err = hipSuccess;
   const int nts[2] = {256, 512}, mws[3] = {4, 3, 2};   // waves per SIMD (3: 256 threads only)
-  const int n_wide = precision == TB_FP32 ? 2 : 1;      // FP32: both H.V item layouts
+  const int n_wide = precision == TB_FP32 ? 3 : 1;      // FP32: the three H.V item layouts
   for (int wd = 0; wd < n_wide && err == hipSuccess; ++wd)
   for (int m = 0; m < 3 && err == hipSuccess; ++m) {
     for (int q = 0; q < 2 && err == hipSuccess; ++q) {
@@ -673,7 +673,8 @@ extern "C" int tb_set_shape(tb_ctx* c, int precision, int threads, int waves_per
   if (waves_per_simd == 3 && threads != 256) return fail(TB_EINVAL, "waves_per_simd=3 needs 256 threads");
   if (wg_per_cu < 1 || wg_per_cu > c->lz_per_cu_max)
     return fail(TB_EINVAL, "wg_per_cu=%d outside [1, %d]", wg_per_cu, c->lz_per_cu_max);
-  if (wide && precision != TB_FP32) return fail(TB_EINVAL, "the wide H.V layout is for TB_FP32 only");
+  if (wide < 0 || wide > 2) return fail(TB_EINVAL, "H.V layout %d is not 0, 1 or 2", wide);
+  if (wide && precision != TB_FP32) return fail(TB_EINVAL, "the wide and MFMA H.V layouts are for TB_FP32 only");
   if (wg_per_cu * threads / 64 > 4 * waves_per_simd)
     return fail(TB_EINVAL, "%d workgroups of %d threads exceed %d waves per SIMD", wg_per_cu, threads,
                 waves_per_simd);
@@ -682,7 +683,7 @@ extern "C" int tb_set_shape(tb_ctx* c, int precision, int threads, int waves_per
   c->lz_nt[precision] = threads;
   c->lz_minw[precision] = waves_per_simd;
   c->lz_per_cu[precision] = wg_per_cu;
-  c->lz_wide[precision] = wide ? 1 : 0;
+  c->lz_wide[precision] = wide;
   return TB_OK;
 }
 

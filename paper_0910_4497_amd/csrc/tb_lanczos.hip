@@ -24,7 +24,9 @@
 // own vectors, and only a chain's own entries enter the estimate.
 // H.V work items: one column of one atom per lane (FP32), or all four
 // columns of every fourth coupling per lane with a reduce-scatter over the
-// four lanes (FP64, and the WIDE FP32 variant).
+// four lanes (FP64, and the WIDE FP32 variant), or (MF, FP32) the 4x4 blocks
+// of 16 target atoms per wave on the matrix cores, one coupling slot per
+// four MFMAs.
 // VT = double (FP64 mode) or float (FP32 mode: basis, W and H.V in FP32 with
 // FP32 accumulation; A_k, Gram, norms, Cholesky and B_k stay FP64). The
 // estimates, FP32 copies of A_j, B_j and a second LDS buffer for V_{k-1} stay
@@ -143,11 +145,12 @@ __device__ __forceinline__ void inv_upper4r(const double (&U)[16], const bool (&
 // every fourth coupling, then a reduce-scatter over the four lanes), which
 // loads each coupling's entry, pair data and V_k rows once instead of once
 // per column: the better choice when spheres have many couplings per atom.
-template <typename VT, int LZ_NT, int MINW, bool BF = false, bool WIDE = false>
+template <typename VT, int LZ_NT, int MINW, bool BF = false, bool WIDE = false, bool MF = false>
 __global__ void __launch_bounds__(LZ_NT, MINW)
 k_lanczos(LanczosArgs g) {
   static_assert(!BF || sizeof(VT) == 4, "BF16 operands with the FP32 recursion only");
   static_assert(!(BF && WIDE), "the wide H.V items take unrounded operands");
+  static_assert(!MF || (sizeof(VT) == 4 && !BF && !WIDE), "the MFMA H.V items are an FP32 layout");
   constexpr int LZ_NW = LZ_NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -252,6 +255,78 @@ k_lanczos(LanczosArgs g) {
         // four lanes leaves lane `part` with column c = part (fewer dependent
         // load rounds). FP32: item (a, c) -- one column per lane over all the
         // couplings of atom a (fewer registers).
+        if constexpr (MF) {
+          // MFMA items: v_mfma_f32_4x4x1_16b_f32 holds 16 blocks of 4 lanes;
+          // block b (lanes 4b .. 4b+3) is target atom a = a0 + b, and per
+          // coupling slot s the four products H_ab[:, k] V_b[k, :] (k = 0..3)
+          // of atom a's s-th coupling (a -> b) accumulate into its 4x4 block
+          // of W: lane 4b + q provides H_ab[q][k] (row q of the Slater-Koster
+          // block, built from the pair data) and V_b[k][q], and ends holding
+          // W[a][0..3][q], the same values as the one-column item (a, q). The
+          // whole wave runs every MFMA (atoms past n and slots past an atom's
+          // last coupling feed zero rows of H).
+          for (int base = 64 * wave; base < 4 * n; base += LZ_NT) {
+            const int item = base + lane, c = cq;
+            const bool valid = item < 4 * n;
+            const int a = valid ? item >> 2 : 0;
+            const int e0 = s_off[a];
+            int e1 = valid ? s_off[a + 1] : e0;
+            if (e1 > g.emax) e1 = (int)g.emax;
+            const int ncp = e1 > e0 ? e1 - e0 : 0;
+            int smax = ncp;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) smax = max(smax, __shfl_xor(smax, off, 64));
+            smax = __builtin_amdgcn_readfirstlane(smax);          // equal on every lane: a scalar trip count
+            const int gid = s_gid[a];
+            const VT* va = s_V + 16 * a + c;
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            f4 acc;
+            acc[0] = valid ? es * va[0] : 0.0f;
+            acc[1] = valid ? ep * va[4] : 0.0f;
+            acc[2] = valid ? ep * va[8] : 0.0f;
+            acc[3] = valid ? ep * va[12] : 0.0f;
+            unsigned int pn = ncp > 0 ? ent[e0] : 0u;
+            for (int sl = 0; sl < smax; ++sl) {
+              const bool has = sl < ncp;
+              const unsigned int pe = pn;
+              pn = (sl + 1 < ncp) ? ent[e0 + sl + 1] : 0u;     // the next entry loads with this pair data
+              const int slot = pe >> LOCAL_BITS, b = pe & NCLUSTER_LIMIT;
+              const V4 hp4 = *(const V4*)(pairs + ((size_t)gid * g.zmax + slot) * 4);
+              const VT hx = hp4.x, hy = hp4.y, hz = hp4.z, sv = has ? hp4.w : (VT)0;
+              // row c of H_ab: s row (vsss, vsps h) or p_u row (-vsps h_u, vdif h_u h + vppp e_u)
+              const VT hu = c == 1 ? hx : (c == 2 ? hy : hz);
+              VT h0, h1, h2, h3;
+              if (c == 0) {
+                h0 = sv * vsss; h1 = sv * vsps * hx; h2 = sv * vsps * hy; h3 = sv * vsps * hz;
+              } else {
+                const VT t = sv * vdif * hu;
+                h0 = -sv * vsps * hu;
+                h1 = t * hx + (c == 1 ? sv * vppp : (VT)0);
+                h2 = t * hy + (c == 2 ? sv * vppp : (VT)0);
+                h3 = t * hz + (c == 3 ? sv * vppp : (VT)0);
+              }
+              const VT* vb = s_V + 16 * b + c;
+              const VT b0 = vb[0], b1 = vb[4], b2 = vb[8], b3 = vb[12];
+              acc = __builtin_amdgcn_mfma_f32_4x4x1f32(h0, b0, acc, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_4x4x1f32(h1, b1, acc, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_4x4x1f32(h2, b2, acc, 0, 0, 0);
+              acc = __builtin_amdgcn_mfma_f32_4x4x1f32(h3, b3, acc, 0, 0, 0);
+            }
+            if (valid) {
+              const VT wb[4] = {acc[0], acc[1], acc[2], acc[3]};
+              VT* wa = s_W + 16 * a + c;
+              wa[0] = wb[0]; wa[4] = wb[1]; wa[8] = wb[2]; wa[12] = wb[3];
+#pragma unroll
+              for (int beta = 0; beta < 4; ++beta) {
+                const V4 vr = *(const V4*)(s_V + 4 * (4 * a + beta));
+                accA[0] += (double)vr.x * (double)wb[beta];
+                accA[1] += (double)vr.y * (double)wb[beta];
+                accA[2] += (double)vr.z * (double)wb[beta];
+                accA[3] += (double)vr.w * (double)wb[beta];
+              }
+            }
+          }
+        } else
         for (int item = tid; item < 4 * n; item += LZ_NT) {
           VT w0, w1, w2, w3;
           const int a = item >> 2, c = cq;
@@ -908,29 +983,30 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, 
   return b + 64;
 }
 
-template <typename VT, bool BF = false, bool WIDE = false>
+template <typename VT, bool BF = false, bool WIDE = false, bool MF = false>
 static void launch_lz(const LanczosArgs& a, int nt, int minw, int n_wg, size_t lds, hipStream_t st) {
   if (minw == 2) {
-    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2, BF, WIDE>), dim3(n_wg), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_lanczos<VT, 512, 2, BF, WIDE>), dim3(n_wg), dim3(512), lds, st, a);
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2, BF, WIDE, MF>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 2, BF, WIDE, MF>), dim3(n_wg), dim3(512), lds, st, a);
   } else if (minw == 3) {                       // 256 threads only
-    hipLaunchKernelGGL((k_lanczos<VT, 256, 3, BF, WIDE>), dim3(n_wg), dim3(256), lds, st, a);
+    hipLaunchKernelGGL((k_lanczos<VT, 256, 3, BF, WIDE, MF>), dim3(n_wg), dim3(256), lds, st, a);
   } else {
-    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4, BF, WIDE>), dim3(n_wg), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_lanczos<VT, 512, 4, BF, WIDE>), dim3(n_wg), dim3(512), lds, st, a);
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4, BF, WIDE, MF>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 4, BF, WIDE, MF>), dim3(n_wg), dim3(512), lds, st, a);
   }
 }
 
-void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int wide, int n_wg, size_t lds,
+void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int layout, int n_wg, size_t lds,
                     hipStream_t st) {
   if (precision == TB_BF16) launch_lz<float, true>(a, nt, minw, n_wg, lds, st);
-  else if (precision == TB_FP32 && wide) launch_lz<float, false, true>(a, nt, minw, n_wg, lds, st);
+  else if (precision == TB_FP32 && layout == 2) launch_lz<float, false, false, true>(a, nt, minw, n_wg, lds, st);
+  else if (precision == TB_FP32 && layout == 1) launch_lz<float, false, true>(a, nt, minw, n_wg, lds, st);
   else if (precision == TB_FP32) launch_lz<float>(a, nt, minw, n_wg, lds, st);
   else launch_lz<double>(a, nt, minw, n_wg, lds, st);
 }
 
 hipError_t lanczos_set_lds(size_t lds) {
-  const void* fn[20] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
+  const void* fn[25] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
                         (const void*)k_lanczos<float, 256, 4>, (const void*)k_lanczos<float, 512, 4>,
                         (const void*)k_lanczos<double, 256, 2>, (const void*)k_lanczos<double, 512, 2>,
                         (const void*)k_lanczos<float, 256, 2>, (const void*)k_lanczos<float, 512, 2>,
@@ -939,8 +1015,13 @@ hipError_t lanczos_set_lds(size_t lds) {
                         (const void*)k_lanczos<float, 256, 4, false, true>, (const void*)k_lanczos<float, 512, 4, false, true>,
                         (const void*)k_lanczos<float, 256, 2, false, true>, (const void*)k_lanczos<float, 512, 2, false, true>,
                         (const void*)k_lanczos<double, 256, 3>, (const void*)k_lanczos<float, 256, 3>,
-                        (const void*)k_lanczos<float, 256, 3, true>, (const void*)k_lanczos<float, 256, 3, false, true>};
-  for (int q = 0; q < 20; ++q) {
+                        (const void*)k_lanczos<float, 256, 3, true>, (const void*)k_lanczos<float, 256, 3, false, true>,
+                        (const void*)k_lanczos<float, 256, 4, false, false, true>,
+                        (const void*)k_lanczos<float, 512, 4, false, false, true>,
+                        (const void*)k_lanczos<float, 256, 2, false, false, true>,
+                        (const void*)k_lanczos<float, 512, 2, false, false, true>,
+                        (const void*)k_lanczos<float, 256, 3, false, false, true>};
+  for (int q = 0; q < 25; ++q) {
     hipError_t e = hipFuncSetAttribute(fn[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }

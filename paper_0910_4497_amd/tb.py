@@ -249,10 +249,11 @@ class TBContext:
         build_local_H."""
         _check(self.lib.tb_set_groups(self.h, int(m)))
 
-    def set_shape(self, precision: str, threads: int, waves_per_simd: int, wg_per_cu: int, wide: bool = False):
-        """Fixes the Krylov launch shape at this precision (see tb_set_shape)."""
+    def set_shape(self, precision: str, threads: int, waves_per_simd: int, wg_per_cu: int, wide: int = 0):
+        """Fixes the Krylov launch shape at this precision (see tb_set_shape); wide:
+        H.V layout for FP32 (0 one column per lane, 1 four columns per lane, 2 MFMA)."""
         _check(self.lib.tb_set_shape(self.h, PRECISIONS[precision], int(threads), int(waves_per_simd),
-                                     int(wg_per_cu), int(bool(wide))))
+                                     int(wg_per_cu), int(wide)))
 
     def set_launch(self, atoms_per_launch: int):
         """0: one launch per per-atom phase; k: launches over groups of k atoms."""

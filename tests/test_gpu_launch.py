@@ -111,30 +111,42 @@ def test_destroy_returns_every_buffer(torch_cuda):
 
 
 def test_fp32_hv_layouts_agree(torch_cuda):
-    """The two FP32 H.V item layouts (one column per lane; four columns per
-    lane over every fourth coupling), fixed with tb_set_shape at the same
-    launch shape, agree to FP32 rounding; invalid shapes are refused."""
+    """The three FP32 H.V item layouts (one column per lane; four columns per
+    lane over every fourth coupling; 4x4 blocks of 16 target atoms per wave on
+    the matrix cores), fixed with tb_set_shape at the same launch shape, agree
+    to FP32 rounding and each meets the FP64 path within the mixed-precision
+    force bar; invalid shapes are refused."""
     from paper_0910_4497_amd.tb import TBContext, TBError
     w = inputs.workload("c60_240")
     ctx = TBContext(w.n_atoms, 130, 30)
     runs = {}
-    for wide in (False, True):
-        ctx.set_shape("fp32", 256, 4, 2, wide=wide)
-        runs[wide] = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
-                             precision="fp32")
-    for bad in (dict(precision="fp64", threads=256, waves_per_simd=4, wg_per_cu=1, wide=True),
+    for layout in (0, 1, 2):
+        ctx.set_shape("fp32", 256, 4, 2, wide=layout)
+        runs[layout] = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                               precision="fp32")
+    ref = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                  precision="fp64")
+    for bad in (dict(precision="fp64", threads=256, waves_per_simd=4, wg_per_cu=1, wide=1),
+                dict(precision="fp64", threads=256, waves_per_simd=4, wg_per_cu=1, wide=2),
+                dict(precision="fp32", threads=256, waves_per_simd=4, wg_per_cu=1, wide=3),
                 dict(precision="fp32", threads=128, waves_per_simd=4, wg_per_cu=1),
                 dict(precision="fp32", threads=512, waves_per_simd=2, wg_per_cu=3)):
         with pytest.raises(TBError) as e:
             ctx.set_shape(**bad)
         assert e.value.name == "TB_EINVAL", bad
     ctx.close()
-    a, b = runs[False], runs[True]
-    assert np.array_equal(a["row_ptr"], b["row_ptr"])
-    df = float(np.abs(a["forces"] - b["forces"]).max())
-    dr = float(np.abs(a["rho"] - b["rho"]).max())
-    print(f"  wide vs narrow FP32 H.V: force {df:.2e} eV/A, rho {dr:.2e}, mu {abs(a['mu'] - b['mu']):.2e}")
-    assert df <= 1e-4 and dr <= 1e-5 and abs(a["mu"] - b["mu"]) <= 1e-6
+    a = runs[0]
+    for layout in (1, 2):
+        b = runs[layout]
+        assert b["stats"]["flags"] == 0
+        assert np.array_equal(a["row_ptr"], b["row_ptr"])
+        df = float(np.abs(a["forces"] - b["forces"]).max())
+        dr = float(np.abs(a["rho"] - b["rho"]).max())
+        fe = float(np.abs(b["forces"] - ref["forces"]).max())
+        print(f"  layout {layout} vs narrow FP32 H.V: force {df:.2e} eV/A, rho {dr:.2e}, "
+              f"mu {abs(a['mu'] - b['mu']):.2e}; vs FP64 {fe:.2e} eV/A")
+        assert df <= 1e-4 and dr <= 1e-5 and abs(a["mu"] - b["mu"]) <= 1e-6
+        assert fe <= 1e-3
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
