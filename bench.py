@@ -83,6 +83,9 @@ def parse():
                          "share their union sphere; 1: each atom's own sphere")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing the candidates first")
+    ap.add_argument("--hv-layout", type=int, choices=(0, 1, 2), default=None,
+                    help="FP32: keep the tuned Krylov launch shape but fix the H.V item layout (0 one "
+                         "column per lane, 1 four columns per lane, 2 matrix-core 4x4 blocks)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the run with each MD step captured in one HIP graph")
     ap.add_argument("--large-workload", default="c60_15360",
@@ -258,6 +261,11 @@ def run_workload(name, precs, args, stream, torch, inputs, TBContext, graph=True
             # untimed: pick the launch shapes on the start geometry (results unchanged)
             ctx.build_local_H(pos0, w.cell, (1, 1, 1), params, w.r_cut)
             shapes[prec] = ctx.autotune(w.r, prec, r_per_atom=rpa)
+            if args.hv_layout is not None and prec == "fp32":
+                sh = shapes[prec]
+                ctx.set_shape(prec, sh["lanczos_threads"], sh["lanczos_waves_per_simd"], sh["lanczos_wg_per_cu"],
+                              wide=args.hv_layout)
+                sh["lanczos_wide"] = args.hv_layout
         results[prec] = run_md(ctx, w, params, pos0, vel0, prec, args.steps, args.warmup, args.dt,
                                torch, inputs, rpa, fixed)
         if graph:

@@ -25,10 +25,10 @@
 //   3. eigenvectors of S: for an eigenvalue with no neighbour closer than
 //      max(1e-6 ||S||, 1e-5 eV), a twisted factorisation of S - lambda I
 //      (its pivots recomputed from sparse checkpoints instead of stored);
-//      inside such a cluster, two steps of inverse iteration (tridiagonal LU
-//      with partial pivoting, deterministic pseudo-random start), then
-//      Gram-Schmidt against the earlier members, one more step and
-//      Gram-Schmidt again (Peters & Wilkinson; LAPACK's stein does the same).
+//      inside such a cluster, inverse iteration (tridiagonal LU with partial
+//      pivoting, deterministic pseudo-random start) with the iterate made
+//      orthogonal to the cluster's earlier members before every solve
+//      (Peters & Wilkinson; the order of LAPACK's stein).
 //      The eigenvector matrix U of S goes to HBM, the columns of the twisted
 //      factorisations unnormalised, with their normalising factors apart;
 //   4. Y[0:4, :] = Z[0:4, :] U, weights w_m = ||Y[0:4, m]||^2, Ritz values.
@@ -305,6 +305,55 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
     x2 = x1; x1 = x;
   }
   return nrm;
+}
+
+// Eigenvector of a cluster member t at position pos > 0 of its cluster, or of
+// the first member (pos = 0), by inverse iteration in the order of Peters &
+// Wilkinson and LAPACK's stein: the iterate is made orthogonal to the
+// earlier members (the pos columns before xc, stride 1 in the column index,
+// already normalised) before every solve, so that each solve amplifies the
+// directions of the cluster's invariant subspace those members do not cover.
+// (Orthogonalising only after the solves fails on an exactly degenerate
+// eigenvalue: the solves converge into the earlier members' span and the
+// Gram-Schmidt remainder is rounding noise.) Two solves for the first member,
+// three for the others; when orthogonalisation removes most of an iterate,
+// the member starts again from another pseudo-random vector. The result in
+// xc (stride ld) is normalised.
+__device__ void cluster_vector(const double* D, const double* E, int d, double lam, double small, int t, int pos,
+                               double* xc, size_t ld, double* scr, int ns) {
+  auto orth = [&]() {
+    for (int rep = 0; rep < 2; ++rep) {
+      for (int p = 1; p <= pos; ++p) {
+        const double* uj = xc - p;
+        double dot = 0.0;
+        for (int k = 0; k < d; ++k) dot += uj[(size_t)k * ld] * xc[(size_t)k * ld];
+        for (int k = 0; k < d; ++k) xc[(size_t)k * ld] -= dot * uj[(size_t)k * ld];
+      }
+    }
+    double nrm = 0.0;
+    for (int k = 0; k < d; ++k) nrm += xc[(size_t)k * ld] * xc[(size_t)k * ld];
+    return nrm;
+  };
+  auto scale = [&](double nrm) {
+    const double sc = 1.0 / sqrt(nrm);
+    for (int k = 0; k < d; ++k) xc[(size_t)k * ld] *= sc;
+  };
+  int seed = t;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    for (int k = 0; k < d; ++k) xc[(size_t)k * ld] = start_val(seed, k);
+    scale(pos > 0 ? orth() : (double)d);
+    bool ok = true;
+    for (int s = 0; s < (pos > 0 ? 3 : 2); ++s) {
+      scale(inv_solve(D, E, d, lam, small, t, xc, xc, ld, scr, ns));
+      if (pos > 0) {
+        const double nrm = orth();
+        if (!(nrm > 0.25)) { ok = false; scale(nrm > 0.0 ? nrm : 1.0); break; }
+        scale(nrm);
+      }
+    }
+    if (ok) return;
+    seed += 7919 * (attempt + 1) + d;
+  }
 }
 
 // Eigenvector of the tridiagonal (D, E; E2 = E^2) for an eigenvalue lam that
@@ -684,35 +733,8 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
           y1o[t] = a0; y1o[dmax + t] = a1; y1o[2 * dmax + t] = a2; y1o[3 * dmax + t] = a3;
           continue;
         }
-        vsc[t] = 1.0;                                // normalised below
-        // cluster members: two steps of inverse iteration (the second one
-        // squares the contamination left by a start vector with a small
-        // target component), then Gram-Schmidt against the earlier members
-        double nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, nullptr, xc, dmax, scr, nt);
-        double sc = 1.0 / sqrt(nrm);
-        for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
-        nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, xc, xc, dmax, scr, nt);
-        sc = 1.0 / sqrt(nrm);
-        for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
-        if (round > 0) {
-          for (int rep = 0; rep < 2; ++rep) {
-            for (int j = t - round; j < t; ++j) {
-              const double* uj = Ua + j;
-              double dot = 0.0;
-              for (int k = 0; k < d; ++k) dot += uj[(size_t)k * dmax] * xc[(size_t)k * dmax];
-              for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] -= dot * uj[(size_t)k * dmax];
-            }
-            nrm = 0.0;
-            for (int k = 0; k < d; ++k) nrm += xc[(size_t)k * dmax] * xc[(size_t)k * dmax];
-            sc = 1.0 / sqrt(nrm);
-            for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
-            if (rep == 0) {
-              nrm = inv_solve(Dg, Eg, d, lam_s[t], small, t, xc, xc, dmax, scr, nt);
-              sc = 1.0 / sqrt(nrm);
-              for (int k = 0; k < d; ++k) xc[(size_t)k * dmax] *= sc;
-            }
-          }
-        }
+        vsc[t] = 1.0;                                // normalised here
+        cluster_vector(Dg, Eg, d, lam_s[t], small, t, round, xc, dmax, scr, nt);
       }
       __syncthreads();
     }
@@ -855,32 +877,8 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
           vsc[t] = twisted_ck<false>(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
           continue;
         }
-        vsc[t] = 1.0;                                // normalised below
-        double nrm = inv_solve(Dc, Ec, K, lam_s[t], small, t, nullptr, xc, ld, scr, nt);
-        double sc = 1.0 / sqrt(nrm);
-        for (int k = 0; k < K; ++k) xc[(size_t)k * ld] *= sc;
-        nrm = inv_solve(Dc, Ec, K, lam_s[t], small, t, xc, xc, ld, scr, nt);
-        sc = 1.0 / sqrt(nrm);
-        for (int k = 0; k < K; ++k) xc[(size_t)k * ld] *= sc;
-        if (round > 0) {
-          for (int rep = 0; rep < 2; ++rep) {
-            for (int j = t - round; j < t; ++j) {
-              const double* uj = Ua + (size_t)c * dmax + j;
-              double dot = 0.0;
-              for (int k = 0; k < K; ++k) dot += uj[(size_t)k * ld] * xc[(size_t)k * ld];
-              for (int k = 0; k < K; ++k) xc[(size_t)k * ld] -= dot * uj[(size_t)k * ld];
-            }
-            nrm = 0.0;
-            for (int k = 0; k < K; ++k) nrm += xc[(size_t)k * ld] * xc[(size_t)k * ld];
-            sc = 1.0 / sqrt(nrm);
-            for (int k = 0; k < K; ++k) xc[(size_t)k * ld] *= sc;
-            if (rep == 0) {
-              nrm = inv_solve(Dc, Ec, K, lam_s[t], small, t, xc, xc, ld, scr, nt);
-              sc = 1.0 / sqrt(nrm);
-              for (int k = 0; k < K; ++k) xc[(size_t)k * ld] *= sc;
-            }
-          }
-        }
+        vsc[t] = 1.0;                                // normalised here
+        cluster_vector(Dc, Ec, K, lam_s[t], small, t, round, xc, ld, scr, nt);
       }
       __syncthreads();
     }

@@ -43,6 +43,10 @@ __device__ __forceinline__ float quad_bcast(float v) {
 }
 
 
+// a * b + c with one rounding
+__device__ __forceinline__ float fmav(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmav(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename VT> struct Vec4;
 template <> struct Vec4<double> { typedef double4 T; };
 template <> struct Vec4<float> { typedef float4 T; };
@@ -360,15 +364,17 @@ k_lanczos(LanczosArgs g) {
                      vy4 = *(const V4*)(s_V + 16 * b + 8), vz4 = *(const V4*)(s_V + 16 * b + 12);
             const VT vs[4] = {vs4.x, vs4.y, vs4.z, vs4.w}, vx[4] = {vx4.x, vx4.y, vx4.z, vx4.w},
                      vy[4] = {vy4.x, vy4.y, vy4.z, vy4.w}, vz[4] = {vz4.x, vz4.y, vz4.z, vz4.w};
-            const VT sp = sv * vppp;
+            // the radial factor enters the four bond integrals once per
+            // coupling, so each column costs 13 multiply-adds
+            const VT css = sv * vsss, csp = sv * vsps, cdf = sv * vdif, sp = sv * vppp;
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) {
-              const VT hp = hx * vx[cc] + hy * vy[cc] + hz * vz[cc];
-              w[cc] += sv * (vsss * vs[cc] + vsps * hp);
-              const VT t = sv * (vdif * hp - vsps * vs[cc]);
-              w[4 + cc] += t * hx + sp * vx[cc];
-              w[8 + cc] += t * hy + sp * vy[cc];
-              w[12 + cc] += t * hz + sp * vz[cc];
+              const VT hp = fmav(hz, vz[cc], fmav(hy, vy[cc], hx * vx[cc]));
+              w[cc] = fmav(csp, hp, fmav(css, vs[cc], w[cc]));
+              const VT t = fmav(-csp, vs[cc], cdf * hp);
+              w[4 + cc] = fmav(sp, vx[cc], fmav(t, hx, w[4 + cc]));
+              w[8 + cc] = fmav(sp, vy[cc], fmav(t, hy, w[8 + cc]));
+              w[12 + cc] = fmav(sp, vz[cc], fmav(t, hz, w[12 + cc]));
             }
           }
           {

@@ -66,6 +66,23 @@ def test_s_only_chain_deflation(torch_cuda):
     check_against_oracle(res, ora, range(15))
 
 
+@pytest.mark.parametrize("r", [3, 4, 5, 7, 8])
+def test_exactly_degenerate_levels(torch_cuda, r):
+    """s-only chain: the three p levels of every atom are exactly degenerate
+    (and so are the deflated slots), so the projected matrix has clusters
+    whose computed eigenvalue can equal diagonal entries of the tridiagonal
+    exactly; the cluster eigenvectors must still be orthogonal (rho and mu to
+    the parity bar at several Krylov orders)."""
+    p = dict(P)
+    p["v_sps"] = p["v_pps"] = p["v_ppp"] = 0.0
+    pos = inputs.chain_positions(15, 1.45)
+    ctx = make_ctx(15, 16, 8)
+    res = gpu_run(ctx, pos, BIG, (0, 0, 0), 9.0, r, 0.1, n_electrons=60.0, params=p)
+    ora = otb.run(pos, BIG, (0, 0, 0), p, 9.0, r, 0.1, n_electrons=60.0, processes=1)
+    assert abs(res["mu"] - ora["mu"]) < 1e-9
+    check_against_oracle(res, ora, range(15))
+
+
 def test_isolated_c60_exact_limit(torch_cuda):
     rng = np.random.default_rng(21)
     mol = inputs.c60_ideal() + rng.normal(0, 0.04, (60, 3))
