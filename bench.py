@@ -83,9 +83,10 @@ def parse():
                          "share their union sphere; 1: each atom's own sphere")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of timing the candidates first")
-    ap.add_argument("--hv-layout", type=int, choices=(0, 1, 2), default=None,
+    ap.add_argument("--hv-layout", type=int, choices=(0, 1, 2, 3), default=None,
                     help="FP32: keep the tuned Krylov launch shape but fix the H.V item layout (0 one "
-                         "column per lane, 1 four columns per lane, 2 matrix-core 4x4 blocks)")
+                         "column per lane, 1 four columns per lane, 2 matrix-core 4x4 blocks, 3 one "
+                         "atom per lane)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the run with each MD step captured in one HIP graph")
     ap.add_argument("--large-workload", default="c60_15360",
@@ -197,7 +198,7 @@ def lanczos_roofline(w_name, head_prec, head, shape, N, dev, torch):
                                                             shape["lanczos_threads"], shape["lanczos_waves_per_simd"],
                                                             "true" if head_prec == "bf16" else "false",
                                                             "true" if layout == 1 else "false",
-                                                            ", true" if layout == 2 else "")
+                                                            {2: ", true", 3: ", false, true"}.get(layout, ""))
         n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
         traffic = measured_traffic(w_name, head_prec, lz_kernel, min(n_cu * shape["lanczos_wg_per_cu"], N))
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -289,11 +289,13 @@ int tb_set_launch(tb_ctx *ctx, int atoms_per_launch);
  * tb_krylov_rho. shape_out (host, nullable) [6]: Krylov threads per
  * workgroup, Krylov workgroups per compute unit, eigensolver workgroups per
  * compute unit, candidates timed, Krylov waves per SIMD of the register
- * budget (4: 128 VGPRs, 2: 256), and for TB_FP32 the layout of the H.V
- * work items (0: one column per lane; 1: four columns per lane over every
- * fourth coupling, which loads each coupling once; 2: the 4x4 Slater-Koster
+ * budget (4: 128 VGPRs, 2: 256), and the layout of the H.V work items
+ * (TB_FP32: 0 one column per lane; 1 four columns per lane over every
+ * fourth coupling, which loads each coupling once; 2 the 4x4 Slater-Koster
  * blocks times the 4x4 blocks of V_k on the matrix cores, 16 target atoms per
- * wave; all three are timed).
+ * wave; 3 one target atom per lane with all four columns in registers; all
+ * four are timed. TB_FP64: 0 the four-lanes-per-atom items of layout 1, or
+ * 3; both timed. TB_BF16: 0).
  * Synchronises the stream (not for graph
  * capture); tb_krylov_rho must run again before tb_energy_forces, and the
  * counters of tb_get_stats are those of before the call.
@@ -306,10 +308,13 @@ int tb_autotune(tb_ctx *ctx, int r, const int *r_per_atom, int precision, int *s
  * VGPRs, 3: 168, with 256 threads only, 2: 256), persistent workgroups per
  * compute unit (they must stay
  * co-resident: wg_per_cu * threads / 64 <= 4 * waves_per_simd, and the
- * sphere capacity must fit their LDS) and, for TB_FP32, the H.V item layout
- * (wide = 0: one column per lane; 1: four columns per lane over every fourth
- * coupling; 2: the 4x4 blocks of 16 target atoms per wave on the matrix cores,
- * v_mfma_f32_4x4x1_16b_f32, one coupling slot per four MFMAs). Results of
+ * sphere capacity must fit their LDS) and the H.V item layout (wide = 0:
+ * one column per lane for TB_FP32 and TB_BF16, four lanes per atom for
+ * TB_FP64; 1, TB_FP32 only: four columns per lane over every fourth
+ * coupling; 2, TB_FP32 only: the 4x4 blocks of 16 target atoms per wave on
+ * the matrix cores, v_mfma_f32_4x4x1_16b_f32, one coupling slot per four
+ * MFMAs; 3, TB_FP32 and TB_FP64: one target atom per lane, all four columns
+ * over all of its couplings). Results of
  * different shapes agree to rounding; one shape gives the same bits on every
  * run. Host-side setting, no device work.
  * Errors: TB_EINVAL (a value outside those sets), TB_ECAPACITY (the LDS

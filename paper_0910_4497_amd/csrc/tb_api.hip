@@ -479,9 +479,13 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
   float best = 3.0e38f;
   hipError_t err = hipSuccess;
   const int nts[2] = {256, 512}, mws[3] = {4, 3, 2};   // waves per SIMD (3: 256 threads only)
-  const int n_wide = precision == TB_FP32 ? 3 : 1;      // FP32: the three H.V item layouts
-  for (int wd = 0; wd < n_wide && err == hipSuccess; ++wd)
+  // H.V item layouts: FP32 all four, FP64 the four-lanes-per-atom (0) and
+  // atom-per-lane (3) items, BF16 the one-column items
+  const int layouts[4] = {0, 1, 2, 3}, layouts64[2] = {0, 3};
+  const int n_wide = precision == TB_FP32 ? 4 : (precision == TB_FP64 ? 2 : 1);
+  for (int wi = 0; wi < n_wide && err == hipSuccess; ++wi)
   for (int m = 0; m < 3 && err == hipSuccess; ++m) {
+    const int wd = precision == TB_FP64 ? layouts64[wi] : layouts[wi];
     for (int q = 0; q < 2 && err == hipSuccess; ++q) {
       if (mws[m] == 3 && nts[q] != 256) continue;
       for (int pc = 1; pc <= c->lz_per_cu_max && err == hipSuccess; ++pc) {
@@ -673,8 +677,10 @@ extern "C" int tb_set_shape(tb_ctx* c, int precision, int threads, int waves_per
   if (waves_per_simd == 3 && threads != 256) return fail(TB_EINVAL, "waves_per_simd=3 needs 256 threads");
   if (wg_per_cu < 1 || wg_per_cu > c->lz_per_cu_max)
     return fail(TB_EINVAL, "wg_per_cu=%d outside [1, %d]", wg_per_cu, c->lz_per_cu_max);
-  if (wide < 0 || wide > 2) return fail(TB_EINVAL, "H.V layout %d is not 0, 1 or 2", wide);
-  if (wide && precision != TB_FP32) return fail(TB_EINVAL, "the wide and MFMA H.V layouts are for TB_FP32 only");
+  if (wide < 0 || wide > 3) return fail(TB_EINVAL, "H.V layout %d is not 0, 1, 2 or 3", wide);
+  if ((wide == 1 || wide == 2) && precision != TB_FP32)
+    return fail(TB_EINVAL, "the wide and MFMA H.V layouts are for TB_FP32 only");
+  if (wide == 3 && precision == TB_BF16) return fail(TB_EINVAL, "the BF16 form has the one-column H.V layout only");
   if (wg_per_cu * threads / 64 > 4 * waves_per_simd)
     return fail(TB_EINVAL, "%d workgroups of %d threads exceed %d waves per SIMD", wg_per_cu, threads,
                 waves_per_simd);

@@ -187,8 +187,9 @@ struct LanczosArgs {
 size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, bool ab_lds, bool vprev_lds);
 // precision: TB_FP64 / TB_FP32 / TB_BF16; nt: 256 or 512 threads; minw: 2, 3
 // (256 threads only) or 4 waves per SIMD (register budget)
-// layout: FP32 only, 1 the four-columns-per-lane H.V items, 2 the MFMA items
-// (see k_lanczos); 0 one column per lane
+// layout: 0 one column per lane (FP32, BF16) or four lanes per atom (FP64);
+// FP32 only: 1 the four-columns-per-lane H.V items, 2 the MFMA items; FP32 and
+// FP64: 3 one target atom per lane (see k_lanczos)
 void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int layout, int n_wg, size_t lds,
                     hipStream_t st);
 hipError_t lanczos_set_lds(size_t lds);

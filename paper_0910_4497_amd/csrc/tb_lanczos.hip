@@ -26,7 +26,8 @@
 // columns of every fourth coupling per lane with a reduce-scatter over the
 // four lanes (FP64, and the WIDE FP32 variant), or (MF, FP32) the 4x4 blocks
 // of 16 target atoms per wave on the matrix cores, one coupling slot per
-// four MFMAs.
+// four MFMAs, or (AL, FP32 and FP64) one target atom per lane with all four
+// columns of its W block in registers.
 // VT = double (FP64 mode) or float (FP32 mode: basis, W and H.V in FP32 with
 // FP32 accumulation; A_k, Gram, norms, Cholesky and B_k stay FP64). The
 // estimates, FP32 copies of A_j, B_j and a second LDS buffer for V_{k-1} stay
@@ -149,12 +150,13 @@ __device__ __forceinline__ void inv_upper4r(const double (&U)[16], const bool (&
 // every fourth coupling, then a reduce-scatter over the four lanes), which
 // loads each coupling's entry, pair data and V_k rows once instead of once
 // per column: the better choice when spheres have many couplings per atom.
-template <typename VT, int LZ_NT, int MINW, bool BF = false, bool WIDE = false, bool MF = false>
+template <typename VT, int LZ_NT, int MINW, bool BF = false, bool WIDE = false, bool MF = false, bool AL = false>
 __global__ void __launch_bounds__(LZ_NT, MINW)
 k_lanczos(LanczosArgs g) {
   static_assert(!BF || sizeof(VT) == 4, "BF16 operands with the FP32 recursion only");
   static_assert(!(BF && WIDE), "the wide H.V items take unrounded operands");
   static_assert(!MF || (sizeof(VT) == 4 && !BF && !WIDE), "the MFMA H.V items are an FP32 layout");
+  static_assert(!AL || (!BF && !WIDE && !MF), "one H.V item layout per instance");
   constexpr int LZ_NW = LZ_NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -259,7 +261,79 @@ k_lanczos(LanczosArgs g) {
         // four lanes leaves lane `part` with column c = part (fewer dependent
         // load rounds). FP32: item (a, c) -- one column per lane over all the
         // couplings of atom a (fewer registers).
-        if constexpr (MF) {
+        if constexpr (AL) {
+          // one target atom per lane: all four columns of W[a] (4 x 4) in
+          // registers over all of atom a's couplings, in groups of four whose
+          // pair data load together with the next group's entries; no
+          // reduction over lanes for W, and the partial sums of A_k = V_k^T W
+          // as 16 values per lane
+          double acc16[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) acc16[q] = 0.0;
+          for (int a = tid; a < n; a += LZ_NT) {
+            VT w[16];                                 // [orbital][column]
+            V4 va[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+              va[o] = *(const V4*)(s_V + 16 * a + 4 * o);
+              const VT eo = o == 0 ? es : ep;
+              w[o * 4] = eo * va[o].x; w[o * 4 + 1] = eo * va[o].y; w[o * 4 + 2] = eo * va[o].z;
+              w[o * 4 + 3] = eo * va[o].w;
+            }
+            const int gid = s_gid[a];
+            const int e0 = s_off[a];
+            int e1 = s_off[a + 1];
+            if (e1 > g.emax) e1 = (int)g.emax;
+            unsigned int pe[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pe[u] = (e0 + u < e1) ? ent[e0 + u] : 0u;
+            for (int eg = e0; eg < e1; eg += 4) {
+              V4 hp4[4];
+              unsigned int pg[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (eg + u < e1) hp4[u] = *(const V4*)(pairs + ((size_t)gid * g.zmax + (pe[u] >> LOCAL_BITS)) * 4);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) pg[u] = (eg + 4 + u < e1) ? ent[eg + 4 + u] : 0u;
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                if (eg + u >= e1) break;
+                const int b = pe[u] & NCLUSTER_LIMIT;
+                const VT hx = hp4[u].x, hy = hp4[u].y, hz = hp4[u].z, sv = hp4[u].w;
+                const V4 vs4 = *(const V4*)(s_V + 16 * b), vx4 = *(const V4*)(s_V + 16 * b + 4),
+                         vy4 = *(const V4*)(s_V + 16 * b + 8), vz4 = *(const V4*)(s_V + 16 * b + 12);
+                const VT vs[4] = {vs4.x, vs4.y, vs4.z, vs4.w}, vx[4] = {vx4.x, vx4.y, vx4.z, vx4.w},
+                         vy[4] = {vy4.x, vy4.y, vy4.z, vy4.w}, vz[4] = {vz4.x, vz4.y, vz4.z, vz4.w};
+                const VT css = sv * vsss, csp = sv * vsps, cdf = sv * vdif, sp = sv * vppp;
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) {
+                  const VT hp = fmav(hz, vz[cc], fmav(hy, vy[cc], hx * vx[cc]));
+                  w[cc] = fmav(csp, hp, fmav(css, vs[cc], w[cc]));
+                  const VT t = fmav(-csp, vs[cc], cdf * hp);
+                  w[4 + cc] = fmav(sp, vx[cc], fmav(t, hx, w[4 + cc]));
+                  w[8 + cc] = fmav(sp, vy[cc], fmav(t, hy, w[8 + cc]));
+                  w[12 + cc] = fmav(sp, vz[cc], fmav(t, hz, w[12 + cc]));
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) pe[u] = pg[u];
+            }
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+              V4 wo;
+              wo.x = w[o * 4]; wo.y = w[o * 4 + 1]; wo.z = w[o * 4 + 2]; wo.w = w[o * 4 + 3];
+              *(V4*)(s_W + 16 * a + 4 * o) = wo;
+              const VT vr[4] = {va[o].x, va[o].y, va[o].z, va[o].w};
+#pragma unroll
+              for (int c2 = 0; c2 < 4; ++c2)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc16[c2 * 4 + c] += (double)vr[c2] * (double)w[o * 4 + c];
+            }
+          }
+          int which;
+          const double sum = wave_sum16(acc16, lane, which);
+          if ((lane & 3) == 0) s_red[wave * 16 + which] = sum;
+        } else if constexpr (MF) {
           // MFMA items: v_mfma_f32_4x4x1_16b_f32 holds 16 blocks of 4 lanes;
           // block b (lanes 4b .. 4b+3) is target atom a = a0 + b, and per
           // coupling slot s the four products H_ab[:, k] V_b[k, :] (k = 0..3)
@@ -330,11 +404,24 @@ k_lanczos(LanczosArgs g) {
               }
             }
           }
-        } else
+        } else {
+        // four-column items: entries e0 + 4u (u < 4) of this lane's first
+        // group of couplings in an item, loaded during the previous item
+        constexpr bool WIDE_ITEMS = sizeof(VT) == 8 || WIDE;
+        auto first_group = [&](int it, unsigned int (&pq)[4]) {
+          const int an = it < 4 * n ? it >> 2 : 0;
+          const int f0 = s_off[an] + cq;
+          int f1 = it < 4 * n ? s_off[an + 1] : 0;
+          if (f1 > g.emax) f1 = (int)g.emax;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pq[u] = (f0 + 4 * u < f1) ? ent[f0 + 4 * u] : 0u;
+        };
+        unsigned int pfx[4] = {0u, 0u, 0u, 0u};
+        if constexpr (WIDE_ITEMS) first_group(tid, pfx);
         for (int item = tid; item < 4 * n; item += LZ_NT) {
           VT w0, w1, w2, w3;
           const int a = item >> 2, c = cq;
-          if constexpr (sizeof(VT) == 8 || WIDE) {
+          if constexpr (WIDE_ITEMS) {
 
           VT w[16];                                   // [orbital][column]
           if (c == 0) {
@@ -351,31 +438,42 @@ k_lanczos(LanczosArgs g) {
           const int gid = s_gid[a];
           int e1 = s_off[a + 1];
           if (e1 > g.emax) e1 = (int)g.emax;
-          // this lane's next coupling entry loads with the current pair data
-          unsigned int pcur = (s_off[a] + c < e1) ? ent[s_off[a] + c] : 0u;
-#pragma unroll 2
-          for (int e = s_off[a] + c; e < e1; e += 4) {
-            const unsigned int pe = pcur;
-            const int slot = pe >> LOCAL_BITS, b = pe & NCLUSTER_LIMIT;
-            const V4 hp4 = *(const V4*)(pairs + ((size_t)gid * g.zmax + slot) * 4);
-            pcur = (e + 4 < e1) ? ent[e + 4] : 0u;
-            const VT hx = hp4.x, hy = hp4.y, hz = hp4.z, sv = hp4.w;
-            const V4 vs4 = *(const V4*)(s_V + 16 * b), vx4 = *(const V4*)(s_V + 16 * b + 4),
-                     vy4 = *(const V4*)(s_V + 16 * b + 8), vz4 = *(const V4*)(s_V + 16 * b + 12);
-            const VT vs[4] = {vs4.x, vs4.y, vs4.z, vs4.w}, vx[4] = {vx4.x, vx4.y, vx4.z, vx4.w},
-                     vy[4] = {vy4.x, vy4.y, vy4.z, vy4.w}, vz[4] = {vz4.x, vz4.y, vz4.z, vz4.w};
-            // the radial factor enters the four bond integrals once per
-            // coupling, so each column costs 13 multiply-adds
-            const VT css = sv * vsss, csp = sv * vsps, cdf = sv * vdif, sp = sv * vppp;
+          unsigned int pe[4] = {pfx[0], pfx[1], pfx[2], pfx[3]};
+          first_group(item + LZ_NT, pfx);           // the next item's, in flight during this one
+          // groups of four of this lane's couplings (every fourth of atom a):
+          // their pair data load together, with the entries of the next group
+          for (int eg = s_off[a] + c; eg < e1; eg += 16) {
+            V4 hp4[4];
+            unsigned int pg[4];
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc) {
-              const VT hp = fmav(hz, vz[cc], fmav(hy, vy[cc], hx * vx[cc]));
-              w[cc] = fmav(csp, hp, fmav(css, vs[cc], w[cc]));
-              const VT t = fmav(-csp, vs[cc], cdf * hp);
-              w[4 + cc] = fmav(sp, vx[cc], fmav(t, hx, w[4 + cc]));
-              w[8 + cc] = fmav(sp, vy[cc], fmav(t, hy, w[8 + cc]));
-              w[12 + cc] = fmav(sp, vz[cc], fmav(t, hz, w[12 + cc]));
+            for (int u = 0; u < 4; ++u)
+              if (eg + 4 * u < e1) hp4[u] = *(const V4*)(pairs + ((size_t)gid * g.zmax + (pe[u] >> LOCAL_BITS)) * 4);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pg[u] = (eg + 16 + 4 * u < e1) ? ent[eg + 16 + 4 * u] : 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (eg + 4 * u >= e1) break;
+              const int b = pe[u] & NCLUSTER_LIMIT;
+              const VT hx = hp4[u].x, hy = hp4[u].y, hz = hp4[u].z, sv = hp4[u].w;
+              const V4 vs4 = *(const V4*)(s_V + 16 * b), vx4 = *(const V4*)(s_V + 16 * b + 4),
+                       vy4 = *(const V4*)(s_V + 16 * b + 8), vz4 = *(const V4*)(s_V + 16 * b + 12);
+              const VT vs[4] = {vs4.x, vs4.y, vs4.z, vs4.w}, vx[4] = {vx4.x, vx4.y, vx4.z, vx4.w},
+                       vy[4] = {vy4.x, vy4.y, vy4.z, vy4.w}, vz[4] = {vz4.x, vz4.y, vz4.z, vz4.w};
+              // the radial factor enters the four bond integrals once per
+              // coupling, so each column costs 13 multiply-adds
+              const VT css = sv * vsss, csp = sv * vsps, cdf = sv * vdif, sp = sv * vppp;
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc) {
+                const VT hp = fmav(hz, vz[cc], fmav(hy, vy[cc], hx * vx[cc]));
+                w[cc] = fmav(csp, hp, fmav(css, vs[cc], w[cc]));
+                const VT t = fmav(-csp, vs[cc], cdf * hp);
+                w[4 + cc] = fmav(sp, vx[cc], fmav(t, hx, w[4 + cc]));
+                w[8 + cc] = fmav(sp, vy[cc], fmav(t, hy, w[8 + cc]));
+                w[12 + cc] = fmav(sp, vz[cc], fmav(t, hz, w[12 + cc]));
+              }
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pe[u] = pg[u];
           }
           {
             const bool hi = c & 2, lo = c & 1;
@@ -451,14 +549,17 @@ k_lanczos(LanczosArgs g) {
             accA[3] += (double)vr.w * (double)wb[beta];
           }
         }
+        }
         // reduce over lanes with equal (lane & 3), then over waves
+        if constexpr (!AL) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+          for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int off = 4; off < 64; off <<= 1) accA[q] += __shfl_xor(accA[q], off, 64);
-        if (lane < 4) {
+            for (int off = 4; off < 64; off <<= 1) accA[q] += __shfl_xor(accA[q], off, 64);
+          if (lane < 4) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) s_red[wave * 16 + q * 4 + lane] = accA[q];
+            for (int q = 0; q < 4; ++q) s_red[wave * 16 + q * 4 + lane] = accA[q];
+          }
         }
         lds_barrier();
         if (tid < 16) {
@@ -544,6 +645,14 @@ k_lanczos(LanczosArgs g) {
           for (int q = 0; q < 16; ++q) Xe[q] = Xr[q];
           s_misc[208] = tn;
           s_flag[6] = ok ? 1 : 0;
+          if (!g.scalar) {
+            // the QR of step 4 factors this same Gram matrix unless a
+            // re-orthogonalisation pass changes W first: its factor, inverse
+            // and path, ready for that case
+#pragma unroll
+            for (int q = 0; q < 16; ++q) { X[q] = Xr[q]; B[q] = Ur[q]; }
+            s_flag[5] = !ok ? 2 : (ratio > 1e-4 ? 0 : 1);
+          }
         }
         lds_barrier();
         const double rnd = 2.0 * g.eps_unit * s_misc[208];
@@ -800,10 +909,12 @@ k_lanczos(LanczosArgs g) {
         if (!again || pass == 1) break;
         ++n2;
       }
-      // ---- 4. QR of W. Every thread factors the 4x4 Gram itself (no serial
-      // section): one Cholesky QR when the factor is well conditioned
+      // ---- 4. QR of W: one Cholesky QR when the factor is well conditioned
       // (pivot ratio > 1e-4, so kappa^2 eps < 1e-12), twice otherwise, and
       // modified Gram-Schmidt with deflation when a pivot is not safely > 0.
+      // Without a re-orthogonalisation pass W is unchanged since step 3a,
+      // whose factorisation of the same Gram matrix is used; after a pass
+      // every thread factors the new Gram itself (no serial section).
       bool act[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) act[c] = s_flag[c] != 0;
@@ -832,7 +943,7 @@ k_lanczos(LanczosArgs g) {
           s_flag[5] = 0;
         }
         lds_barrier();
-      } else {
+      } else if (reorth) {
         double Gf[16], Ur[16], Xr[16], ratio;
 #pragma unroll
         for (int q = 0; q < 16; ++q) Gf[q] = G[map[q]];
@@ -989,30 +1100,32 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, 
   return b + 64;
 }
 
-template <typename VT, bool BF = false, bool WIDE = false, bool MF = false>
+template <typename VT, bool BF = false, bool WIDE = false, bool MF = false, bool AL = false>
 static void launch_lz(const LanczosArgs& a, int nt, int minw, int n_wg, size_t lds, hipStream_t st) {
   if (minw == 2) {
-    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2, BF, WIDE, MF>), dim3(n_wg), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_lanczos<VT, 512, 2, BF, WIDE, MF>), dim3(n_wg), dim3(512), lds, st, a);
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 2, BF, WIDE, MF, AL>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 2, BF, WIDE, MF, AL>), dim3(n_wg), dim3(512), lds, st, a);
   } else if (minw == 3) {                       // 256 threads only
-    hipLaunchKernelGGL((k_lanczos<VT, 256, 3, BF, WIDE, MF>), dim3(n_wg), dim3(256), lds, st, a);
+    hipLaunchKernelGGL((k_lanczos<VT, 256, 3, BF, WIDE, MF, AL>), dim3(n_wg), dim3(256), lds, st, a);
   } else {
-    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4, BF, WIDE, MF>), dim3(n_wg), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_lanczos<VT, 512, 4, BF, WIDE, MF>), dim3(n_wg), dim3(512), lds, st, a);
+    if (nt == 256) hipLaunchKernelGGL((k_lanczos<VT, 256, 4, BF, WIDE, MF, AL>), dim3(n_wg), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL((k_lanczos<VT, 512, 4, BF, WIDE, MF, AL>), dim3(n_wg), dim3(512), lds, st, a);
   }
 }
 
 void launch_lanczos(const LanczosArgs& a, int precision, int nt, int minw, int layout, int n_wg, size_t lds,
                     hipStream_t st) {
   if (precision == TB_BF16) launch_lz<float, true>(a, nt, minw, n_wg, lds, st);
+  else if (precision == TB_FP32 && layout == 3) launch_lz<float, false, false, false, true>(a, nt, minw, n_wg, lds, st);
   else if (precision == TB_FP32 && layout == 2) launch_lz<float, false, false, true>(a, nt, minw, n_wg, lds, st);
   else if (precision == TB_FP32 && layout == 1) launch_lz<float, false, true>(a, nt, minw, n_wg, lds, st);
   else if (precision == TB_FP32) launch_lz<float>(a, nt, minw, n_wg, lds, st);
+  else if (layout == 3) launch_lz<double, false, false, false, true>(a, nt, minw, n_wg, lds, st);
   else launch_lz<double>(a, nt, minw, n_wg, lds, st);
 }
 
 hipError_t lanczos_set_lds(size_t lds) {
-  const void* fn[25] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
+  const void* fn[35] = {(const void*)k_lanczos<double, 256, 4>, (const void*)k_lanczos<double, 512, 4>,
                         (const void*)k_lanczos<float, 256, 4>, (const void*)k_lanczos<float, 512, 4>,
                         (const void*)k_lanczos<double, 256, 2>, (const void*)k_lanczos<double, 512, 2>,
                         (const void*)k_lanczos<float, 256, 2>, (const void*)k_lanczos<float, 512, 2>,
@@ -1026,8 +1139,18 @@ hipError_t lanczos_set_lds(size_t lds) {
                         (const void*)k_lanczos<float, 512, 4, false, false, true>,
                         (const void*)k_lanczos<float, 256, 2, false, false, true>,
                         (const void*)k_lanczos<float, 512, 2, false, false, true>,
-                        (const void*)k_lanczos<float, 256, 3, false, false, true>};
-  for (int q = 0; q < 25; ++q) {
+                        (const void*)k_lanczos<float, 256, 3, false, false, true>,
+                        (const void*)k_lanczos<float, 256, 4, false, false, false, true>,
+                        (const void*)k_lanczos<float, 512, 4, false, false, false, true>,
+                        (const void*)k_lanczos<float, 256, 2, false, false, false, true>,
+                        (const void*)k_lanczos<float, 512, 2, false, false, false, true>,
+                        (const void*)k_lanczos<float, 256, 3, false, false, false, true>,
+                        (const void*)k_lanczos<double, 256, 4, false, false, false, true>,
+                        (const void*)k_lanczos<double, 512, 4, false, false, false, true>,
+                        (const void*)k_lanczos<double, 256, 2, false, false, false, true>,
+                        (const void*)k_lanczos<double, 512, 2, false, false, false, true>,
+                        (const void*)k_lanczos<double, 256, 3, false, false, false, true>};
+  for (int q = 0; q < 35; ++q) {
     hipError_t e = hipFuncSetAttribute(fn[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
@@ -1035,3 +1158,4 @@ hipError_t lanczos_set_lds(size_t lds) {
 }
 
 }  // namespace tbk
+

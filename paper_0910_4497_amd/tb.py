@@ -251,7 +251,8 @@ class TBContext:
 
     def set_shape(self, precision: str, threads: int, waves_per_simd: int, wg_per_cu: int, wide: int = 0):
         """Fixes the Krylov launch shape at this precision (see tb_set_shape); wide:
-        H.V layout for FP32 (0 one column per lane, 1 four columns per lane, 2 MFMA)."""
+        H.V layout (0 one column per lane, FP64 four lanes per atom; FP32 only: 1 four
+        columns per lane, 2 MFMA; FP32 and FP64: 3 one atom per lane)."""
         _check(self.lib.tb_set_shape(self.h, PRECISIONS[precision], int(threads), int(waves_per_simd),
                                      int(wg_per_cu), int(wide)))
 

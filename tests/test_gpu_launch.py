@@ -111,32 +111,42 @@ def test_destroy_returns_every_buffer(torch_cuda):
 
 
 def test_fp32_hv_layouts_agree(torch_cuda):
-    """The three FP32 H.V item layouts (one column per lane; four columns per
+    """The four FP32 H.V item layouts (one column per lane; four columns per
     lane over every fourth coupling; 4x4 blocks of 16 target atoms per wave on
-    the matrix cores), fixed with tb_set_shape at the same launch shape, agree
-    to FP32 rounding and each meets the FP64 path within the mixed-precision
-    force bar; invalid shapes are refused."""
+    the matrix cores; one target atom per lane), fixed with tb_set_shape at the
+    same launch shape, agree to FP32 rounding and each meets the FP64 path
+    within the mixed-precision force bar; the two FP64 layouts agree to FP64
+    rounding; invalid shapes are refused."""
     from paper_0910_4497_amd.tb import TBContext, TBError
     w = inputs.workload("c60_240")
     ctx = TBContext(w.n_atoms, 130, 30)
     runs = {}
-    for layout in (0, 1, 2):
+    for layout in (0, 1, 2, 3):
         ctx.set_shape("fp32", 256, 4, 2, wide=layout)
         runs[layout] = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
                                precision="fp32")
     ref = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
                   precision="fp64")
+    ctx.set_shape("fp64", 256, 2, 1, wide=3)
+    ref3 = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, w.r, w.kT, n_electrons=w.n_electrons,
+                   precision="fp64")
     for bad in (dict(precision="fp64", threads=256, waves_per_simd=4, wg_per_cu=1, wide=1),
                 dict(precision="fp64", threads=256, waves_per_simd=4, wg_per_cu=1, wide=2),
-                dict(precision="fp32", threads=256, waves_per_simd=4, wg_per_cu=1, wide=3),
+                dict(precision="bf16", threads=256, waves_per_simd=4, wg_per_cu=1, wide=3),
+                dict(precision="fp32", threads=256, waves_per_simd=4, wg_per_cu=1, wide=4),
                 dict(precision="fp32", threads=128, waves_per_simd=4, wg_per_cu=1),
                 dict(precision="fp32", threads=512, waves_per_simd=2, wg_per_cu=3)):
         with pytest.raises(TBError) as e:
             ctx.set_shape(**bad)
         assert e.value.name == "TB_EINVAL", bad
     ctx.close()
+    # FP64: the atom-per-lane items against the four-lanes-per-atom ones
+    df64 = float(np.abs(ref3["forces"] - ref["forces"]).max())
+    dr64 = float(np.abs(ref3["rho"] - ref["rho"]).max())
+    print(f"  FP64 layout 3 vs 0: force {df64:.2e} eV/A, rho {dr64:.2e}, mu {abs(ref3['mu'] - ref['mu']):.2e}")
+    assert df64 <= 1e-8 and dr64 <= 1e-9 and abs(ref3["mu"] - ref["mu"]) <= 1e-10
     a = runs[0]
-    for layout in (1, 2):
+    for layout in (1, 2, 3):
         b = runs[layout]
         assert b["stats"]["flags"] == 0
         assert np.array_equal(a["row_ptr"], b["row_ptr"])

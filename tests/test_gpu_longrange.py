@@ -5,7 +5,7 @@ neighbour.
 
 * an isolated pair of C60 molecules (120 atoms, spheres of R_cut = 8 A):
   every atom, mu by bisection, FP64 to the parity bar and FP32 forces within
-  1e-3 eV/A with each of the three FP32 H.V item layouts;
+  1e-3 eV/A with each of the four FP32 H.V item layouts;
 * c60_1920_long at fixed mu: rho blocks of sampled targets, and the forces
   on two atoms whose hop closures the oracle solves;
 * a hop capacity too small for the geometry is reported (TB_ECAPACITY).
@@ -61,7 +61,7 @@ def test_parity_long_range_c60_pair(torch_cuda):
     print(f"  force rel err {ef:.3e}")
     assert ef <= 1e-8
     assert abs(res["e"][3] - ora["e_total"]) <= 1e-10 * abs(ora["e_total"])
-    for layout in (0, 1, 2):
+    for layout in (0, 1, 2, 3):
         ctx.set_shape("fp32", 512, 4, 1, wide=layout)
         r32 = gpu_run(ctx, pos, BIG, (0, 0, 0), r_cut, r, 0.1, n_electrons=480.0, precision="fp32", params=PL)
         fe = float(np.abs(r32["forces"] - ora["forces"]).max())
