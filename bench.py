@@ -194,11 +194,10 @@ def lanczos_roofline(w_name, head_prec, head, shape, N, dev, torch):
     traffic = None
     if shape:
         layout = shape.get("lanczos_wide", 0)
-        lz_kernel = "k_lanczos<{}, {}, {}, {}, {}{}>".format("double" if head_prec == "fp64" else "float",
-                                                            shape["lanczos_threads"], shape["lanczos_waves_per_simd"],
-                                                            "true" if head_prec == "bf16" else "false",
-                                                            "true" if layout == 1 else "false",
-                                                            {2: ", true", 3: ", false, true"}.get(layout, ""))
+        tf = lambda b: "true" if b else "false"
+        lz_kernel = "k_lanczos<{}, {}, {}, {}, {}, {}, {}>".format(
+            "double" if head_prec == "fp64" else "float", shape["lanczos_threads"],
+            shape["lanczos_waves_per_simd"], tf(head_prec == "bf16"), tf(layout == 1), tf(layout == 2), tf(layout == 3))
         n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
         traffic = measured_traffic(w_name, head_prec, lz_kernel, min(n_cu * shape["lanczos_wg_per_cu"], N))
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
