@@ -310,8 +310,8 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
 // Eigenvector of a cluster member t at position pos > 0 of its cluster, or of
 // the first member (pos = 0), by inverse iteration in the order of Peters &
 // Wilkinson and LAPACK's stein: the iterate is made orthogonal to the
-// earlier members (the pos columns before xc, stride 1 in the column index,
-// already normalised) before every solve, so that each solve amplifies the
+// earlier members (the pos columns before xc, cs elements apart, already
+// normalised) before every solve, so that each solve amplifies the
 // directions of the cluster's invariant subspace those members do not cover.
 // (Orthogonalising only after the solves fails on an exactly degenerate
 // eigenvalue: the solves converge into the earlier members' span and the
@@ -320,11 +320,11 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
 // the member starts again from another pseudo-random vector. The result in
 // xc (stride ld) is normalised.
 __device__ void cluster_vector(const double* D, const double* E, int d, double lam, double small, int t, int pos,
-                               double* xc, size_t ld, double* scr, int ns) {
+                               double* xc, size_t ld, size_t cs, double* scr, int ns) {
   auto orth = [&]() {
     for (int rep = 0; rep < 2; ++rep) {
       for (int p = 1; p <= pos; ++p) {
-        const double* uj = xc - p;
+        const double* uj = xc - (size_t)p * cs;
         double dot = 0.0;
         for (int k = 0; k < d; ++k) dot += uj[(size_t)k * ld] * xc[(size_t)k * ld];
         for (int k = 0; k < d; ++k) xc[(size_t)k * ld] -= dot * uj[(size_t)k * ld];
@@ -535,11 +535,17 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
         const double sig = x1 * x1 + x2 * x2 + x3 * x3;
         double v1 = 0.0, v2 = 0.0, v3 = 0.0, tau = 0.0, beta = x0;
         if (sig != 0.0) {
-          const double mu = sqrt(fma(x0, x0, sig));
+          // |x| and 1/|x| from the hardware reciprocal square root, each
+          // refined by one Newton step; tau = (beta - x0) / beta = 1 + |x0| / |x|
+          const double s2 = fma(x0, x0, sig);
+          double rs = __builtin_amdgcn_rsq(s2);
+          rs = rs * fma(-0.5 * s2 * rs, rs, 1.5);
+          double mu = s2 * rs;
+          mu = fma(fma(-mu, mu, s2), 0.5 * rs, mu);
           beta = x0 >= 0.0 ? -mu : mu;
-          const double iv0 = 1.0 / (x0 - beta);
+          const double iv0 = rcp_nr(x0 - beta);
           v1 = x1 * iv0; v2 = x2 * iv0; v3 = x3 * iv0;
-          tau = (beta - x0) / beta;
+          tau = fma(fabs(x0), rs, 1.0);
         }
         const double vv[4] = {1.0, v1, v2, v3};
         const double vq = vv[q];
@@ -713,18 +719,18 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     if (lane == 0) atomicMax(&s_maxpos, mp);
     __syncthreads();
     const int maxpos = s_maxpos;
-    double* Ua = g.evec + (size_t)atom * dmax * dmax;       // U[k][t], row stride dmax
+    double* Ua = g.evec + (size_t)atom * dmax * dmax;       // column t of U at Ua + t dmax
     double* vsc = g.vsc + (size_t)atom * dmax;              // normalising factor of column t
     for (int round = 0; round <= maxpos; ++round) {
       for (int t = tid; t < d; t += nt) {
         if (pos_s[t] != round) continue;
-        double* xc = Ua + t;
+        double* xc = Ua + (size_t)t * dmax;
         if (round == 0 && (t + 1 >= d || pos_s[t + 1] == 0)) {
           // not in a cluster: twisted factorisation (column scale kept apart),
           // which also forms Y[0:4, t] = Z[0:4, :] U[:, t]; the outputs of
           // the column are written here and skipped in step 4
           double ya[4];
-          const double sc = twisted_ck<true>(Dg, Eg, E2, d, lam_s[t], small, xc, dmax, scr, nt, R1, ya);
+          const double sc = twisted_ck<true>(Dg, Eg, E2, d, lam_s[t], small, xc, 1, scr, nt, R1, ya);
           vsc[t] = sc;
           double* y1o = g.y1 + (size_t)atom * 4 * dmax;
           const double a0 = ya[0] * sc, a1 = ya[1] * sc, a2 = ya[2] * sc, a3 = ya[3] * sc;
@@ -734,7 +740,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
           continue;
         }
         vsc[t] = 1.0;                                // normalised here
-        cluster_vector(Dg, Eg, d, lam_s[t], small, t, round, xc, dmax, scr, nt);
+        cluster_vector(Dg, Eg, d, lam_s[t], small, t, round, xc, 1, dmax, scr, nt);
       }
       __syncthreads();
     }
@@ -745,11 +751,11 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     for (int t = tid; t < dmax; t += nt) {
       if (t < d && pos_s[t] == 0 && (t + 1 >= d || pos_s[t + 1] == 0)) continue;   // written in step 3
       if (t < d) {
-        const double* xc = Ua + t;
+        const double* xc = Ua + (size_t)t * dmax;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll 8
         for (int k = 0; k < d; ++k) {
-          const double x = xc[(size_t)k * dmax];
+          const double x = xc[k];
           a0 += R1[k] * x; a1 += R1[(size_t)d + k] * x; a2 += R1[(size_t)2 * d + k] * x; a3 += R1[(size_t)3 * d + k] * x;
         }
         const double sc = vsc[t];
@@ -794,7 +800,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
   __shared__ int s_atom, s_maxpos;
   __shared__ double s_lo, s_hi, s_e2max;
   double* scr = g.scratch + (size_t)blockIdx.x * dmax * 4 * nt + tid;
-  const size_t ld = 4 * (size_t)dmax;      // chain row k -> row 4k + c of U
+  const size_t ld = 4;                     // chain row k -> row 4k + c of its column of U
 
   for (;;) {
     if (tid == 0) s_atom = atomicAdd(g.counter, 1);
@@ -859,11 +865,11 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
     if (lane == 0) atomicMax(&s_maxpos, mp);
     __syncthreads();
     const int maxpos = s_maxpos;
-    double* Ua = g.evec + (size_t)atom * dmax * dmax;       // U[k][t], row stride dmax
+    double* Ua = g.evec + (size_t)atom * dmax * dmax;       // column t of U at Ua + t dmax
     double* vsc = g.vsc + (size_t)atom * dmax;              // normalising factor of column t
     for (int q = tid; q < d * d; q += nt) {                  // rows of the other chains
-      const int row = q / d, t = q - row * d;
-      if ((row & 3) != t / K) Ua[(size_t)row * dmax + t] = 0.0;
+      const int t = q / d, row = q - t * d;
+      if ((row & 3) != t / K) Ua[(size_t)t * dmax + row] = 0.0;
     }
     for (int round = 0; round <= maxpos; ++round) {
       for (int t = tid; t < d; t += nt) {
@@ -872,13 +878,13 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
         const double* Dc = Dg + c * Kp;
         const double* Ec = Eg + c * Kp;
         const double* E2c = E2 + c * Kp;
-        double* xc = Ua + (size_t)c * dmax + t;
+        double* xc = Ua + (size_t)t * dmax + c;
         if (round == 0 && (t + 1 >= cend || pos_s[t + 1] == 0)) {
           vsc[t] = twisted_ck<false>(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
           continue;
         }
         vsc[t] = 1.0;                                // normalised here
-        cluster_vector(Dc, Ec, K, lam_s[t], small, t, round, xc, ld, scr, nt);
+        cluster_vector(Dc, Ec, K, lam_s[t], small, t, round, xc, ld, dmax, scr, nt);
       }
       __syncthreads();
     }
@@ -887,7 +893,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
     double* y1 = g.y1 + (size_t)atom * 4 * dmax;
     for (int t = tid; t < dmax; t += nt) {
       const int c = t < d ? t / K : -1;
-      const double a = t < d ? Ua[(size_t)c * dmax + t] * vsc[t] : 0.0;   // chain row 0 = block row c
+      const double a = t < d ? Ua[(size_t)t * dmax + c] * vsc[t] : 0.0;   // chain row 0 = block row c
       lam[t] = t < d ? lam_s[t] : 0.0;
       wgt[t] = a * a;
 #pragma unroll
@@ -929,25 +935,19 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
     }
   }
   __syncthreads();
-  // x = U v (eigenvectors of the tridiagonal): four rows of U at a time per
-  // wave, read along the row by the lanes (coalesced), 16 sums reduced over
-  // the wave
+  // x = U v (eigenvectors of the tridiagonal): one row of x per thread, over
+  // the columns of U (stored column by column: the lanes read consecutive
+  // rows of a column), v_m broadcast from LDS
   const double* Ua = g.evec + (size_t)atom * dmax * dmax;
-  for (int k0 = 4 * wave; k0 < d; k0 += 4 * NW) {
-    double acc[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    for (int m = lane; m < d; m += 64) {
-      const double v0 = v[4 * m], v1 = v[4 * m + 1], v2 = v[4 * m + 2], v3 = v[4 * m + 3];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double u = Ua[(size_t)(k0 + r) * dmax + m];
-        acc[r * 4] += u * v0; acc[r * 4 + 1] += u * v1; acc[r * 4 + 2] += u * v2; acc[r * 4 + 3] += u * v3;
-      }
+  for (int k = tid; k < d; k += RHO_NT) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < d; ++m) {
+      const double u = Ua[(size_t)m * dmax + k];
+      a0 += u * v[4 * m]; a1 += u * v[4 * m + 1]; a2 += u * v[4 * m + 2]; a3 += u * v[4 * m + 3];
     }
-    int which;
-    const double sum = wave_sum16(acc, lane, which);
-    if ((lane & 3) == 0) x[xrow(k0 + (which >> 2)) + (which & 3)] = sum;
+    double* xk = x + xrow(k);
+    xk[0] = a0; xk[1] = a1; xk[2] = a2; xk[3] = a3;
   }
   __syncthreads();
   // c = Z x: the reflector segments in reverse; the reflectors of one segment

@@ -202,7 +202,7 @@ struct EigArgs {
   int* seg; int* seg_n; int seg_max;   // [N][seg_max] segment starts; [N][2]: segment counts
   int* counter;                        // persistent-kernel atom queue (zeroed before launch)
   double* scratch;                     // [WG][4 r_max][4][threads]: LU factors of inverse iteration
-  double* evec;                        // [N][4 r_max][4 r_max]: eigenvectors of the tridiagonal, [k][t]
+  double* evec;                        // [N][4 r_max][4 r_max]: eigenvectors of the tridiagonal, column t at t * 4 r_max
   double* vsc;                         // [N][4 r_max]: factor that normalises column t of evec
   double* tri;                         // [N][2][4 r_max]: diagonal and off-diagonal of the tridiagonal
   int64_t* stats;
@@ -328,7 +328,7 @@ struct tb_ctx {
   double* lam; double* wgt; double* y1;                    // [N][D], [N][D], [N][4][D]
   double* ref_v; uint16_t* ref_p; int* ref_n;             // [N][REF][4] (v1 v2 v3 tau), [N][REF] (row), [N]
   int* seg; int* seg_n; int seg_max;                       // [N][SEG], [N][2]
-  double* evec;                                            // [N][D][D]
+  double* evec;                                            // [N][D][D], column by column
   double* vsc;                                             // [N][D] normalising factors of the evec columns
   double* tri;                                             // [N][2][D]
   double* eig_scratch;                                     // [WG_EIG][D][4][EIG_NT]
