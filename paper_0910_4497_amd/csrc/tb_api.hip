@@ -344,8 +344,9 @@ static LanczosArgs lanczos_args(const tb_ctx* c, int n, int r, const int* r_per_
   return la;
 }
 
-static EigArgs eig_args(const tb_ctx* c, int n) {
+static EigArgs eig_args(const tb_ctx* c, int n, int precision) {
   EigArgs ea;
+  ea.u_fp32 = precision != TB_FP64 ? 1 : 0;      // U in the recursion's precision (k_rho reads it so)
   ea.atom0 = 0; ea.n_atoms = n; ea.r_max = c->r_max; ea.tab = c->tab; ea.kused = c->kused;
   ea.lam = c->lam; ea.wgt = c->wgt; ea.y1 = c->y1;
   ea.ref_v = c->ref_v; ea.ref_p = c->ref_p; ea.ref_n = c->ref_n; ea.ref_max = c->ref_max;
@@ -400,7 +401,7 @@ extern "C" int tb_krylov_rho(tb_ctx* c, int r, const int* r_per_atom, double kT,
   }
   prof_end(c, pk);
   // K5: projected eigensolve
-  EigArgs ea = eig_args(c, n);
+  EigArgs ea = eig_args(c, n, precision);
   pk = prof_begin(c, 2);
   for (int a0 = 0; a0 < n; a0 += chunk) {
     const int a1 = n - a0 > chunk ? a0 + chunk : n;
@@ -511,7 +512,7 @@ extern "C" int tb_autotune(tb_ctx* c, int r, const int* r_per_atom, int precisio
     c->lz_per_cu[precision] = best_pc;
     c->lz_wide[precision] = best_wide;
     // k_eig consumes the recursion of the last Krylov run (identical for every shape)
-    EigArgs ea = eig_args(c, n);
+    EigArgs ea = eig_args(c, n, precision);
     const int cand[5] = {2, 3, 4, 6, 8};
     float beste = 3.0e38f;
     for (int q = 0; q < 5 && err == hipSuccess; ++q) {

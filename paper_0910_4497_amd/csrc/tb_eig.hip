@@ -269,9 +269,12 @@ __device__ __forceinline__ double start_val(int t, int k) {
 // (stride ld; may alias bcol). The right-hand side is scaled by the pivot
 // floor so that a near-singular last pivot gives |x| of order one rather than
 // 1/eps. Scratch: 4 values per row at scr[(k * 4 + f) * ns] (coalesced
-// over the workgroup). Returns ||x||^2.
+// over the workgroup). UT: element type of the columns of U (double, or
+// float after the FP32 recursion). Returns ||x||^2 of the computed x (before
+// its rounding to UT).
+template <typename UT>
 __device__ double inv_solve(const double* D, const double* E, int d, double lam, double small, int t,
-                            const double* bcol, double* xcol, size_t ld, double* scr, int ns) {
+                            const UT* bcol, UT* xcol, size_t ld, double* scr, int ns) {
   double cd = D[0] - lam;
   double cu = d > 1 ? E[0] : 0.0;
   double cb = small * (bcol ? bcol[0] : start_val(t, 0));
@@ -300,7 +303,7 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
     double piv = sk[0];
     if (fabs(piv) < small) piv = (piv < 0.0) ? -small : small;
     const double x = (sk[3 * ns] - sk[ns] * x1 - sk[2 * ns] * x2) / piv;
-    xcol[(size_t)k * ld] = x;
+    xcol[(size_t)k * ld] = (UT)x;
     nrm += x * x;
     x2 = x1; x1 = x;
   }
@@ -319,32 +322,34 @@ __device__ double inv_solve(const double* D, const double* E, int d, double lam,
 // three for the others; when orthogonalisation removes most of an iterate,
 // the member starts again from another pseudo-random vector. The result in
 // xc (stride ld) is normalised.
+template <typename UT>
 __device__ void cluster_vector(const double* D, const double* E, int d, double lam, double small, int t, int pos,
-                               double* xc, size_t ld, size_t cs, double* scr, int ns) {
+                               UT* xc, size_t ld, size_t cs, double* scr, int ns) {
   auto orth = [&]() {
     for (int rep = 0; rep < 2; ++rep) {
       for (int p = 1; p <= pos; ++p) {
-        const double* uj = xc - (size_t)p * cs;
+        const UT* uj = xc - (size_t)p * cs;
         double dot = 0.0;
-        for (int k = 0; k < d; ++k) dot += uj[(size_t)k * ld] * xc[(size_t)k * ld];
-        for (int k = 0; k < d; ++k) xc[(size_t)k * ld] -= dot * uj[(size_t)k * ld];
+        for (int k = 0; k < d; ++k) dot += (double)uj[(size_t)k * ld] * (double)xc[(size_t)k * ld];
+        for (int k = 0; k < d; ++k)
+          xc[(size_t)k * ld] = (UT)((double)xc[(size_t)k * ld] - dot * (double)uj[(size_t)k * ld]);
       }
     }
     double nrm = 0.0;
-    for (int k = 0; k < d; ++k) nrm += xc[(size_t)k * ld] * xc[(size_t)k * ld];
+    for (int k = 0; k < d; ++k) nrm += (double)xc[(size_t)k * ld] * (double)xc[(size_t)k * ld];
     return nrm;
   };
   auto scale = [&](double nrm) {
     const double sc = 1.0 / sqrt(nrm);
-    for (int k = 0; k < d; ++k) xc[(size_t)k * ld] *= sc;
+    for (int k = 0; k < d; ++k) xc[(size_t)k * ld] = (UT)((double)xc[(size_t)k * ld] * sc);
   };
   int seed = t;
   for (int attempt = 0; attempt < 4; ++attempt) {
-    for (int k = 0; k < d; ++k) xc[(size_t)k * ld] = start_val(seed, k);
+    for (int k = 0; k < d; ++k) xc[(size_t)k * ld] = (UT)start_val(seed, k);
     scale(pos > 0 ? orth() : (double)d);
     bool ok = true;
     for (int s = 0; s < (pos > 0 ? 3 : 2); ++s) {
-      scale(inv_solve(D, E, d, lam, small, t, xc, xc, ld, scr, ns));
+      scale(inv_solve<UT>(D, E, d, lam, small, t, xc, xc, ld, scr, ns));
       if (pos > 0) {
         const double nrm = orth();
         if (!(nrm > 0.25)) { ok = false; scale(nrm > 0.0 ? nrm : 1.0); break; }
@@ -377,9 +382,9 @@ __device__ void cluster_vector(const double* D, const double* E, int d, double l
 // twist index; z_k for k < r (forward pivots recomputed per run, consumed in
 // reverse); z_k for k > r (backward pivots recomputed per run from the next
 // run's checkpoint, consumed in order).
-template <bool ACC>
+template <bool ACC, typename UT>
 __device__ double twisted_ck(const double* D, const double* E, const double* E2, int d, double lam, double small,
-                             double* xcol, size_t ld, double* ck, int ns, const double* R1 = nullptr,
+                             UT* xcol, size_t ld, double* ck, int ns, const double* R1 = nullptr,
                              double* y = nullptr) {
   constexpr int CK = 8;
   const int nck = (d + CK - 1) / CK;
@@ -419,11 +424,11 @@ __device__ double twisted_ck(const double* D, const double* E, const double* E2,
     ckb[(size_t)c * ns] = m;                     // d-_{k0}
   }
   double z = 1.0, nrm = 1.0;
-  xcol[(size_t)r * ld] = 1.0;
+  xcol[(size_t)r * ld] = (UT)1.0;
   double y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
   if constexpr (ACC) { y0 = R1[r]; y1 = R1[(size_t)d + r]; y2 = R1[(size_t)2 * d + r]; y3 = R1[(size_t)3 * d + r]; }
   auto acc = [&](int k, double zk) {
-    xcol[(size_t)k * ld] = zk;
+    xcol[(size_t)k * ld] = (UT)zk;
     nrm += zk * zk;
     if constexpr (ACC) {
       y0 += R1[k] * zk; y1 += R1[(size_t)d + k] * zk; y2 += R1[(size_t)2 * d + k] * zk; y3 += R1[(size_t)3 * d + k] * zk;
@@ -627,6 +632,7 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
   }
 }
 
+template <typename UT>
 __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
   extern __shared__ double esm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -719,18 +725,18 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     if (lane == 0) atomicMax(&s_maxpos, mp);
     __syncthreads();
     const int maxpos = s_maxpos;
-    double* Ua = g.evec + (size_t)atom * dmax * dmax;       // column t of U at Ua + t dmax
+    UT* Ua = (UT*)g.evec + (size_t)atom * dmax * dmax;      // column t of U at Ua + t dmax
     double* vsc = g.vsc + (size_t)atom * dmax;              // normalising factor of column t
     for (int round = 0; round <= maxpos; ++round) {
       for (int t = tid; t < d; t += nt) {
         if (pos_s[t] != round) continue;
-        double* xc = Ua + (size_t)t * dmax;
+        UT* xc = Ua + (size_t)t * dmax;
         if (round == 0 && (t + 1 >= d || pos_s[t + 1] == 0)) {
           // not in a cluster: twisted factorisation (column scale kept apart),
           // which also forms Y[0:4, t] = Z[0:4, :] U[:, t]; the outputs of
           // the column are written here and skipped in step 4
           double ya[4];
-          const double sc = twisted_ck<true>(Dg, Eg, E2, d, lam_s[t], small, xc, 1, scr, nt, R1, ya);
+          const double sc = twisted_ck<true, UT>(Dg, Eg, E2, d, lam_s[t], small, xc, 1, scr, nt, R1, ya);
           vsc[t] = sc;
           double* y1o = g.y1 + (size_t)atom * 4 * dmax;
           const double a0 = ya[0] * sc, a1 = ya[1] * sc, a2 = ya[2] * sc, a3 = ya[3] * sc;
@@ -740,7 +746,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
           continue;
         }
         vsc[t] = 1.0;                                // normalised here
-        cluster_vector(Dg, Eg, d, lam_s[t], small, t, round, xc, 1, dmax, scr, nt);
+        cluster_vector<UT>(Dg, Eg, d, lam_s[t], small, t, round, xc, 1, dmax, scr, nt);
       }
       __syncthreads();
     }
@@ -751,11 +757,11 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
     for (int t = tid; t < dmax; t += nt) {
       if (t < d && pos_s[t] == 0 && (t + 1 >= d || pos_s[t + 1] == 0)) continue;   // written in step 3
       if (t < d) {
-        const double* xc = Ua + (size_t)t * dmax;
+        const UT* xc = Ua + (size_t)t * dmax;
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll 8
         for (int k = 0; k < d; ++k) {
-          const double x = xc[k];
+          const double x = (double)xc[k];
           a0 += R1[k] * x; a1 += R1[(size_t)d + k] * x; a2 += R1[(size_t)2 * d + k] * x; a3 += R1[(size_t)3 * d + k] * x;
         }
         const double sc = vsc[t];
@@ -784,6 +790,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig(EigArgs g) {
 // nonzero in row c only. The chains are stored chain-major at a stride Kp =
 // K rounded up to 4 (the Sturm count reads four rows at a time), padded with
 // D = 1e30, E = 0: rows that add no sign change below any eigenvalue.
+template <typename UT>
 __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
   extern __shared__ double esm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -865,11 +872,11 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
     if (lane == 0) atomicMax(&s_maxpos, mp);
     __syncthreads();
     const int maxpos = s_maxpos;
-    double* Ua = g.evec + (size_t)atom * dmax * dmax;       // column t of U at Ua + t dmax
+    UT* Ua = (UT*)g.evec + (size_t)atom * dmax * dmax;      // column t of U at Ua + t dmax
     double* vsc = g.vsc + (size_t)atom * dmax;              // normalising factor of column t
     for (int q = tid; q < d * d; q += nt) {                  // rows of the other chains
       const int t = q / d, row = q - t * d;
-      if ((row & 3) != t / K) Ua[(size_t)t * dmax + row] = 0.0;
+      if ((row & 3) != t / K) Ua[(size_t)t * dmax + row] = (UT)0.0;
     }
     for (int round = 0; round <= maxpos; ++round) {
       for (int t = tid; t < d; t += nt) {
@@ -878,13 +885,13 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
         const double* Dc = Dg + c * Kp;
         const double* Ec = Eg + c * Kp;
         const double* E2c = E2 + c * Kp;
-        double* xc = Ua + (size_t)t * dmax + c;
+        UT* xc = Ua + (size_t)t * dmax + c;
         if (round == 0 && (t + 1 >= cend || pos_s[t + 1] == 0)) {
-          vsc[t] = twisted_ck<false>(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
+          vsc[t] = twisted_ck<false, UT>(Dc, Ec, E2c, K, lam_s[t], small, xc, ld, scr, nt);
           continue;
         }
         vsc[t] = 1.0;                                // normalised here
-        cluster_vector(Dc, Ec, K, lam_s[t], small, t, round, xc, ld, dmax, scr, nt);
+        cluster_vector<UT>(Dc, Ec, K, lam_s[t], small, t, round, xc, ld, dmax, scr, nt);
       }
       __syncthreads();
     }
@@ -893,7 +900,7 @@ __global__ void __launch_bounds__(EIG_NT, 4) k_eig_chains(EigArgs g) {
     double* y1 = g.y1 + (size_t)atom * 4 * dmax;
     for (int t = tid; t < dmax; t += nt) {
       const int c = t < d ? t / K : -1;
-      const double a = t < d ? Ua[(size_t)t * dmax + c] * vsc[t] : 0.0;   // chain row 0 = block row c
+      const double a = t < d ? (double)Ua[(size_t)t * dmax + c] * vsc[t] : 0.0;   // chain row 0 = block row c
       lam[t] = t < d ? lam_s[t] : 0.0;
       wgt[t] = a * a;
 #pragma unroll
@@ -938,12 +945,12 @@ __global__ void __launch_bounds__(RHO_NT) k_rho(RhoArgs g) {
   // x = U v (eigenvectors of the tridiagonal): one row of x per thread, over
   // the columns of U (stored column by column: the lanes read consecutive
   // rows of a column), v_m broadcast from LDS
-  const double* Ua = g.evec + (size_t)atom * dmax * dmax;
+  const VJ* Ua = (const VJ*)g.evec + (size_t)atom * dmax * dmax;   // U in the recursion's precision
   for (int k = tid; k < d; k += RHO_NT) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll 8
     for (int m = 0; m < d; ++m) {
-      const double u = Ua[(size_t)m * dmax + k];
+      const double u = (double)Ua[(size_t)m * dmax + k];
       a0 += u * v[4 * m]; a1 += u * v[4 * m + 1]; a2 += u * v[4 * m + 2]; a3 += u * v[4 * m + 3];
     }
     double* xk = x + xrow(k);
@@ -1077,12 +1084,13 @@ int eig_threads(int r_max) {
 }
 
 hipError_t eig_set_lds(int r_max) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_eig, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)eig_lds_bytes(r_max));
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_eig_chains, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)eig_lds_bytes(r_max));
-  if (e != hipSuccess) return e;
+  const void* eig_fn[4] = {(const void*)k_eig<double>, (const void*)k_eig<float>,
+                           (const void*)k_eig_chains<double>, (const void*)k_eig_chains<float>};
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < 4; ++q) {
+    e = hipFuncSetAttribute(eig_fn[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)eig_lds_bytes(r_max));
+    if (e != hipSuccess) return e;
+  }
   e = hipFuncSetAttribute((const void*)k_band, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)band_lds_bytes(r_max));
   if (e != hipSuccess) return e;
@@ -1095,11 +1103,15 @@ hipError_t eig_set_lds(int r_max) {
 
 void launch_eig(const EigArgs& a, int n_wg, hipStream_t st) {
   if (a.scalar) {
-    hipLaunchKernelGGL(k_eig_chains, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
+    if (a.u_fp32)
+      hipLaunchKernelGGL(k_eig_chains<float>, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
+    else
+      hipLaunchKernelGGL(k_eig_chains<double>, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
     return;
   }
   hipLaunchKernelGGL(k_band, dim3(a.n_atoms - a.atom0), dim3(BAND_NT), band_lds_bytes(a.r_max), st, a);
-  hipLaunchKernelGGL(k_eig, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
+  if (a.u_fp32) hipLaunchKernelGGL(k_eig<float>, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
+  else hipLaunchKernelGGL(k_eig<double>, dim3(n_wg), dim3(eig_threads(a.r_max)), eig_lds_bytes(a.r_max), st, a);
 }
 void launch_rho(const RhoArgs& a, hipStream_t st) {
   if (a.vj_fp32) hipLaunchKernelGGL(k_rho<float>, dim3(a.n_atoms - a.atom0), dim3(RHO_NT), rho_lds_bytes(a.r_max), st, a);

@@ -202,7 +202,8 @@ struct EigArgs {
   int* seg; int* seg_n; int seg_max;   // [N][seg_max] segment starts; [N][2]: segment counts
   int* counter;                        // persistent-kernel atom queue (zeroed before launch)
   double* scratch;                     // [WG][4 r_max][4][threads]: LU factors of inverse iteration
-  double* evec;                        // [N][4 r_max][4 r_max]: eigenvectors of the tridiagonal, column t at t * 4 r_max
+  void* evec;                          // [N][4 r_max][4 r_max]: eigenvectors of the tridiagonal, column t at t * 4 r_max
+  int u_fp32;                          // evec holds float (after the FP32 recursion) or double
   double* vsc;                         // [N][4 r_max]: factor that normalises column t of evec
   double* tri;                         // [N][2][4 r_max]: diagonal and off-diagonal of the tridiagonal
   int64_t* stats;
@@ -215,7 +216,7 @@ struct RhoArgs {
   const double* lam; const double* y1;
   const double* ref_v; const uint16_t* ref_p; const int* ref_n; int64_t ref_max;
   const int* seg; const int* seg_n; int seg_max;
-  const double* evec; const double* vsc;
+  const void* evec; const double* vsc;     // evec: float when vj_fp32, else double
   const void* vj; int vj_fp32;
   const int64_t* row_ptr;
   const double* mu_state; double kT;
