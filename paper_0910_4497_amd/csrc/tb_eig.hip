@@ -58,6 +58,19 @@ constexpr int SBR_LS = 9;          // LDS doubles per band column: concurrent ta
                                    // 16 different bank pairs (a stride of 8 put them on 2)
 constexpr int SBR_LAG = 3;         // time steps between the starts of consecutive sweeps
 
+// Lane permutations within each quad of lanes (DPP quad_perm, no LDS round
+// trip), for FP64 values: the value of lane (l & ~3) + P_j, P = (P0, P1, P2,
+// P3) for the four lanes of the quad.
+template <int PERM>
+__device__ __forceinline__ double quad_perm_d(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), PERM, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), PERM, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int QP_XOR1 = 0xB1;    // (1, 0, 3, 2)
+constexpr int QP_XOR2 = 0x4E;    // (2, 3, 0, 1)
+template <int C> constexpr int QP_BCAST = C * 0x55;   // (C, C, C, C)
+
 // Row m of the 4-column vectors in k_rho's LDS. The reflectors a replay step
 // applies at once start 11 rows apart; with this skew their 16 leading rows
 // in a wave fall on 16 different bank pairs (with a plain stride of 4
@@ -485,7 +498,7 @@ __device__ double twisted_ck(const double* D, const double* E, const double* E2,
 // column p0 - 3 + q left of the window (q < 3, tasks after the first of a
 // sweep), row q of the symmetric 4x4 window block (rank-2 form
 // A <- A - v w^T - w v^T, w = p - (tau/2)(p.v) v, p = tau A v; the four p_q
-// summed over the quad by shuffles), row p0 + 4 + q below the window, and
+// summed over the quad by DPP permutes), row p0 + 4 + q below the window, and
 // row q of Z. Every lane loads everything it needs before any store, and the
 // LDS operations of a wave complete in issue order; wave-scope fences order
 // the time steps.
@@ -515,7 +528,7 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
   double* lv = g.ref_v + (size_t)atom * g.ref_max * 4;
   uint16_t* lp = g.ref_p + (size_t)atom * g.ref_max;
   int* seg = g.seg + (size_t)atom * g.seg_max;
-  const int grp = lane >> 2, q = lane & 3, qb = lane & ~3;
+  const int grp = lane >> 2, q = lane & 3;
   int64_t nref = 0;
   int nseg = 0;
   const int T = d >= 3 ? SBR_LAG * (d - 3) + 1 : 0;
@@ -580,12 +593,12 @@ __global__ void __launch_bounds__(BAND_NT) k_band(EigArgs g) {
         // window block: p_q = tau (A v)_q, K = (tau/2) sum p v, w = p - K v
         const double pq = tau * (yd[0] + v1 * yd[1] + v2 * yd[2] + v3 * yd[3]);
         double kq = pq * vq;
-        kq += __shfl_xor(kq, 1, 64);
-        kq += __shfl_xor(kq, 2, 64);
+        kq += quad_perm_d<QP_XOR1>(kq);
+        kq += quad_perm_d<QP_XOR2>(kq);
         const double wq = pq - 0.5 * tau * kq * vq;
         double wm[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) wm[m] = __shfl(wq, qb + m, 64);
+        wm[0] = quad_perm_d<QP_BCAST<0>>(wq); wm[1] = quad_perm_d<QP_BCAST<1>>(wq);
+        wm[2] = quad_perm_d<QP_BCAST<2>>(wq); wm[3] = quad_perm_d<QP_BCAST<3>>(wq);
 #pragma unroll
         for (int m = 0; m < 4; ++m) yd[m] -= vq * wm[m] + wq * vv[m];
         // stores
