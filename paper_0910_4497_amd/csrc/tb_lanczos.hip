@@ -44,6 +44,21 @@ __device__ __forceinline__ float quad_bcast(float v) {
 }
 
 
+// Lane permutations within each quad of lanes (DPP quad_perm, no LDS round
+// trip): lane (l & ~3) + P_j's value for the j-th lane of the quad.
+template <int PERM>
+__device__ __forceinline__ float quad_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), PERM, 0xF, 0xF, false));
+}
+template <int PERM>
+__device__ __forceinline__ double quad_perm(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), PERM, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), PERM, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int QP_XOR1 = 0xB1;    // (1, 0, 3, 2)
+constexpr int QP_XOR2 = 0x4E;    // (2, 3, 0, 1)
+
 // a * b + c with one rounding
 __device__ __forceinline__ float fmav(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmav(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -484,14 +499,14 @@ k_lanczos(LanczosArgs g) {
               for (int cc = 0; cc < 2; ++cc) {
                 const VT keep = hi ? w[o * 4 + 2 + cc] : w[o * 4 + cc];
                 const VT send = hi ? w[o * 4 + cc] : w[o * 4 + 2 + cc];
-                h[o * 2 + cc] = keep + __shfl_xor(send, 2, 64);
+                h[o * 2 + cc] = keep + quad_perm<QP_XOR2>(send);
               }
             VT r[4];
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
               const VT keep = lo ? h[o * 2 + 1] : h[o * 2];
               const VT send = lo ? h[o * 2] : h[o * 2 + 1];
-              r[o] = keep + __shfl_xor(send, 1, 64);
+              r[o] = keep + quad_perm<QP_XOR1>(send);
             }
             w0 = r[0]; w1 = r[1]; w2 = r[2]; w3 = r[3];
           }
@@ -727,9 +742,8 @@ k_lanczos(LanczosArgs g) {
               }
               m = acc + copysignf(rndf, acc);
             }
-            float o = 0.0f;
-  #pragma unroll
-            for (int c = 0; c < 4; ++c) o += __shfl(m, (lane & ~3) | c, 64) * Xcol[c];
+            const float o = quad_bcast<0>(m) * Xcol[0] + quad_bcast<1>(m) * Xcol[1] +
+                            quad_bcast<2>(m) * Xcol[2] + quad_bcast<3>(m) * Xcol[3];
             Okp[j * 16 + a * 4 + b] = o;
             // orbital seeds: only a chain's own entries estimate a loss of
             // orthogonality (different chains are not orthogonal)
