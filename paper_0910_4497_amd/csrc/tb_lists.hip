@@ -105,6 +105,7 @@ k_lists(int n, const double* __restrict__ pos, Box box, CellGrid cg, const int* 
   __shared__ int s_hj[ZMAX_CAP];
   __shared__ double s_hd[ZMAX_CAP][4];
   __shared__ int s_nh, s_nc;
+  __shared__ int s_cb[27], s_co[28];            // scanned cells: first candidate, range offsets
   const int i = blockIdx.x;
   const int tid = threadIdx.x;
   if (tid == 0) { s_nh = 0; s_nc = 0; }
@@ -121,32 +122,77 @@ k_lists(int n, const double* __restrict__ pos, Box box, CellGrid cg, const int* 
     if (cg.n[a] >= 3) { lo[a] = cc[a] - 1; cnt[a] = 3; }
     else { lo[a] = 0; cnt[a] = cg.n[a]; }
   }
+  // The candidates of all scanned cells form one flat range: the first
+  // threads read the cells' bounds (one round trip), wave 0 scans their
+  // sizes, and every thread then takes candidates q = tid, tid + LIST_NT, ...
+  // of the range in batches whose loads are all issued before the distances
+  // are formed (two round trips per batch instead of three per cell). The
+  // hop and sphere members are put in index order below, so the order in
+  // which they are found does not matter.
+  const int ncs = cnt[0] * cnt[1] * cnt[2];     // <= 27 distinct cells
+  if (tid < ncs) {
+    const int u0 = tid / (cnt[1] * cnt[2]), u1 = (tid / cnt[2]) % cnt[1], u2 = tid % cnt[2];
+    const int a0 = (lo[0] + u0 + cg.n[0]) % cg.n[0], a1 = (lo[1] + u1 + cg.n[1]) % cg.n[1],
+              a2 = (lo[2] + u2 + cg.n[2]) % cg.n[2];
+    const int cell = (a0 * cg.n[1] + a1) * cg.n[2] + a2;
+    const int b0 = cell_start[cell];
+    s_cb[tid] = b0;
+    s_co[tid + 1] = cell_start[cell + 1] - b0;
+  }
   __syncthreads();
-  for (int u0 = 0; u0 < cnt[0]; ++u0)
-    for (int u1 = 0; u1 < cnt[1]; ++u1)
-      for (int u2 = 0; u2 < cnt[2]; ++u2) {
-        const int a0 = (lo[0] + u0 + cg.n[0]) % cg.n[0], a1 = (lo[1] + u1 + cg.n[1]) % cg.n[1],
-                  a2 = (lo[2] + u2 + cg.n[2]) % cg.n[2];
-        const int cell = (a0 * cg.n[1] + a1) * cg.n[2] + a2;
-        const int b0 = cell_start[cell], b1 = cell_start[cell + 1];
-        for (int q = b0 + tid; q < b1; q += LIST_NT) {
-          const int j = cell_atoms[q];
-          if (j == i) continue;
-          const double dx = mic(pos[3 * j] - xi, box.L[0], box.per[0]);
-          const double dy = mic(pos[3 * j + 1] - yi, box.L[1], box.per[1]);
-          const double dz = mic(pos[3 * j + 2] - zi, box.L[2], box.per[2]);
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (!isfinite(r2)) nonfinite = true;
-          if (r2 < rl2) {
-            const int slot = atomicAdd(&s_nh, 1);
-            if (slot < zmax) { s_hj[slot] = j; s_hd[slot][0] = dx; s_hd[slot][1] = dy; s_hd[slot][2] = dz; s_hd[slot][3] = sqrt(r2); }
-          }
-          if (r2 < rc2) {
-            const int slot = atomicAdd(&s_nc, 1);
-            if (slot < nc_max - 1) s_cj[slot] = j;
-          }
+  if (tid < 64) {                               // inclusive scan of the sizes, one wave
+    int v = tid < ncs ? s_co[tid + 1] : 0;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+      const int u = __shfl_up(v, off, 64);
+      if (tid >= off) v += u;
+    }
+    if (tid < ncs) s_co[tid + 1] = v;
+    if (tid == 0) s_co[0] = 0;
+  }
+  __syncthreads();
+  const int total = s_co[ncs];
+  constexpr int LB = 4;                         // candidates per thread and batch
+  for (int q0 = tid; q0 < total; q0 += LB * LIST_NT) {
+    int jj[LB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int q = q0 + u * LIST_NT;
+      jj[u] = -1;
+      if (q < total) {
+        int c = 0, hi = ncs - 1;                // the last cell whose range starts at or before q
+        while (c < hi) {
+          const int mid = (c + hi + 1) >> 1;
+          if (s_co[mid] <= q) c = mid; else hi = mid - 1;
         }
+        jj[u] = cell_atoms[s_cb[c] + (q - s_co[c])];
       }
+    }
+    double px[LB], py[LB], pz[LB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int j = jj[u] < 0 ? i : jj[u];
+      px[u] = pos[3 * j]; py[u] = pos[3 * j + 1]; pz[u] = pos[3 * j + 2];
+    }
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int j = jj[u];
+      if (j < 0 || j == i) continue;
+      const double dx = mic(px[u] - xi, box.L[0], box.per[0]);
+      const double dy = mic(py[u] - yi, box.L[1], box.per[1]);
+      const double dz = mic(pz[u] - zi, box.L[2], box.per[2]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (!isfinite(r2)) nonfinite = true;
+      if (r2 < rl2) {
+        const int slot = atomicAdd(&s_nh, 1);
+        if (slot < zmax) { s_hj[slot] = j; s_hd[slot][0] = dx; s_hd[slot][1] = dy; s_hd[slot][2] = dz; s_hd[slot][3] = sqrt(r2); }
+      }
+      if (r2 < rc2) {
+        const int slot = atomicAdd(&s_nc, 1);
+        if (slot < nc_max - 1) s_cj[slot] = j;
+      }
+    }
+  }
   __syncthreads();
   const int nh = s_nh, ncl = s_nc + 1;          // the sphere counts its target
   const int mh = nh < zmax ? nh : zmax, mc = ncl - 1 < nc_max - 1 ? ncl - 1 : nc_max - 1;
@@ -313,7 +359,7 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
         const int* __restrict__ hop_n, const int* __restrict__ hop_j, const double* __restrict__ hop_d,
         const double* __restrict__ pair64, const int* __restrict__ clu_n, const int* __restrict__ clu_j,
         int* __restrict__ loc_off, uint32_t* __restrict__ loc_ent, double* __restrict__ hnorm,
-        int* __restrict__ jloc, int64_t* stats) {
+        int* __restrict__ jloc, int64_t* stats, int cache_b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int i = blockIdx.x, tid = threadIdx.x;
   const int n = clu_n[i];
@@ -322,7 +368,11 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
   // [nc_max][3], 8-byte aligned; addressed from smem by a byte offset so that
   // its accesses stay LDS accesses (not flat ones)
   double* s_x = (double*)(smem + ((((size_t)(2 * nc_max + 2) * sizeof(int)) + 7) & ~(size_t)7));
+  // [nc_max][zmax] local partner of each hop slot, or -1 (cache_b: short hop
+  // lists whose table fits the LDS budget; else pass 2 repeats the tests)
+  int16_t* s_b = (int16_t*)(s_x + 3 * (size_t)nc_max);
   __shared__ double s_red[LIST_NT / 64];
+  __shared__ int s_wsum[LIST_NT / 64];
   const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
   for (int a = tid; a < n; a += LIST_NT) {
     const int g = clu_j[(int64_t)i * nc_max + a];
@@ -369,17 +419,41 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
       if (lane == 0) s_cnt[a + 1] = cnt;
     }
   } else {
+    // the slots' distance, partner and hopping scale are loaded a batch at
+    // a time, all before they are used; the local partner (or -1) of every
+    // slot is kept for pass 2
+    constexpr int SB = 8;
     for (int a = tid; a < n; a += LIST_NT) {
       const int g = s_c[a];
       const int nh = hop_n[g];
       int cnt = 0;
       fro += M.eps_s * M.eps_s + 3 * M.eps_p * M.eps_p;
-      for (int t = 0; t < nh; ++t) {
-        int b;
-        if (!coupling(a, g, t, b)) continue;
-        ++cnt;
-        const double sv = pair64[4 * ((int64_t)g * zmax + t) + 3];
-        fro += kfro * sv * sv;
+      for (int t0 = 0; t0 < nh; t0 += SB) {
+        double dd[SB], sv[SB];
+        int hj[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int64_t q = (int64_t)g * zmax + (t0 + u < nh ? t0 + u : t0);
+          dd[u] = hop_d[4 * q + 3]; hj[u] = hop_j[q]; sv[u] = pair64[4 * q + 3];
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int t = t0 + u;
+          if (t >= nh) break;
+          int b = -1;
+          if (dd[u] < M.rm) {
+            b = find_local(s_c, n, hj[u]);
+            if (b >= 0) {
+              const double ex = s_x[3 * b] - s_x[3 * a], ey = s_x[3 * b + 1] - s_x[3 * a + 1],
+                           ez = s_x[3 * b + 2] - s_x[3 * a + 2];
+              if (!(ex * ex + ey * ey + ez * ez < rm2)) b = -1;   // it wraps behind the target
+            }
+          }
+          if (cache_b) s_b[a * zmax + t] = (int16_t)b;
+          if (b < 0) continue;
+          ++cnt;
+          fro += kfro * sv[u] * sv[u];
+        }
       }
       s_cnt[a + 1] = cnt;
     }
@@ -388,11 +462,30 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
   fro = wave_sum(fro);
   if ((tid & 63) == 0) s_red[tid >> 6] = fro;
   __syncthreads();
+  // offsets: inclusive scan of s_cnt[1..n], each thread over a contiguous
+  // chunk, the chunk totals scanned across the workgroup
+  {
+    const int ch = (n + LIST_NT - 1) / LIST_NT;
+    const int a0 = 1 + tid * ch, a1 = a0 + ch < n + 1 ? a0 + ch : n + 1;
+    int tot = 0;
+    for (int a = a0; a < a1; ++a) tot += s_cnt[a];
+    int v = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(v, off, 64);
+      if (lane >= off) v += u;
+    }
+    if (lane == 63) s_wsum[wave] = v;
+    __syncthreads();
+    int run = v - tot;                                 // exclusive within the wave
+    for (int w = 0; w < wave; ++w) run += s_wsum[w];
+    for (int a = a0; a < a1; ++a) { run += s_cnt[a]; s_cnt[a] = run; }
+  }
+  __syncthreads();
   if (tid == 0) {
     double f = 0.0;
     for (int w = 0; w < LIST_NT / 64; ++w) f += s_red[w];
     hnorm[i] = sqrt(f);
-    for (int a = 0; a < n; ++a) s_cnt[a + 1] += s_cnt[a];   // inclusive offsets
     if (s_cnt[n] > emax) stat_flag(stats, FL_COUPLING_OVERFLOW);
     stat_max(stats, ST_MAX_COUPLINGS, s_cnt[n]);
   }
@@ -421,7 +514,9 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
       int64_t e = s_cnt[a];
       for (int t = 0; t < nh; ++t) {
         int b;
-        if (!coupling(a, g, t, b)) continue;
+        if (cache_b) b = s_b[a * zmax + t];
+        else if (!coupling(a, g, t, b)) b = -1;
+        if (b < 0) continue;
         if (e < emax) loc_ent[(int64_t)i * emax + e] = (uint32_t)b | ((uint32_t)t << LOCAL_BITS);
         ++e;
       }
@@ -502,10 +597,13 @@ void launch_build(tb_ctx* c, const double* pos, double r_list, hipStream_t st) {
   const int64_t np = (int64_t)n * c->zmax;
   hipLaunchKernelGGL(k_pairs, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, n, c->zmax, c->model, c->hop_n,
                      c->hop_j, c->hop_d, c->pair64, c->pair32, c->hop_rev);
-  const size_t lds_local = (size_t)c->nc_max * (4 + 4 + 24) + 64;
+  const size_t lds_base = (size_t)c->nc_max * (4 + 4 + 24) + 64;
+  const size_t lds_b = (size_t)c->nc_max * c->zmax * sizeof(int16_t);
+  const int cache_b = c->zmax <= 32 && lds_base + lds_b <= 48 * 1024;
+  const size_t lds_local = lds_base + (cache_b ? lds_b : 0);
   hipLaunchKernelGGL(k_local, dim3(n), dim3(LIST_NT), lds_local, st, n, c->model, pos, c->box, c->nc_max,
                      c->zmax, c->emax, c->hop_n, c->hop_j, c->hop_d, c->pair64, c->clu_n, c->clu_j, c->loc_off,
-                     c->loc_ent, c->hnorm, c->jloc, c->stats);
+                     c->loc_ent, c->hnorm, c->jloc, c->stats, cache_b);
   hipLaunchKernelGGL(k_rowptr, dim3(1), dim3(LIST_NT), 0, st, n, c->hop_n, c->row_ptr);
   const int64_t nq = (int64_t)n * (c->zmax + 1);
   hipLaunchKernelGGL(k_colj, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, n, c->zmax, c->hop_n, c->hop_j,
