@@ -34,6 +34,31 @@ __device__ __forceinline__ void stat_flag(int64_t* stats, int64_t bits) {
   atomicOr((unsigned long long*)&stats[ST_FLAGS], (unsigned long long)bits);
 }
 
+// Inclusive scan of one value per thread over a LIST_NT-thread workgroup
+// (shuffles within each wave, then the wave totals); every thread also gets
+// the workgroup total. s_w: LIST_NT / 64 entries of shared memory.
+template <typename T>
+__device__ __forceinline__ T block_scan(T v, T* s_w, T& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  if (lane == 63) s_w[wave] = v;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < LIST_NT / 64; ++w) {
+    const T x = s_w[w];
+    pre += w < wave ? x : 0;
+    tot += x;
+  }
+  __syncthreads();                                   // s_w is reused by the next call
+  total = tot;
+  return v + pre;
+}
+
 __global__ void k_cell_zero(int* __restrict__ cnt, int m) {
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < m; q += gridDim.x * blockDim.x) cnt[q] = 0;
 }
@@ -61,31 +86,21 @@ __global__ void k_cell_count(int n, const double* __restrict__ pos, Box box, Cel
 // the counts reset to serve as scatter cursors
 __global__ void __launch_bounds__(LIST_NT) k_cell_scan(int m, int* __restrict__ cell_cnt,
                                                        int* __restrict__ cell_start) {
-  __shared__ int s_part[LIST_NT];
-  __shared__ int s_base;
+  __shared__ int s_w[LIST_NT / 64];
   const int tid = threadIdx.x;
-  if (tid == 0) s_base = 0;
-  __syncthreads();
-  for (int base = 0; base < m; base += LIST_NT) {
-    const int q = base + tid;
+  int base = 0;                                      // the same in every thread
+  for (int b0 = 0; b0 < m; b0 += LIST_NT) {
+    const int q = b0 + tid;
     const int v = q < m ? cell_cnt[q] : 0;
-    s_part[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < LIST_NT; off <<= 1) {
-      const int add = tid >= off ? s_part[tid - off] : 0;
-      __syncthreads();
-      s_part[tid] += add;
-      __syncthreads();
-    }
+    int tot;
+    const int incl = block_scan(v, s_w, tot);
     if (q < m) {
-      cell_start[q] = s_base + s_part[tid] - v;
-      cell_cnt[q] = s_base + s_part[tid] - v;
+      cell_start[q] = base + incl - v;
+      cell_cnt[q] = base + incl - v;
     }
-    __syncthreads();
-    if (tid == LIST_NT - 1) s_base += s_part[tid];
-    __syncthreads();
+    base += tot;
   }
-  if (tid == 0) cell_start[m] = s_base;
+  if (tid == 0) cell_start[m] = base;
 }
 
 __global__ void k_cell_fill(int n, const int* __restrict__ cell_of, int* __restrict__ cursor,
@@ -354,7 +369,9 @@ __device__ __forceinline__ int find_local(const int* c, int n, int g) {
   return -1;
 }
 
-__global__ void __launch_bounds__(LIST_NT)
+// 64 VGPRs: eight workgroups per compute unit, so that one round of
+// workgroups covers 2048 spheres
+__global__ void __launch_bounds__(LIST_NT, 8)
 k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_max, int zmax, int64_t emax,
         const int* __restrict__ hop_n, const int* __restrict__ hop_j, const double* __restrict__ hop_d,
         const double* __restrict__ pair64, const int* __restrict__ clu_n, const int* __restrict__ clu_j,
@@ -422,7 +439,7 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
     // the slots' distance, partner and hopping scale are loaded a batch at
     // a time, all before they are used; the local partner (or -1) of every
     // slot is kept for pass 2
-    constexpr int SB = 8;
+    constexpr int SB = 6;
     for (int a = tid; a < n; a += LIST_NT) {
       const int g = s_c[a];
       const int nh = hop_n[g];
@@ -531,29 +548,20 @@ k_local(int n_atoms, Model M, const double* __restrict__ pos, Box box, int nc_ma
   }
 }
 
-__global__ void k_rowptr(int n, const int* __restrict__ hop_n, int64_t* __restrict__ row_ptr) {
-  // single workgroup: sequential chunks with a workgroup scan
-  __shared__ int64_t s_part[LIST_NT];
-  __shared__ int64_t s_base;
+__global__ void __launch_bounds__(LIST_NT) k_rowptr(int n, const int* __restrict__ hop_n,
+                                                    int64_t* __restrict__ row_ptr) {
+  // single workgroup: chunks of LIST_NT rows, each a workgroup scan
+  __shared__ int64_t s_w[LIST_NT / 64];
   const int tid = threadIdx.x;
-  if (tid == 0) { s_base = 0; row_ptr[0] = 0; }
-  __syncthreads();
-  for (int base = 0; base < n; base += LIST_NT) {
-    const int i = base + tid;
+  if (tid == 0) row_ptr[0] = 0;
+  int64_t base = 0;                                  // the same in every thread
+  for (int b0 = 0; b0 < n; b0 += LIST_NT) {
+    const int i = b0 + tid;
     const int64_t v = (i < n) ? 1 + hop_n[i] : 0;
-    s_part[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < LIST_NT; off <<= 1) {
-      int64_t add = (tid >= off) ? s_part[tid - off] : 0;
-      __syncthreads();
-      s_part[tid] += add;
-      __syncthreads();
-    }
-    const int64_t start = s_base + s_part[tid] - v;
-    if (i < n) row_ptr[i + 1] = start + v;
-    __syncthreads();
-    if (tid == LIST_NT - 1) s_base += s_part[tid];
-    __syncthreads();
+    int64_t tot;
+    const int64_t incl = block_scan(v, s_w, tot);
+    if (i < n) row_ptr[i + 1] = base + incl;
+    base += tot;
   }
 }
 
