@@ -9,7 +9,7 @@
 // D = V_pps - V_ppp, u_a = X_{s,a} - X_{a,s}. The pair adds +g to the energy
 // gradient on R_j and -g on R_i, so for atom k
 //   F_k = sum_{j in hop(k)} (g_kj - g_jk) + repulsive part,
-// gathered per atom by a quad of lanes (no atomics, fixed order). Repulsion
+// gathered per atom by 16 lanes (no atomics, fixed order). Repulsion
 // E_rep = sum_i F(x_i), x_i = sum_j phi(r_ij), gives
 //   F_k += sum_j (F'(x_k) + F'(x_j)) phi'(r_kj) d_kj / r_kj.
 // Virial (pressure of the diamond cell, Sec. 5): with the same pair terms,
@@ -59,32 +59,47 @@ __device__ __forceinline__ void pair_grad(const Model& M, const double* dvec, co
   for (int c = 0; c < 3; ++c) g[c] = h[c] * radial + sr * (M.v_sps * u[c] + D * (Xh[c] + XTh[c]));
 }
 
+// Sixteen lanes per atom: lane q adds the pair terms of hops q, q + 16, ...,
+// the group sums them in a fixed order (shuffles) and its first lane
+// evaluates the embedding polynomial.
+constexpr int RX_LPA = 16;
+
 __global__ void __launch_bounds__(F_NT) k_rep_x(ForceArgs g) {
-  const int i = blockIdx.x * F_NT + threadIdx.x;
-  if (i >= g.n_atoms) return;
+  const int gid = blockIdx.x * F_NT + threadIdx.x;
+  const int i = gid / RX_LPA, q = gid % RX_LPA;
   double x = 0.0;
-  const int nh = g.hop_n[i];
-  for (int t = 0; t < nh; ++t) {
-    double phi, dphi;
-    pair_term(g.M, g.hop_d[((size_t)i * g.zmax + t) * 4 + 3], phi, dphi);
-    x += phi;
+  if (i < g.n_atoms) {
+    const int nh = g.hop_n[i];
+    for (int t = q; t < nh; t += RX_LPA) {
+      double phi, dphi;
+      pair_term(g.M, g.hop_d[((size_t)i * g.zmax + t) * 4 + 3], phi, dphi);
+      x += phi;
+    }
   }
-  const double* c = g.M.frep;
-  const double F = c[0] + x * (c[1] + x * (c[2] + x * (c[3] + x * c[4])));
-  const double dF = c[1] + x * (2.0 * c[2] + x * (3.0 * c[3] + x * 4.0 * c[4]));
-  g.xrep[2 * i] = dF;
-  g.xrep[2 * i + 1] = F;
+#pragma unroll
+  for (int off = 1; off < RX_LPA; off <<= 1) x += __shfl_xor(x, off, 64);
+  if (i < g.n_atoms && q == 0) {
+    const double* c = g.M.frep;
+    const double F = c[0] + x * (c[1] + x * (c[2] + x * (c[3] + x * c[4])));
+    const double dF = c[1] + x * (2.0 * c[2] + x * (3.0 * c[3] + x * 4.0 * c[4]));
+    g.xrep[2 * i] = dF;
+    g.xrep[2 * i + 1] = F;
+  }
 }
 
-// Four lanes per atom: lane q of the quad takes hop pairs q, q + 4, ...;
-// the quad then sums in a fixed order (shuffles), so the result does not
-// depend on timing.
-constexpr int F_APB = F_NT / 4;     // atoms per block
+// Sixteen lanes per atom: lane q of the group takes hop pairs q, q + 16,
+// ... (a hop list is rarely longer than 16, so a lane's pair terms are one
+// chain of dependent loads, not several in a row); the group then sums in a
+// fixed order (shuffles), so the result does not depend on timing. 64 atoms
+// per block of 1024 threads.
+constexpr int FF_LPA = 16;                 // lanes per atom
+constexpr int FF_NT = 1024;
+constexpr int F_APB = FF_NT / FF_LPA;      // atoms per block
 
-__global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
-  __shared__ double s_w[F_NT / 64][9];
-  const int q4 = threadIdx.x & 3;
-  const int k = blockIdx.x * F_APB + (threadIdx.x >> 2);
+__global__ void __launch_bounds__(FF_NT) k_forces(ForceArgs g) {
+  __shared__ double s_w[FF_NT / 64][9];
+  const int q4 = threadIdx.x & (FF_LPA - 1);
+  const int k = blockIdx.x * F_APB + threadIdx.x / FF_LPA;
   double W[9], F[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < 9; ++q) W[q] = 0.0;
@@ -92,7 +107,7 @@ __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
     const int nh = g.hop_n[k];
     const int64_t pk = g.row_ptr[k];
     const double dFk = g.xrep[2 * k];
-    for (int t = q4; t < nh; t += 4) {
+    for (int t = q4; t < nh; t += FF_LPA) {
       const size_t q = (size_t)k * g.zmax + t;
       const int j = g.hop_j[q];
       const double* dv = g.hop_d + 4 * q;
@@ -119,8 +134,8 @@ __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    F[c] += __shfl_xor(F[c], 1, 64);
-    F[c] += __shfl_xor(F[c], 2, 64);
+#pragma unroll
+    for (int off = 1; off < FF_LPA; off <<= 1) F[c] += __shfl_xor(F[c], off, 64);
   }
   if (k < g.n_atoms && q4 == 0 && g.forces) {
     // backward of E_tot: grad_pos = -g F with the upstream gradient g
@@ -138,7 +153,7 @@ __global__ void __launch_bounds__(F_NT) k_forces(ForceArgs g) {
   __syncthreads();
   if (threadIdx.x < 9) {
     double t = 0.0;
-    for (int w = 0; w < F_NT / 64; ++w) t += s_w[w][threadIdx.x];
+    for (int w = 0; w < FF_NT / 64; ++w) t += s_w[w][threadIdx.x];
     g.wpart[(size_t)blockIdx.x * 9 + threadIdx.x] = t;
   }
 }
@@ -171,10 +186,10 @@ __global__ void __launch_bounds__(F_NT) k_energy(ForceArgs g, int with_virial) {
 }
 
 void launch_forces(const ForceArgs& a, bool with_forces, hipStream_t st) {
-  const int nb = (a.n_atoms + F_NT - 1) / F_NT;
+  const int nb = (int)(((int64_t)a.n_atoms * RX_LPA + F_NT - 1) / F_NT);
   hipLaunchKernelGGL(k_rep_x, dim3(nb), dim3(F_NT), 0, st, a);
   if (with_forces)
-    hipLaunchKernelGGL(k_forces, dim3((a.n_atoms + F_APB - 1) / F_APB), dim3(F_NT), 0, st, a);
+    hipLaunchKernelGGL(k_forces, dim3((a.n_atoms + F_APB - 1) / F_APB), dim3(FF_NT), 0, st, a);
   hipLaunchKernelGGL(k_energy, dim3(1), dim3(F_NT), 0, st, a, with_forces ? 1 : 0);
 }
 

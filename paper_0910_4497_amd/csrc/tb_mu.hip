@@ -141,6 +141,25 @@ __global__ void __launch_bounds__(MU_NT) k_mu_bracket(MuArgs g) {
   store_partials<2, 1>(v, g.partial);
 }
 
+// Adds f(x_p) w for the NE evenly spaced points x_p (E_p = exp((l - x_p)/kT)
+// by products from E_0 = exp(z0), or one exponential per point when |z0| is
+// beyond 600).
+template <int NE>
+__device__ __forceinline__ void even_points(double (&v)[MU_P], const double (&xs)[MU_P], double l, double z0,
+                                            double qstep, double ikT, double w) {
+  if (fabs(z0) <= 600.0) {
+    double E = exp(z0);
+#pragma unroll
+    for (int p = 0; p < NE; ++p) {
+      if (p > 0) E *= qstep;
+      v[p] += 2.0 / (1.0 + E) * w;
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < NE; ++p) v[p] += 2.0 / (1.0 + exp((l - xs[p]) * ikT)) * w;
+  }
+}
+
 // Multisection launch `it` (0-based). The bracket of this launch's points is
 // that of the previous state updated with the previous launch's partials
 // (it = 0: the bracket [min lambda - 50 kT, max lambda + 50 kT] from the
@@ -184,9 +203,34 @@ __global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g, int it) {
   if (st[MS_DONE] != 0.0) return;
   const double lo = st[MS_LO], hi = st[MS_HI];
   const double cut = 40.0 * g.kT;                 // f = 0 or 2 to rounding beyond this
+  const double ikT = 1.0 / g.kT;
   double xs[MU_P];
 #pragma unroll
   for (int p = 0; p < MU_P; ++p) xs[p] = mu_point(st, g.n_e, p);
+  // f(x_p) = 2 / (1 + E_p), E_p = exp((l - x_p) / kT). The evenly spaced
+  // points x_p = lo + (p + 1) h give E_{p+1} = E_p exp(-h / kT): one
+  // exponential per Ritz value and a product per point. The points about the
+  // line's root, x = m -+ o_i (when not clamped to the bracket), give
+  // E = E_m exp(+-o_i / kT). The products add a few ulp of relative error to
+  // E, far below what decides a bracket. A Ritz value more than 600 kT from
+  // the first point or the root takes one exponential per point instead, so
+  // no product starts from an overflowed or underflowed value.
+  const bool first = st[MS_IT] == 0.0;
+  const double h = first ? (hi - lo) / (MU_P + 1) : (hi - lo) / (MU_U + 1);
+  const double qstep = exp(-h * ikT);
+  constexpr int NC = MU_P - MU_U;                 // points about the root (after the first step)
+  double cfac[NC];
+  bool cprod = !first;
+  if (!first) {
+    const double m = xs[MU_U];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double off = c == 0 ? 0.0 : (hi - lo) * __builtin_amdgcn_ldexp(1.0, -20 + 8 * ((c - 1) >> 1));
+      const double xc = (c & 1) ? m - off : m + off;
+      cprod = cprod && xc == xs[MU_U + c];        // not clamped (uniform over the launch)
+      cfac[c] = c == 0 ? 1.0 : exp(((c & 1) ? off : -off) * ikT);
+    }
+  }
   double v[MU_P];
 #pragma unroll
   for (int p = 0; p < MU_P; ++p) v[p] = 0.0;
@@ -198,12 +242,19 @@ __global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g, int it) {
 #pragma unroll
       for (int p = 0; p < MU_P; ++p) v[p] += 2.0 * w;
     } else if (l <= hi + cut) {
+      const double z0 = (l - xs[0]) * ikT;
+      const double zm = first ? 0.0 : (l - xs[MU_U]) * ikT;
+      if (first) even_points<MU_P>(v, xs, l, z0, qstep, ikT, w);
+      else even_points<MU_U>(v, xs, l, z0, qstep, ikT, w);
+      if (!first) {
+        if (cprod && fabs(zm) <= 600.0) {
+          const double Em = exp(zm);
 #pragma unroll
-      for (int p = 0; p < MU_P; ++p) {
-        const double z = (l - xs[p]) / g.kT;
-        const double e = exp(-fabs(z));
-        const double f = (z > 0.0) ? 2.0 * e / (1.0 + e) : 2.0 / (1.0 + e);
-        v[p] += f * w;
+          for (int c = 0; c < NC; ++c) v[MU_U + c] += 2.0 / (1.0 + Em * cfac[c]) * w;
+        } else {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) v[MU_U + c] += 2.0 / (1.0 + exp((l - xs[MU_U + c]) * ikT)) * w;
+        }
       }
     }
   }
