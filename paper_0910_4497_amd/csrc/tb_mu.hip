@@ -89,19 +89,27 @@ __device__ void reduce_partials(const double* partial, int nb, double* out) {
   block_reduce<M, OP>(acc, out);
 }
 
-// Point p of a multisection step on the bracket held in s.
-__device__ __forceinline__ double mu_point(const double* s, double ne, int p) {
+// The MU_P points of a multisection step on the bracket held in s.
+__device__ __forceinline__ void mu_points(const double* s, double ne, double (&xs)[MU_P]) {
   const double lo = s[MS_LO], hi = s[MS_HI], w = hi - lo;
-  if (s[MS_IT] == 0.0) return lo + (p + 1) * (w / (MU_P + 1));
-  if (p < MU_U) return lo + (p + 1) * (w / (MU_U + 1));
-  const double nlo = s[MS_NLO], nhi = s[MS_NHI];
-  double ms = (nhi > nlo) ? lo + (ne - nlo) / (nhi - nlo) * w : 0.5 * (lo + hi);
-  const int q = p - MU_U;                        // 0: the line's root; 2i-1, 2i: -+ 2^(-20+8(i-1)) w
-  if (q > 0) {
-    const double off = w * __builtin_amdgcn_ldexp(1.0, -20 + 8 * ((q - 1) >> 1));
-    ms += (q & 1) ? -off : off;
+  if (s[MS_IT] == 0.0) {
+#pragma unroll
+    for (int p = 0; p < MU_P; ++p) xs[p] = lo + (p + 1) * (w / (MU_P + 1));
+    return;
   }
-  return fmin(fmax(ms, lo), hi);
+#pragma unroll
+  for (int p = 0; p < MU_U; ++p) xs[p] = lo + (p + 1) * (w / (MU_U + 1));
+  const double nlo = s[MS_NLO], nhi = s[MS_NHI];
+  const double ms0 = (nhi > nlo) ? lo + (ne - nlo) / (nhi - nlo) * w : 0.5 * (lo + hi);
+#pragma unroll
+  for (int q = 0; q < MU_P - MU_U; ++q) {        // 0: the line's root; 2i-1, 2i: -+ 2^(-20+8(i-1)) w
+    double ms = ms0;
+    if (q > 0) {
+      const double off = w * __builtin_amdgcn_ldexp(1.0, -20 + 8 * ((q - 1) >> 1));
+      ms += (q & 1) ? -off : off;
+    }
+    xs[MU_U + q] = fmin(fmax(ms, lo), hi);
+  }
 }
 
 // The bracket after a step that evaluated N at the points of s (Np[p]):
@@ -110,9 +118,12 @@ __device__ __forceinline__ double mu_point(const double* s, double ne, int p) {
 __device__ void mu_update(const double* s, const double* Np, double ne, double* t) {
   const double lo = s[MS_LO], hi = s[MS_HI];
   double nlo = lo, nhi = hi, Nlo = s[MS_NLO], Nhi = s[MS_NHI];
+  double xs[MU_P];
+  mu_points(s, ne, xs);
   int exact = -1;
+#pragma unroll
   for (int p = 0; p < MU_P; ++p) {
-    const double x = mu_point(s, ne, p);
+    const double x = xs[p];
     if (Np[p] < ne) {
       if (x > nlo) { nlo = x; Nlo = Np[p]; }
     } else {
@@ -121,7 +132,8 @@ __device__ void mu_update(const double* s, const double* Np, double ne, double* 
     }
   }
   double x_exact = 0.0;
-  if (exact >= 0) x_exact = mu_point(s, ne, exact);
+#pragma unroll
+  for (int p = 0; p < MU_P; ++p) x_exact = p == exact ? xs[p] : x_exact;
   if (exact >= 0) nlo = nhi = x_exact;
   else if (nlo >= nhi) nlo = nhi = 0.5 * (nlo + nhi);   // N not monotone at rounding level
   t[MS_LO] = nlo; t[MS_HI] = nhi; t[MS_NLO] = Nlo; t[MS_NHI] = Nhi; t[MS_IT] = s[MS_IT] + 1.0;
@@ -205,8 +217,7 @@ __global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g, int it) {
   const double cut = 40.0 * g.kT;                 // f = 0 or 2 to rounding beyond this
   const double ikT = 1.0 / g.kT;
   double xs[MU_P];
-#pragma unroll
-  for (int p = 0; p < MU_P; ++p) xs[p] = mu_point(st, g.n_e, p);
+  mu_points(st, g.n_e, xs);
   // f(x_p) = 2 / (1 + E_p), E_p = exp((l - x_p) / kT). The evenly spaced
   // points x_p = lo + (p + 1) h give E_{p+1} = E_p exp(-h / kT): one
   // exponential per Ritz value and a product per point. The points about the
