@@ -33,11 +33,13 @@ def traffic_record_path(workload):
     return os.path.join(ROOT, "profiles", f"k_lanczos_{workload}_traffic.md")
 
 
-def measured_traffic(workload, precision, kernel, workgroups):
+def measured_traffic(workload, precision, kernel, workgroups, seeds, groups):
     """HBM bytes per k_lanczos launch from the committed FETCH_SIZE/WRITE_SIZE
-    record, if it was taken on this workload and precision, with the current
-    kernel source, for the same kernel instance and workgroup count (the
-    fetched bytes depend on how many spheres share each L2), else None."""
+    record, if it was taken on this workload, precision, seeding and grouping
+    (a record without the last two was taken with block seeds, ungrouped),
+    with the current kernel source, for the same kernel instance and workgroup
+    count (the fetched bytes depend on how many spheres share each L2), else
+    None."""
     import hashlib
     try:
         rec = None
@@ -46,6 +48,8 @@ def measured_traffic(workload, precision, kernel, workgroups):
                 if line.startswith("traffic-record:"):
                     rec = json.loads(line.split(":", 1)[1])
         if rec is None or rec["workload"] != workload or rec["precision"] != precision:
+            return None
+        if rec.get("seeds", "block") != seeds or int(rec.get("groups", 1)) != int(groups):
             return None
         if rec["kernel"] != kernel or int(rec["workgroups"]) != int(workgroups):
             return None
@@ -181,13 +185,14 @@ def run_graph(ctx, w, params, pos0, vel0, precision, steps, warmup, dt, stream, 
     return {"seconds": t1 - t0, "stats": stats, "e_last": e_last}
 
 
-def lanczos_roofline(w_name, head_prec, head, shape, N, dev, torch):
+def lanczos_roofline(w_name, head_prec, head, shape, N, dev, torch, seeds, groups):
     """k_lanczos HBM roofline of a timed run: the algorithmic basis bytes the
     kernel counted (V_0 and every new block written once, V_{k-1} read once per
     step, 2 (k+1) blocks of 4n x 4 values per re-orthogonalisation pass at
     step k) over its average launch time from HIP events on the library
     stream; traffic from the committed FETCH_SIZE/WRITE_SIZE record when it
-    matches this source, kernel instance and workgroup count."""
+    matches this workload, seeding, grouping, source, kernel instance and
+    workgroup count."""
     lz_ms, lz_n = head["phases"]["lanczos"]
     lz_avg_ms = lz_ms / max(lz_n, 1)
     bytes_launch = float(head["stats"]["basis_bytes"])
@@ -200,7 +205,8 @@ def lanczos_roofline(w_name, head_prec, head, shape, N, dev, torch):
             "double" if head_prec == "fp64" else "float", shape["lanczos_threads"],
             shape["lanczos_waves_per_simd"], tf(head_prec == "bf16"), tf(layout == 1), tf(layout == 2), tf(layout == 3))
         n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
-        traffic = measured_traffic(w_name, head_prec, lz_kernel, min(n_cu * shape["lanczos_wg_per_cu"], N))
+        traffic = measured_traffic(w_name, head_prec, lz_kernel, min(n_cu * shape["lanczos_wg_per_cu"], N),
+                                   seeds, groups)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": "k_lanczos", "avg_ms": round(lz_avg_ms, 4),
@@ -354,7 +360,8 @@ def main():
     N = w.n_atoms
     head_prec = headline_of(results)
     head = results[head_prec]
-    roof = lanczos_roofline(args.workload, head_prec, head, shapes.get(head_prec), N, dev, torch)
+    roof = lanczos_roofline(args.workload, head_prec, head, shapes.get(head_prec), N, dev, torch,
+                            args.seeds, args.groups)
 
     # the metric's second size: the 15360-atom crystal, mixed vs batched FP64
     large = None
@@ -369,7 +376,7 @@ def main():
                  "ms_per_step": round(lres[lhp]["ms_per_step"], 3),
                  "steps_from": "one fixed start state" if lfixed else "a velocity-Verlet trajectory",
                  "roofline": lanczos_roofline(args.large_workload, lhp, lres[lhp], lshapes.get(lhp),
-                                              lw.n_atoms, dev, torch),
+                                              lw.n_atoms, dev, torch, args.seeds, args.groups),
                  "modes": {p: mode_record(r, lw.n_atoms, lshapes, p) for p, r in lres.items()}}
         if lhp != "fp64":
             large["mixed_over_fp64"] = round(lres[lhp]["steps_per_s"] / lres["fp64"]["steps_per_s"], 3)
