@@ -414,10 +414,14 @@ __device__ double twisted_ck(const double* D, const double* E, const double* E2,
   }
   int r = d - 1;
   double best = 3.0e300, m = 0.0;
+  // each sweep over the runs loads the next run's checkpoint while the
+  // current run is recomputed (the load is off the recurrence's chain)
+  double ckn = ckf[(size_t)(nck - 1) * ns];
   for (int c = nck - 1; c >= 0; --c) {
     const int k0 = c * CK;
     double pv[CK];
-    pv[0] = ckf[(size_t)c * ns];
+    pv[0] = ckn;
+    if (c > 0) ckn = ckf[(size_t)(c - 1) * ns];
 #pragma unroll
     for (int u = 1; u < CK; ++u) pv[u] = (k0 + u < d) ? fwd(pv[u - 1], k0 + u) : 0.0;
 #pragma unroll
@@ -448,10 +452,12 @@ __device__ double twisted_ck(const double* D, const double* E, const double* E2,
     }
   };
   // k < r: z_k = -E_k z_{k+1} / d+_k
+  ckn = ckf[(size_t)((r - 1) / CK) * ns];
   for (int c = (r - 1) / CK; r > 0 && c >= 0; --c) {
     const int k0 = c * CK;
     double pv[CK];
-    pv[0] = ckf[(size_t)c * ns];
+    pv[0] = ckn;
+    if (c > 0) ckn = ckf[(size_t)(c - 1) * ns];
 #pragma unroll
     for (int u = 1; u < CK; ++u) pv[u] = (k0 + u < d) ? fwd(pv[u - 1], k0 + u) : 1.0;
 #pragma unroll
@@ -464,11 +470,13 @@ __device__ double twisted_ck(const double* D, const double* E, const double* E2,
   }
   // k > r: z_k = -E_{k-1} z_{k-1} / d-_k
   z = 1.0;
+  ckn = ((r + 1) / CK + 1 < nck) ? ckb[(size_t)((r + 1) / CK + 1) * ns] : 0.0;
   for (int c = (r + 1) / CK; c < nck; ++c) {
     const int k0 = c * CK;
     double mv[CK];
     // d- over the run, downward from the next run's checkpoint (or from row d - 1)
-    double mm = (c + 1 < nck) ? ckb[(size_t)(c + 1) * ns] : 0.0;
+    double mm = ckn;
+    ckn = (c + 2 < nck) ? ckb[(size_t)(c + 2) * ns] : 0.0;
 #pragma unroll
     for (int u = CK - 1; u >= 0; --u) {
       const int k = k0 + u;
