@@ -186,6 +186,37 @@ def test_large_r_max_capacity_agrees(torch_cuda, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_sphere_capacity_agrees(torch_cuda, precision):
+    """The sphere capacity nc_max sizes the local-structure kernel's LDS: with
+    hop lists of at most 32 slots it keeps each slot's local partner in LDS for
+    its second pass while nc_max (32 + 2 zmax) bytes fit in 48 KB, and repeats
+    the coupling tests otherwise. At hop capacity 32, a context sized for
+    spheres of 560 atoms (the second path; the FP64 Krylov kernel's LDS admits
+    at most about 588) and one sized for 130 (the first) give the same result
+    on c60_240, to rounding."""
+    from paper_0910_4497_amd.tb import TBContext
+    w = inputs.workload("c60_240")
+    runs = {}
+    for nc in (130, 560):
+        assert (nc * (32 + 2 * 32) + 64 <= 48 * 1024) == (nc == 130)
+        ctx = TBContext(w.n_atoms, nc, 30, hop_max=32)
+        runs[nc] = gpu_run(ctx, w.pos, w.cell, (1, 1, 1), w.r_cut, 30, w.kT, n_electrons=w.n_electrons,
+                           precision=precision)
+        ctx.close()
+    a, b = runs[130], runs[560]
+    assert a["stats"]["flags"] == 0 and b["stats"]["flags"] == 0
+    assert a["stats"]["max_cluster"] == b["stats"]["max_cluster"] <= 130
+    assert np.array_equal(a["col_j"], b["col_j"])
+    drho = float(np.abs(a["rho"] - b["rho"]).max())
+    df = float(np.abs(a["forces"] - b["forces"]).max())
+    print(f"  {precision}: |d rho| {drho:.2e}, |d F| {df:.2e} eV/A, d mu {abs(a['mu'] - b['mu']):.2e}")
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert abs(a["mu"] - b["mu"]) <= tol * max(1.0, abs(a["mu"]))
+    assert drho <= tol * float(np.abs(a["rho"]).max())
+    assert df <= (1e-10 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_three_waves_per_simd_shape_agrees(torch_cuda, precision):
     """The 168-VGPR build of the Krylov kernel (3 waves per SIMD, 256
     threads) runs the same arithmetic as the 128-VGPR one (4 waves per SIMD):
