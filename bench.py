@@ -97,6 +97,11 @@ def parse():
     ap.add_argument("--large-workload", default="c60_15360",
                     help="second size of the metric, run after the headline workload at FP32 and "
                          "FP64 (batched; '' to skip)")
+    ap.add_argument("--scaling-series", default="",
+                    help="comma-separated k: after the other runs, time FP32 and FP64 MD steps on the "
+                         "k x k x k C60 crystals at the c60_1920 settings (N = 240 k^3; '' to skip)")
+    ap.add_argument("--scaling-steps", type=int, default=10,
+                    help="timed steps per precision and size of the scaling series (1 warm-up step)")
     ap.add_argument("--histogram-workload", default="c60_6480_strained",
                     help="report the cutoff-sphere size histogram of this workload's start ('' to skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -382,6 +387,29 @@ def main():
             large["mixed_over_fp64"] = round(lres[lhp]["steps_per_s"] / lres["fp64"]["steps_per_s"], 3)
             large["force_err_vs_fp64_eV_per_A"] = lres[lhp]["force_err"]
 
+    # cost against N at fixed sphere settings (Sec. 2: O(n^3 N)): atom solves
+    # per second should not depend on N
+    series = None
+    if args.scaling_series:
+        import copy
+        sargs = copy.copy(args)
+        sargs.steps, sargs.warmup = args.scaling_steps, 1
+        points = []
+        for k in [int(x) for x in args.scaling_series.split(",") if x.strip()]:
+            sw, sres, sshapes, _, sncl, snmax, sfixed = run_workload(
+                f"c60_scale_k{k}", ["fp32", "fp64"], sargs, stream, torch, inputs, TBContext, graph=False)
+            pt = {"k": k, "n_atoms": sw.n_atoms, "cluster_atoms_mean": round(float(np.mean(sncl)), 2),
+                  "cluster_atoms_max": snmax,
+                  "steps_from": "one fixed start state" if sfixed else "a velocity-Verlet trajectory"}
+            for p, r in sres.items():
+                m = mode_record(r, sw.n_atoms, sshapes, p)
+                pt[p] = {key: m[key] for key in ("ms_per_step", "atom_solves_per_s", "phase_ms_per_step",
+                                                 "force_err_vs_fp64_eV_per_A", "launch_shape") if key in m}
+            points.append(pt)
+        series = {"what": "MD steps at fixed sphere settings against N: k x k x k fcc C60 cells, "
+                          "lattice 12.0 A, jitter 0.05 A, R_cut 7 A, r = 40, kT 0.1 eV",
+                  "steps": sargs.steps, "warmup": sargs.warmup, "points": points}
+
     hist = None
     if args.histogram_workload:
         hist = sphere_histogram(args.histogram_workload, torch, inputs, TBContext)
@@ -452,6 +480,8 @@ def main():
                           "ratio": ratio, "force_err_eV_per_A": large.get("force_err_vs_fp64_eV_per_A"),
                           "met": bool(ratio is not None and ratio >= 5.0
                                       and large.get("force_err_vs_fp64_eV_per_A", 1.0) <= 1e-3)}
+    if series is not None:
+        line["scaling_series"] = series
     if hist is not None:
         line["sphere_histogram_" + args.histogram_workload] = hist
     print(json.dumps(line))

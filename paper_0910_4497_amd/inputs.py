@@ -150,8 +150,10 @@ class Workload:
 
 def workload(name: str) -> Workload:
     """The five C60 workloads (names 'c60_240' ... 'c60_15360'), the
-    4 x 4 x 4 cubic-diamond cell 'diamond_512', and 'c60_1920_long' (the
-    1920-atom crystal with the long-range hopping of PARAMS_LONG)."""
+    4 x 4 x 4 cubic-diamond cell 'diamond_512', 'c60_1920_long' (the
+    1920-atom crystal with the long-range hopping of PARAMS_LONG) and the
+    size series 'c60_scale_k<k>' (k x k x k cells, lattice constant, jitter,
+    cutoff radius and Krylov order of c60_1920; k = 2 is c60_1920 itself)."""
     if name == "c60_240":           # one compressed conventional cell
         pos, L, _ = fcc_c60(1, 12.5, 0.02, 1001)
         return Workload(name, pos, L, r_cut=6.0, r=30)
@@ -175,6 +177,12 @@ def workload(name: str) -> Workload:
     if name == "c60_1920_long":     # the 1920-atom crystal with hopping to 7 A (dense local H)
         pos, L, _ = fcc_c60(2, 12.0, 0.05, 1002)
         return Workload(name, pos, L, r_cut=8.0, r=40, params=PARAMS_LONG, hop_max=256)
+    if name.startswith("c60_scale_k"):  # k x k x k cells at the c60_1920 settings (N = 240 k^3)
+        k = int(name[len("c60_scale_k"):])
+        if not 1 <= k <= 8:
+            raise KeyError(name)
+        pos, L, _ = fcc_c60(k, 12.0, 0.05, 1002 if k == 2 else 1010 + k)
+        return Workload(name, pos, L, r_cut=7.0, r=40)
     raise KeyError(name)
 
 
