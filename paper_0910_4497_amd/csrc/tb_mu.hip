@@ -43,12 +43,52 @@ enum { MS_LO = 0, MS_HI = 1, MS_DONE = 3, MS_IT = 6, MS_NLO = 7, MS_NHI = 8 };
 constexpr int MU_FINAL = 2;        // the chemical potential the density matrix uses
 constexpr int MU_STATE0 = 16;      // state buffers at 16 and 32
 
+// 1/q: the hardware reciprocal refined by one Newton step.
+__device__ __forceinline__ double rcp_nr(double q) {
+  const double r = __builtin_amdgcn_rcp(q);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
+// Sums of the MU_P point values over a wave by a reduce-scatter: at each of
+// the five halvings a lane keeps one half of its values and adds its
+// partner's copy of that half (16 + 8 + 4 + 2 + 1 shuffles), then a last
+// exchange with the neighbouring lane; lane l ends with the wave's total of
+// value l / 2 (l even and odd alike).
+__device__ __forceinline__ double wave_sum_points(const double (&v)[MU_P], int lane) {
+  double a[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) a[q] = q < MU_P ? v[q] : 0.0;
+#pragma unroll
+  for (int h = 16, off = 32; h >= 1; h >>= 1, off >>= 1) {
+    const bool upper = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const double keep = upper ? a[i + h] : a[i], send = upper ? a[i] : a[i + h];
+      a[i] = keep + __shfl_xor(send, off, 64);
+    }
+  }
+  return a[0] + __shfl_xor(a[0], 1, 64);
+}
+
 // Per-block sums of M values over the workgroup (waves in order, then the
 // waves' results): the totals land in out[0..M-1] (shared memory).
 template <int M, int OP>
 __device__ void block_reduce(double (&v)[M], double* out) {
-  __shared__ double red[MU_NT / 64][M];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if constexpr (M == MU_P && OP == 0) {
+    __shared__ double redp[MU_NT / 64][32];
+    const double t = wave_sum_points(v, lane);
+    if ((lane & 1) == 0) redp[wave][lane >> 1] = t;
+    __syncthreads();
+    if (tid < M) {
+      double sm = 0.0;
+      for (int w = 0; w < MU_NT / 64; ++w) sm += redp[w][tid];
+      out[tid] = sm;
+    }
+    __syncthreads();
+    return;
+  }
+  __shared__ double red[MU_NT / 64][M];
   auto comb = [](double a, double b) { return OP == 0 ? a + b : fmin(a, b); };
   const double ident = OP == 0 ? 0.0 : 1e300;
 #pragma unroll
@@ -155,7 +195,8 @@ __global__ void __launch_bounds__(MU_NT) k_mu_bracket(MuArgs g) {
 
 // Adds f(x_p) w for the NE evenly spaced points x_p (E_p = exp((l - x_p)/kT)
 // by products from E_0 = exp(z0), or one exponential per point when |z0| is
-// beyond 600).
+// beyond 600; f = 2 / (1 + E) by the refined hardware reciprocal, E kept
+// below 1e300 so that 1 + E stays finite).
 template <int NE>
 __device__ __forceinline__ void even_points(double (&v)[MU_P], const double (&xs)[MU_P], double l, double z0,
                                             double qstep, double ikT, double w) {
@@ -164,11 +205,11 @@ __device__ __forceinline__ void even_points(double (&v)[MU_P], const double (&xs
 #pragma unroll
     for (int p = 0; p < NE; ++p) {
       if (p > 0) E *= qstep;
-      v[p] += 2.0 / (1.0 + E) * w;
+      v[p] += 2.0 * rcp_nr(1.0 + E) * w;
     }
   } else {
 #pragma unroll
-    for (int p = 0; p < NE; ++p) v[p] += 2.0 / (1.0 + exp((l - xs[p]) * ikT)) * w;
+    for (int p = 0; p < NE; ++p) v[p] += 2.0 * rcp_nr(1.0 + fmin(exp((l - xs[p]) * ikT), 1e300)) * w;
   }
 }
 
@@ -261,10 +302,11 @@ __global__ void __launch_bounds__(MU_NT) k_mu_iter(MuArgs g, int it) {
         if (cprod && fabs(zm) <= 600.0) {
           const double Em = exp(zm);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) v[MU_U + c] += 2.0 / (1.0 + Em * cfac[c]) * w;
+          for (int c = 0; c < NC; ++c) v[MU_U + c] += 2.0 * rcp_nr(1.0 + fmin(Em * cfac[c], 1e300)) * w;
         } else {
 #pragma unroll
-          for (int c = 0; c < NC; ++c) v[MU_U + c] += 2.0 / (1.0 + exp((l - xs[MU_U + c]) * ikT)) * w;
+          for (int c = 0; c < NC; ++c)
+            v[MU_U + c] += 2.0 * rcp_nr(1.0 + fmin(exp((l - xs[MU_U + c]) * ikT), 1e300)) * w;
         }
       }
     }
