@@ -71,14 +71,26 @@ template <> struct Vec4<float> { typedef float4 T; };
 // Sum m values (m <= 16) over the workgroup; result in out[0..m-1] (LDS).
 // FULL: the first barrier is a full one (global stores become visible to the
 // workgroup); otherwise both order LDS only.
+// More than four values are summed over the wave by the reduce-scatter of
+// wave_sum16 (17 shuffles for up to 16 values instead of 6 per value).
 template <int M, int NW, bool FULL = false>
 __device__ __forceinline__ void block_sum(double (&v)[M], double* red, double* out) {
+  static_assert(M <= 16, "at most 16 values");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if constexpr (M > 4) {
+    double a[16];
 #pragma unroll
-  for (int q = 0; q < M; ++q) v[q] = wave_sum(v[q]);
-  if (lane == 0) {
+    for (int q = 0; q < 16; ++q) a[q] = q < M ? v[q] : 0.0;
+    int which;
+    const double sum = wave_sum16(a, lane, which);
+    if ((lane & 3) == 0 && which < M) red[wave * 16 + which] = sum;
+  } else {
 #pragma unroll
-    for (int q = 0; q < M; ++q) red[wave * 16 + q] = v[q];
+    for (int q = 0; q < M; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < M; ++q) red[wave * 16 + q] = v[q];
+    }
   }
   if (FULL) __syncthreads(); else lds_barrier();
   if (tid < M) {
