@@ -577,16 +577,21 @@ k_lanczos(LanczosArgs g) {
           }
         }
         }
-        // reduce over lanes with equal (lane & 3), then over waves
+        // reduce over lanes with equal (lane & 3), then over waves: a
+        // reduce-scatter on lane bits 2 and 3 (each lane keeps half of its
+        // values and adds its partner's copy of that half), then bits 4 and 5;
+        // the pairwise additions are those of a butterfly over offsets 4, 8,
+        // 16, 32 in that order. Lane l < 16 ends with value (l >> 2) of
+        // column l & 3.
         if constexpr (!AL) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int off = 4; off < 64; off <<= 1) accA[q] += __shfl_xor(accA[q], off, 64);
-          if (lane < 4) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) s_red[wave * 16 + q * 4 + lane] = accA[q];
-          }
+          const bool h2 = lane & 4, h3 = lane & 8;
+          const double k0 = h2 ? accA[1] : accA[0], k1 = h2 ? accA[3] : accA[2];
+          const double s0 = h2 ? accA[0] : accA[1], s1 = h2 ? accA[2] : accA[3];
+          const double b0 = k0 + __shfl_xor(s0, 4, 64), b1 = k1 + __shfl_xor(s1, 4, 64);
+          double t = (h3 ? b1 : b0) + __shfl_xor(h3 ? b0 : b1, 8, 64);
+          t += __shfl_xor(t, 16, 64);
+          t += __shfl_xor(t, 32, 64);
+          if (lane < 16) s_red[wave * 16 + lane] = t;
         }
         lds_barrier();
         if (tid < 16) {
