@@ -144,11 +144,16 @@ __global__ void __launch_bounds__(FF_NT) k_forces(ForceArgs g) {
     g.forces[3 * k + 1] = sc * F[1];
     g.forces[3 * k + 2] = sc * F[2];
   }
+  {
+    // the nine sums over the wave by the reduce-scatter of wave_sum16 (its
+    // pairwise additions are those of wave_sum, in the same order)
+    double a[16];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) W[q] = wave_sum(W[q]);
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int q = 0; q < 9; ++q) s_w[threadIdx.x >> 6][q] = W[q];
+    for (int q = 0; q < 16; ++q) a[q] = q < 9 ? W[q] : 0.0;
+    int which;
+    const int lane = threadIdx.x & 63;
+    const double sum = wave_sum16(a, lane, which);
+    if ((lane & 3) == 0 && which < 9) s_w[threadIdx.x >> 6][which] = sum;
   }
   __syncthreads();
   if (threadIdx.x < 9) {
