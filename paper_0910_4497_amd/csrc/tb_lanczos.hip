@@ -197,10 +197,13 @@ k_lanczos(LanczosArgs g) {
   };
   VT* s_Va = (VT*)smem;                                     // [Rcap][4] current V_k
   VT* s_W = s_Va + (size_t)Rcap * 4;                        // [Rcap][4]
-  double* s_C = (double*)at16(s_W + (size_t)Rcap * 4);
-  // s_C: [max(r_max, LZ_NW)][16] projection coefficients / partials
+  // s_C: [max(r_max, 2 LZ_NW)][16] projection coefficients of a
+  // re-orthogonalisation pass in the recursion's precision (they are only
+  // used rounded to it), with the FP64 partial sums of a short basis behind
+  // the coefficient blocks
+  VT* s_C = (VT*)at16(s_W + (size_t)Rcap * 4);
   const int cslots = (g.r_max > 2 * LZ_NW ? g.r_max : 2 * LZ_NW);
-  double* s_red = s_C + (size_t)cslots * 16;                // [LZ_NW][16]
+  double* s_red = (double*)at16(s_C + (size_t)cslots * 16);  // [LZ_NW][16]
   double* s_misc = s_red + LZ_NW * 16;                      // 224 doubles
   int* s_off = (int*)(s_misc + 224);                        // [ncap+1]
   int* s_gid = s_off + ncap + 1;                            // [ncap]
@@ -802,10 +805,10 @@ k_lanczos(LanczosArgs g) {
         // short bases are split over the waves by rows; the partial sums go
         // to the free slots of s_C behind the nb coefficient blocks
         int parts = (nb >= 2 * LZ_NW) ? 1 : (2 * LZ_NW + nb - 1) / nb;
-        const int pmax = (cslots - nb) / nb;
+        const int pmax = (int)(((size_t)(cslots - nb) * sizeof(VT) / sizeof(double)) / nb);
         parts = parts <= pmax ? parts : (pmax > 1 ? pmax : 1);
         const int items = nb * parts;
-        double* s_Cp = s_C + nb * 16;
+        double* s_Cp = (double*)(s_C + nb * 16);
         for (int it = wave; it < items; it += LZ_NW) {
           const int j = it / parts, part = it % parts;
           const VT* Vj = vbase + (size_t)j * Rcap * 4;
@@ -858,7 +861,7 @@ k_lanczos(LanczosArgs g) {
           if ((lane & 3) == 0) {
             // orbital seeds: a chain is orthogonalised against its own vectors only
             const double cv = (g.scalar && (which >> 2) != (which & 3)) ? 0.0 : sum;
-            if (parts == 1) s_C[j * 16 + which] = cv;
+            if (parts == 1) s_C[j * 16 + which] = (VT)cv;
             else s_Cp[it * 16 + which] = cv;
           }
           if (want_norm) {
@@ -873,7 +876,7 @@ k_lanczos(LanczosArgs g) {
             const int j = q >> 4, e = q & 15;
             double sum = 0.0;
             for (int p = 0; p < parts; ++p) sum += s_Cp[(j * parts + p) * 16 + e];
-            s_C[q] = sum;
+            s_C[q] = (VT)sum;
           }
         }
         if (tid < 4) {
@@ -899,7 +902,7 @@ k_lanczos(LanczosArgs g) {
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
               const VT v0[4] = {av[u].x, av[u].y, av[u].z, av[u].w};
-              const double* C0 = s_C + (j + u) * 16;
+              const VT* C0 = s_C + (j + u) * 16;
 #pragma unroll
               for (int d = 0; d < 4; ++d) {
                 VT t = w[d];
@@ -912,7 +915,7 @@ k_lanczos(LanczosArgs g) {
           for (; j < nb; ++j) {
             const V4 a0 = *(const V4*)(vbase + (size_t)j * Rcap * 4 + 4 * row);
             const VT v0[4] = {a0.x, a0.y, a0.z, a0.w};
-            const double* C0 = s_C + j * 16;
+            const VT* C0 = s_C + j * 16;
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
               VT t = w[d];
@@ -1123,7 +1126,7 @@ size_t lanczos_lds_bytes(int nc_max, int r_max, bool fp32, int nt, bool om_lds, 
   const int nw = nt / 64;
   size_t b = 2 * Rcap * 4 * vt + 16;
   const int cslots = r_max > 2 * nw ? r_max : 2 * nw;
-  b += (size_t)cslots * 16 * 8 + nw * 16 * 8 + 224 * 8;
+  b += (size_t)cslots * 16 * vt + 16 + nw * 16 * 8 + 224 * 8;
   b += (size_t)(nc_max + 1) * 4 + (size_t)nc_max * 4 + (size_t)nc_max * 2 + 16;
   if (om_lds) b += (size_t)3 * r_max * 16 * 4;
   if (ab_lds) b += (size_t)r_max * 32 * 4;
