@@ -39,6 +39,25 @@ def test_fcc_workload_shapes():
     assert np.array_equal(w.pos, w2.pos)                 # seeded, reproducible
 
 
+def test_size_series_workloads():
+    """The size series keeps the c60_1920 settings at k x k x k cells: N =
+    240 k^3, box 12 k A, R_cut 7 A, r = 40, and k = 2 is c60_1920 itself; the
+    starts have no contact shorter than 1.1 A (no atom near the turnover of
+    the repulsive embedding)."""
+    from scipy.spatial import cKDTree
+    ref = inputs.workload("c60_1920")
+    for k in (2, 3, 4):
+        w = inputs.workload(f"c60_scale_k{k}")
+        assert w.pos.shape == (240 * k ** 3, 3)
+        assert np.allclose(w.cell, 12.0 * k) and w.r_cut == ref.r_cut and w.r == ref.r and w.kT == ref.kT
+        assert np.all((w.pos >= 0) & (w.pos < w.cell[0]))
+        nn, _ = cKDTree(w.pos, boxsize=w.cell).query(w.pos, k=2)
+        assert nn[:, 1].min() > 1.1
+    assert np.array_equal(inputs.workload("c60_scale_k2").pos, ref.pos)
+    with pytest.raises(KeyError):
+        inputs.workload("c60_scale_k9")
+
+
 def _derive_tail(head, dhead, r1, rm):
     """Cubic c0 + c1 x + c2 x^2 + c3 x^3 (x = r - r1) with the value and slope
     of `head` at r1 and value = slope = 0 at rm."""
